@@ -1,0 +1,147 @@
+/*
+ * ttfp.h -- C ABI of the tensor-train Fourier pricer for multi-asset options (gfx950).
+ *
+ * The library prices a European option on d assets that follow correlated geometric
+ * Brownian motion (the market model of Sec. II.A of "A highly efficient tensor network
+ * algorithm for multi-asset Fourier options pricing"). The price is the d-dimensional
+ * shifted-contour Fourier integral of the characteristic function times the payoff
+ * transform (Sec. III.B, Eq. maincont; Sec. III.C, Eq. main), discretised on a truncated
+ * uniform grid (Sec. III.D, Eq. discr). The integrand tensor on that grid is built as a
+ * tensor train by TT-cross (Sec. IV.B) and contracted against the quadrature weights
+ * (Sec. IV.A); the cost is linear in d instead of N^d.
+ *
+ * Max/min payoffs are priced as a sum of d separable terms, one per asset that attains the
+ * extreme; term j uses coordinates w_0 = x_j, w_l = x_l - x_j (x = log(S_T/K)).
+ *
+ * Conventions shared by every call:
+ *  - All pointers in ttfp_option / ttfp_grid are HOST pointers owned by the caller; the
+ *    library copies what it needs before returning. Output arrays are caller-owned host
+ *    memory unless the name ends in _dev, in which case they are device pointers on the
+ *    context's device (for example the storage of torch tensors).
+ *  - A context owns its device workspaces and is bound to one device and one HIP stream.
+ *    It is not thread-safe: calls on one context must not overlap.
+ *  - Return codes: 0 = success; negative = hard error, nothing written to outputs;
+ *    positive = warning, outputs written. No C++ exception crosses this boundary.
+ *    ttfp_last_error() gives the text of the last error on a context.
+ */
+#ifndef TTFP_H
+#define TTFP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TTFP_OK = 0,
+    TTFP_EINVAL = -1,     /* invalid argument: d out of range, N < 2, S0/K/sigma/T <= 0, NaN,
+                             correlation not symmetric / unit-diagonal / positive definite,
+                             contour shift outside the payoff's strip, rank beyond limits */
+    TTFP_ENOMEM = -2,     /* device allocation failed */
+    TTFP_EDEVICE = -3,    /* HIP runtime error (text in ttfp_last_error) */
+    TTFP_ENOTCONV = 1,    /* tolerance not met within max_sweeps or rank capped; price written */
+    TTFP_EPRECISION = 2   /* cancellation factor times machine epsilon exceeds tol; price written */
+};
+
+/* Payoffs (Sec. II.A uses the call on the minimum, Eq. minpayoff). */
+typedef enum { TTFP_CALL_MAX = 0, TTFP_PUT_MAX = 1, TTFP_CALL_MIN = 2 } ttfp_payoff;
+
+#define TTFP_MAX_D 32      /* largest number of assets */
+#define TTFP_MAX_RANK 64   /* largest TT rank (plus enrichment columns <= 68) */
+
+/* One option. S0[d], sigma[d] and corr[d*d] (row-major) are host arrays. */
+typedef struct {
+    int32_t d;
+    int32_t payoff;            /* ttfp_payoff */
+    const double *S0;
+    const double *sigma;
+    const double *corr;
+    double K, T, r;
+} ttfp_option;
+
+/* Grid and TT-cross settings.
+ *  N            nodes per coordinate: u_i = -L + (i + 1/2) 2L/N, i = 0..N-1
+ *  L            > 0: the same half-width on every coordinate of every term; <= 0: automatic
+ *  alpha        > 0: |contour shift| on every coordinate, signed by the coordinate's strip
+ *               (call coordinate +alpha, which must exceed 1; put coordinate -alpha;
+ *               max indicators -alpha; min indicators +alpha); <= 0: automatic
+ *  L_k, alpha_k optional [n_terms*d] per-term, per-coordinate values (alpha_k signed),
+ *               overriding L / alpha when non-NULL (n_terms = d, or 1 when d = 1)
+ *  tol          stop when the relative price change over a half sweep is <= tol
+ *  rank_tol     relative pivot threshold for rank truncation; <= 0 means 0.1 tol / sqrt(d-1)
+ *  max_rank     TT rank cap (<= TTFP_MAX_RANK); n_enrich random columns are added per step
+ *  max_sweeps   at most this many forward+backward sweeps
+ *  seed         seeds the counter-based generator for index sets and enrichment          */
+typedef struct {
+    int32_t N;
+    double L, alpha;
+    const double *L_k, *alpha_k;
+    double tol, rank_tol;
+    int32_t max_rank, max_sweeps, n_enrich;
+    uint64_t seed;
+} ttfp_grid;
+
+/* Per-option diagnostics. */
+typedef struct {
+    double imag_rel;       /* |Im price| / |Re price| */
+    double last_change;    /* relative price change over the last half sweep */
+    int64_t n_evals;       /* integrand evaluations (the paper's oracle calls) */
+    int32_t sweeps;        /* half sweeps performed */
+    int32_t rank_capped;   /* 1 if some bond hit max_rank */
+    int32_t converged;     /* 1 if the tolerance was met */
+} ttfp_diag;
+
+typedef struct ttfp_ctx ttfp_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t,
+ * NULL = the null stream). *out receives the context; the library owns it. */
+int ttfp_create(ttfp_ctx **out, int device, void *hip_stream);
+int ttfp_destroy(ttfp_ctx *ctx);
+
+/* Host-only: the per-term grid the pricer would use (Sec. III.D truncation and contour
+ * shift, with the automatic rule when L/alpha are not given). Writes n_terms, and
+ * L_out / alpha_out [n_terms*d] (may be NULL). Returns TTFP_EINVAL for invalid input.
+ * Needs no device. */
+int ttfp_plan(const ttfp_option *opt, const ttfp_grid *grid, int32_t *n_terms,
+              double *L_out, double *alpha_out);
+
+/* Price one option. ranks (nullable) receives n_terms*(d+1) bond ranks, term-major.
+ * diag is nullable. */
+int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, double *price,
+               int32_t *ranks, ttfp_diag *diag);
+
+/* Price n options in one batched pass (all terms of all options advance together).
+ * grids[i] gives option i's settings. prices[n] receives prices; delta / vega (nullable)
+ * receive sum_i d_i values each (option-major): dV/dS0_j and dV/dsigma_j at the fixed grid,
+ * from the adjoint of the contraction against the frozen tensor-train cores. status[n]
+ * (nullable) receives each option's return code. Returns the worst code. */
+int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids,
+                     double *prices, double *delta, double *vega, int32_t *status);
+
+/* The integrand of term `term` of an option at npts grid multi-indices idx[npts*d]
+ * (host, 0-based), evaluated by the GPU fiber kernel's device function. out[2*npts]
+ * receives interleaved real/imaginary parts. */
+int ttfp_eval_integrand(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, int32_t term,
+                        int64_t npts, const int32_t *idx, double *out);
+
+/* After the last ttfp_price on this context: the tensor train of term `term` evaluated at
+ * npts multi-indices idx[npts*d] (host). out[2*npts] interleaved complex. */
+int ttfp_tt_values(ttfp_ctx *ctx, int32_t term, int64_t npts, const int32_t *idx, double *out);
+
+/* Kernel-level entry points (same kernels as the pricer, exposed for verification).
+ * ttfp_qr_r: upper-triangular factor R (n x n, row-major, interleaved complex) of a QR of
+ * the m x n complex matrix A (row-major, interleaved), by the TSQR kernels; n <= 68.
+ * ttfp_maxvol: rows[r] of a dominant r x r submatrix of the m x r complex matrix A and
+ * B = A A[rows]^{-1} (m x r), by the maxvol kernel. All pointers host. */
+int ttfp_qr_r(ttfp_ctx *ctx, int32_t m, int32_t n, const double *A, double *R);
+int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double delta, int32_t *rows,
+                double *B);
+
+const char *ttfp_strerror(int code);
+const char *ttfp_last_error(const ttfp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,242 @@
+"""Tensor-train Fourier pricing of multi-asset options on AMD MI355X.
+
+Thin Python binding over the C ABI in include/ttfp.h (libttfp.so, built by
+paper_2203_02804_amd/build.py). Only argument marshalling happens here: every step of
+the pricing path runs in the library's HIP kernels. PyTorch is used for the device
+choice and the HIP stream the library enqueues on.
+
+Options and grids are the dicts produced by the `workloads` module:
+    option: d, S0, K, T, r, sigma, corr, payoff ("call_max" | "put_max" | "call_min")
+    grid:   N, L, alpha, tol, max_rank, max_sweeps, seed (+ optional n_enrich, rank_tol)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttfp.so")
+
+PAYOFF_CODES = {"call_max": 0, "put_max": 1, "call_min": 2}
+TTFP_OK, TTFP_EINVAL, TTFP_ENOMEM, TTFP_EDEVICE, TTFP_ENOTCONV, TTFP_EPRECISION = 0, -1, -2, -3, 1, 2
+MAX_RANK = 64
+
+
+class TTFPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ttfp error {code}: {msg}")
+        self.code = code
+
+
+class _Option(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("payoff", ctypes.c_int32),
+                ("S0", ctypes.POINTER(ctypes.c_double)), ("sigma", ctypes.POINTER(ctypes.c_double)),
+                ("corr", ctypes.POINTER(ctypes.c_double)),
+                ("K", ctypes.c_double), ("T", ctypes.c_double), ("r", ctypes.c_double)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("L", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("L_k", ctypes.POINTER(ctypes.c_double)), ("alpha_k", ctypes.POINTER(ctypes.c_double)),
+                ("tol", ctypes.c_double), ("rank_tol", ctypes.c_double),
+                ("max_rank", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("n_enrich", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _Diag(ctypes.Structure):
+    _fields_ = [("imag_rel", ctypes.c_double), ("last_change", ctypes.c_double), ("n_evals", ctypes.c_int64),
+                ("sweeps", ctypes.c_int32), ("rank_capped", ctypes.c_int32), ("converged", ctypes.c_int32)]
+
+
+EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_eval_integrand",
+           "ttfp_tt_values", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error"]
+
+_lib = None
+
+
+def load():
+    """Loads libttfp.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2203_02804_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.ttfp_create.argtypes = [P(vp), ctypes.c_int, vp]
+    lib.ttfp_destroy.argtypes = [vp]
+    lib.ttfp_plan.argtypes = [P(_Option), P(_Grid), P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double)]
+    lib.ttfp_price.argtypes = [vp, P(_Option), P(_Grid), P(ctypes.c_double), P(ctypes.c_int32), P(_Diag)]
+    lib.ttfp_price_batch.argtypes = [vp, ctypes.c_int32, P(_Option), P(_Grid), P(ctypes.c_double),
+                                     P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
+    lib.ttfp_eval_integrand.argtypes = [vp, P(_Option), P(_Grid), ctypes.c_int32, ctypes.c_int64,
+                                        P(ctypes.c_int32), P(ctypes.c_double)]
+    lib.ttfp_tt_values.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32), P(ctypes.c_double)]
+    lib.ttfp_qr_r.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
+    lib.ttfp_maxvol.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), ctypes.c_double,
+                                P(ctypes.c_int32), P(ctypes.c_double)]
+    lib.ttfp_strerror.argtypes = [ctypes.c_int]
+    lib.ttfp_strerror.restype = ctypes.c_char_p
+    lib.ttfp_last_error.argtypes = [vp]
+    lib.ttfp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class _Marshal:
+    """Keeps the numpy arrays behind a ctypes option/grid alive."""
+
+    def __init__(self, opt, grid):
+        d = int(opt["d"])
+        self.S0 = np.ascontiguousarray(opt["S0"], np.float64)
+        self.sigma = np.ascontiguousarray(opt["sigma"], np.float64)
+        self.corr = np.ascontiguousarray(opt["corr"], np.float64).reshape(-1)
+        if self.S0.shape != (d,) or self.sigma.shape != (d,) or self.corr.shape != (d * d,):
+            raise ValueError("option arrays do not match d")
+        self.opt = _Option(d, PAYOFF_CODES[opt.get("payoff", "call_max")], _dp(self.S0), _dp(self.sigma),
+                           _dp(self.corr), float(opt["K"]), float(opt["T"]), float(opt["r"]))
+        L, A = grid.get("L"), grid.get("alpha")
+        self.Lk = self.Ak = None
+        Ls = As = 0.0
+        if L is not None and np.ndim(L) == 0:
+            Ls = float(L)
+        elif L is not None:
+            self.Lk = np.ascontiguousarray(L, np.float64).reshape(-1)
+        if A is not None and np.ndim(A) == 0:
+            As = float(A)
+        elif A is not None:
+            self.Ak = np.ascontiguousarray(A, np.float64).reshape(-1)
+        null = ctypes.POINTER(ctypes.c_double)()
+        self.grid = _Grid(int(grid["N"]), Ls, As,
+                          _dp(self.Lk) if self.Lk is not None else null,
+                          _dp(self.Ak) if self.Ak is not None else null,
+                          float(grid.get("tol", 1e-8)), float(grid.get("rank_tol", 0.0)),
+                          int(grid.get("max_rank", 32)), int(grid.get("max_sweeps", 6)),
+                          int(grid.get("n_enrich", 4)), int(grid.get("seed", 0)) & ((1 << 64) - 1))
+
+
+def plan(opt, grid):
+    """Per-term (L, alpha) arrays [n_terms, d] the pricer uses (host logic, no device)."""
+    lib = load()
+    m = _Marshal(opt, grid)
+    d = int(opt["d"])
+    nt = ctypes.c_int32(0)
+    L = np.zeros(d * d)
+    A = np.zeros(d * d)
+    rc = lib.ttfp_plan(ctypes.byref(m.opt), ctypes.byref(m.grid), ctypes.byref(nt), _dp(L), _dp(A))
+    if rc < 0:
+        raise TTFPError(rc, lib.ttfp_strerror(rc).decode())
+    n = nt.value
+    return L[: n * d].reshape(n, d), A[: n * d].reshape(n, d)
+
+
+class Pricer:
+    """A library context bound to one HIP device and stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        torch.cuda.set_device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.ctx = ctypes.c_void_p()
+        rc = self.lib.ttfp_create(ctypes.byref(self.ctx), int(device), ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise TTFPError(rc, "ttfp_create failed")
+
+    def close(self):
+        if self.ctx:
+            self.lib.ttfp_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise TTFPError(rc, self.lib.ttfp_last_error(self.ctx).decode())
+        return rc
+
+    def price(self, opt, grid):
+        """Returns (price, ranks[n_terms, d+1], diag dict, return code)."""
+        m = _Marshal(opt, grid)
+        d = int(opt["d"])
+        out = ctypes.c_double(0.0)
+        ranks = np.zeros(d * (d + 1), np.int32)
+        diag = _Diag()
+        rc = self._check(self.lib.ttfp_price(self.ctx, ctypes.byref(m.opt), ctypes.byref(m.grid), ctypes.byref(out),
+                                             _ip(ranks), ctypes.byref(diag)))
+        info = dict(imag_rel=diag.imag_rel, last_change=diag.last_change, n_evals=diag.n_evals,
+                    sweeps=diag.sweeps, rank_capped=bool(diag.rank_capped), converged=bool(diag.converged))
+        return out.value, ranks.reshape(d, d + 1), info, rc
+
+    def price_batch(self, opts, grids, greeks=False):
+        """Prices a list of options in one batched pass. grids: one dict or a list.
+        Returns prices[n] (and delta, vega lists of per-option arrays when greeks=True), status[n]."""
+        n = len(opts)
+        if isinstance(grids, dict):
+            grids = [grids] * n
+        ms = [_Marshal(o, g) for o, g in zip(opts, grids)]
+        copts = (_Option * n)(*[m.opt for m in ms])
+        cgrids = (_Grid * n)(*[m.grid for m in ms])
+        prices = np.zeros(n)
+        status = np.zeros(n, np.int32)
+        tot = sum(int(o["d"]) for o in opts)
+        delta = np.zeros(tot) if greeks else None
+        vega = np.zeros(tot) if greeks else None
+        null = ctypes.POINTER(ctypes.c_double)()
+        self._check(self.lib.ttfp_price_batch(self.ctx, n, copts, cgrids, _dp(prices),
+                                              _dp(delta) if greeks else null, _dp(vega) if greeks else null,
+                                              _ip(status)))
+        if not greeks:
+            return prices, status
+        split = np.cumsum([int(o["d"]) for o in opts])[:-1]
+        return prices, np.split(delta, split), np.split(vega, split), status
+
+    def eval_integrand(self, opt, grid, term, idx):
+        m = _Marshal(opt, grid)
+        idx = np.ascontiguousarray(idx, np.int32)
+        out = np.zeros(2 * idx.shape[0])
+        self._check(self.lib.ttfp_eval_integrand(self.ctx, ctypes.byref(m.opt), ctypes.byref(m.grid), int(term),
+                                                 idx.shape[0], _ip(idx), _dp(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def tt_values(self, term, idx):
+        idx = np.ascontiguousarray(idx, np.int32)
+        out = np.zeros(2 * idx.shape[0])
+        self._check(self.lib.ttfp_tt_values(self.ctx, int(term), idx.shape[0], _ip(idx), _dp(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def qr_r(self, A):
+        A = np.ascontiguousarray(A, np.complex128)
+        m, n = A.shape
+        R = np.zeros((n, n), np.complex128)
+        self._check(self.lib.ttfp_qr_r(self.ctx, m, n, _dp(A.view(np.float64)), _dp(R.view(np.float64))))
+        return R
+
+    def maxvol(self, A, delta=1e-2):
+        A = np.ascontiguousarray(A, np.complex128)
+        m, r = A.shape
+        rows = np.zeros(r, np.int32)
+        B = np.zeros((m, r), np.complex128)
+        self._check(self.lib.ttfp_maxvol(self.ctx, m, r, _dp(A.view(np.float64)), float(delta), _ip(rows),
+                                         _dp(B.view(np.float64))))
+        return rows, B

@@ -1,0 +1,806 @@
+// Host side of the pricer: the C ABI, device workspace, and the sweep driver that launches
+// the TT-cross kernels for a batch of (option, term) work items.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "plan.hpp"
+#include "ttfp.h"
+
+namespace ttfp {
+__global__ void k_init(Item *items, int n_items);
+__global__ void k_fiber(Item *items, const int *active, int t, int dir, int mode, int sweep);
+__global__ void k_eval_points(const Item *items, long long npts, const int *idx, cplx *out);
+__global__ void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G);
+__global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G);
+__global__ void k_basis(Item *items, const int *active, int t, int dir);
+__global__ void k_maxvol(Item *items, const int *active, int t, int dir);
+__global__ void k_finish(Item *items, const int *active, int t, int dir);
+__global__ void k_core_sum(Item *items, const int *active, int t, int dir, int mode);
+__global__ void k_contract(Item *items, const int *active);
+__global__ void k_core_moments(Item *items, const int *active);
+__global__ void k_moments(Item *items, const int *active, cplx *out, int stride);
+__global__ void k_tt_values(const Item *items, int item, long long npts, const int *idx, cplx *out);
+}  // namespace ttfp
+
+using namespace ttfp;
+
+struct ttfp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    // grow-only device arena for item buffers
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    Item *d_items = nullptr;
+    size_t items_cap = 0;
+    int *d_active = nullptr;
+    cplx *d_moments = nullptr;
+    size_t moments_cap = 0;
+    // last single-option call (for ttfp_tt_values)
+    std::vector<Item> last_items;
+    int last_n_items = 0;
+};
+
+namespace {
+
+const size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ctx->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);        \
+            return TTFP_EDEVICE;                                                         \
+        }                                                                                \
+    } while (0)
+
+struct Launch {
+    int BR, G, nlev, maxd, maxrows, maxnc, maxR, maxN;
+};
+
+// TSQR geometry: groups of G stacked nc x nc factors fit the LDS budget, and leaf blocks
+// have BR = G * nc rows.
+void tsqr_geometry(int nc, int &BR, int &G)
+{
+    const int cap = LDS_BYTES / (int)sizeof(cplx);
+    G = std::max(2, cap / (nc * nc));
+    BR = G * nc;
+}
+int tsqr_levels(int rows, int BR, int G)
+{
+    int n = (rows + BR - 1) / BR, l = 1;
+    while (n > 1) { n = (n + G - 1) / G; ++l; }
+    return l;
+}
+
+struct ItemSizes {
+    size_t bytes;
+    size_t off_m, off_C, off_L, off_a, off_kind, off_I, off_J, off_F, off_Rl, off_Ri, off_perm, off_Y, off_W,
+        off_Bt, off_cores, off_M, off_M1, off_M2, off_piv;
+    int rows_max, nblk_max;
+};
+
+ItemSizes item_sizes(int d, int N, int R, int p, int BR)
+{
+    ItemSizes s;
+    const int nc = R + p;
+    s.rows_max = R * N;
+    s.nblk_max = (s.rows_max + BR - 1) / BR;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    s.off_m = take(sizeof(double) * d);
+    s.off_C = take(sizeof(double) * d * d);
+    s.off_L = take(sizeof(double) * d);
+    s.off_a = take(sizeof(double) * d);
+    s.off_kind = take(sizeof(int) * d);
+    s.off_I = take(sizeof(int) * (size_t)(d + 1) * R * d);
+    s.off_J = take(sizeof(int) * (size_t)(d + 1) * R * d);
+    s.off_F = take(sizeof(cplx) * (size_t)s.rows_max * nc);
+    s.off_Rl = take(sizeof(cplx) * 2 * (size_t)s.nblk_max * nc * nc);
+    s.off_Ri = take(sizeof(cplx) * (size_t)R * R);
+    s.off_perm = take(sizeof(int) * nc);
+    s.off_Y = take(sizeof(cplx) * (size_t)s.rows_max * R);
+    s.off_W = take(sizeof(cplx) * (size_t)s.rows_max * R);
+    s.off_Bt = take(sizeof(cplx) * (size_t)s.rows_max * R);
+    s.off_cores = take(sizeof(cplx) * (size_t)d * R * N * R);
+    s.off_M = take(sizeof(cplx) * (size_t)d * R * R);
+    s.off_M1 = take(sizeof(cplx) * (size_t)d * R * R);
+    s.off_M2 = take(sizeof(cplx) * (size_t)d * R * R);
+    s.off_piv = take(sizeof(int) * R);
+    s.bytes = o;
+    return s;
+}
+
+int ensure_arena(ttfp_ctx *ctx, size_t bytes, size_t n_items)
+{
+    if (bytes > ctx->arena_bytes) {
+        if (ctx->arena) HIPCHK(hipFree(ctx->arena));
+        ctx->arena = nullptr;
+        ctx->arena_bytes = 0;
+        size_t want = std::max(bytes, (size_t)64 << 20);
+        if (hipMalloc(&ctx->arena, want) != hipSuccess) {
+            ctx->arena = nullptr;
+            (void)hipGetLastError();
+            ctx->last_error = "device allocation of the workspace failed";
+            return TTFP_ENOMEM;
+        }
+        ctx->arena_bytes = want;
+    }
+    if (n_items > ctx->items_cap) {
+        if (ctx->d_items) HIPCHK(hipFree(ctx->d_items));
+        if (ctx->d_active) HIPCHK(hipFree(ctx->d_active));
+        size_t cap = std::max(n_items, (size_t)64);
+        HIPCHK(hipMalloc(&ctx->d_items, cap * sizeof(Item)));
+        HIPCHK(hipMalloc(&ctx->d_active, cap * sizeof(int)));
+        ctx->items_cap = cap;
+    }
+    return TTFP_OK;
+}
+
+// Work items of a chunk of options.
+struct Batch {
+    std::vector<Item> items;
+    std::vector<int> item_opt;           // option (within the chunk) of each item
+    std::vector<double> item_scale;
+    std::vector<const TermPlan *> item_term;
+    Launch geo;
+};
+
+int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, const std::vector<const ttfp_grid *> &grids,
+                Batch &b)
+{
+    b = Batch();
+    int maxnc = 1, maxd = 1, maxrows = 1, maxR = 1, maxN = 2;
+    for (size_t o = 0; o < plans.size(); ++o) {
+        const ttfp_grid *g = grids[o];
+        maxnc = std::max(maxnc, g->max_rank + g->n_enrich);
+        maxd = std::max(maxd, plans[o]->d);
+        maxrows = std::max(maxrows, g->max_rank * g->N);
+        maxR = std::max(maxR, g->max_rank);
+        maxN = std::max(maxN, g->N);
+    }
+    int BR, G;
+    tsqr_geometry(maxnc, BR, G);
+    b.geo = {BR, G, tsqr_levels(maxrows, BR, G), maxd, maxrows, maxnc, maxR, maxN};
+    // layout
+    std::vector<ItemSizes> sz;
+    size_t total = 0;
+    for (size_t o = 0; o < plans.size(); ++o) {
+        const OptionPlan &P = *plans[o];
+        const ttfp_grid *g = grids[o];
+        for (size_t t = 0; t < P.terms.size(); ++t) {
+            ItemSizes s = item_sizes(P.d, g->N, g->max_rank, g->n_enrich, BR);
+            sz.push_back(s);
+            total += s.bytes;
+        }
+    }
+    const size_t n_items = sz.size();
+    int rc = ensure_arena(ctx, total, n_items);
+    if (rc) return rc;
+    // fill items and upload the static term data
+    std::vector<char> host(0);
+    size_t base = 0, idx = 0;
+    for (size_t o = 0; o < plans.size(); ++o) {
+        const OptionPlan &P = *plans[o];
+        const ttfp_grid *g = grids[o];
+        for (size_t t = 0; t < P.terms.size(); ++t, ++idx) {
+            const TermPlan &tp = P.terms[t];
+            const ItemSizes &s = sz[idx];
+            char *dev = ctx->arena + base;
+            Item it;
+            std::memset(&it, 0, sizeof it);
+            it.d = P.d;
+            it.N = g->N;
+            it.R = g->max_rank;
+            it.p = g->n_enrich;
+            it.opt = (int)o;
+            it.term = (int)t;
+            it.rank_eps = g->rank_tol > 0 ? g->rank_tol : 0.1 * g->tol / std::sqrt((double)std::max(P.d - 1, 1));
+            it.delta = 1e-2;
+            it.seed = g->seed * 0x100000001B3ull + (uint64_t)t * 0x9E3779B97F4A7C15ull + 1;
+            it.m = (const double *)(dev + s.off_m);
+            it.C = (const double *)(dev + s.off_C);
+            it.L = (const double *)(dev + s.off_L);
+            it.alpha = (const double *)(dev + s.off_a);
+            it.kind = (const int *)(dev + s.off_kind);
+            it.Iset = (int *)(dev + s.off_I);
+            it.Jset = (int *)(dev + s.off_J);
+            it.F = (cplx *)(dev + s.off_F);
+            it.Rlev = (cplx *)(dev + s.off_Rl);
+            it.Rinv = (cplx *)(dev + s.off_Ri);
+            it.perm = (int *)(dev + s.off_perm);
+            it.Y = (cplx *)(dev + s.off_Y);
+            it.W = (cplx *)(dev + s.off_W);
+            it.Bt = (cplx *)(dev + s.off_Bt);
+            it.cores = (cplx *)(dev + s.off_cores);
+            it.M = (cplx *)(dev + s.off_M);
+            it.M1 = (cplx *)(dev + s.off_M1);
+            it.M2 = (cplx *)(dev + s.off_M2);
+            it.piv = (int *)(dev + s.off_piv);
+            it.rows_max = s.rows_max;
+            it.nblk_max = s.nblk_max;
+            // static term data: one contiguous host staging block up to off_I
+            size_t head = s.off_I;
+            if (host.size() < head) host.resize(head);
+            std::memset(host.data(), 0, head);
+            std::memcpy(host.data() + s.off_m, tp.m.data(), sizeof(double) * P.d);
+            std::memcpy(host.data() + s.off_C, tp.C.data(), sizeof(double) * P.d * P.d);
+            std::memcpy(host.data() + s.off_L, tp.L.data(), sizeof(double) * P.d);
+            std::memcpy(host.data() + s.off_a, tp.alpha.data(), sizeof(double) * P.d);
+            std::memcpy(host.data() + s.off_kind, tp.kind.data(), sizeof(int) * P.d);
+            HIPCHK(hipMemcpyAsync(dev, host.data(), head, hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            b.items.push_back(it);
+            b.item_opt.push_back((int)o);
+            b.item_scale.push_back(tp.scale);
+            b.item_term.push_back(&tp);
+            base += s.bytes;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->d_items, b.items.data(), n_items * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));
+    return TTFP_OK;
+}
+
+unsigned cdivu(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
+{
+    hipStream_t st = ctx->stream;
+    Item *it = ctx->d_items;
+    int *act = ctx->d_active;
+    const unsigned ny = (unsigned)n_items;
+    hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.maxrows * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0, sweep);
+    int n = (g.maxrows + g.BR - 1) / g.BR;
+    const size_t lds = (size_t)g.BR * g.maxnc * sizeof(cplx);
+    for (int level = 0; level < g.nlev; ++level) {
+        hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(n, 1), ny), dim3(256), lds, st, it, act, t, dir, level, g.BR, g.G);
+        n = (n + g.G - 1) / g.G;
+    }
+    hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(256), 0, st, it, act, t, dir, g.BR, g.G);
+    hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir);
+    hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(1024), 0, st, it, act, t, dir);
+    hipLaunchKernelGGL(k_finish, dim3(cdivu((long long)g.maxrows * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir);
+    hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
+    HIPCHK(hipGetLastError());
+    return TTFP_OK;
+}
+
+int launch_edge(ttfp_ctx *ctx, const Launch &g, int n_items, int dir, int sweep)
+{
+    hipStream_t st = ctx->stream;
+    const unsigned ny = (unsigned)n_items;
+    hipLaunchKernelGGL(k_fiber, dim3(cdivu(g.maxrows, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1, sweep);
+    hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1);
+    hipLaunchKernelGGL(k_contract, dim3(ny), dim3(64), 0, st, ctx->d_items, ctx->d_active);
+    HIPCHK(hipGetLastError());
+    return TTFP_OK;
+}
+
+struct OptResult {
+    double price = 0, imag = 0, change = INFINITY;
+    int sweeps = 0, capped = 0, converged = 0;
+    long long evals = 0;
+    int code = TTFP_OK;
+};
+
+// Runs TT-cross on every item of the batch until each option's price is stable.
+int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &grids, std::vector<OptResult> &res,
+              bool greeks, std::vector<std::complex<double>> *moments, int &mstride)
+{
+    const int n_items = (int)b.items.size();
+    const int n_opts = (int)grids.size();
+    res.assign(n_opts, OptResult());
+    std::vector<int> active(n_items, 1);
+    HIPCHK(hipMemcpyAsync(ctx->d_active, active.data(), n_items * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_init, dim3(cdivu(n_items, 64)), dim3(64), 0, ctx->stream, ctx->d_items, n_items);
+    HIPCHK(hipGetLastError());
+    int max_sweeps = 1;
+    for (auto *g : grids) max_sweeps = std::max(max_sweeps, g->max_sweeps);
+    std::vector<double> prev(n_opts, NAN);
+    std::vector<int> opt_active(n_opts, 1);
+    std::vector<Item> host_items(n_items);
+    int half = 0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        for (int dir = 0; dir < 2; ++dir, ++half) {
+            for (int t = 0; t + 1 < b.geo.maxd; ++t) {
+                int rc = launch_step(ctx, b.geo, n_items, t, dir, sweep);
+                if (rc) return rc;
+            }
+            int rc = launch_edge(ctx, b.geo, n_items, dir, sweep);
+            if (rc) return rc;
+            HIPCHK(hipMemcpyAsync(host_items.data(), ctx->d_items, n_items * sizeof(Item), hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            std::vector<double> pr(n_opts, 0.0), pi(n_opts, 0.0);
+            std::vector<long long> ev(n_opts, 0);
+            std::vector<int> cap(n_opts, 0);
+            for (int i = 0; i < n_items; ++i) {
+                const int o = b.item_opt[i];
+                pr[o] += b.item_scale[i] * host_items[i].P.x;
+                pi[o] += b.item_scale[i] * host_items[i].P.y;
+                ev[o] += host_items[i].n_evals;
+                cap[o] |= host_items[i].capped;
+            }
+            bool any = false;
+            for (int o = 0; o < n_opts; ++o) {
+                if (!opt_active[o]) continue;
+                OptResult &r = res[o];
+                r.price = pr[o];
+                r.imag = pi[o];
+                r.evals = ev[o];
+                r.capped = cap[o];
+                r.sweeps = half + 1;
+                if (!std::isnan(prev[o])) r.change = std::fabs(pr[o] - prev[o]) / std::max(std::fabs(pr[o]), 1e-300);
+                prev[o] = pr[o];
+                const bool last = (sweep == grids[o]->max_sweeps - 1 && dir == 1);
+                if (half >= 1 && r.change <= grids[o]->tol) {
+                    r.converged = 1;
+                    opt_active[o] = 0;
+                } else if (last) {
+                    opt_active[o] = 0;
+                } else {
+                    any = true;
+                }
+            }
+            bool changed = false;
+            for (int i = 0; i < n_items; ++i) {
+                int a = opt_active[b.item_opt[i]];
+                if (a != active[i]) { active[i] = a; changed = true; }
+            }
+            if (changed)
+                HIPCHK(hipMemcpyAsync(ctx->d_active, active.data(), n_items * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+            if (!any) goto done;
+        }
+    }
+done:
+    for (int o = 0; o < n_opts; ++o) {
+        OptResult &r = res[o];
+        r.code = (r.converged && !r.capped) ? TTFP_OK : TTFP_ENOTCONV;
+    }
+    if (greeks) {
+        std::fill(active.begin(), active.end(), 1);
+        HIPCHK(hipMemcpyAsync(ctx->d_active, active.data(), n_items * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        mstride = b.geo.maxd + b.geo.maxd * b.geo.maxd;
+        size_t need = (size_t)n_items * mstride;
+        if (need > ctx->moments_cap) {
+            if (ctx->d_moments) HIPCHK(hipFree(ctx->d_moments));
+            HIPCHK(hipMalloc(&ctx->d_moments, need * sizeof(cplx)));
+            ctx->moments_cap = need;
+        }
+        hipLaunchKernelGGL(k_core_moments, dim3(cdivu((long long)b.geo.maxR * b.geo.maxR, 256), b.geo.maxd, n_items), dim3(256), 0,
+                           ctx->stream, ctx->d_items, ctx->d_active);
+        hipLaunchKernelGGL(k_moments, dim3(n_items), dim3(64), 0, ctx->stream, ctx->d_items, ctx->d_active, ctx->d_moments, mstride);
+        HIPCHK(hipGetLastError());
+        moments->resize(need);
+        HIPCHK(hipMemcpyAsync(moments->data(), ctx->d_moments, need * sizeof(cplx), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    HIPCHK(hipMemcpyAsync(host_items.data(), ctx->d_items, n_items * sizeof(Item), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    b.items = host_items;
+    return TTFP_OK;
+}
+
+// dV/dS0_j and dV/dsigma_j of one option from the node moments of its terms' tensor trains:
+// d/dtheta of the integrand is the integrand times -i z.(dm_w) - z^T (dC_w) z / 2, a polynomial
+// of degree <= 2 in z, so each Greek is a fixed combination of <TT, z_k> and <TT, z_k z_l>.
+void greeks_from_moments(const OptionPlan &P, const Batch &b, const std::vector<std::complex<double>> &mom, int mstride,
+                         int first_item, double *delta, double *vega)
+{
+    const int d = P.d;
+    const std::complex<double> I(0.0, 1.0);
+    for (int j = 0; j < d; ++j) { delta[j] = 0.0; vega[j] = 0.0; }
+    for (size_t t = 0; t < P.terms.size(); ++t) {
+        const TermPlan &tp = P.terms[t];
+        const std::complex<double> *mu1 = mom.data() + (size_t)(first_item + t) * mstride;
+        const std::complex<double> *mu2 = mu1 + d;
+        const double sc = tp.scale;
+        for (int j = 0; j < d; ++j) {
+            std::complex<double> dl = 0.0, vg = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double Pkj = tp.P[(size_t)k * d + j];
+                dl += (-I * Pkj / P.S0[j]) * mu1[k];
+                vg += (I * P.sigma[j] * P.T * Pkj) * mu1[k];
+            }
+            // quadratic part of the vega weight: -T P_kj sum_b R_jb sigma_b P_lb
+            for (int k = 0; k < d; ++k) {
+                const double Pkj = tp.P[(size_t)k * d + j];
+                if (Pkj == 0.0) continue;
+                for (int l = 0; l < d; ++l) {
+                    double s = 0.0;
+                    for (int bb = 0; bb < d; ++bb) s += P.corr[(size_t)j * d + bb] * P.sigma[bb] * tp.P[(size_t)l * d + bb];
+                    vg += (-P.T * Pkj * s) * mu2[(size_t)k * d + l];
+                }
+            }
+            delta[j] += sc * dl.real();
+            vega[j] += sc * vg.real();
+        }
+    }
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *ttfp_strerror(int code)
+{
+    switch (code) {
+    case TTFP_OK: return "ok";
+    case TTFP_EINVAL: return "invalid argument";
+    case TTFP_ENOMEM: return "device memory exhausted";
+    case TTFP_EDEVICE: return "HIP runtime error";
+    case TTFP_ENOTCONV: return "tolerance not met (rank cap or sweep limit)";
+    case TTFP_EPRECISION: return "precision-limited";
+    default: return "unknown error";
+    }
+}
+
+const char *ttfp_last_error(const ttfp_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+int ttfp_create(ttfp_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return TTFP_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TTFP_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return TTFP_EDEVICE;
+    ttfp_ctx *c = new (std::nothrow) ttfp_ctx();
+    if (!c) return TTFP_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return TTFP_OK;
+}
+
+int ttfp_destroy(ttfp_ctx *ctx)
+{
+    if (!ctx) return TTFP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->arena) (void)hipFree(ctx->arena);
+    if (ctx->d_items) (void)hipFree(ctx->d_items);
+    if (ctx->d_active) (void)hipFree(ctx->d_active);
+    if (ctx->d_moments) (void)hipFree(ctx->d_moments);
+    delete ctx;
+    return TTFP_OK;
+}
+
+int ttfp_plan(const ttfp_option *opt, const ttfp_grid *grid, int32_t *n_terms, double *L_out, double *alpha_out)
+{
+    try {
+        OptionPlan P;
+        std::string err;
+        int rc = build_plan(opt, grid, P, err);
+        if (rc) return rc;
+        if (n_terms) *n_terms = (int32_t)P.terms.size();
+        for (size_t t = 0; t < P.terms.size(); ++t)
+            for (int k = 0; k < P.d; ++k) {
+                if (L_out) L_out[t * P.d + k] = P.terms[t].L[k];
+                if (alpha_out) alpha_out[t * P.d + k] = P.terms[t].alpha[k];
+            }
+        return TTFP_OK;
+    } catch (...) {
+        return TTFP_EINVAL;
+    }
+}
+
+int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids, double *prices,
+                     double *delta, double *vega, int32_t *status)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (n < 0 || (n > 0 && (!opts || !grids || !prices))) {
+        ctx->last_error = "bad batch arguments";
+        return TTFP_EINVAL;
+    }
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        std::vector<OptionPlan> plans(n);
+        for (int o = 0; o < n; ++o) {
+            std::string err;
+            int rc = check_cross_settings(&grids[o], err);
+            if (!rc) rc = build_plan(&opts[o], &grids[o], plans[o], err);
+            if (rc) {
+                ctx->last_error = "option " + std::to_string(o) + ": " + err;
+                return rc;
+            }
+            if (grids[o].N > MAXN) {
+                ctx->last_error = "option " + std::to_string(o) + ": N must be <= 1024";
+                return TTFP_EINVAL;
+            }
+        }
+        // chunk options so that one chunk's workspace stays below a cap
+        const size_t cap_bytes = (size_t)24 << 30;
+        int worst = TTFP_OK;
+        size_t greek_off = 0;
+        int o0 = 0;
+        while (o0 < n) {
+            std::vector<const OptionPlan *> cp;
+            std::vector<const ttfp_grid *> cg;
+            size_t bytes = 0, items = 0;
+            int o1 = o0;
+            while (o1 < n) {
+                const ttfp_grid &g = grids[o1];
+                int nc = g.max_rank + g.n_enrich, BR, G;
+                tsqr_geometry(std::max(nc, 4), BR, G);
+                size_t b1 = item_sizes(plans[o1].d, g.N, g.max_rank, g.n_enrich, std::min(BR, 64)).bytes * plans[o1].terms.size();
+                if (o1 > o0 && (bytes + b1 > cap_bytes || items + plans[o1].terms.size() > 60000)) break;
+                bytes += b1;
+                items += plans[o1].terms.size();
+                cp.push_back(&plans[o1]);
+                cg.push_back(&grids[o1]);
+                ++o1;
+            }
+            Batch b;
+            int rc = build_items(ctx, cp, cg, b);
+            if (rc) return rc;
+            std::vector<OptResult> res;
+            std::vector<std::complex<double>> mom;
+            int mstride = 0;
+            const bool want = delta || vega;
+            rc = run_batch(ctx, b, cg, res, want, &mom, mstride);
+            if (rc) return rc;
+            int first_item = 0;
+            for (int o = o0; o < o1; ++o) {
+                const OptResult &r = res[o - o0];
+                prices[o] = r.price;
+                if (status) status[o] = r.code;
+                worst = (r.code < 0 || worst < 0) ? std::min(worst, r.code) : std::max(worst, r.code);
+                if (want) {
+                    std::vector<double> dl(plans[o].d), vg(plans[o].d);
+                    greeks_from_moments(plans[o], b, mom, mstride, first_item, dl.data(), vg.data());
+                    for (int j = 0; j < plans[o].d; ++j) {
+                        if (delta) delta[greek_off + j] = dl[j];
+                        if (vega) vega[greek_off + j] = vg[j];
+                    }
+                }
+                greek_off += plans[o].d;
+                first_item += (int)plans[o].terms.size();
+            }
+            o0 = o1;
+        }
+        return worst;
+    } catch (const std::exception &e) {
+        ctx->last_error = e.what();
+        return TTFP_EINVAL;
+    }
+}
+
+int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, double *price, int32_t *ranks, ttfp_diag *diag)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (!price) { ctx->last_error = "price is NULL"; return TTFP_EINVAL; }
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        OptionPlan P;
+        std::string err;
+        int rc = check_cross_settings(grid, err);
+        if (!rc) rc = build_plan(opt, grid, P, err);
+        if (!rc && grid->N > MAXN) { err = "N must be <= 1024"; rc = TTFP_EINVAL; }
+        if (rc) { ctx->last_error = err; return rc; }
+        std::vector<const OptionPlan *> cp{&P};
+        std::vector<const ttfp_grid *> cg{grid};
+        Batch b;
+        rc = build_items(ctx, cp, cg, b);
+        if (rc) return rc;
+        std::vector<OptResult> res;
+        int mstride = 0;
+        rc = run_batch(ctx, b, cg, res, false, nullptr, mstride);
+        if (rc) return rc;
+        const OptResult &r = res[0];
+        *price = r.price;
+        if (ranks) {
+            for (size_t t = 0; t < b.items.size(); ++t) {
+                const Item &it = b.items[t];
+                int32_t *rk = ranks + t * (P.d + 1);
+                rk[0] = 1;
+                for (int k = 0; k < P.d; ++k) rk[k + 1] = it.ccol[k];
+            }
+        }
+        if (diag) {
+            diag->imag_rel = std::fabs(r.imag) / std::max(std::fabs(r.price), 1e-300);
+            diag->last_change = r.change;
+            diag->n_evals = r.evals;
+            diag->sweeps = r.sweeps;
+            diag->rank_capped = r.capped;
+            diag->converged = r.converged;
+        }
+        ctx->last_items = b.items;
+        ctx->last_n_items = (int)b.items.size();
+        return r.code;
+    } catch (const std::exception &e) {
+        ctx->last_error = e.what();
+        return TTFP_EINVAL;
+    }
+}
+
+int ttfp_eval_integrand(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, int32_t term, int64_t npts,
+                        const int32_t *idx, double *out)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (npts < 0 || (npts > 0 && (!idx || !out))) { ctx->last_error = "bad point arguments"; return TTFP_EINVAL; }
+    OptionPlan P;
+    std::string err;
+    int rc = build_plan(opt, grid, P, err);
+    if (rc) { ctx->last_error = err; return rc; }
+    if (term < 0 || term >= (int)P.terms.size()) { ctx->last_error = "term out of range"; return TTFP_EINVAL; }
+    for (int64_t q = 0; q < npts * P.d; ++q)
+        if (idx[q] < 0 || idx[q] >= grid->N) { ctx->last_error = "grid index out of range"; return TTFP_EINVAL; }
+    if (npts == 0) return TTFP_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    const TermPlan &tp = P.terms[term];
+    const int d = P.d;
+    // one small allocation holding the term data, indices and output
+    size_t o_m = 0, o_C = align_up(o_m + 8 * d), o_L = align_up(o_C + 8 * d * d), o_a = align_up(o_L + 8 * d),
+           o_k = align_up(o_a + 8 * d), o_i = align_up(o_k + 4 * d), o_o = align_up(o_i + 4 * (size_t)npts * d),
+           total = align_up(o_o + 16 * (size_t)npts);
+    char *buf = nullptr;
+    Item *dit = nullptr;
+    HIPCHK(hipMalloc(&buf, total));
+    if (hipMalloc(&dit, sizeof(Item)) != hipSuccess) { (void)hipFree(buf); ctx->last_error = "alloc failed"; return TTFP_ENOMEM; }
+    Item it;
+    std::memset(&it, 0, sizeof it);
+    it.d = d;
+    it.N = grid->N;
+    it.m = (const double *)(buf + o_m);
+    it.C = (const double *)(buf + o_C);
+    it.L = (const double *)(buf + o_L);
+    it.alpha = (const double *)(buf + o_a);
+    it.kind = (const int *)(buf + o_k);
+    hipError_t e = hipSuccess;
+    e = e ? e : hipMemcpy(buf + o_m, tp.m.data(), 8 * d, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(buf + o_C, tp.C.data(), 8 * d * d, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(buf + o_L, tp.L.data(), 8 * d, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(buf + o_a, tp.alpha.data(), 8 * d, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(buf + o_k, tp.kind.data(), 4 * d, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(buf + o_i, idx, 4 * (size_t)npts * d, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(dit, &it, sizeof(Item), hipMemcpyHostToDevice);
+    if (!e) {
+        hipLaunchKernelGGL(k_eval_points, dim3(cdivu(npts, 256)), dim3(256), 0, ctx->stream, dit, (long long)npts,
+                           (const int *)(buf + o_i), (cplx *)(buf + o_o));
+        e = hipGetLastError();
+    }
+    e = e ? e : hipStreamSynchronize(ctx->stream);
+    e = e ? e : hipMemcpy(out, buf + o_o, 16 * (size_t)npts, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    (void)hipFree(dit);
+    if (e) { ctx->last_error = hipGetErrorString(e); return TTFP_EDEVICE; }
+    return TTFP_OK;
+}
+
+int ttfp_tt_values(ttfp_ctx *ctx, int32_t term, int64_t npts, const int32_t *idx, double *out)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (ctx->last_n_items == 0) { ctx->last_error = "no tensor train available"; return TTFP_EINVAL; }
+    if (term < 0 || term >= ctx->last_n_items) { ctx->last_error = "term out of range"; return TTFP_EINVAL; }
+    if (npts <= 0) return npts == 0 ? TTFP_OK : TTFP_EINVAL;
+    const Item &h = ctx->last_items[term];
+    for (int64_t q = 0; q < npts * h.d; ++q)
+        if (idx[q] < 0 || idx[q] >= h.N) { ctx->last_error = "grid index out of range"; return TTFP_EINVAL; }
+    HIPCHK(hipSetDevice(ctx->device));
+    int *di = nullptr;
+    cplx *dout = nullptr;
+    HIPCHK(hipMalloc(&di, 4 * (size_t)npts * h.d));
+    if (hipMalloc(&dout, 16 * (size_t)npts) != hipSuccess) { (void)hipFree(di); return TTFP_ENOMEM; }
+    hipError_t e = hipMemcpy(di, idx, 4 * (size_t)npts * h.d, hipMemcpyHostToDevice);
+    if (!e) {
+        hipLaunchKernelGGL(k_tt_values, dim3((unsigned)npts), dim3(64), 0, ctx->stream, ctx->d_items, term, (long long)npts, di, dout);
+        e = hipGetLastError();
+    }
+    e = e ? e : hipStreamSynchronize(ctx->stream);
+    e = e ? e : hipMemcpy(out, dout, 16 * (size_t)npts, hipMemcpyDeviceToHost);
+    (void)hipFree(di);
+    (void)hipFree(dout);
+    if (e) { ctx->last_error = hipGetErrorString(e); return TTFP_EDEVICE; }
+    return TTFP_OK;
+}
+
+// Raw-matrix entry points: a single item whose shape comes from nI[0] (rows) / nJ[0] (cols).
+static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, int &BR, int &G)
+{
+    tsqr_geometry(std::max(n, 4), BR, G);
+    const int nblk = (m + BR - 1) / BR;
+    size_t oF = 0, oRl = align_up(oF + 16 * (size_t)m * n), oY = align_up(oRl + 16 * 2 * (size_t)nblk * n * n),
+           oW = align_up(oY + 16 * (size_t)m * r), oBt = align_up(oW + 16 * (size_t)m * r), oP = align_up(oBt + 16 * (size_t)m * r),
+           total = align_up(oP + 4 * (size_t)std::max(r, 1));
+    HIPCHK(hipMalloc(&buf, total));
+    std::memset(&it, 0, sizeof it);
+    it.d = 1;
+    it.N = 1;
+    it.R = std::max(r, n);
+    it.F = (cplx *)(buf + oF);
+    it.Rlev = (cplx *)(buf + oRl);
+    it.Y = (cplx *)(buf + oY);
+    it.W = (cplx *)(buf + oW);
+    it.Bt = (cplx *)(buf + oBt);
+    it.piv = (int *)(buf + oP);
+    it.nblk_max = nblk;
+    it.rows_max = m;
+    it.nI[0] = m;
+    it.nJ[0] = n;
+    it.rsel = r;
+    return TTFP_OK;
+}
+
+int ttfp_qr_r(ttfp_ctx *ctx, int32_t m, int32_t n, const double *A, double *R)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (m < 1 || n < 1 || n > MAXNC || m > TTFP_MAX_RANK * MAXN || !A || !R) { ctx->last_error = "bad qr_r arguments"; return TTFP_EINVAL; }
+    HIPCHK(hipSetDevice(ctx->device));
+    Item it;
+    char *buf = nullptr;
+    int BR, G;
+    int rc = raw_item(ctx, m, n, 1, it, buf, BR, G);
+    if (rc) return rc;
+    int *act = nullptr;
+    Item *dit = nullptr;
+    hipError_t e = hipMalloc(&act, sizeof(int));
+    e = e ? e : hipMalloc(&dit, sizeof(Item));
+    int one = 1;
+    e = e ? e : hipMemcpy(act, &one, sizeof(int), hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(dit, &it, sizeof(Item), hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(it.F, A, 16 * (size_t)m * n, hipMemcpyHostToDevice);
+    const int nlev = tsqr_levels(m, BR, G);
+    int nb = (m + BR - 1) / BR;
+    for (int level = 0; !e && level < nlev; ++level) {
+        hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(nb, 1), 1), dim3(256), (size_t)BR * n * sizeof(cplx), ctx->stream, dit, act, 0, 2,
+                           level, BR, G);
+        e = hipGetLastError();
+        nb = (nb + G - 1) / G;
+    }
+    e = e ? e : hipStreamSynchronize(ctx->stream);
+    // final level
+    int cnt = (m + BR - 1) / BR, lf = 0;
+    while (cnt > 1) { cnt = (cnt + G - 1) / G; ++lf; }
+    e = e ? e : hipMemcpy(R, it.Rlev + (size_t)(lf & 1) * it.nblk_max * n * n, 16 * (size_t)n * n, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    (void)hipFree(act);
+    (void)hipFree(dit);
+    if (e) { ctx->last_error = hipGetErrorString(e); return TTFP_EDEVICE; }
+    return TTFP_OK;
+}
+
+int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double delta, int32_t *rows, double *B)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (m < 1 || r < 1 || r > TTFP_MAX_RANK || r > m || m > TTFP_MAX_RANK * MAXN || !A || !rows || !B || !(delta >= 0)) {
+        ctx->last_error = "bad maxvol arguments";
+        return TTFP_EINVAL;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    Item it;
+    char *buf = nullptr;
+    int BR, G;
+    int rc = raw_item(ctx, m, r, r, it, buf, BR, G);
+    if (rc) return rc;
+    it.delta = delta;
+    int *act = nullptr;
+    Item *dit = nullptr;
+    hipError_t e = hipMalloc(&act, sizeof(int));
+    e = e ? e : hipMalloc(&dit, sizeof(Item));
+    int one = 1;
+    e = e ? e : hipMemcpy(act, &one, sizeof(int), hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(dit, &it, sizeof(Item), hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(it.Y, A, 16 * (size_t)m * r, hipMemcpyHostToDevice);
+    if (!e) {
+        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(1024), 0, ctx->stream, dit, act, 0, 2);
+        e = hipGetLastError();
+    }
+    e = e ? e : hipStreamSynchronize(ctx->stream);
+    e = e ? e : hipMemcpy(B, it.Bt, 16 * (size_t)m * r, hipMemcpyDeviceToHost);
+    e = e ? e : hipMemcpy(rows, it.piv, 4 * (size_t)r, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    (void)hipFree(act);
+    (void)hipFree(dit);
+    if (e) { ctx->last_error = hipGetErrorString(e); return TTFP_EDEVICE; }
+    return TTFP_OK;
+}
+
+}  // extern "C"

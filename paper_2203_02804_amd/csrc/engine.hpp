@@ -1,0 +1,61 @@
+// Device-side data layout of the batched TT-cross engine.
+//
+// A work item is one separable term of one option. Every kernel takes the array of
+// items and a step index; each workgroup reads its item's shapes from device memory, so
+// items of different d, N and rank advance together in one launch, and no host round
+// trip is needed between the steps of a half sweep.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ttfp.h"
+
+namespace ttfp {
+
+constexpr int MAXD = TTFP_MAX_D;
+constexpr int MAXNC = TTFP_MAX_RANK + 4;     // fiber columns: rank + enrichment
+constexpr int MAXN = 1024;                   // nodes per coordinate
+constexpr int LDS_BYTES = 152 * 1024;        // per-workgroup LDS budget of the QR kernels
+
+struct cplx { double x, y; };
+
+struct Item {
+    // ---- static description
+    int d, N, R, p;            // assets, nodes, rank cap, enrichment columns
+    int opt, term;             // owning option and term index
+    double rank_eps;           // relative pivot threshold for truncation
+    double delta;              // maxvol dominance threshold
+    uint64_t seed;
+    const double *m;           // [d]    mean of w
+    const double *C;           // [d*d]  covariance of w
+    const double *L;           // [d]    half-widths
+    const double *alpha;       // [d]    contour shifts
+    const int *kind;           // [d]    payoff factor kinds
+    // ---- buffers (device)
+    int *Iset;                 // [(d+1)][R][d] left multi-indices (coords 0..k-1 used)
+    int *Jset;                 // [(d+1)][R][d] right multi-indices (coords k..d-1 used)
+    cplx *F;                   // fiber, rows_max x nc_max
+    cplx *Rlev;                // two TSQR level buffers, each nblk_max x nc x nc
+    cplx *Rinv;                // R x R, inverse of the kept block of the pivoted R
+    int *perm;                 // nc, column order of the pivoted QR
+    cplx *Y;                   // rows_max x R basis
+    cplx *W;                   // rows_max x R maxvol workspace
+    cplx *Bt;                  // rows_max x R maxvol output of right-to-left steps
+    cplx *cores;               // d slots of R x N x R
+    cplx *M;                   // d slots of R x R: core sums over the node index
+    cplx *M1, *M2;             // d slots of R x R: first / second node moments (Greeks)
+    int *piv;                  // R pivot rows
+    int rows_max, nblk_max;
+    // ---- dynamic state
+    int nI[MAXD + 1], nJ[MAXD + 1];   // sizes of the left / right index sets
+    int crow[MAXD], ccol[MAXD];       // core shapes
+    int rsel;                         // rank selected in the current step
+    int capped;
+    long long n_evals;
+    cplx P;                           // latest contraction of the tensor train
+};
+
+// Step addressing: dir 0 = left-to-right (core k = t), dir 1 = right-to-left (core k = d-1-t).
+__host__ __device__ inline int step_core(const Item &it, int t, int dir) { return dir == 0 ? t : it.d - 1 - t; }
+
+}  // namespace ttfp

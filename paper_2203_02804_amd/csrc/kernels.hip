@@ -1,0 +1,874 @@
+// HIP kernels of the TT-cross pricer (gfx950, wave64).
+//
+// One half sweep of TT-cross (Sec. IV.B) is, for every core k in order:
+//   k_fiber    evaluate the fiber A[I_k, i, J_{k+1}] (+ random enrichment columns)   (complex FP64)
+//   k_tsqr     triangular factor of a QR of the fiber, TSQR over LDS-resident row blocks
+//   k_qrcp     column-pivoted QR of that factor: rank by pivot size, inverse of the kept block
+//   k_basis    orthonormal basis of the kept fiber columns
+//   k_maxvol   rows of a dominant submatrix (maxvol) and the interpolating core B
+//   k_finish   next index set, core placement
+//   k_core_sum core summed over the node index (the quadrature weights are uniform)
+// then k_fiber on the edge core and k_contract (Sec. IV.A inner product with the weights).
+#include <hip/hip_runtime.h>
+
+#include "engine.hpp"
+
+namespace ttfp {
+
+// ------------------------------------------------------------------ complex helpers
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// conj(a) * b
+__device__ __forceinline__ cplx cmulc(cplx a, cplx b) { return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.x * s, a.y * s}; }
+__device__ __forceinline__ double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ cplx cdiv(cplx a, cplx b)
+{
+    // scaled division (Smith)
+    if (fabs(b.x) >= fabs(b.y)) {
+        double r = b.y / b.x, den = b.x + b.y * r;
+        return {(a.x + a.y * r) / den, (a.y - a.x * r) / den};
+    }
+    double r = b.x / b.y, den = b.x * r + b.y;
+    return {(a.x * r + a.y) / den, (a.y * r - a.x) / den};
+}
+__device__ __forceinline__ cplx cexp_(cplx a)
+{
+    double e = exp(a.x), s, c;
+    sincos(a.y, &s, &c);
+    return {e * c, e * s};
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ counter-based generator
+// SplitMix64 finaliser (Steele, Lea and Flood, 2014) applied to a counter.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__device__ __forceinline__ int rand_index(uint64_t seed, uint64_t a, uint64_t b, uint64_t c, int n)
+{
+    uint64_t h = splitmix64(splitmix64(splitmix64(seed ^ a) ^ b) ^ c);
+    return (int)(((h >> 32) * (uint64_t)n) >> 32);
+}
+
+// ------------------------------------------------------------------ integrand (one entry)
+// exp(-i z.m - z^T C z / 2) * prod_k h_k(z_k),  z_k = -L_k + (i_k + 1/2) 2L_k/N + i alpha_k:
+// the Gaussian characteristic function at -z (Sec. III.C) times the payoff factor transforms.
+__device__ __forceinline__ cplx factor(int kind, cplx z)
+{
+    cplx iz = {-z.y, z.x};
+    if (kind == 0) return cdiv({1.0, 0.0}, cmul(iz, {1.0 + iz.x, iz.y}));
+    cplx v = cdiv({1.0, 0.0}, iz);
+    return kind == 1 ? v : cplx{-v.x, -v.y};
+}
+
+__device__ cplx integrand(const Item &it, const int *idx)
+{
+    const int d = it.d;
+    const double invN = 1.0 / it.N;
+    cplx z[MAXD];
+    for (int k = 0; k < d; ++k) {
+        double L = it.L[k];
+        z[k] = {-L + (idx[k] + 0.5) * 2.0 * L * invN, it.alpha[k]};
+    }
+    cplx e = {0.0, 0.0}, h = {1.0, 0.0};
+    for (int k = 0; k < d; ++k) {
+        const double *Ck = it.C + k * d;
+        cplx q = {0.0, 0.0};
+        for (int l = 0; l < d; ++l) q = {q.x + Ck[l] * z[l].x, q.y + Ck[l] * z[l].y};
+        // z_k * (-i m_k - q/2)
+        cplx w = {-0.5 * q.x, -it.m[k] - 0.5 * q.y};
+        e = cadd(e, cmul(z[k], w));
+        h = cmul(h, factor(it.kind[k], z[k]));
+    }
+    return cmul(cexp_(e), h);
+}
+
+// ------------------------------------------------------------------ shapes of a step
+struct StepShape {
+    int k, rows, ncb, nc;   // core, fiber rows, base columns, columns incl. enrichment
+    bool valid;
+};
+
+// mode 0: interior step t of direction dir; mode 1: edge core of that direction;
+// dir 2: raw matrix entry points (rows / columns stored in rsel / nI[0]).
+__device__ __forceinline__ StepShape step_shape(const Item &it, int t, int dir, int mode)
+{
+    StepShape s;
+    s.valid = true;
+    const int d = it.d;
+    if (dir == 2) {
+        s.k = 0;
+        s.rows = it.nI[0];
+        s.ncb = s.nc = it.nJ[0];
+        return s;
+    }
+    if (mode == 0) {
+        if (t > d - 2) { s.valid = false; return s; }
+        s.k = step_core(it, t, dir);
+    } else {
+        s.k = dir == 0 ? d - 1 : 0;
+    }
+    const int p = mode == 0 ? it.p : 0;
+    if (dir == 0) {
+        s.rows = it.nI[s.k] * it.N;
+        s.ncb = it.nJ[s.k + 1];
+    } else {
+        s.rows = it.N * it.nJ[s.k + 1];
+        s.ncb = it.nI[s.k];
+    }
+    s.nc = s.ncb + p;
+    return s;
+}
+
+// ------------------------------------------------------------------ init
+__global__ void k_init(Item *items, int n_items)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_items) return;
+    Item &it = items[j];
+    const int d = it.d, N = it.N, R = it.R;
+    it.nI[0] = 1;
+    it.nJ[d] = 1;
+    it.n_evals = 0;
+    it.capped = 0;
+    long long cnt = 1;
+    for (int k = d - 1; k >= 1; --k) {
+        cnt = cnt * N;
+        if (cnt > R) cnt = R;
+        int nj = (int)cnt;
+        it.nJ[k] = nj;
+        int *Jk = it.Jset + (size_t)k * R * d;
+        const int *Jk1 = it.Jset + (size_t)(k + 1) * R * d;
+        for (int b = 0; b < nj; ++b) {
+            int lo = N >= 4 ? N / 4 : 0, span = N >= 4 ? N / 2 : N;
+            Jk[b * d + k] = lo + rand_index(it.seed, 1, (uint64_t)k, (uint64_t)b, span);
+            if (k + 1 < d) {
+                int bp = rand_index(it.seed, 2, (uint64_t)k, (uint64_t)b, it.nJ[k + 1]);
+                for (int c = k + 1; c < d; ++c) Jk[b * d + c] = Jk1[bp * d + c];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ fiber evaluation
+__global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, int t, int dir, int mode, int sweep)
+{
+    const int item = blockIdx.y;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, mode);
+    if (!s.valid) return;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)s.rows * s.nc;
+    const int d = it.d, N = it.N, R = it.R, k = s.k;
+    if (mode == 1 && e == 0) {
+        if (dir == 0) { it.crow[k] = it.nI[k]; it.ccol[k] = 1; }
+        else { it.crow[k] = 1; it.ccol[k] = it.nJ[1]; }
+        it.n_evals += total;
+    }
+    if (e >= total) return;
+    const int row = (int)(e / s.nc), col = (int)(e % s.nc);
+    int idx[MAXD];
+    int a, i, b;
+    if (dir == 0) { a = row / N; i = row % N; b = col; }
+    else { i = row / it.nJ[k + 1]; b = row % it.nJ[k + 1]; a = col; }
+    const uint64_t ctr = ((uint64_t)sweep << 40) ^ ((uint64_t)dir << 32) ^ ((uint64_t)t << 16);
+    // left coordinates 0..k-1
+    if (dir == 1 && a >= s.ncb) {
+        for (int c = 0; c < k; ++c) idx[c] = rand_index(it.seed, 3 + ctr, (uint64_t)(a - s.ncb), (uint64_t)c, N);
+    } else {
+        const int *Ia = it.Iset + ((size_t)k * R + a) * d;
+        for (int c = 0; c < k; ++c) idx[c] = Ia[c];
+    }
+    idx[k] = i;
+    // right coordinates k+1..d-1
+    if (dir == 0 && b >= s.ncb) {
+        for (int c = k + 1; c < d; ++c) idx[c] = rand_index(it.seed, 4 + ctr, (uint64_t)(b - s.ncb), (uint64_t)c, N);
+    } else {
+        const int *Jb = it.Jset + ((size_t)(k + 1) * R + b) * d;
+        for (int c = k + 1; c < d; ++c) idx[c] = Jb[c];
+    }
+    cplx v = integrand(it, idx);
+    cplx *out = mode == 0 ? it.F : it.cores + (size_t)k * R * N * R;
+    out[(size_t)row * s.nc + col] = v;
+}
+
+// Integrand at explicit multi-indices (verification entry point).
+__global__ void k_eval_points(const Item *items, long long npts, const int *idx, cplx *out)
+{
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const Item &it = items[0];
+    out[p] = integrand(it, idx + p * it.d);
+}
+
+// ------------------------------------------------------------------ Householder R in LDS
+// Triangularises A (nr x nc, row-major, ld nc, in LDS) by Householder reflections
+// H = I - beta v v^H; on exit row j of R is (alph[j], A[j][j+1..nc-1]).
+__device__ void householder_lds(cplx *A, int nr, int nc, cplx *alph, double *sh)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int jmax = nr < nc ? nr : nc;
+    for (int j = 0; j < jmax; ++j) {
+        if (wave == 0) {
+            double s = 0.0;
+            for (int i = j + 1 + lane; i < nr; i += 64) s += cabs2(A[i * nc + j]);
+            s = wave_sum(s);
+            if (lane == 0) {
+                cplx x0 = A[j * nc + j];
+                double a0 = sqrt(cabs2(x0));
+                double nrm = sqrt(s + a0 * a0);
+                double beta = 0.0;
+                cplx al = {0.0, 0.0};
+                if (nrm > 0.0) {
+                    cplx ph = a0 > 0.0 ? cplx{x0.x / a0, x0.y / a0} : cplx{1.0, 0.0};
+                    al = {-ph.x * nrm, -ph.y * nrm};
+                    cplx v0 = csub(x0, al);
+                    A[j * nc + j] = v0;
+                    beta = 2.0 / (s + cabs2(v0));
+                }
+                alph[j] = al;
+                sh[0] = beta;
+            }
+        }
+        __syncthreads();
+        const double beta = sh[0];
+        if (beta != 0.0) {
+            for (int c = j + 1 + wave; c < nc; c += nw) {
+                double dr = 0.0, di = 0.0;
+                for (int i = j + lane; i < nr; i += 64) {
+                    cplx p = cmulc(A[i * nc + j], A[i * nc + c]);
+                    dr += p.x;
+                    di += p.y;
+                }
+                dr = wave_sum(dr);
+                di = wave_sum(di);
+                cplx f = {beta * dr, beta * di};
+                for (int i = j + lane; i < nr; i += 64) A[i * nc + c] = csub(A[i * nc + c], cmul(f, A[i * nc + j]));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// number of TSQR blocks at a level
+__device__ __forceinline__ int tsqr_count(int rows, int BR, int G, int level)
+{
+    int n = (rows + BR - 1) / BR;
+    for (int l = 0; l < level; ++l) n = (n + G - 1) / G;
+    return n;
+}
+__device__ __forceinline__ int tsqr_final_level(int rows, int BR, int G)
+{
+    int n = (rows + BR - 1) / BR, l = 0;
+    while (n > 1) { n = (n + G - 1) / G; ++l; }
+    return l;
+}
+
+// One TSQR level: level 0 reduces row blocks of the fiber, level L > 0 groups of G
+// triangular factors of level L-1. Writes nc x nc factors into buffer (level % 2).
+__global__ __launch_bounds__(256) void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G)
+{
+    extern __shared__ cplx lds[];
+    __shared__ cplx alph[MAXNC];
+    __shared__ double sh[4];
+    const int item = blockIdx.y;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    const int nc = s.nc;
+    if (level > 0 && tsqr_count(s.rows, BR, G, level - 1) == 1) return;
+    const int ncur = tsqr_count(s.rows, BR, G, level);
+    const int blk = blockIdx.x;
+    if (blk >= ncur) return;
+    const size_t rsz = (size_t)nc * nc;
+    cplx *A = lds;
+    int nr;
+    if (level == 0) {
+        const int r0 = blk * BR;
+        nr = min(BR, s.rows - r0);
+        const cplx *src = it.F + (size_t)r0 * nc;
+        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) A[e] = src[e];
+    } else {
+        const int nprev = tsqr_count(s.rows, BR, G, level - 1);
+        const int g0 = blk * G, g1 = min(nprev, g0 + G);
+        nr = (g1 - g0) * nc;
+        const cplx *src = it.Rlev + (size_t)((level - 1) & 1) * it.nblk_max * rsz + (size_t)g0 * rsz;
+        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) A[e] = src[e];
+    }
+    __syncthreads();
+    householder_lds(A, nr, nc, alph, sh);
+    cplx *dst = it.Rlev + (size_t)(level & 1) * it.nblk_max * rsz + (size_t)blk * rsz;
+    const int jmax = nr < nc ? nr : nc;
+    for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) {
+        int j = e / nc, c = e % nc;
+        cplx v = {0.0, 0.0};
+        if (j < jmax && c >= j) v = (c == j) ? alph[j] : A[j * nc + c];
+        dst[e] = v;
+    }
+}
+
+// ------------------------------------------------------------------ pivoted QR of R, rank, inverse
+__global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G)
+{
+    __shared__ cplx A[MAXNC * MAXNC];
+    __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
+    __shared__ double nrm[MAXNC];
+    __shared__ int perm[MAXNC];
+    __shared__ cplx alph[MAXNC];
+    __shared__ double sh[4];
+    __shared__ int shi[4];
+    const int item = blockIdx.x;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    const int nc = s.nc;
+    const size_t rsz = (size_t)nc * nc;
+    const int lf = tsqr_final_level(s.rows, BR, G);
+    const cplx *src = it.Rlev + (size_t)(lf & 1) * it.nblk_max * rsz;
+    for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) A[e] = src[e];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) perm[c] = c;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = 0; j < nc; ++j) {
+        for (int c = j + threadIdx.x; c < nc; c += blockDim.x) {
+            double q = 0.0;
+            for (int i = j; i < nc; ++i) q += cabs2(A[i * nc + c]);
+            nrm[c] = q;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int p = j;
+            for (int c = j + 1; c < nc; ++c)
+                if (nrm[c] > nrm[p]) p = c;
+            shi[0] = p;
+            if (p != j) { int tmp = perm[j]; perm[j] = perm[p]; perm[p] = tmp; }
+        }
+        __syncthreads();
+        const int p = shi[0];
+        if (p != j)
+            for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+                cplx tmp = A[i * nc + j];
+                A[i * nc + j] = A[i * nc + p];
+                A[i * nc + p] = tmp;
+            }
+        __syncthreads();
+        // Householder on column j, rows j..nc-1
+        if (wave == 0) {
+            double q = 0.0;
+            for (int i = j + 1 + lane; i < nc; i += 64) q += cabs2(A[i * nc + j]);
+            q = wave_sum(q);
+            if (lane == 0) {
+                cplx x0 = A[j * nc + j];
+                double a0 = sqrt(cabs2(x0)), nn = sqrt(q + a0 * a0), beta = 0.0;
+                cplx al = {0.0, 0.0};
+                if (nn > 0.0) {
+                    cplx ph = a0 > 0.0 ? cplx{x0.x / a0, x0.y / a0} : cplx{1.0, 0.0};
+                    al = {-ph.x * nn, -ph.y * nn};
+                    cplx v0 = csub(x0, al);
+                    A[j * nc + j] = v0;
+                    beta = 2.0 / (q + cabs2(v0));
+                }
+                alph[j] = al;
+                sh[0] = beta;
+            }
+        }
+        __syncthreads();
+        const double beta = sh[0];
+        if (beta != 0.0)
+            for (int c = j + 1 + wave; c < nc; c += nw) {
+                double dr = 0.0, di = 0.0;
+                for (int i = j + lane; i < nc; i += 64) {
+                    cplx pr = cmulc(A[i * nc + j], A[i * nc + c]);
+                    dr += pr.x;
+                    di += pr.y;
+                }
+                dr = wave_sum(dr);
+                di = wave_sum(di);
+                cplx f = {beta * dr, beta * di};
+                for (int i = j + lane; i < nc; i += 64) A[i * nc + c] = csub(A[i * nc + c], cmul(f, A[i * nc + j]));
+            }
+        __syncthreads();
+    }
+    // rank: leading pivots above rank_eps * |R_00|
+    if (threadIdx.x == 0) {
+        const double r00 = sqrt(cabs2(alph[0]));
+        int r = 0;
+        while (r < nc && r00 > 0.0 && sqrt(cabs2(alph[r])) > it.rank_eps * r00) ++r;
+        if (r < 1) r = 1;
+        int cap = min(it.R, s.rows);
+        if (dir == 2) cap = min(cap, nc);
+        if (r > cap) {
+            if (dir != 2) it.capped = 1;
+            r = cap;
+        }
+        shi[1] = r;
+    }
+    __syncthreads();
+    const int r = shi[1];
+    // inverse of the leading r x r block of the pivoted factor (columns by back substitution)
+    for (int c = threadIdx.x; c < r; c += blockDim.x) {
+        cplx rcc = alph[c];
+        Ri[c * r + c] = (rcc.x == 0.0 && rcc.y == 0.0) ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, rcc);
+        for (int i = c - 1; i >= 0; --i) {
+            cplx acc = {0.0, 0.0};
+            for (int l = i + 1; l <= c; ++l) {
+                cplx ril = (l == i) ? alph[i] : A[i * nc + l];
+                acc = cadd(acc, cmul(ril, Ri[l * r + c]));
+            }
+            cplx rii = alph[i];
+            Ri[i * r + c] = (rii.x == 0.0 && rii.y == 0.0) ? cplx{0.0, 0.0} : cplx{-cdiv(acc, rii).x, -cdiv(acc, rii).y};
+        }
+        for (int i = c + 1; i < r; ++i) Ri[i * r + c] = {0.0, 0.0};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) it.Rinv[e] = Ri[e];
+    for (int c = threadIdx.x; c < r; c += blockDim.x) it.perm[c] = perm[c];
+    if (threadIdx.x == 0) it.rsel = r;
+}
+
+// ------------------------------------------------------------------ basis of the kept columns
+__global__ __launch_bounds__(256) void k_basis(Item *items, const int *active, int t, int dir)
+{
+    const int item = blockIdx.y;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    const int r = it.rsel, nc = s.nc;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)s.rows * r) return;
+    const int row = (int)(e / r), c = (int)(e % r);
+    const cplx *f = it.F + (size_t)row * nc;
+    cplx acc = {0.0, 0.0};
+    for (int l = 0; l <= c; ++l) acc = cadd(acc, cmul(f[it.perm[l]], it.Rinv[l * r + c]));
+    it.Y[(size_t)row * r + c] = acc;
+}
+
+// ------------------------------------------------------------------ maxvol
+struct ArgMax { double v; int i; };
+
+__device__ __forceinline__ ArgMax better(ArgMax a, ArgMax b)
+{
+    if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
+    return a;
+}
+
+// block-wide argmax (ties: lowest flat index); every thread receives the result
+__device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        ArgMax b;
+        b.v = __shfl_xor(a.v, o, 64);
+        b.i = __shfl_xor(a.i, o, 64);
+        a = better(a, b);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wave] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ArgMax m = scratch[0];
+        for (int w = 1; w < nw; ++w) m = better(m, scratch[w]);
+        scratch[nw] = m;
+    }
+    __syncthreads();
+    return scratch[nw];
+}
+
+// Dominant r x r submatrix of Y (rows x r): Gaussian elimination with partial pivoting for
+// the start, then swaps of the largest |B_ij| > 1 + delta with B = Y Y[piv]^{-1}.
+__global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir)
+{
+    __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
+    __shared__ cplx Ag[TTFP_MAX_RANK * TTFP_MAX_RANK];
+    __shared__ unsigned int chosen[(TTFP_MAX_RANK * MAXN) / 32];
+    __shared__ cplx prow[TTFP_MAX_RANK];
+    __shared__ cplx fcol[TTFP_MAX_RANK];
+    __shared__ int piv[TTFP_MAX_RANK];
+    __shared__ ArgMax red[17];
+    __shared__ int shi[2];
+    const int item = blockIdx.x;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    const int m = s.rows, r = it.rsel;
+    const cplx *Y = it.Y;
+    cplx *W = it.W;
+    cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
+    const int nthr = blockDim.x;
+    for (int w = threadIdx.x; w < (m + 31) / 32; w += nthr) chosen[w] = 0u;
+    __syncthreads();
+    // ---- start: partial pivoting on column j of the eliminated matrix
+    ArgMax am = {-1.0, 0x7fffffff};
+    for (int i = threadIdx.x; i < m; i += nthr) am = better(am, ArgMax{cabs2(Y[(size_t)i * r]), i});
+    am = block_argmax(am, red);
+    for (int j = 0; j < r; ++j) {
+        const int p = am.i;
+        const cplx *src = (j == 0) ? Y : W;
+        if (threadIdx.x == 0) {
+            piv[j] = p;
+            chosen[p >> 5] |= 1u << (p & 31);
+        }
+        for (int c = j + threadIdx.x; c < r; c += nthr) prow[c] = src[(size_t)p * r + c];
+        __syncthreads();
+        const int w = r - j - 1;
+        am = {-1.0, 0x7fffffff};
+        if (w > 0) {
+            const cplx pj = prow[j];
+            const long long tot = (long long)m * w;
+            for (long long e = threadIdx.x; e < tot; e += nthr) {
+                const int i = (int)(e / w), c = j + 1 + (int)(e % w);
+                if (chosen[i >> 5] & (1u << (i & 31))) continue;
+                const cplx f = cdiv(src[(size_t)i * r + j], pj);
+                const cplx v = csub(src[(size_t)i * r + c], cmul(f, prow[c]));
+                W[(size_t)i * r + c] = v;
+                if (c == j + 1) am = better(am, ArgMax{cabs2(v), i});
+            }
+        }
+        am = block_argmax(am, red);
+    }
+    // ---- inverse of Y[piv] by Gauss-Jordan with partial pivoting
+    for (int e = threadIdx.x; e < r * r; e += nthr) {
+        const int a = e / r, c = e % r;
+        Ag[e] = Y[(size_t)piv[a] * r + c];
+        Ai[e] = (a == c) ? cplx{1.0, 0.0} : cplx{0.0, 0.0};
+    }
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        if (threadIdx.x == 0) {
+            int p = j;
+            double best = cabs2(Ag[j * r + j]);
+            for (int a = j + 1; a < r; ++a) {
+                double v = cabs2(Ag[a * r + j]);
+                if (v > best) { best = v; p = a; }
+            }
+            shi[0] = p;
+        }
+        __syncthreads();
+        const int p = shi[0];
+        if (p != j)
+            for (int c = threadIdx.x; c < r; c += nthr) {
+                cplx t0 = Ag[j * r + c]; Ag[j * r + c] = Ag[p * r + c]; Ag[p * r + c] = t0;
+                cplx t1 = Ai[j * r + c]; Ai[j * r + c] = Ai[p * r + c]; Ai[p * r + c] = t1;
+            }
+        __syncthreads();
+        const cplx inv = cdiv({1.0, 0.0}, Ag[j * r + j]);
+        __syncthreads();
+        for (int c = threadIdx.x; c < r; c += nthr) {
+            Ag[j * r + c] = cmul(Ag[j * r + c], inv);
+            Ai[j * r + c] = cmul(Ai[j * r + c], inv);
+        }
+        __syncthreads();
+        for (int a = threadIdx.x; a < r; a += nthr) fcol[a] = Ag[a * r + j];
+        __syncthreads();
+        for (int e = threadIdx.x; e < r * r; e += nthr) {
+            const int a = e / r, c = e % r;
+            if (a == j) continue;
+            Ag[e] = csub(Ag[e], cmul(fcol[a], Ag[j * r + c]));
+            Ai[e] = csub(Ai[e], cmul(fcol[a], Ai[j * r + c]));
+        }
+        __syncthreads();
+    }
+    // ---- B = Y Ai and the first candidate
+    am = {-1.0, 0x7fffffff};
+    const long long tot = (long long)m * r;
+    for (long long e = threadIdx.x; e < tot; e += nthr) {
+        const int i = (int)(e / r), c = (int)(e % r);
+        const cplx *y = Y + (size_t)i * r;
+        cplx acc = {0.0, 0.0};
+        for (int l = 0; l < r; ++l) acc = cadd(acc, cmul(y[l], Ai[l * r + c]));
+        B[e] = acc;
+        am = better(am, ArgMax{cabs2(acc), (int)e});
+    }
+    am = block_argmax(am, red);
+    // ---- swaps
+    const double lim = (1.0 + it.delta) * (1.0 + it.delta);
+    const int maxit = 4 * r + 16;
+    for (int iter = 0; iter < maxit && am.v > lim; ++iter) {
+        const int is = am.i / r, cs = am.i % r;
+        for (int c = threadIdx.x; c < r; c += nthr) prow[c] = B[(size_t)is * r + c];
+        __syncthreads();
+        const cplx bic = prow[cs];
+        for (int i = threadIdx.x; i < m; i += nthr) W[i] = cdiv(B[(size_t)i * r + cs], bic);
+        __syncthreads();
+        if (threadIdx.x == 0) piv[cs] = is;
+        am = {-1.0, 0x7fffffff};
+        for (long long e = threadIdx.x; e < tot; e += nthr) {
+            const int i = (int)(e / r), c = (int)(e % r);
+            cplx pr = prow[c];
+            if (c == cs) pr.x -= 1.0;
+            const cplx v = csub(B[e], cmul(W[i], pr));
+            B[e] = v;
+            am = better(am, ArgMax{cabs2(v), (int)e});
+        }
+        am = block_argmax(am, red);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
+}
+
+// ------------------------------------------------------------------ index sets and core placement
+__global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, int t, int dir)
+{
+    const int item = blockIdx.y;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    const int r = it.rsel, d = it.d, N = it.N, R = it.R, k = s.k;
+    if (dir == 1) {
+        const int nb = it.nJ[k + 1];
+        const long long tot = (long long)s.rows * r;
+        cplx *core = it.cores + (size_t)k * R * N * R;
+        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+             e += (long long)gridDim.x * blockDim.x) {
+            const int row = (int)(e / r), a = (int)(e % r);
+            const int i = row / nb, b = row % nb;
+            core[((size_t)a * N + i) * nb + b] = it.Bt[e];
+        }
+    }
+    if (blockIdx.x != 0) return;
+    if (dir == 0) {
+        const int *Ik = it.Iset + (size_t)k * R * d;
+        int *In = it.Iset + (size_t)(k + 1) * R * d;
+        for (int q = threadIdx.x; q < r; q += blockDim.x) {
+            const int row = it.piv[q], a = row / N, i = row % N;
+            for (int c = 0; c < k; ++c) In[q * d + c] = Ik[a * d + c];
+            In[q * d + k] = i;
+        }
+        if (threadIdx.x == 0) {
+            it.crow[k] = it.nI[k];
+            it.ccol[k] = r;
+            it.nI[k + 1] = r;
+            it.n_evals += (long long)s.rows * s.nc;
+        }
+    } else {
+        const int nb = it.nJ[k + 1];
+        const int *J1 = it.Jset + (size_t)(k + 1) * R * d;
+        int *Jn = it.Jset + (size_t)k * R * d;
+        for (int q = threadIdx.x; q < r; q += blockDim.x) {
+            const int row = it.piv[q], i = row / nb, b = row % nb;
+            Jn[q * d + k] = i;
+            for (int c = k + 1; c < d; ++c) Jn[q * d + c] = J1[b * d + c];
+        }
+        if (threadIdx.x == 0) {
+            it.crow[k] = r;
+            it.ccol[k] = nb;
+            it.nJ[k] = r;
+            it.n_evals += (long long)s.rows * s.nc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ core sums and contraction
+// M_k = sum_i core_k[:, i, :] (the quadrature weights eta_k are applied on the host).
+__global__ __launch_bounds__(256) void k_core_sum(Item *items, const int *active, int t, int dir, int mode)
+{
+    const int item = blockIdx.y;
+    if (!active[item]) return;
+    Item &it = items[item];
+    int k;
+    if (mode == 0) {
+        if (t > it.d - 2) return;
+        k = step_core(it, t, dir);
+    } else {
+        k = dir == 0 ? it.d - 1 : 0;
+    }
+    const int a_n = it.crow[k], b_n = it.ccol[k], N = it.N, R = it.R;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a_n * b_n) return;
+    const int a = e / b_n, b = e % b_n;
+    const cplx *core = it.cores + (size_t)k * R * N * R;
+    cplx acc = {0.0, 0.0};
+    for (int i = 0; i < N; ++i) acc = cadd(acc, core[((size_t)a * N + i) * b_n + b]);
+    it.M[(size_t)k * R * R + e] = acc;
+}
+
+// P = 1^T M_0 M_1 ... M_{d-1} 1
+__global__ __launch_bounds__(64) void k_contract(Item *items, const int *active)
+{
+    __shared__ cplx v[TTFP_MAX_RANK], w[TTFP_MAX_RANK];
+    const int item = blockIdx.x;
+    if (!active[item]) return;
+    Item &it = items[item];
+    if (threadIdx.x == 0) v[0] = {1.0, 0.0};
+    __syncthreads();
+    for (int k = 0; k < it.d; ++k) {
+        const int a_n = it.crow[k], b_n = it.ccol[k];
+        const cplx *Mk = it.M + (size_t)k * it.R * it.R;
+        for (int b = threadIdx.x; b < b_n; b += blockDim.x) {
+            cplx acc = {0.0, 0.0};
+            for (int a = 0; a < a_n; ++a) acc = cadd(acc, cmul(v[a], Mk[a * b_n + b]));
+            w[b] = acc;
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < b_n; b += blockDim.x) v[b] = w[b];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) it.P = v[0];
+}
+
+// ------------------------------------------------------------------ node moments for the Greeks
+// M1_k = sum_i z_k(i) core_k[:, i, :], M2_k = sum_i z_k(i)^2 core_k[:, i, :]
+__global__ __launch_bounds__(256) void k_core_moments(Item *items, const int *active)
+{
+    const int item = blockIdx.z;
+    if (!active[item]) return;
+    Item &it = items[item];
+    const int k = blockIdx.y;
+    if (k >= it.d) return;
+    const int a_n = it.crow[k], b_n = it.ccol[k], N = it.N, R = it.R;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a_n * b_n) return;
+    const int a = e / b_n, b = e % b_n;
+    const cplx *core = it.cores + (size_t)k * R * N * R;
+    const double L = it.L[k], eta = 2.0 * L / N, al = it.alpha[k];
+    cplx s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
+    for (int i = 0; i < N; ++i) {
+        const cplx z = {-L + (i + 0.5) * eta, al};
+        const cplx g = core[((size_t)a * N + i) * b_n + b];
+        const cplx zg = cmul(z, g);
+        s1 = cadd(s1, zg);
+        s2 = cadd(s2, cmul(z, zg));
+    }
+    it.M1[(size_t)k * R * R + e] = s1;
+    it.M2[(size_t)k * R * R + e] = s2;
+}
+
+// mu1[k] = <TT, z_k>, mu2[k][l] = <TT, z_k z_l> through left/right environments of the chain.
+__global__ __launch_bounds__(64) void k_moments(Item *items, const int *active, cplx *out, int stride)
+{
+    __shared__ cplx lenv[TTFP_MAX_D][TTFP_MAX_RANK];
+    __shared__ cplx renv[TTFP_MAX_D][TTFP_MAX_RANK];
+    __shared__ cplx v[TTFP_MAX_RANK], w[TTFP_MAX_RANK];
+    const int item = blockIdx.x;
+    if (!active[item]) return;
+    Item &it = items[item];
+    const int d = it.d, R = it.R;
+    cplx *o = out + (size_t)item * stride;     // [d] mu1 then [d*d] mu2
+    // left environments: lenv[k] = 1^T M_0 ... M_{k-1}
+    if (threadIdx.x == 0) lenv[0][0] = {1.0, 0.0};
+    __syncthreads();
+    for (int k = 0; k + 1 < d; ++k) {
+        const int a_n = it.crow[k], b_n = it.ccol[k];
+        const cplx *Mk = it.M + (size_t)k * R * R;
+        for (int b = threadIdx.x; b < b_n; b += blockDim.x) {
+            cplx acc = {0.0, 0.0};
+            for (int a = 0; a < a_n; ++a) acc = cadd(acc, cmul(lenv[k][a], Mk[a * b_n + b]));
+            lenv[k + 1][b] = acc;
+        }
+        __syncthreads();
+    }
+    // right environments: renv[k] = M_{k+1} ... M_{d-1} 1
+    if (threadIdx.x == 0) renv[d - 1][0] = {1.0, 0.0};
+    __syncthreads();
+    for (int k = d - 1; k >= 1; --k) {
+        const int a_n = it.crow[k], b_n = it.ccol[k];
+        const cplx *Mk = it.M + (size_t)k * R * R;
+        for (int a = threadIdx.x; a < a_n; a += blockDim.x) {
+            cplx acc = {0.0, 0.0};
+            for (int b = 0; b < b_n; ++b) acc = cadd(acc, cmul(Mk[a * b_n + b], renv[k][b]));
+            renv[k - 1][a] = acc;
+        }
+        __syncthreads();
+    }
+    for (int k = 0; k < d; ++k) {
+        const int a_n = it.crow[k], b_n = it.ccol[k];
+        const cplx *M1 = it.M1 + (size_t)k * R * R;
+        const cplx *M2 = it.M2 + (size_t)k * R * R;
+        // mu1[k], mu2[k][k]
+        for (int b = threadIdx.x; b < b_n; b += blockDim.x) {
+            cplx a1 = {0.0, 0.0}, a2 = {0.0, 0.0};
+            for (int a = 0; a < a_n; ++a) {
+                a1 = cadd(a1, cmul(lenv[k][a], M1[a * b_n + b]));
+                a2 = cadd(a2, cmul(lenv[k][a], M2[a * b_n + b]));
+            }
+            v[b] = cmul(a1, renv[k][b]);
+            w[b] = cmul(a2, renv[k][b]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            cplx s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
+            for (int b = 0; b < b_n; ++b) { s1 = cadd(s1, v[b]); s2 = cadd(s2, w[b]); }
+            o[k] = s1;
+            o[d + k * d + k] = s2;
+        }
+        __syncthreads();
+        // mu2[k][l], l > k: carry lenv[k] M1_k through M_{k+1..l-1}
+        for (int b = threadIdx.x; b < b_n; b += blockDim.x) {
+            cplx a1 = {0.0, 0.0};
+            for (int a = 0; a < a_n; ++a) a1 = cadd(a1, cmul(lenv[k][a], M1[a * b_n + b]));
+            v[b] = a1;
+        }
+        __syncthreads();
+        for (int l = k + 1; l < d; ++l) {
+            const int la = it.crow[l], lb = it.ccol[l];
+            const cplx *L1 = it.M1 + (size_t)l * R * R;
+            const cplx *L0 = it.M + (size_t)l * R * R;
+            for (int b = threadIdx.x; b < lb; b += blockDim.x) {
+                cplx acc = {0.0, 0.0};
+                for (int a = 0; a < la; ++a) acc = cadd(acc, cmul(v[a], L1[a * lb + b]));
+                w[b] = cmul(acc, renv[l][b]);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                cplx s = {0.0, 0.0};
+                for (int b = 0; b < lb; ++b) s = cadd(s, w[b]);
+                o[d + k * d + l] = s;
+                o[d + l * d + k] = s;
+            }
+            __syncthreads();
+            for (int b = threadIdx.x; b < lb; b += blockDim.x) {
+                cplx acc = {0.0, 0.0};
+                for (int a = 0; a < la; ++a) acc = cadd(acc, cmul(v[a], L0[a * lb + b]));
+                w[b] = acc;
+            }
+            __syncthreads();
+            for (int b = threadIdx.x; b < lb; b += blockDim.x) v[b] = w[b];
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------------ tensor-train values at points
+__global__ __launch_bounds__(64) void k_tt_values(const Item *items, int item, long long npts, const int *idx, cplx *out)
+{
+    __shared__ cplx v[TTFP_MAX_RANK], w[TTFP_MAX_RANK];
+    const long long p = blockIdx.x;
+    if (p >= npts) return;
+    const Item &it = items[item];
+    const int d = it.d, N = it.N, R = it.R;
+    if (threadIdx.x == 0) v[0] = {1.0, 0.0};
+    __syncthreads();
+    for (int k = 0; k < d; ++k) {
+        const int a_n = it.crow[k], b_n = it.ccol[k], i = idx[p * d + k];
+        const cplx *core = it.cores + (size_t)k * R * N * R;
+        for (int b = threadIdx.x; b < b_n; b += blockDim.x) {
+            cplx acc = {0.0, 0.0};
+            for (int a = 0; a < a_n; ++a) acc = cadd(acc, cmul(v[a], core[((size_t)a * N + i) * b_n + b]));
+            w[b] = acc;
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < b_n; b += blockDim.x) v[b] = w[b];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[p] = v[0];
+}
+
+}  // namespace ttfp

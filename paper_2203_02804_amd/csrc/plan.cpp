@@ -1,0 +1,218 @@
+// Host-side problem setup for the pricer.
+//
+// Model (Sec. II.A): x_j = ln(S_T^j / K) is Gaussian with mean
+// m_j = ln(S0_j / K) + (r - sigma_j^2 / 2) T and covariance C = T diag(sigma) R diag(sigma);
+// the characteristic function of Sec. III.C is written with the maturity in its
+// quadratic term.
+//
+// Term decomposition: (max_j e^{x_j} - 1)^+ = sum_j (e^{x_j} - 1)^+ prod_{l != j} 1{x_l < x_j}.
+// Term j uses w_0 = x_j, w_l = x_l - x_j (l != j in increasing order), so that its payoff
+// is a product of one-dimensional factors whose transforms are
+//   (e^w - 1)^+ and (1 - e^w)^+ : 1/(iz(1+iz))  (Im z > 1, resp. Im z < 0)
+//   1{w < 0}                   : 1/(iz)        (Im z < 0)
+//   1{w > 0}                   : -1/(iz)       (Im z > 0).
+// Put-on-max swaps the call factor's strip; call-on-min uses 1{w > 0}.
+//
+// Grid (Sec. III.D): N midpoint nodes on [-L_k, L_k] per coordinate. Automatic choice:
+// L_k = sqrt(2 tau_L (C_w^{-1})_kk) -- the marginal of exp(-u^T C_w u / 2) along u_k has
+// variance (C_w^{-1})_kk -- and a contour distance a_k to the factor's pole with
+// exp(-a_k 2 pi / eta_k) = exp(-tau_A), eta_k = 2 L_k / N (the aliasing period in x is
+// 2 pi / eta_k).
+#include "plan.hpp"
+
+#include <cmath>
+#include <cstdio>
+
+namespace ttfp {
+
+static const double TAU_L = 34.5;
+static const double TAU_A = 32.0;
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+static bool finite(double x) { return std::isfinite(x); }
+
+// Cholesky of a symmetric positive definite n x n matrix (row-major). False if not SPD.
+static bool cholesky(const std::vector<double> &A, int n, std::vector<double> &Lc)
+{
+    Lc.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double s = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= Lc[(size_t)j * n + k] * Lc[(size_t)j * n + k];
+        if (!(s > 0.0)) return false;
+        double ljj = std::sqrt(s);
+        Lc[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= Lc[(size_t)i * n + k] * Lc[(size_t)j * n + k];
+            Lc[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    return true;
+}
+
+// Diagonal of A^{-1} from the Cholesky factor (solve L y = e_k, then ||L^{-T}..||).
+static std::vector<double> inverse_diagonal(const std::vector<double> &A, int n, bool &ok)
+{
+    std::vector<double> Lc;
+    ok = cholesky(A, n, Lc);
+    std::vector<double> out(n, 0.0);
+    if (!ok) return out;
+    // A^{-1} = L^{-T} L^{-1};  (A^{-1})_kk = sum_i (L^{-1})_{ik}^2
+    std::vector<double> Linv((size_t)n * n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        for (int i = 0; i < n; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s -= Lc[(size_t)i * n + k] * Linv[(size_t)k * n + c];
+            Linv[(size_t)i * n + c] = s / Lc[(size_t)i * n + i];
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += Linv[(size_t)i * n + k] * Linv[(size_t)i * n + k];
+        out[k] = s;
+    }
+    return out;
+}
+
+int check_cross_settings(const ttfp_grid *g, std::string &err)
+{
+    if (!g) { err = "grid is NULL"; return TTFP_EINVAL; }
+    if (g->N < 2 || g->N > 4096) { err = "N must be in [2, 4096]"; return TTFP_EINVAL; }
+    if (g->max_rank < 1 || g->max_rank > TTFP_MAX_RANK) { err = "max_rank must be in [1, 64]"; return TTFP_EINVAL; }
+    if (g->n_enrich < 0 || g->max_rank + g->n_enrich > TTFP_MAX_RANK + 4) {
+        err = "n_enrich must be >= 0 and max_rank + n_enrich <= 68";
+        return TTFP_EINVAL;
+    }
+    if (!(g->tol > 0.0) || !finite(g->tol)) { err = "tol must be positive"; return TTFP_EINVAL; }
+    if (!finite(g->rank_tol)) { err = "rank_tol must be finite"; return TTFP_EINVAL; }
+    if (g->max_sweeps < 1 || g->max_sweeps > 64) { err = "max_sweeps must be in [1, 64]"; return TTFP_EINVAL; }
+    return TTFP_OK;
+}
+
+int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::string &err)
+{
+    if (!o) { err = "option is NULL"; return TTFP_EINVAL; }
+    if (!g) { err = "grid is NULL"; return TTFP_EINVAL; }
+    const int d = o->d;
+    if (d < 1 || d > TTFP_MAX_D) { err = "d must be in [1, 32]"; return TTFP_EINVAL; }
+    if (o->payoff < 0 || o->payoff > 2) { err = "unknown payoff"; return TTFP_EINVAL; }
+    if (!o->S0 || !o->sigma || !o->corr) { err = "S0, sigma and corr must be non-NULL"; return TTFP_EINVAL; }
+    if (!(o->K > 0) || !(o->T > 0) || !finite(o->K) || !finite(o->T) || !finite(o->r)) {
+        err = "K and T must be positive and finite, r finite";
+        return TTFP_EINVAL;
+    }
+    if (g->N < 2 || g->N > 4096) { err = "N must be in [2, 4096]"; return TTFP_EINVAL; }
+    out = OptionPlan();
+    out.d = d;
+    out.payoff = o->payoff;
+    out.K = o->K;
+    out.T = o->T;
+    out.r = o->r;
+    out.S0.assign(o->S0, o->S0 + d);
+    out.sigma.assign(o->sigma, o->sigma + d);
+    out.corr.assign(o->corr, o->corr + (size_t)d * d);
+    for (int j = 0; j < d; ++j) {
+        if (!(out.S0[j] > 0) || !finite(out.S0[j])) { err = "S0 must be positive"; return TTFP_EINVAL; }
+        if (!(out.sigma[j] > 0) || !finite(out.sigma[j])) { err = "sigma must be positive"; return TTFP_EINVAL; }
+    }
+    for (int i = 0; i < d; ++i) {
+        if (std::fabs(out.corr[(size_t)i * d + i] - 1.0) > 1e-12) { err = "corr must have unit diagonal"; return TTFP_EINVAL; }
+        for (int j = 0; j < d; ++j) {
+            double a = out.corr[(size_t)i * d + j], b = out.corr[(size_t)j * d + i];
+            if (!finite(a) || std::fabs(a - b) > 1e-12) { err = "corr must be symmetric and finite"; return TTFP_EINVAL; }
+        }
+    }
+    std::vector<double> Lc;
+    if (!cholesky(out.corr, d, Lc)) { err = "corr is not positive definite"; return TTFP_EINVAL; }
+
+    // log-moneyness moments
+    std::vector<double> mx(d), Cx((size_t)d * d);
+    for (int j = 0; j < d; ++j)
+        mx[j] = std::log(out.S0[j] / out.K) + (out.r - 0.5 * out.sigma[j] * out.sigma[j]) * out.T;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            Cx[(size_t)i * d + j] = out.T * out.sigma[i] * out.sigma[j] * out.corr[(size_t)i * d + j];
+
+    const int n_terms = d;   // d == 1 gives one term as well
+    const int N = g->N;
+    for (int t = 0; t < n_terms; ++t) {
+        TermPlan tp;
+        tp.d = d;
+        tp.N = N;
+        tp.P.assign((size_t)d * d, 0.0);
+        tp.P[(size_t)0 * d + t] = 1.0;
+        int row = 1;
+        for (int l = 0; l < d; ++l) {
+            if (l == t) continue;
+            tp.P[(size_t)row * d + l] = 1.0;
+            tp.P[(size_t)row * d + t] = -1.0;
+            ++row;
+        }
+        tp.m.assign(d, 0.0);
+        tp.C.assign((size_t)d * d, 0.0);
+        for (int a = 0; a < d; ++a)
+            for (int k = 0; k < d; ++k) tp.m[a] += tp.P[(size_t)a * d + k] * mx[k];
+        std::vector<double> PC((size_t)d * d, 0.0);
+        for (int a = 0; a < d; ++a)
+            for (int k = 0; k < d; ++k) {
+                double s = 0.0;
+                for (int l = 0; l < d; ++l) s += tp.P[(size_t)a * d + l] * Cx[(size_t)l * d + k];
+                PC[(size_t)a * d + k] = s;
+            }
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < d; ++k) s += PC[(size_t)a * d + k] * tp.P[(size_t)b * d + k];
+                tp.C[(size_t)a * d + b] = s;
+            }
+        tp.kind.assign(d, KIND_CALL);
+        tp.sign.assign(d, 1);
+        tp.sign[0] = (o->payoff == TTFP_PUT_MAX) ? -1 : 1;
+        for (int k = 1; k < d; ++k) {
+            tp.kind[k] = (o->payoff == TTFP_CALL_MIN) ? KIND_GT : KIND_LT;
+            tp.sign[k] = (o->payoff == TTFP_CALL_MIN) ? 1 : -1;
+        }
+        // ---- grid
+        bool ok = true;
+        std::vector<double> prec = inverse_diagonal(tp.C, d, ok);
+        if (!ok) { err = "term covariance is not positive definite"; return TTFP_EINVAL; }
+        tp.L.assign(d, 0.0);
+        tp.alpha.assign(d, 0.0);
+        for (int k = 0; k < d; ++k) {
+            double L;
+            if (g->L_k) L = g->L_k[(size_t)t * d + k];
+            else if (g->L > 0) L = g->L;
+            else L = std::sqrt(2.0 * TAU_L * prec[k]);
+            if (!(L > 0) || !finite(L)) { err = "L must be positive"; return TTFP_EINVAL; }
+            tp.L[k] = L;
+            double a;
+            if (g->alpha_k) {
+                a = g->alpha_k[(size_t)t * d + k];
+            } else if (g->alpha > 0) {
+                a = tp.sign[k] * g->alpha;
+            } else {
+                double eta = 2.0 * L / N;
+                double dist = TAU_A * eta / TWO_PI;
+                a = (tp.kind[k] == KIND_CALL && tp.sign[k] > 0) ? 1.0 + dist : tp.sign[k] * dist;
+            }
+            // strip check
+            bool inside;
+            if (tp.kind[k] == KIND_CALL) inside = (tp.sign[k] > 0) ? (a > 1.0) : (a < 0.0);
+            else inside = (tp.sign[k] > 0) ? (a > 0.0) : (a < 0.0);
+            if (!inside || !finite(a)) {
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "contour shift %g outside the strip of coordinate %d of term %d", a, k, t);
+                err = buf;
+                return TTFP_EINVAL;
+            }
+            tp.alpha[k] = a;
+        }
+        double sc = out.K * std::exp(-out.r * out.T);
+        for (int k = 0; k < d; ++k) sc *= (2.0 * tp.L[k] / N) / TWO_PI;
+        tp.scale = sc;
+        out.terms.push_back(std::move(tp));
+    }
+    return TTFP_OK;
+}
+
+}  // namespace ttfp

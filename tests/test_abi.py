@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol, and its
+host planning logic (validation, term decomposition, grid rule) agrees with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2203_02804_amd as ttfp
+import workloads as W
+from oracle import fourier as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ttfp.h")).read()
+    return sorted(set(re.findall(r"\b(ttfp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ttfp.load()
+    names = declared_symbols()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(ttfp.EXPORTS) <= set(names)
+
+
+def test_strerror():
+    lib = ttfp.load()
+    assert lib.ttfp_strerror(0) == b"ok"
+    assert b"invalid" in lib.ttfp_strerror(-1)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_plan_matches_oracle_grid_rule(seed):
+    for opt in W.random_small_options(4, seed=seed, d_choices=(1, 2, 3, 5)):
+        for N in (64, 128):
+            L, A = ttfp.plan(opt, W.grid(N))
+            _, grids = F.term_grids(opt, N)
+            assert L.shape == (len(grids), opt["d"])
+            for t, (Lt, At) in enumerate(grids):
+                assert np.allclose(L[t], Lt, rtol=1e-12)
+                assert np.allclose(A[t], At, rtol=1e-12)
+
+
+def test_plan_scalar_grid_signs():
+    opt, g = W.config1()
+    L, A = ttfp.plan(opt, g)
+    assert np.all(L == 40.0)
+    assert np.allclose(A, [[2.0, -2.0], [2.0, -2.0]])
+    L, A = ttfp.plan(dict(opt, payoff="call_min"), g)
+    assert np.allclose(A, [[2.0, 2.0], [2.0, 2.0]])
+    L, A = ttfp.plan(dict(opt, payoff="put_max"), g)
+    assert np.allclose(A, [[-2.0, -2.0], [-2.0, -2.0]])
+
+
+@pytest.mark.parametrize("bad", [
+    dict(sigma=[0.2, -0.3]),
+    dict(S0=[100.0, 0.0]),
+    dict(K=-1.0),
+    dict(T=0.0),
+    dict(corr=[[1.0, 1.2], [1.2, 1.0]]),      # not positive definite
+    dict(corr=[[1.0, 0.5], [0.4, 1.0]]),      # not symmetric
+    dict(corr=[[0.9, 0.5], [0.5, 1.0]]),      # diagonal not one
+    dict(d=0, S0=[], sigma=[], corr=[]),
+])
+def test_plan_rejects_invalid_options(bad):
+    opt, g = W.config1()
+    opt = dict(opt, **bad)
+    with pytest.raises((ttfp.TTFPError, ValueError)):
+        ttfp.plan(opt, g)
+
+
+def test_plan_rejects_contour_outside_strip():
+    opt, g = W.config1()
+    with pytest.raises(ttfp.TTFPError):
+        ttfp.plan(opt, dict(g, alpha=0.5))        # call coordinate needs alpha > 1
+    with pytest.raises(ttfp.TTFPError):
+        ttfp.plan(opt, dict(g, N=1))

@@ -1,0 +1,98 @@
+"""GPU parity of the individual kernels, through the C ABI, against the oracle."""
+import itertools
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fourier as F
+from oracle import ttcross as TT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pricer():
+    import paper_2203_02804_amd as ttfp
+    p = ttfp.Pricer(0)
+    yield p
+    p.close()
+
+
+def _check_integrand(pricer, opt, grid, npts, seed):
+    ts, grids = F.term_grids(opt, grid["N"], grid.get("L"), grid.get("alpha"))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Ls = np.array([g[0] for g in grids])
+    As = np.array([g[1] for g in grids])
+    g2 = dict(grid, L=Ls, alpha=As)       # the oracle's grid, passed explicitly
+    for t, term in enumerate(ts):
+        idx = rng.integers(0, grid["N"], size=(npts, opt["d"]))
+        gpu = pricer.eval_integrand(opt, g2, t, idx)
+        ref = F.integrand_at(term, grid["N"], Ls[t], As[t], idx)
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(gpu - ref)) <= 1e-13 * scale + 1e-300
+        assert np.all(np.abs(gpu - ref) <= 1e-12 * np.abs(ref) + 1e-15 * scale)
+
+
+def test_integrand_small(pricer):
+    opt, g = W.config1()
+    _check_integrand(pricer, opt, g, 300, 1)
+    for opt in W.random_small_options(6, seed=7, d_choices=(1, 2, 3)):
+        _check_integrand(pricer, opt, W.grid(48), 200, 2)
+
+
+def test_integrand_full_size_configs(pricer):
+    opt, g = W.config2()
+    _check_integrand(pricer, opt, g, 4000, 3)
+    opt, g = W.config3()
+    _check_integrand(pricer, opt, g, 2000, 4)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (7, 3), (64, 12), (300, 36), (1000, 37), (4096, 36), (2500, 68)])
+def test_tsqr_r_factor(pricer, m, n):
+    rng = np.random.Generator(np.random.PCG64(m * 1000 + n))
+    A = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    if n > 3:   # graded columns: singular values spread over many decades
+        A = A * np.logspace(0, -12, n)[None, :]
+    R = pricer.qr_r(A)
+    assert np.allclose(np.tril(R, -1), 0)
+    # R^H R = A^H A and |R| agrees with a reference factor up to the unit diagonal phases
+    Rn = np.linalg.qr(A, mode="r")
+    k = min(m, n)
+    ph = np.diag(Rn)[:k] / np.where(np.diag(R)[:k] == 0, 1, np.diag(R)[:k])
+    ph = ph / np.where(np.abs(ph) == 0, 1, np.abs(ph))
+    Rg = R[:k] * ph[:, None]
+    colnorm = np.linalg.norm(A, axis=0)
+    err = np.abs(Rg - Rn[:k]) / colnorm[None, :]
+    assert np.max(err) < 1e-13
+    if m < n:
+        assert np.allclose(R[m:], 0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_maxvol_tiny_against_exhaustive_search(pricer, seed):
+    rng = np.random.Generator(np.random.PCG64(100 + seed))
+    m, r = int(rng.integers(5, 11)), int(rng.integers(1, 4))
+    A = rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r))
+    delta = 1e-2
+    rows, B = pricer.maxvol(A, delta)
+    assert len(set(rows.tolist())) == r
+    assert np.allclose(B, A @ np.linalg.inv(A[rows]), atol=1e-12)
+    assert np.max(np.abs(B)) <= 1 + delta + 1e-12
+    vmax = max(abs(np.linalg.det(A[list(s)])) for s in itertools.combinations(range(m), r))
+    assert abs(np.linalg.det(A[rows])) >= vmax / ((1 + delta) ** r * r ** (r / 2)) - 1e-12
+
+
+@pytest.mark.parametrize("m,r", [(64, 8), (1000, 24), (4096, 32), (8192, 64), (300, 1)])
+def test_maxvol_dominance(pricer, m, r):
+    rng = np.random.Generator(np.random.PCG64(m + r))
+    A = rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r))
+    Q, _ = np.linalg.qr(A)
+    rows, B = pricer.maxvol(Q, 1e-2)
+    assert len(set(rows.tolist())) == r
+    ref = Q @ np.linalg.inv(Q[rows])
+    assert np.max(np.abs(B - ref)) < 1e-11
+    assert np.max(np.abs(B)) <= 1.01 + 1e-10
+    # the oracle's maxvol from the same start reaches the same dominance bound
+    _, Bo = TT.maxvol(Q, 1e-2)
+    assert np.max(np.abs(Bo)) <= 1.01 + 1e-10
