@@ -61,7 +61,7 @@ typedef struct {
 } ttfp_option;
 
 /* Grid and TT-cross settings.
- *  N            nodes per coordinate: u_i = -L + (i + 1/2) 2L/N, i = 0..N-1
+ *  N            nodes per coordinate, 2..1024: u_i = -L + (i + 1/2) 2L/N, i = 0..N-1
  *  L            > 0: the same half-width on every coordinate of every term; <= 0: automatic
  *  alpha        > 0: |contour shift| on every coordinate, signed by the coordinate's strip
  *               (call coordinate +alpha, which must exceed 1; put coordinate -alpha;
@@ -85,6 +85,7 @@ typedef struct {
 /* Per-option diagnostics. */
 typedef struct {
     double imag_rel;       /* |Im price| / |Re price| */
+    double kappa;          /* cancellation factor: estimated sum |integrand| / |price| */
     double last_change;    /* relative price change over the last half sweep */
     int64_t n_evals;       /* integrand evaluations (the paper's oracle calls) */
     int32_t sweeps;        /* half sweeps performed */
@@ -137,6 +138,17 @@ int ttfp_tt_values(ttfp_ctx *ctx, int32_t term, int64_t npts, const int32_t *idx
 int ttfp_qr_r(ttfp_ctx *ctx, int32_t m, int32_t n, const double *A, double *R);
 int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double delta, int32_t *rows,
                 double *B);
+
+/* Kernel timing: when enabled, HIP events recorded on the context's stream bracket every
+ * launch of each kernel family; ttfp_profile_read returns the number of launches and their
+ * summed device time since the last enable. */
+enum {
+    TTFP_KERNEL_FIBER = 0, TTFP_KERNEL_TSQR = 1, TTFP_KERNEL_QRCP = 2, TTFP_KERNEL_BASIS = 3,
+    TTFP_KERNEL_MAXVOL = 4, TTFP_KERNEL_FINISH = 5, TTFP_KERNEL_CORESUM = 6, TTFP_KERNEL_CONTRACT = 7,
+    TTFP_KERNEL_COUNT = 8
+};
+int ttfp_profile_enable(ttfp_ctx *ctx, int enable);
+int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms);
 
 const char *ttfp_strerror(int code);
 const char *ttfp_last_error(const ttfp_ctx *ctx);

@@ -57,12 +57,12 @@ static double complex integrand(int d, const double complex *z, const double *m,
     return cexp(e) * h;
 }
 
-/* out[0] + i out[1] = S ; out[2] = sum |F| (for the cancellation diagnostic). */
-void dense_term_sum(int d, int N, const double *m, const double *C, const double *L,
-                    const double *alpha, const int *kind, int nthreads, double *out)
+/* Partial sum over the rows [row_begin, row_end) of the grid (a row fixes every index but
+ * the last). out[0] + i out[1] = S ; out[2] = sum |F| (for the cancellation diagnostic). */
+void dense_term_sum_rows(int d, int N, const double *m, const double *C, const double *L,
+                         const double *alpha, const int *kind, int nthreads, int64_t row_begin,
+                         int64_t row_end, double *out)
 {
-    int64_t rows = 1;
-    for (int k = 0; k < d - 1; ++k) rows *= N;
     double sre = 0.0, sim = 0.0, sabs = 0.0;
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel
@@ -70,7 +70,7 @@ void dense_term_sum(int d, int N, const double *m, const double *C, const double
         double complex z[64];
         double are = 0.0, aim = 0.0, cre = 0.0, cim = 0.0, aabs = 0.0;
 #pragma omp for schedule(dynamic, 64)
-        for (int64_t row = 0; row < rows; ++row) {
+        for (int64_t row = row_begin; row < row_end; ++row) {
             int64_t t = row;
             for (int k = d - 2; k >= 0; --k) {
                 z[k] = node(k, (int)(t % N), N, L, alpha);
@@ -105,6 +105,15 @@ void dense_term_sum(int d, int N, const double *m, const double *C, const double
     out[0] = sre;
     out[1] = sim;
     out[2] = sabs;
+}
+
+/* The full sum over all N^d points. */
+void dense_term_sum(int d, int N, const double *m, const double *C, const double *L,
+                    const double *alpha, const int *kind, int nthreads, double *out)
+{
+    int64_t rows = 1;
+    for (int k = 0; k < d - 1; ++k) rows *= N;
+    dense_term_sum_rows(d, N, m, C, L, alpha, kind, nthreads, 0, rows, out);
 }
 
 /* Integrand values at npts multi-indices idx[p*d + k] (0-based grid indices). */

@@ -33,12 +33,14 @@ characteristic function; the d-dimensional normalisation is (2 pi)^{-d}; the sum
 uses N midpoint nodes u_i = -L + (i + 1/2) 2L/N (a symmetric grid); the bilinear
 (non-conjugated) product phi(-z) v(z) is summed and its real part taken.
 
-Grid rule (grid_rule): per term and coordinate, L_k = sqrt(2 tau_L (C_w^{-1})_kk)
+Grid rule (grid_rule): per term and coordinate, L_k = sqrt(2 tau (C_w^{-1})_kk)
 (the marginal of exp(-u^T C_w u / 2) along u_k has variance (C_w^{-1})_kk), and the
 contour shift is set from the aliasing distance X_k = 2 pi / eta_k so that
-exp(-a_k X_k) = exp(-tau_A), with a_k the distance to the factor's pole
+exp(-a_k X_k) = exp(-tau), with a_k the distance to the factor's pole
 (alpha_0 = 1 + a_0 for a call coordinate, -a_0 for a put coordinate, -a_k / +a_k
-for max / min indicators).
+for max / min indicators). tau = ln(100 / tol) clamped to [18, 34.5]: a tighter target
+costs a larger shift, and the shift's damping e^{alpha.w} multiplies the absolute
+size of the summand (the cancellation factor) faster than it removes aliasing.
 
 Parity: pinned in tests/test_oracle_fourier.py against Black-Scholes (d=1), the
 two-asset closed forms (d=2), the one-factor quadrature (d=3, 5), put-call parity,
@@ -55,8 +57,12 @@ import numpy as np
 from . import build as _build
 
 KIND_CALL, KIND_LT, KIND_GT = 0, 1, 2
-TAU_L = 34.5    # truncation: exp(-34.5) ~ 1e-15 of the Gaussian mass
-TAU_A = 32.0    # aliasing: exp(-32) ~ 1.3e-14
+DEFAULT_TOL = 1e-12
+
+
+def grid_tau(tol):
+    """Exponent of the truncation / aliasing targets for a requested tolerance."""
+    return min(34.5, max(18.0, math.log(100.0 / tol)))
 
 _lib = None
 
@@ -72,6 +78,9 @@ def _load():
         ip = ctypes.POINTER(ctypes.c_int)
         lib.dense_term_sum.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip, ctypes.c_int, dp]
         lib.dense_term_sum.restype = None
+        lib.dense_term_sum_rows.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip, ctypes.c_int,
+                                            ctypes.c_int64, ctypes.c_int64, dp]
+        lib.dense_term_sum_rows.restype = None
         lib.integrand_points.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip,
                                          ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), dp]
         lib.integrand_points.restype = None
@@ -131,13 +140,14 @@ def terms(opt):
     return out
 
 
-def grid_rule(term, N, tau_L=TAU_L, tau_A=TAU_A):
+def grid_rule(term, N, tol=DEFAULT_TOL):
     """Automatic (L_k, alpha_k) for one term (see module docstring)."""
+    tau = grid_tau(tol)
     Cw = term["C"]
     prec = np.diag(np.linalg.inv(Cw))
-    L = np.sqrt(2.0 * tau_L * prec)
+    L = np.sqrt(2.0 * tau * prec)
     eta = 2.0 * L / N
-    a = tau_A * eta / (2.0 * math.pi)
+    a = tau * eta / (2.0 * math.pi)
     alpha = np.empty_like(L)
     for k in range(len(L)):
         if term["kind"][k] == KIND_CALL and term["sign"][k] > 0:
@@ -147,7 +157,7 @@ def grid_rule(term, N, tau_L=TAU_L, tau_A=TAU_A):
     return L, alpha
 
 
-def term_grids(opt, N, L=None, alpha=None):
+def term_grids(opt, N, L=None, alpha=None, tol=DEFAULT_TOL):
     """Per-term (L[d], alpha[d]) arrays. L/alpha may be None (automatic rule),
     a positive scalar (same half-width / same |shift| on every coordinate, with the
     sign of each coordinate's strip; a call coordinate takes +alpha), or an array of
@@ -155,7 +165,7 @@ def term_grids(opt, N, L=None, alpha=None):
     ts = terms(opt)
     out = []
     for t, term in enumerate(ts):
-        Lauto, Aauto = grid_rule(term, N)
+        Lauto, Aauto = grid_rule(term, N, tol)
         if L is None:
             Lt = Lauto
         elif np.isscalar(L):
@@ -167,7 +177,7 @@ def term_grids(opt, N, L=None, alpha=None):
                 At = Aauto
             else:   # rule for alpha given this L
                 eta = 2.0 * Lt / N
-                a = TAU_A * eta / (2.0 * math.pi)
+                a = grid_tau(tol) * eta / (2.0 * math.pi)
                 At = np.where((term["kind"] == KIND_CALL) & (term["sign"] > 0), 1.0 + a, term["sign"] * a)
         elif np.isscalar(alpha):
             At = term["sign"] * float(alpha)
@@ -192,15 +202,31 @@ def dense_term(term, N, L, alpha, nthreads=0):
     return complex(out[0], out[1]), float(out[2])
 
 
+def dense_term_rows(term, N, L, alpha, row_begin, row_end, nthreads=0):
+    """Partial dense sum over grid rows [row_begin, row_end) (a row fixes all but the last index)."""
+    lib = _load()
+    d = len(term["m"])
+    m = np.ascontiguousarray(term["m"], float)
+    C = np.ascontiguousarray(term["C"], float)
+    kind = np.ascontiguousarray(term["kind"], np.int32)
+    L = np.ascontiguousarray(L, float)
+    alpha = np.ascontiguousarray(alpha, float)
+    out = np.zeros(3)
+    lib.dense_term_sum_rows(d, N, _dp(m), _dp(C), _dp(L), _dp(alpha),
+                            kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(nthreads),
+                            int(row_begin), int(row_end), _dp(out))
+    return complex(out[0], out[1]), float(out[2])
+
+
 def term_scale(opt, L, N):
     """K e^{-rT} prod_k (eta_k / 2 pi) for one term with half-widths L."""
     eta = 2.0 * np.asarray(L, float) / N
     return opt["K"] * math.exp(-opt["r"] * opt["T"]) * float(np.prod(eta / (2.0 * math.pi)))
 
 
-def dense_price(opt, N, L=None, alpha=None, nthreads=0, details=False):
-    """The Fourier price on the full N^d grid of every term."""
-    ts, grids = term_grids(opt, N, L, alpha)
+def dense_price(opt, N, L=None, alpha=None, nthreads=0, details=False, tol=DEFAULT_TOL):
+    """The Fourier price on the full N^d grid of every term (tol selects the automatic grid)."""
+    ts, grids = term_grids(opt, N, L, alpha, tol)
     total = 0.0 + 0.0j
     abs_total = 0.0
     per_term = []

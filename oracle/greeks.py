@@ -20,15 +20,15 @@ import numpy as np
 from . import fourier
 
 
-def fixed_grid(opt, N, L=None, alpha=None):
-    _, grids = fourier.term_grids(opt, N, L, alpha)
+def fixed_grid(opt, N, L=None, alpha=None, tol=fourier.DEFAULT_TOL):
+    _, grids = fourier.term_grids(opt, N, L, alpha, tol)
     Ls = np.array([g[0] for g in grids])
     As = np.array([g[1] for g in grids])
     return Ls, As
 
 
-def fd_greeks(opt, N, L=None, alpha=None, h=1e-4, nthreads=0):
-    Ls, As = fixed_grid(opt, N, L, alpha)
+def fd_greeks(opt, N, L=None, alpha=None, h=1e-4, nthreads=0, tol=fourier.DEFAULT_TOL):
+    Ls, As = fixed_grid(opt, N, L, alpha, tol)
     d = opt["d"]
     delta = np.zeros(d)
     vega = np.zeros(d)

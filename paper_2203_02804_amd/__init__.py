@@ -46,12 +46,15 @@ class _Grid(ctypes.Structure):
 
 
 class _Diag(ctypes.Structure):
-    _fields_ = [("imag_rel", ctypes.c_double), ("last_change", ctypes.c_double), ("n_evals", ctypes.c_int64),
+    _fields_ = [("imag_rel", ctypes.c_double), ("kappa", ctypes.c_double), ("last_change", ctypes.c_double),
+                ("n_evals", ctypes.c_int64),
                 ("sweeps", ctypes.c_int32), ("rank_capped", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
 
 EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_eval_integrand",
-           "ttfp_tt_values", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error"]
+           "ttfp_tt_values", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
+           "ttfp_profile_enable", "ttfp_profile_read"]
+KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract"]
 
 _lib = None
 
@@ -78,6 +81,8 @@ def load():
     lib.ttfp_qr_r.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
     lib.ttfp_maxvol.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), ctypes.c_double,
                                 P(ctypes.c_int32), P(ctypes.c_double)]
+    lib.ttfp_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.ttfp_profile_read.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_double)]
     lib.ttfp_strerror.argtypes = [ctypes.c_int]
     lib.ttfp_strerror.restype = ctypes.c_char_p
     lib.ttfp_last_error.argtypes = [vp]
@@ -184,7 +189,7 @@ class Pricer:
         diag = _Diag()
         rc = self._check(self.lib.ttfp_price(self.ctx, ctypes.byref(m.opt), ctypes.byref(m.grid), ctypes.byref(out),
                                              _ip(ranks), ctypes.byref(diag)))
-        info = dict(imag_rel=diag.imag_rel, last_change=diag.last_change, n_evals=diag.n_evals,
+        info = dict(imag_rel=diag.imag_rel, kappa=diag.kappa, last_change=diag.last_change, n_evals=diag.n_evals,
                     sweeps=diag.sweeps, rank_capped=bool(diag.rank_capped), converged=bool(diag.converged))
         return out.value, ranks.reshape(d, d + 1), info, rc
 
@@ -210,6 +215,20 @@ class Pricer:
             return prices, status
         split = np.cumsum([int(o["d"]) for o in opts])[:-1]
         return prices, np.split(delta, split), np.split(vega, split), status
+
+    def profile(self, enable=True):
+        """Starts (and resets) or stops per-kernel device timing with HIP events."""
+        self._check(self.lib.ttfp_profile_enable(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel: (launches, total_ms)} since the last profile(True)."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            n = ctypes.c_int64(0)
+            ms = ctypes.c_double(0.0)
+            self._check(self.lib.ttfp_profile_read(self.ctx, k, ctypes.byref(n), ctypes.byref(ms)))
+            out[name] = (n.value, ms.value)
+        return out
 
     def eval_integrand(self, opt, grid, term, idx):
         m = _Marshal(opt, grid)

@@ -47,6 +47,12 @@ struct ttfp_ctx {
     // last single-option call (for ttfp_tt_values)
     std::vector<Item> last_items;
     int last_n_items = 0;
+    // kernel timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
+    long long prof_launches[TTFP_KERNEL_COUNT] = {0};
+    double prof_ms[TTFP_KERNEL_COUNT] = {0};
 };
 
 namespace {
@@ -150,7 +156,7 @@ int ensure_arena(ttfp_ctx *ctx, size_t bytes, size_t n_items)
 struct Batch {
     std::vector<Item> items;
     std::vector<int> item_opt;           // option (within the chunk) of each item
-    std::vector<double> item_scale;
+    std::vector<double> item_scale, item_mass;
     std::vector<const TermPlan *> item_term;
     Launch geo;
 };
@@ -242,6 +248,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             b.items.push_back(it);
             b.item_opt.push_back((int)o);
             b.item_scale.push_back(tp.scale);
+            b.item_mass.push_back(tp.absmass);
             b.item_term.push_back(&tp);
             base += s.bytes;
         }
@@ -252,24 +259,90 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
 
 unsigned cdivu(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+// ---- kernel timing: an event pair around each launch of a kernel family
+hipEvent_t prof_event(ttfp_ctx *ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+struct ProfScope {
+    ttfp_ctx *ctx;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(ttfp_ctx *c, int k) : ctx(c), kind(k)
+    {
+        if (!ctx->prof) return;
+        a = prof_event(ctx);
+        b = prof_event(ctx);
+        if (a) (void)hipEventRecord(a, ctx->stream);
+    }
+    ~ProfScope()
+    {
+        if (!ctx->prof || !a || !b) return;
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->ev_open.push_back({kind, {a, b}});
+    }
+};
+// called after a stream synchronisation: folds the finished event pairs into the totals
+void prof_collect(ttfp_ctx *ctx)
+{
+    for (auto &p : ctx->ev_open) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            ctx->prof_launches[p.first] += 1;
+            ctx->prof_ms[p.first] += ms;
+        }
+        ctx->ev_pool.push_back(p.second.first);
+        ctx->ev_pool.push_back(p.second.second);
+    }
+    ctx->ev_open.clear();
+}
+
 int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
 {
     hipStream_t st = ctx->stream;
     Item *it = ctx->d_items;
     int *act = ctx->d_active;
     const unsigned ny = (unsigned)n_items;
-    hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.maxrows * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0, sweep);
-    int n = (g.maxrows + g.BR - 1) / g.BR;
-    const size_t lds = (size_t)g.BR * g.maxnc * sizeof(cplx);
-    for (int level = 0; level < g.nlev; ++level) {
-        hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(n, 1), ny), dim3(256), lds, st, it, act, t, dir, level, g.BR, g.G);
-        n = (n + g.G - 1) / g.G;
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_FIBER);
+        hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.maxrows * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0, sweep);
     }
-    hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(256), 0, st, it, act, t, dir, g.BR, g.G);
-    hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir);
-    hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(1024), 0, st, it, act, t, dir);
-    hipLaunchKernelGGL(k_finish, dim3(cdivu((long long)g.maxrows * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir);
-    hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_TSQR);
+        int n = (g.maxrows + g.BR - 1) / g.BR;
+        const size_t lds = (size_t)g.BR * g.maxnc * sizeof(cplx);
+        for (int level = 0; level < g.nlev; ++level) {
+            hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(n, 1), ny), dim3(256), lds, st, it, act, t, dir, level, g.BR, g.G);
+            n = (n + g.G - 1) / g.G;
+        }
+    }
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_QRCP);
+        hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(256), 0, st, it, act, t, dir, g.BR, g.G);
+    }
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_BASIS);
+        hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir);
+    }
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
+        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(1024), 0, st, it, act, t, dir);
+    }
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_FINISH);
+        hipLaunchKernelGGL(k_finish, dim3(cdivu((long long)g.maxrows * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir);
+    }
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_CORESUM);
+        hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
+    }
     HIPCHK(hipGetLastError());
     return TTFP_OK;
 }
@@ -278,15 +351,24 @@ int launch_edge(ttfp_ctx *ctx, const Launch &g, int n_items, int dir, int sweep)
 {
     hipStream_t st = ctx->stream;
     const unsigned ny = (unsigned)n_items;
-    hipLaunchKernelGGL(k_fiber, dim3(cdivu(g.maxrows, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1, sweep);
-    hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1);
-    hipLaunchKernelGGL(k_contract, dim3(ny), dim3(64), 0, st, ctx->d_items, ctx->d_active);
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_FIBER);
+        hipLaunchKernelGGL(k_fiber, dim3(cdivu(g.maxrows, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1, sweep);
+    }
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_CORESUM);
+        hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1);
+    }
+    {
+        ProfScope ps(ctx, TTFP_KERNEL_CONTRACT);
+        hipLaunchKernelGGL(k_contract, dim3(ny), dim3(64), 0, st, ctx->d_items, ctx->d_active);
+    }
     HIPCHK(hipGetLastError());
     return TTFP_OK;
 }
 
 struct OptResult {
-    double price = 0, imag = 0, change = INFINITY;
+    double price = 0, imag = 0, change = INFINITY, kappa = 0;
     int sweeps = 0, capped = 0, converged = 0;
     long long evals = 0;
     int code = TTFP_OK;
@@ -319,6 +401,7 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
             if (rc) return rc;
             HIPCHK(hipMemcpyAsync(host_items.data(), ctx->d_items, n_items * sizeof(Item), hipMemcpyDeviceToHost, ctx->stream));
             HIPCHK(hipStreamSynchronize(ctx->stream));
+            if (ctx->prof) prof_collect(ctx);
             std::vector<double> pr(n_opts, 0.0), pi(n_opts, 0.0);
             std::vector<long long> ev(n_opts, 0);
             std::vector<int> cap(n_opts, 0);
@@ -361,9 +444,15 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
         }
     }
 done:
-    for (int o = 0; o < n_opts; ++o) {
-        OptResult &r = res[o];
-        r.code = (r.converged && !r.capped) ? TTFP_OK : TTFP_ENOTCONV;
+    {
+        std::vector<double> mass(n_opts, 0.0);
+        for (int i = 0; i < n_items; ++i) mass[b.item_opt[i]] += b.item_mass[i];
+        for (int o = 0; o < n_opts; ++o) {
+            OptResult &r = res[o];
+            r.kappa = mass[o] / std::max(std::fabs(r.price), 1e-300);
+            r.code = (r.converged && !r.capped) ? TTFP_OK : TTFP_ENOTCONV;
+            if (r.code == TTFP_OK && r.kappa * 2.220446049250313e-16 > grids[o]->tol) r.code = TTFP_EPRECISION;
+        }
     }
     if (greeks) {
         std::fill(active.begin(), active.end(), 1);
@@ -461,10 +550,36 @@ int ttfp_create(ttfp_ctx **out, int device, void *hip_stream)
     return TTFP_OK;
 }
 
+int ttfp_profile_enable(ttfp_ctx *ctx, int enable)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (!ctx->ev_open.empty()) {
+        (void)hipStreamSynchronize(ctx->stream);
+        prof_collect(ctx);
+    }
+    ctx->prof = enable != 0;
+    for (int k = 0; k < TTFP_KERNEL_COUNT; ++k) { ctx->prof_launches[k] = 0; ctx->prof_ms[k] = 0.0; }
+    return TTFP_OK;
+}
+
+int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms)
+{
+    if (!ctx || kernel < 0 || kernel >= TTFP_KERNEL_COUNT) return TTFP_EINVAL;
+    if (!ctx->ev_open.empty()) {
+        (void)hipStreamSynchronize(ctx->stream);
+        prof_collect(ctx);
+    }
+    if (launches) *launches = ctx->prof_launches[kernel];
+    if (total_ms) *total_ms = ctx->prof_ms[kernel];
+    return TTFP_OK;
+}
+
 int ttfp_destroy(ttfp_ctx *ctx)
 {
     if (!ctx) return TTFP_EINVAL;
     (void)hipSetDevice(ctx->device);
+    if (!ctx->ev_open.empty()) { (void)hipStreamSynchronize(ctx->stream); prof_collect(ctx); }
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->d_items) (void)hipFree(ctx->d_items);
     if (ctx->d_active) (void)hipFree(ctx->d_active);
@@ -510,10 +625,6 @@ int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
             if (rc) {
                 ctx->last_error = "option " + std::to_string(o) + ": " + err;
                 return rc;
-            }
-            if (grids[o].N > MAXN) {
-                ctx->last_error = "option " + std::to_string(o) + ": N must be <= 1024";
-                return TTFP_EINVAL;
             }
         }
         // chunk options so that one chunk's workspace stays below a cap
@@ -583,7 +694,6 @@ int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, dou
         std::string err;
         int rc = check_cross_settings(grid, err);
         if (!rc) rc = build_plan(opt, grid, P, err);
-        if (!rc && grid->N > MAXN) { err = "N must be <= 1024"; rc = TTFP_EINVAL; }
         if (rc) { ctx->last_error = err; return rc; }
         std::vector<const OptionPlan *> cp{&P};
         std::vector<const ttfp_grid *> cg{grid};
@@ -606,6 +716,7 @@ int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, dou
         }
         if (diag) {
             diag->imag_rel = std::fabs(r.imag) / std::max(std::fabs(r.price), 1e-300);
+            diag->kappa = r.kappa;
             diag->last_change = r.change;
             diag->n_evals = r.evals;
             diag->sweeps = r.sweeps;

@@ -14,22 +14,24 @@
 // Put-on-max swaps the call factor's strip; call-on-min uses 1{w > 0}.
 //
 // Grid (Sec. III.D): N midpoint nodes on [-L_k, L_k] per coordinate. Automatic choice:
-// L_k = sqrt(2 tau_L (C_w^{-1})_kk) -- the marginal of exp(-u^T C_w u / 2) along u_k has
+// L_k = sqrt(2 tau (C_w^{-1})_kk) -- the marginal of exp(-u^T C_w u / 2) along u_k has
 // variance (C_w^{-1})_kk -- and a contour distance a_k to the factor's pole with
-// exp(-a_k 2 pi / eta_k) = exp(-tau_A), eta_k = 2 L_k / N (the aliasing period in x is
-// 2 pi / eta_k).
+// exp(-a_k 2 pi / eta_k) = exp(-tau), eta_k = 2 L_k / N (the aliasing period in x is
+// 2 pi / eta_k). tau = ln(100 / tol) clamped to [18, 34.5]: the damping e^{alpha.w} of a
+// larger shift inflates the absolute size of the summand faster than it cuts aliasing.
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
 namespace ttfp {
 
-static const double TAU_L = 34.5;
-static const double TAU_A = 32.0;
 static const double TWO_PI = 6.283185307179586476925286766559;
 
 static bool finite(double x) { return std::isfinite(x); }
+
+static double grid_tau(double tol) { return std::min(34.5, std::max(18.0, std::log(100.0 / tol))); }
 
 // Cholesky of a symmetric positive definite n x n matrix (row-major). False if not SPD.
 static bool cholesky(const std::vector<double> &A, int n, std::vector<double> &Lc)
@@ -77,7 +79,7 @@ static std::vector<double> inverse_diagonal(const std::vector<double> &A, int n,
 int check_cross_settings(const ttfp_grid *g, std::string &err)
 {
     if (!g) { err = "grid is NULL"; return TTFP_EINVAL; }
-    if (g->N < 2 || g->N > 4096) { err = "N must be in [2, 4096]"; return TTFP_EINVAL; }
+    if (g->N < 2 || g->N > 1024) { err = "N must be in [2, 1024]"; return TTFP_EINVAL; }
     if (g->max_rank < 1 || g->max_rank > TTFP_MAX_RANK) { err = "max_rank must be in [1, 64]"; return TTFP_EINVAL; }
     if (g->n_enrich < 0 || g->max_rank + g->n_enrich > TTFP_MAX_RANK + 4) {
         err = "n_enrich must be >= 0 and max_rank + n_enrich <= 68";
@@ -101,7 +103,7 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
         err = "K and T must be positive and finite, r finite";
         return TTFP_EINVAL;
     }
-    if (g->N < 2 || g->N > 4096) { err = "N must be in [2, 4096]"; return TTFP_EINVAL; }
+    if (g->N < 2 || g->N > 1024) { err = "N must be in [2, 1024]"; return TTFP_EINVAL; }
     out = OptionPlan();
     out.d = d;
     out.payoff = o->payoff;
@@ -135,6 +137,7 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
 
     const int n_terms = d;   // d == 1 gives one term as well
     const int N = g->N;
+    const double tau = grid_tau(g->tol > 0 ? g->tol : 1e-12);
     for (int t = 0; t < n_terms; ++t) {
         TermPlan tp;
         tp.d = d;
@@ -182,7 +185,7 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
             double L;
             if (g->L_k) L = g->L_k[(size_t)t * d + k];
             else if (g->L > 0) L = g->L;
-            else L = std::sqrt(2.0 * TAU_L * prec[k]);
+            else L = std::sqrt(2.0 * tau * prec[k]);
             if (!(L > 0) || !finite(L)) { err = "L must be positive"; return TTFP_EINVAL; }
             tp.L[k] = L;
             double a;
@@ -192,7 +195,7 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
                 a = tp.sign[k] * g->alpha;
             } else {
                 double eta = 2.0 * L / N;
-                double dist = TAU_A * eta / TWO_PI;
+                double dist = tau * eta / TWO_PI;
                 a = (tp.kind[k] == KIND_CALL && tp.sign[k] > 0) ? 1.0 + dist : tp.sign[k] * dist;
             }
             // strip check
@@ -210,6 +213,28 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
         double sc = out.K * std::exp(-out.r * out.T);
         for (int k = 0; k < d; ++k) sc *= (2.0 * tp.L[k] / N) / TWO_PI;
         tp.scale = sc;
+        // Absolute size of the sum, by the Gaussian peak approximation:
+        // sum |integrand| ~ e^{alpha.m + alpha^T C alpha / 2} prod_k |h_k(i alpha_k)|
+        //                  x (2 pi)^{d/2} det(C)^{-1/2} / prod_k eta_k;
+        // divided by the price it estimates the cancellation factor of the quadrature.
+        double expo = 0.0;
+        for (int a = 0; a < d; ++a) {
+            expo += tp.alpha[a] * tp.m[a];
+            for (int b = 0; b < d; ++b) expo += 0.5 * tp.alpha[a] * tp.C[(size_t)a * d + b] * tp.alpha[b];
+        }
+        std::vector<double> Lw;
+        cholesky(tp.C, d, Lw);
+        double logdet = 0.0;
+        for (int k = 0; k < d; ++k) logdet += 2.0 * std::log(Lw[(size_t)k * d + k]);
+        double lmass = expo + 0.5 * d * std::log(TWO_PI) - 0.5 * logdet;
+        for (int k = 0; k < d; ++k) {
+            const double v = tp.alpha[k];
+            double h = 1.0 / std::fabs(v);                       // |1/(i z)| at z = i v
+            if (tp.kind[k] == KIND_CALL) h /= std::fabs(1.0 - v);   // |1/(1 + i z)|
+            lmass += std::log(h) - std::log(2.0 * tp.L[k] / N);
+        }
+        double mass = std::exp(std::min(lmass, 700.0));
+        tp.absmass = sc * mass;
         out.terms.push_back(std::move(tp));
     }
     return TTFP_OK;

@@ -21,6 +21,7 @@ struct TermPlan {
     std::vector<int> kind;      // payoff factor per coordinate
     std::vector<int> sign;      // +1 strip above the real axis, -1 below
     double scale = 0.0;         // K e^{-rT} prod_k eta_k / (2 pi)
+    double absmass = 0.0;       // estimate of scale * sum |integrand| over the grid
 };
 
 struct OptionPlan {

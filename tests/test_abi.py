@@ -38,12 +38,13 @@ def test_strerror():
 def test_plan_matches_oracle_grid_rule(seed):
     for opt in W.random_small_options(4, seed=seed, d_choices=(1, 2, 3, 5)):
         for N in (64, 128):
-            L, A = ttfp.plan(opt, W.grid(N))
-            _, grids = F.term_grids(opt, N)
-            assert L.shape == (len(grids), opt["d"])
-            for t, (Lt, At) in enumerate(grids):
-                assert np.allclose(L[t], Lt, rtol=1e-12)
-                assert np.allclose(A[t], At, rtol=1e-12)
+            for tol in (1e-8, 1e-12):
+                L, A = ttfp.plan(opt, W.grid(N, tol=tol))
+                _, grids = F.term_grids(opt, N, tol=tol)
+                assert L.shape == (len(grids), opt["d"])
+                for t, (Lt, At) in enumerate(grids):
+                    assert np.allclose(L[t], Lt, rtol=1e-12)
+                    assert np.allclose(A[t], At, rtol=1e-12)
 
 
 def test_plan_scalar_grid_signs():

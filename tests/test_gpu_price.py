@@ -64,7 +64,7 @@ def test_config1_closed_form(pricer):
     g = W.grid(64, tol=1e-11, max_rank=48)          # automatic L / alpha
     p, ranks, info, rc = pricer.price(opt, g)
     assert abs(p / stulz - 1) < 1e-6, (p, stulz)
-    ref = F.dense_price(opt, 64)
+    ref = F.dense_price(opt, 64, tol=1e-11)
     assert abs(p / ref - 1) < 1e-8
 
 
@@ -82,11 +82,12 @@ def test_d3_one_factor(pricer):
     for payoff in ("call_max", "put_max"):
         opt = W.option(3, [95.0, 100.0, 110.0], 100.0, 0.8, 0.03, [0.25, 0.2, 0.3],
                        W.equicorrelation(3, 1 / 3), payoff)
-        N = 48
-        Ls, As = oracle_grid(opt, N)
-        ref = F.dense_price(opt, N, Ls, As)
-        p, ranks, info, rc = pricer.price(opt, dict(W.grid(N, tol=1e-10, max_rank=48), L=Ls, alpha=As))
+        N = 96
+        ref = F.dense_price(opt, N, tol=1e-10)
+        p, ranks, info, rc = pricer.price(opt, W.grid(N, tol=1e-10, max_rank=64))
         assert abs(p / ref - 1) < 1e-8, (payoff, p, ref, ranks, info)
+        exact = CF.one_factor_price(opt["S0"], opt["K"], opt["T"], opt["r"], opt["sigma"], 1 / 3, payoff)
+        assert abs(p / exact - 1) < 1e-7
 
 
 def test_d4_random_correlation_ragged_grid(pricer):
@@ -127,12 +128,12 @@ def test_tt_interpolates_last_fibers_and_approximates_elsewhere(pricer):
 
 def test_batch_matches_single(pricer):
     opts = W.random_small_options(6, seed=51, d_choices=(1, 2, 3))
-    grid = W.grid(32, tol=1e-11, max_rank=32)
+    grid = dict(W.grid(32, tol=1e-11, max_rank=32), L=16.0, alpha=1.5)
     single = [pricer.price(o, grid)[0] for o in opts]
     batch, status = pricer.price_batch(opts, grid)
     assert np.allclose(batch, single, rtol=1e-9, atol=0)
     for o, p in zip(opts, batch):
-        ref = F.dense_price(o, 32)
+        ref = F.dense_price(o, 32, 16.0, 1.5)
         assert abs(p / ref - 1) < 1e-8
 
 
@@ -145,3 +146,13 @@ def test_invalid_input_errors(pricer):
         pricer.price(opt, dict(g, max_rank=65))
     with pytest.raises(ttfp.TTFPError):
         pricer.price(opt, dict(g, N=2048))
+
+
+def test_precision_flag_on_too_coarse_grid(pricer):
+    import paper_2203_02804_amd as ttfp
+    opt = W.option(3, [95.0, 100.0, 110.0], 100.0, 0.8, 0.03, [0.25, 0.2, 0.3], W.equicorrelation(3, 1 / 3))
+    p, ranks, info, rc = pricer.price(opt, W.grid(48, tol=1e-12, max_rank=48))
+    det = F.dense_price(opt, 48, tol=1e-12, details=True)
+    assert det["kappa"] > 1e8                      # the oracle's own cancellation factor
+    assert info["kappa"] > 1e5                     # the pricer's estimate flags it too
+    assert rc != ttfp.TTFP_OK
