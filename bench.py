@@ -40,7 +40,7 @@ def cpu_baseline(opt, grid, budget_s=12.0):
 
     N = grid["N"]
     d = opt["d"]
-    ts, grids = F.term_grids(opt, N)
+    ts, grids = F.term_grids(opt, N, tol=grid["tol"])
     term, (L, A) = ts[0], grids[0]
     rows_total = N ** (d - 1)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -108,10 +108,12 @@ def main():
 
     # per-option diagnostics of the timed batches (outside the timed region)
     diag_opts = batches[args.warmup][: min(B, 8)]
-    evals, kappas, capped, conv = [], [], 0, 0
+    evals, kappas, capped, conv, swaps, halves = [], [], 0, 0, [], []
     for o in diag_opts:
         p, ranks, info, rc = pricer.price(o, grid)
         evals.append(info["n_evals"])
+        swaps.append(info["maxvol_swaps"])
+        halves.append(info["sweeps"])
         kappas.append(info["kappa"])
         capped += int(info["rank_capped"])
         conv += int(info["converged"])
@@ -175,6 +177,8 @@ def main():
         "accuracy": {"sampled_options": len(diag_opts), "converged": conv, "rank_capped": capped,
                      "median_kappa": sorted(kappas)[len(kappas) // 2],
                      "evals_per_option": evals_per_option,
+                     "maxvol_swaps_per_option": sum(swaps) / len(swaps),
+                     "half_sweeps_per_option": sum(halves) / len(halves),
                      "status_counts": {str(k): status_all.count(k) for k in sorted(set(status_all))}},
     }
     print(json.dumps(out), flush=True)

@@ -88,8 +88,10 @@ typedef struct {
     double kappa;          /* cancellation factor: estimated sum |integrand| / |price| */
     double last_change;    /* relative price change over the last half sweep */
     int64_t n_evals;       /* integrand evaluations (the paper's oracle calls) */
+    int64_t maxvol_swaps;  /* row swaps made by maxvol after its starting rows */
     int32_t sweeps;        /* half sweeps performed */
-    int32_t rank_capped;   /* 1 if some bond hit max_rank */
+    int32_t rank_capped;   /* 1 if some bond hit max_rank (a capped cross also stops once its
+                              change stops halving over a full sweep) */
     int32_t converged;     /* 1 if the tolerance was met */
 } ttfp_diag;
 

@@ -40,7 +40,9 @@ exp(-a_k X_k) = exp(-tau), with a_k the distance to the factor's pole
 (alpha_0 = 1 + a_0 for a call coordinate, -a_0 for a put coordinate, -a_k / +a_k
 for max / min indicators). tau = ln(100 / tol) clamped to [18, 34.5]: a tighter target
 costs a larger shift, and the shift's damping e^{alpha.w} multiplies the absolute
-size of the summand (the cancellation factor) faster than it removes aliasing.
+size of the summand (the cancellation factor) faster than it removes aliasing. When the
+damping exponent Phi = alpha.m + alpha^T C_w alpha / 2 of that choice exceeds 12 (coarse
+grids), tau is lowered by bisection on [2, tau] (60 halvings) until Phi <= 12.
 
 Parity: pinned in tests/test_oracle_fourier.py against Black-Scholes (d=1), the
 two-asset closed forms (d=2), the one-factor quadrature (d=3, 5), put-call parity,
@@ -140,11 +142,10 @@ def terms(opt):
     return out
 
 
-def grid_rule(term, N, tol=DEFAULT_TOL):
-    """Automatic (L_k, alpha_k) for one term (see module docstring)."""
-    tau = grid_tau(tol)
-    Cw = term["C"]
-    prec = np.diag(np.linalg.inv(Cw))
+PHI_MAX = 12.0
+
+
+def _rule_at(term, N, tau, prec):
     L = np.sqrt(2.0 * tau * prec)
     eta = 2.0 * L / N
     a = tau * eta / (2.0 * math.pi)
@@ -154,6 +155,24 @@ def grid_rule(term, N, tol=DEFAULT_TOL):
             alpha[k] = 1.0 + a[k]
         else:
             alpha[k] = term["sign"][k] * a[k]
+    phi = float(alpha @ term["m"] + 0.5 * alpha @ term["C"] @ alpha)
+    return L, alpha, phi
+
+
+def grid_rule(term, N, tol=DEFAULT_TOL):
+    """Automatic (L_k, alpha_k) for one term (see module docstring)."""
+    tau = grid_tau(tol)
+    prec = np.diag(np.linalg.inv(term["C"]))
+    L, alpha, phi = _rule_at(term, N, tau, prec)
+    if phi > PHI_MAX:
+        lo, hi = 2.0, tau
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            if _rule_at(term, N, mid, prec)[2] <= PHI_MAX:
+                lo = mid
+            else:
+                hi = mid
+        L, alpha, phi = _rule_at(term, N, lo, prec)
     return L, alpha
 
 

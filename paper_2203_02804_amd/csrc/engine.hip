@@ -78,7 +78,7 @@ struct Launch {
 void tsqr_geometry(int nc, int &BR, int &G)
 {
     const int cap = LDS_BYTES / (int)sizeof(cplx);
-    G = std::max(2, cap / (nc * nc));
+    G = std::max(2, std::min(cap / (nc * nc), 512 / nc));
     BR = G * nc;
 }
 int tsqr_levels(int rows, int BR, int G)
@@ -211,7 +211,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             it.opt = (int)o;
             it.term = (int)t;
             it.rank_eps = g->rank_tol > 0 ? g->rank_tol : 0.1 * g->tol / std::sqrt((double)std::max(P.d - 1, 1));
-            it.delta = 1e-2;
+            it.delta = 5e-2;
             it.seed = g->seed * 0x100000001B3ull + (uint64_t)t * 0x9E3779B97F4A7C15ull + 1;
             it.m = (const double *)(dev + s.off_m);
             it.C = (const double *)(dev + s.off_C);
@@ -370,7 +370,8 @@ int launch_edge(ttfp_ctx *ctx, const Launch &g, int n_items, int dir, int sweep)
 struct OptResult {
     double price = 0, imag = 0, change = INFINITY, kappa = 0;
     int sweeps = 0, capped = 0, converged = 0;
-    long long evals = 0;
+    long long evals = 0, swaps = 0;
+    double hist[64] = {0};                 // relative change after each half sweep
     int code = TTFP_OK;
 };
 
@@ -403,13 +404,14 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
             HIPCHK(hipStreamSynchronize(ctx->stream));
             if (ctx->prof) prof_collect(ctx);
             std::vector<double> pr(n_opts, 0.0), pi(n_opts, 0.0);
-            std::vector<long long> ev(n_opts, 0);
+            std::vector<long long> ev(n_opts, 0), sw(n_opts, 0);
             std::vector<int> cap(n_opts, 0);
             for (int i = 0; i < n_items; ++i) {
                 const int o = b.item_opt[i];
                 pr[o] += b.item_scale[i] * host_items[i].P.x;
                 pi[o] += b.item_scale[i] * host_items[i].P.y;
                 ev[o] += host_items[i].n_evals;
+                sw[o] += host_items[i].mv_iters;
                 cap[o] |= host_items[i].capped;
             }
             bool any = false;
@@ -419,15 +421,19 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
                 r.price = pr[o];
                 r.imag = pi[o];
                 r.evals = ev[o];
+                r.swaps = sw[o];
                 r.capped = cap[o];
                 r.sweeps = half + 1;
                 if (!std::isnan(prev[o])) r.change = std::fabs(pr[o] - prev[o]) / std::max(std::fabs(pr[o]), 1e-300);
                 prev[o] = pr[o];
+                if (half < 64) r.hist[half] = r.change;
                 const bool last = (sweep == grids[o]->max_sweeps - 1 && dir == 1);
+                // a rank-capped cross whose change no longer halves over a full sweep has stagnated
+                const bool stalled = r.capped && half >= 3 && half < 64 && r.change > 0.5 * r.hist[half - 2];
                 if (half >= 1 && r.change <= grids[o]->tol) {
                     r.converged = 1;
                     opt_active[o] = 0;
-                } else if (last) {
+                } else if (last || stalled) {
                     opt_active[o] = 0;
                 } else {
                     any = true;
@@ -719,6 +725,7 @@ int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, dou
             diag->kappa = r.kappa;
             diag->last_change = r.change;
             diag->n_evals = r.evals;
+            diag->maxvol_swaps = r.swaps;
             diag->sweeps = r.sweeps;
             diag->rank_capped = r.capped;
             diag->converged = r.converged;

@@ -52,6 +52,7 @@ struct Item {
     int rsel;                         // rank selected in the current step
     int capped;
     long long n_evals;
+    long long mv_iters;               // maxvol swaps performed (diagnostic)
     cplx P;                           // latest contraction of the tensor train
 };
 

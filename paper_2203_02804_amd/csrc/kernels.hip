@@ -142,6 +142,7 @@ __global__ void k_init(Item *items, int n_items)
     it.nI[0] = 1;
     it.nJ[d] = 1;
     it.n_evals = 0;
+    it.mv_iters = 0;
     it.capped = 0;
     long long cnt = 1;
     for (int k = d - 1; k >= 1; --k) {
@@ -215,19 +216,23 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 }
 
 // ------------------------------------------------------------------ Householder R in LDS
-// Triangularises A (nr x nc, row-major, ld nc, in LDS) by Householder reflections
-// H = I - beta v v^H; on exit row j of R is (alph[j], A[j][j+1..nc-1]).
+// Triangularises A (nr x nc, column-major in LDS with leading dimension nr, nr <= 512) by
+// Householder reflections H = I - beta v v^H. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
+// Column-major storage makes the lanes of a wave read consecutive 16-byte elements.
+constexpr int TSQR_MAX_ROWS = 512;
+
 __device__ void householder_lds(cplx *A, int nr, int nc, cplx *alph, double *sh)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int jmax = nr < nc ? nr : nc;
     for (int j = 0; j < jmax; ++j) {
+        cplx *vj = A + (size_t)j * nr;
         if (wave == 0) {
             double s = 0.0;
-            for (int i = j + 1 + lane; i < nr; i += 64) s += cabs2(A[i * nc + j]);
+            for (int i = j + 1 + lane; i < nr; i += 64) s += cabs2(vj[i]);
             s = wave_sum(s);
             if (lane == 0) {
-                cplx x0 = A[j * nc + j];
+                cplx x0 = vj[j];
                 double a0 = sqrt(cabs2(x0));
                 double nrm = sqrt(s + a0 * a0);
                 double beta = 0.0;
@@ -236,7 +241,7 @@ __device__ void householder_lds(cplx *A, int nr, int nc, cplx *alph, double *sh)
                     cplx ph = a0 > 0.0 ? cplx{x0.x / a0, x0.y / a0} : cplx{1.0, 0.0};
                     al = {-ph.x * nrm, -ph.y * nrm};
                     cplx v0 = csub(x0, al);
-                    A[j * nc + j] = v0;
+                    vj[j] = v0;
                     beta = 2.0 / (s + cabs2(v0));
                 }
                 alph[j] = al;
@@ -246,17 +251,33 @@ __device__ void householder_lds(cplx *A, int nr, int nc, cplx *alph, double *sh)
         __syncthreads();
         const double beta = sh[0];
         if (beta != 0.0) {
+            // this lane's part of v stays in registers for every trailing column
+            cplx v[TSQR_MAX_ROWS / 64];
+#pragma unroll
+            for (int q = 0; q < TSQR_MAX_ROWS / 64; ++q) {
+                const int i = j + lane + 64 * q;
+                v[q] = i < nr ? vj[i] : cplx{0.0, 0.0};
+            }
             for (int c = j + 1 + wave; c < nc; c += nw) {
+                cplx *ac = A + (size_t)c * nr;
                 double dr = 0.0, di = 0.0;
-                for (int i = j + lane; i < nr; i += 64) {
-                    cplx p = cmulc(A[i * nc + j], A[i * nc + c]);
-                    dr += p.x;
-                    di += p.y;
+#pragma unroll
+                for (int q = 0; q < TSQR_MAX_ROWS / 64; ++q) {
+                    const int i = j + lane + 64 * q;
+                    if (i < nr) {
+                        cplx p = cmulc(v[q], ac[i]);
+                        dr += p.x;
+                        di += p.y;
+                    }
                 }
                 dr = wave_sum(dr);
                 di = wave_sum(di);
-                cplx f = {beta * dr, beta * di};
-                for (int i = j + lane; i < nr; i += 64) A[i * nc + c] = csub(A[i * nc + c], cmul(f, A[i * nc + j]));
+                const cplx f = {beta * dr, beta * di};
+#pragma unroll
+                for (int q = 0; q < TSQR_MAX_ROWS / 64; ++q) {
+                    const int i = j + lane + 64 * q;
+                    if (i < nr) ac[i] = csub(ac[i], cmul(f, v[q]));
+                }
             }
         }
         __syncthreads();
@@ -297,17 +318,21 @@ __global__ __launch_bounds__(256) void k_tsqr(Item *items, const int *active, in
     const size_t rsz = (size_t)nc * nc;
     cplx *A = lds;
     int nr;
+    const cplx *src;
     if (level == 0) {
         const int r0 = blk * BR;
         nr = min(BR, s.rows - r0);
-        const cplx *src = it.F + (size_t)r0 * nc;
-        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) A[e] = src[e];
+        src = it.F + (size_t)r0 * nc;
     } else {
         const int nprev = tsqr_count(s.rows, BR, G, level - 1);
         const int g0 = blk * G, g1 = min(nprev, g0 + G);
         nr = (g1 - g0) * nc;
-        const cplx *src = it.Rlev + (size_t)((level - 1) & 1) * it.nblk_max * rsz + (size_t)g0 * rsz;
-        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) A[e] = src[e];
+        src = it.Rlev + (size_t)((level - 1) & 1) * it.nblk_max * rsz + (size_t)g0 * rsz;
+    }
+    // coalesced read of nr row-major rows, transposed into column-major LDS
+    for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
+        const int i = e / nc, c = e % nc;
+        A[(size_t)c * nr + i] = src[e];
     }
     __syncthreads();
     householder_lds(A, nr, nc, alph, sh);
@@ -316,7 +341,7 @@ __global__ __launch_bounds__(256) void k_tsqr(Item *items, const int *active, in
     for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) {
         int j = e / nc, c = e % nc;
         cplx v = {0.0, 0.0};
-        if (j < jmax && c >= j) v = (c == j) ? alph[j] : A[j * nc + c];
+        if (j < jmax && c >= j) v = (c == j) ? alph[j] : A[(size_t)c * nr + j];
         dst[e] = v;
     }
 }
@@ -490,18 +515,29 @@ __device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
     return scratch[nw];
 }
 
-// Dominant r x r submatrix of Y (rows x r): Gaussian elimination with partial pivoting for
-// the start, then swaps of the largest |B_ij| > 1 + delta with B = Y Y[piv]^{-1}.
+// Dominant r x r submatrix of Y (rows x r).
+//  1. start: the K rows of largest norm (Y has orthonormal columns, so these are the rows
+//     of largest leverage) are selected by bisection on the norm; Gaussian elimination with
+//     partial pivoting on that K x r block (in LDS) picks r starting rows.
+//  2. B = Y Y[piv]^{-1} (Gauss-Jordan inverse in LDS, one pass over Y).
+//  3. maxvol swaps: while max |B_ij| > 1 + delta, row i replaces pivot j and B takes the
+//     rank-one update B -= B[:,j] (B[i,:] - e_j) / B[i,j]; the next argmax is found in the
+//     same pass. Termination: every swap multiplies |det Y[piv]| by more than 1 + delta, and
+//     the loop is also bounded by 4 r + 16 swaps.
+constexpr int MV_KEYS = (2 * TTFP_MAX_RANK * TTFP_MAX_RANK * (int)sizeof(cplx)) / (int)sizeof(float);
+
 __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir)
 {
-    __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
-    __shared__ cplx Ag[TTFP_MAX_RANK * TTFP_MAX_RANK];
-    __shared__ unsigned int chosen[(TTFP_MAX_RANK * MAXN) / 32];
+    __shared__ cplx Abuf[2 * TTFP_MAX_RANK * TTFP_MAX_RANK];
+    cplx *Ag = Abuf, *Ai = Abuf + TTFP_MAX_RANK * TTFP_MAX_RANK;
     __shared__ cplx prow[TTFP_MAX_RANK];
     __shared__ cplx fcol[TTFP_MAX_RANK];
     __shared__ int piv[TTFP_MAX_RANK];
+    __shared__ int cand[256];
+    __shared__ int chosen[256];
     __shared__ ArgMax red[17];
-    __shared__ int shi[2];
+    __shared__ int shi[4];
+    __shared__ float shf[2];
     const int item = blockIdx.x;
     if (!active[item]) return;
     Item &it = items[item];
@@ -511,39 +547,116 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     const cplx *Y = it.Y;
     cplx *W = it.W;
     cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
-    const int nthr = blockDim.x;
-    for (int w = threadIdx.x; w < (m + 31) / 32; w += nthr) chosen[w] = 0u;
-    __syncthreads();
-    // ---- start: partial pivoting on column j of the eliminated matrix
-    ArgMax am = {-1.0, 0x7fffffff};
-    for (int i = threadIdx.x; i < m; i += nthr) am = better(am, ArgMax{cabs2(Y[(size_t)i * r]), i});
-    am = block_argmax(am, red);
-    for (int j = 0; j < r; ++j) {
-        const int p = am.i;
-        const cplx *src = (j == 0) ? Y : W;
-        if (threadIdx.x == 0) {
-            piv[j] = p;
-            chosen[p >> 5] |= 1u << (p & 31);
+    const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // ---- 1a. row norms (one key per group of gsz consecutive rows: its largest norm)
+    int K = (2 * TTFP_MAX_RANK * TTFP_MAX_RANK) / r;     // K x r block fits in Abuf
+    if (K > 256) K = 256;
+    if (K > m) K = m;
+    const int gsz = (m + MV_KEYS - 1) / MV_KEYS;        // 1 unless m exceeds the key buffer
+    const int nk = (m + gsz - 1) / gsz;
+    float *key = (float *)Abuf;
+    float kmax = 0.0f;
+    for (int g = threadIdx.x; g < nk; g += nthr) {
+        float best = -1.0f;
+        for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
+            const cplx *y = Y + (size_t)i * r;
+            double q = 0.0;
+            for (int c = 0; c < r; ++c) q += cabs2(y[c]);
+            best = fmaxf(best, (float)q);
         }
-        for (int c = j + threadIdx.x; c < r; c += nthr) prow[c] = src[(size_t)p * r + c];
+        key[g] = best;
+        kmax = fmaxf(kmax, best);
+    }
+    {
+        ArgMax a = {(double)kmax, 0};
+        a = block_argmax(a, red);
+        kmax = (float)a.v;
+    }
+    // ---- 1b. bisection for a threshold with at least K keys above it
+    if (threadIdx.x == 0) { shf[0] = 0.0f; shf[1] = kmax; }
+    __syncthreads();
+    for (int it2 = 0; it2 < 40; ++it2) {
+        const float lo = shf[0], hi = shf[1], mid = 0.5f * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        int cnt = 0;
+        for (int g = threadIdx.x; g < nk; g += nthr) cnt += key[g] >= mid;
+        ArgMax a = {(double)cnt, 0};
+        // block sum through the argmax scratch: reduce counts by waves
+        for (int o = 32; o > 0; o >>= 1) a.v += __shfl_xor(a.v, o, 64);
         __syncthreads();
-        const int w = r - j - 1;
-        am = {-1.0, 0x7fffffff};
-        if (w > 0) {
-            const cplx pj = prow[j];
-            const long long tot = (long long)m * w;
-            for (long long e = threadIdx.x; e < tot; e += nthr) {
-                const int i = (int)(e / w), c = j + 1 + (int)(e % w);
-                if (chosen[i >> 5] & (1u << (i & 31))) continue;
-                const cplx f = cdiv(src[(size_t)i * r + j], pj);
-                const cplx v = csub(src[(size_t)i * r + c], cmul(f, prow[c]));
-                W[(size_t)i * r + c] = v;
-                if (c == j + 1) am = better(am, ArgMax{cabs2(v), i});
+        if (lane == 0) red[wave] = a;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < (nthr >> 6); ++w) tot += red[w].v;
+            if (tot >= K) shf[0] = mid; else shf[1] = mid;
+        }
+        __syncthreads();
+    }
+    const float thr = shf[0];
+    if (threadIdx.x == 0) shi[2] = 0;
+    __syncthreads();
+    for (int g = threadIdx.x; g < nk; g += nthr)
+        if (key[g] >= thr) {
+            const int slot = atomicAdd(&shi[2], 1);
+            if (slot < K) cand[slot] = g;      // group index; resolved to a row below
+        }
+    __syncthreads();
+    const int Kc = min(K, shi[2]);
+    // resolve groups to their largest-norm row
+    for (int q = threadIdx.x; q < Kc; q += nthr) {
+        const int g = cand[q];
+        int bi = g * gsz;
+        double best = -1.0;
+        for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
+            const cplx *y = Y + (size_t)i * r;
+            double v = 0.0;
+            for (int c = 0; c < r; ++c) v += cabs2(y[c]);
+            if (v > best) { best = v; bi = i; }
+        }
+        cand[q] = bi;
+    }
+    __syncthreads();
+    cplx *S = Abuf;                                // Kc x r candidate block
+    for (int e = threadIdx.x; e < Kc * r; e += nthr) {
+        const int g = e / r, c = e % r;
+        S[e] = Y[(size_t)cand[g] * r + c];
+    }
+    for (int g = threadIdx.x; g < Kc; g += nthr) chosen[g] = 0;
+    __syncthreads();
+    // ---- 1c. partial pivoting on the candidate block
+    for (int j = 0; j < r; ++j) {
+        if (wave == 0) {
+            ArgMax am = {-1.0, 0x7fffffff};
+            for (int g = lane; g < Kc; g += 64)
+                if (!chosen[g]) am = better(am, ArgMax{cabs2(S[g * r + j]), g});
+            for (int o = 32; o > 0; o >>= 1) {
+                ArgMax b2;
+                b2.v = __shfl_xor(am.v, o, 64);
+                b2.i = __shfl_xor(am.i, o, 64);
+                am = better(am, b2);
+            }
+            if (lane == 0) {
+                shi[0] = am.i;
+                chosen[am.i] = 1;
+                piv[j] = cand[am.i];
             }
         }
-        am = block_argmax(am, red);
+        __syncthreads();
+        const int p = shi[0];
+        const int w = r - j - 1;
+        if (w > 0) {
+            const cplx pj = S[p * r + j];
+            for (int e = threadIdx.x; e < Kc * w; e += nthr) {
+                const int g = e / w, c = j + 1 + e % w;
+                if (chosen[g]) continue;
+                const cplx f = cdiv(S[g * r + j], pj);
+                S[g * r + c] = csub(S[g * r + c], cmul(f, S[p * r + c]));
+            }
+        }
+        __syncthreads();
     }
-    // ---- inverse of Y[piv] by Gauss-Jordan with partial pivoting
+    // ---- 2. inverse of Y[piv] by Gauss-Jordan with partial pivoting
     for (int e = threadIdx.x; e < r * r; e += nthr) {
         const int a = e / r, c = e % r;
         Ag[e] = Y[(size_t)piv[a] * r + c];
@@ -586,7 +699,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         __syncthreads();
     }
     // ---- B = Y Ai and the first candidate
-    am = {-1.0, 0x7fffffff};
+    ArgMax am = {-1.0, 0x7fffffff};
     const long long tot = (long long)m * r;
     for (long long e = threadIdx.x; e < tot; e += nthr) {
         const int i = (int)(e / r), c = (int)(e % r);
@@ -597,10 +710,11 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         am = better(am, ArgMax{cabs2(acc), (int)e});
     }
     am = block_argmax(am, red);
-    // ---- swaps
+    // ---- 3. swaps
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     const int maxit = 4 * r + 16;
-    for (int iter = 0; iter < maxit && am.v > lim; ++iter) {
+    int iter = 0;
+    for (; iter < maxit && am.v > lim; ++iter) {
         const int is = am.i / r, cs = am.i % r;
         for (int c = threadIdx.x; c < r; c += nthr) prow[c] = B[(size_t)is * r + c];
         __syncthreads();
@@ -621,6 +735,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     }
     __syncthreads();
     for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
+    if (threadIdx.x == 0) it.mv_iters += iter;
 }
 
 // ------------------------------------------------------------------ index sets and core placement

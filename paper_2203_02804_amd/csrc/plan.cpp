@@ -18,7 +18,9 @@
 // variance (C_w^{-1})_kk -- and a contour distance a_k to the factor's pole with
 // exp(-a_k 2 pi / eta_k) = exp(-tau), eta_k = 2 L_k / N (the aliasing period in x is
 // 2 pi / eta_k). tau = ln(100 / tol) clamped to [18, 34.5]: the damping e^{alpha.w} of a
-// larger shift inflates the absolute size of the summand faster than it cuts aliasing.
+// larger shift inflates the absolute size of the summand faster than it cuts aliasing. When
+// the damping exponent Phi = alpha.m + alpha^T C_w alpha / 2 exceeds 12 (coarse grids), tau
+// is lowered by bisection on [2, tau] (60 halvings) until Phi <= 12.
 #include "plan.hpp"
 
 #include <algorithm>
@@ -32,6 +34,28 @@ static const double TWO_PI = 6.283185307179586476925286766559;
 static bool finite(double x) { return std::isfinite(x); }
 
 static double grid_tau(double tol) { return std::min(34.5, std::max(18.0, std::log(100.0 / tol))); }
+
+static const double PHI_MAX = 12.0;
+
+// Automatic (L, alpha) of one term for exponent tau; returns the damping exponent Phi.
+static double rule_at(const TermPlan &tp, int N, double tau, const std::vector<double> &prec,
+                      std::vector<double> &L, std::vector<double> &alpha)
+{
+    const int d = tp.d;
+    L.assign(d, 0.0);
+    alpha.assign(d, 0.0);
+    for (int k = 0; k < d; ++k) {
+        L[k] = std::sqrt(2.0 * tau * prec[k]);
+        const double dist = tau * (2.0 * L[k] / N) / TWO_PI;
+        alpha[k] = (tp.kind[k] == KIND_CALL && tp.sign[k] > 0) ? 1.0 + dist : tp.sign[k] * dist;
+    }
+    double phi = 0.0;
+    for (int a = 0; a < d; ++a) {
+        phi += alpha[a] * tp.m[a];
+        for (int b = 0; b < d; ++b) phi += 0.5 * alpha[a] * tp.C[(size_t)a * d + b] * alpha[b];
+    }
+    return phi;
+}
 
 // Cholesky of a symmetric positive definite n x n matrix (row-major). False if not SPD.
 static bool cholesky(const std::vector<double> &A, int n, std::vector<double> &Lc)
@@ -181,11 +205,25 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
         if (!ok) { err = "term covariance is not positive definite"; return TTFP_EINVAL; }
         tp.L.assign(d, 0.0);
         tp.alpha.assign(d, 0.0);
+        std::vector<double> Lauto, Aauto;
+        if (!g->L_k && !(g->L > 0)) {
+            double tu = tau;
+            if (rule_at(tp, N, tu, prec, Lauto, Aauto) > PHI_MAX) {
+                double lo = 2.0, hi = tau;
+                for (int itb = 0; itb < 60; ++itb) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (rule_at(tp, N, mid, prec, Lauto, Aauto) <= PHI_MAX) lo = mid;
+                    else hi = mid;
+                }
+                tu = lo;
+                rule_at(tp, N, tu, prec, Lauto, Aauto);
+            }
+        }
         for (int k = 0; k < d; ++k) {
             double L;
             if (g->L_k) L = g->L_k[(size_t)t * d + k];
             else if (g->L > 0) L = g->L;
-            else L = std::sqrt(2.0 * tau * prec[k]);
+            else L = Lauto[k];
             if (!(L > 0) || !finite(L)) { err = "L must be positive"; return TTFP_EINVAL; }
             tp.L[k] = L;
             double a;
@@ -193,6 +231,8 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
                 a = g->alpha_k[(size_t)t * d + k];
             } else if (g->alpha > 0) {
                 a = tp.sign[k] * g->alpha;
+            } else if (!Aauto.empty()) {
+                a = Aauto[k];
             } else {
                 double eta = 2.0 * L / N;
                 double dist = tau * eta / TWO_PI;
