@@ -152,6 +152,33 @@ enum {
 int ttfp_profile_enable(ttfp_ctx *ctx, int enable);
 int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms);
 
+/* ---------------------------------------------------------------------------------------
+ * Price surrogate (an addition to the paper's method): an ensemble of n_models MLPs
+ * n_in -> width (x depth, SiLU) -> 1 with BF16 weights and activations, FP32 accumulation
+ * (MFMA), FP32 master weights and Adam, trained on prices produced by the TT path.
+ * Parameters of one model, as a flat FP32 vector: for each layer l (depth hidden layers then
+ * the head) W_l [out x in] row-major, then b_l [out].
+ * x_dev / t_dev / y_dev are device pointers (FP32): x [batch x n_in] row-major, t and y
+ * [batch]. The context owns its weights and activation buffers (sized for max_batch) and
+ * enqueues on `stream`; calls on one context must not overlap.
+ * ------------------------------------------------------------------------------------- */
+typedef struct ttfp_mlp ttfp_mlp;
+int ttfp_mlp_create(ttfp_mlp **out, int device, void *stream, int n_in, int width, int depth,
+                    int n_models, int max_batch, uint64_t seed);
+int ttfp_mlp_destroy(ttfp_mlp *m);
+int ttfp_mlp_n_params(const ttfp_mlp *m, int64_t *n);
+int ttfp_mlp_get_params(ttfp_mlp *m, int model, float *params);          /* host out */
+int ttfp_mlp_set_params(ttfp_mlp *m, int model, const float *params);    /* host in; resets Adam */
+/* y_dev[batch] = network(x_dev) for one model */
+int ttfp_mlp_forward(ttfp_mlp *m, int model, int batch, const float *x_dev, float *y_dev);
+/* gradient (host, n_params, nullable) and loss (host, nullable) of the mean squared error */
+int ttfp_mlp_grad(ttfp_mlp *m, int model, int batch, const float *x_dev, const float *t_dev,
+                  float *grad, float *loss);
+/* one Adam step (beta 0.9 / 0.999) on the mean squared error; loss (host, nullable) before the step */
+int ttfp_mlp_train_step(ttfp_mlp *m, int model, int batch, const float *x_dev, const float *t_dev,
+                        float lr, float *loss);
+const char *ttfp_mlp_last_error(const ttfp_mlp *m);
+
 const char *ttfp_strerror(int code);
 const char *ttfp_last_error(const ttfp_ctx *ctx);
 

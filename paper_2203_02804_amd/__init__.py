@@ -53,7 +53,9 @@ class _Diag(ctypes.Structure):
 
 EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_eval_integrand",
            "ttfp_tt_values", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
-           "ttfp_profile_enable", "ttfp_profile_read"]
+           "ttfp_profile_enable", "ttfp_profile_read", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
+           "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
+           "ttfp_mlp_last_error"]
 KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract"]
 
 _lib = None

@@ -603,6 +603,19 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         }
     __syncthreads();
     const int Kc = min(K, shi[2]);
+    // the slots above were taken in arrival order: sort them by group index so that the
+    // start, and with it the result, does not depend on the order of the atomics
+    {
+        int mine = 0, rank = 0;
+        const bool have = threadIdx.x < Kc;
+        if (have) {
+            mine = cand[threadIdx.x];
+            for (int q = 0; q < Kc; ++q) rank += cand[q] < mine;
+        }
+        __syncthreads();
+        if (have) cand[rank] = mine;
+        __syncthreads();
+    }
     // resolve groups to their largest-norm row
     for (int q = threadIdx.x; q < Kc; q += nthr) {
         const int g = cand[q];

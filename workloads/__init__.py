@@ -143,9 +143,10 @@ def config4(n=8192, seed=22030):
 
 # --- configuration 5: surrogate training/inference inputs -------------------------------------
 
-def config5_options(n, seed=5):
+def config5_options(n, seed=5, corr_kind="wishart"):
     """d=5 call-on-max options for the price surrogate: vols ~ U[0.1,0.4], S0 ~ U[80,120],
-    K = 100, T ~ U[0.25,2], r ~ U[0,0.06], Wishart correlation (10 dof)."""
+    K = 100, T ~ U[0.25,2], r ~ U[0,0.06], Wishart correlation (10 dof), or for
+    corr_kind='beta' the family Sigma(beta) with beta ~ U[0,1]."""
     rng = _rng(seed)
     out = []
     for _ in range(n):
@@ -153,7 +154,10 @@ def config5_options(n, seed=5):
         S0 = rng.uniform(80.0, 120.0, size=5)
         T = rng.uniform(0.25, 2.0)
         r = rng.uniform(0.0, 0.06)
-        corr = wishart_correlation(rng, 5, 10)
+        if corr_kind == "wishart":
+            corr = wishart_correlation(rng, 5, 10)
+        else:
+            corr = sigma_beta(5, rng.uniform(0.0, 1.0))
         out.append(option(5, S0, 100.0, T, r, sigma, corr, "call_max"))
     return out
 
