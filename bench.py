@@ -26,7 +26,8 @@ if ROOT not in sys.path:
 
 METRIC = "options priced/sec at ≤1e-6 rel. err (TT plain vs batched vs surrogate), 1 GPU"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6          # FP64 vector (and matrix) peak of MI355X
+BF16_PEAK_TFLOPS = 2500.0        # dense BF16 MFMA peak of MI355X
 
 
 def log(*a):
@@ -60,6 +61,53 @@ def cpu_baseline(opt, grid, budget_s=12.0):
                       f"{N}^{d} points"}
 
 
+def surrogate_leg(pricer, grid, n_train, tt_rate):
+    """Trains the BF16 surrogate ensemble on TT prices (outside any timed region), then times
+    its inference on a batch of 65 536 options and reports its gate statistics."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2203_02804_amd.surrogate import Surrogate
+
+    t0 = time.perf_counter()
+    train = W.config5_options(n_train, seed=5)
+    labels, _ = pricer.price_batch(train, grid)
+    t_label = time.perf_counter() - t0
+    sur = Surrogate(d=5, n_models=4, max_batch=65536, seed=3)
+    t0 = time.perf_counter()
+    info = sur.fit(train, labels, steps=1500, batch=1024, lr=2e-3, holdout=0.1)
+    t_fit = time.perf_counter() - t0
+    log(f"bench: surrogate labels {t_label:.1f} s, training {t_fit:.1f} s, "
+        f"holdout median rel err {np.median(info['holdout_rel_err']):.2e}")
+    infer = W.config5_options(65536, seed=55)
+    X = sur._x(infer)
+    for m in range(sur.n_models):
+        sur.net.forward(m, X)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for m in range(sur.n_models):
+            sur.net.forward(m, X)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / reps
+    mean, spread = sur.predict(infer)
+    est = sur.factor * spread / np.abs(mean)
+    rate = len(infer) / t_inf
+    gates = {}
+    for g in (1e-2, 1e-4, 1e-6):
+        frac = float(np.mean(est <= g))
+        # rows failing the gate are re-priced by the batched TT path
+        eff = 1.0 / (1.0 / rate + (1.0 - frac) / tt_rate)
+        gates[str(g)] = {"served_fraction": frac, "options_per_s_with_fallback": eff}
+    flops = 2.0 * len(infer) * sur.net.n_params * sur.n_models
+    return {"inference_options_per_s": rate, "batch": len(infer), "models": sur.n_models,
+            "mfma_bf16_tflops": flops / t_inf / 1e12, "mfma_bf16_frac": flops / t_inf / 1e12 / BF16_PEAK_TFLOPS,
+            "train_options": n_train, "holdout_median_rel_err": float(np.median(info["holdout_rel_err"])),
+            "calibration_factor": sur.factor, "gates": gates}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +118,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-train", type=int, default=4096, help="TT-priced training options")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharding design is "
@@ -119,22 +169,30 @@ def main():
         conv += int(info["converged"])
     evals_per_option = sum(evals) / len(evals)
 
-    # the dominant kernel and its roofline
+    # every kernel family: launches, device time, algorithmic rate; the dominant one's roofline
+    def rate(name, ms, work):
+        if ms <= 0 or work <= 0:
+            return None
+        if name == "fiber":          # bytes written (16 per complex entry)
+            return {"bound": "hbm", "achieved": work / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        return {"bound": "alu", "achieved": work / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+
     roofline = None
-    breakdown = {k: {"launches": n, "ms": round(ms, 3)} for k, (n, ms) in prof.items()}
+    breakdown = {}
+    for k, (n, ms, work) in prof.items():
+        breakdown[k] = {"launches": n, "ms": round(ms, 3)}
+        rr = rate(k, ms, work)
+        if rr:
+            breakdown[k].update({"achieved": rr["achieved"], "unit": rr["unit"], "frac": rr["achieved"] / rr["peak"]})
     if prof:
         dom = max(prof, key=lambda k: prof[k][1])
-        n_l, ms = prof[dom]
-        # algorithmic bytes of the fiber evaluation: each complex FP64 entry written once (16 B)
-        if dom == "fiber":
-            units = evals_per_option * B * args.steps
-            achieved = 16.0 * units / (ms * 1e-3) / 1e9
-            roofline = {"kernel": "k_fiber", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                        "avg_launch_ms": ms / max(n_l, 1)}
-        else:
-            roofline = {"kernel": "k_" + dom, "bound": None, "achieved": None, "peak": None, "unit": None,
-                        "frac": None, "traffic": None, "avg_launch_ms": ms / max(n_l, 1)}
+        n_l, ms, work = prof[dom]
+        rr = rate(dom, ms, work)
+        roofline = {"kernel": "k_" + dom, "bound": rr["bound"] if rr else None,
+                    "achieved": rr["achieved"] if rr else None, "peak": rr["peak"] if rr else None,
+                    "unit": rr["unit"] if rr else None, "frac": rr["achieved"] / rr["peak"] if rr else None,
+                    "traffic": None, "avg_launch_ms": ms / max(n_l, 1), "launches": n_l,
+                    "work_per_launch": work / max(n_l, 1)}
 
     plain = None
     if not args.no_plain:
@@ -147,6 +205,10 @@ def main():
         torch.cuda.synchronize()
         plain = len(opts) / (time.perf_counter() - tp0)
         log(f"bench: plain single-option path {plain:.1f} options/s")
+
+    surrogate = None
+    if not args.no_surrogate:
+        surrogate = surrogate_leg(pricer, grid, args.surrogate_train, value)
 
     base = None
     if not args.no_cpu_baseline:
@@ -173,6 +235,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": base,
         "plain_options_per_s": plain,
+        "surrogate": surrogate,
         "kernel_ms": breakdown,
         "accuracy": {"sampled_options": len(diag_opts), "converged": conv, "rank_capped": capped,
                      "median_kappa": sorted(kappas)[len(kappas) // 2],

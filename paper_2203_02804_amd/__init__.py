@@ -84,7 +84,7 @@ def load():
     lib.ttfp_maxvol.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), ctypes.c_double,
                                 P(ctypes.c_int32), P(ctypes.c_double)]
     lib.ttfp_profile_enable.argtypes = [vp, ctypes.c_int]
-    lib.ttfp_profile_read.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_double)]
+    lib.ttfp_profile_read.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_double)]
     lib.ttfp_strerror.argtypes = [ctypes.c_int]
     lib.ttfp_strerror.restype = ctypes.c_char_p
     lib.ttfp_last_error.argtypes = [vp]
@@ -224,13 +224,15 @@ class Pricer:
         self._check(self.lib.ttfp_profile_enable(self.ctx, 1 if enable else 0))
 
     def profile_read(self):
-        """{kernel: (launches, total_ms)} since the last profile(True)."""
+        """{kernel: (launches, total_ms, work)} since the last profile(True); work is bytes
+        (fiber) or FP64 flops (tsqr, basis, maxvol)."""
         out = {}
         for k, name in enumerate(KERNELS):
             n = ctypes.c_int64(0)
             ms = ctypes.c_double(0.0)
-            self._check(self.lib.ttfp_profile_read(self.ctx, k, ctypes.byref(n), ctypes.byref(ms)))
-            out[name] = (n.value, ms.value)
+            w = ctypes.c_double(0.0)
+            self._check(self.lib.ttfp_profile_read(self.ctx, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)))
+            out[name] = (n.value, ms.value, w.value)
         return out
 
     def eval_integrand(self, opt, grid, term, idx):

@@ -53,6 +53,7 @@ struct ttfp_ctx {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
     long long prof_launches[TTFP_KERNEL_COUNT] = {0};
     double prof_ms[TTFP_KERNEL_COUNT] = {0};
+    double prof_work[TTFP_KERNEL_COUNT] = {0};
 };
 
 namespace {
@@ -480,6 +481,9 @@ done:
     }
     HIPCHK(hipMemcpyAsync(host_items.data(), ctx->d_items, n_items * sizeof(Item), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->prof)
+        for (const Item &it : host_items)
+            for (int q = 0; q < TTFP_KERNEL_COUNT; ++q) ctx->prof_work[q] += it.work[q];
     b.items = host_items;
     return TTFP_OK;
 }
@@ -564,11 +568,11 @@ int ttfp_profile_enable(ttfp_ctx *ctx, int enable)
         prof_collect(ctx);
     }
     ctx->prof = enable != 0;
-    for (int k = 0; k < TTFP_KERNEL_COUNT; ++k) { ctx->prof_launches[k] = 0; ctx->prof_ms[k] = 0.0; }
+    for (int k = 0; k < TTFP_KERNEL_COUNT; ++k) { ctx->prof_launches[k] = 0; ctx->prof_ms[k] = 0.0; ctx->prof_work[k] = 0.0; }
     return TTFP_OK;
 }
 
-int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms)
+int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms, double *work)
 {
     if (!ctx || kernel < 0 || kernel >= TTFP_KERNEL_COUNT) return TTFP_EINVAL;
     if (!ctx->ev_open.empty()) {
@@ -577,6 +581,7 @@ int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *tota
     }
     if (launches) *launches = ctx->prof_launches[kernel];
     if (total_ms) *total_ms = ctx->prof_ms[kernel];
+    if (work) *work = ctx->prof_work[kernel];
     return TTFP_OK;
 }
 

@@ -53,6 +53,7 @@ struct Item {
     int capped;
     long long n_evals;
     long long mv_iters;               // maxvol swaps performed (diagnostic)
+    double work[8];                   // algorithmic work per kernel family (bytes or flops)
     cplx P;                           // latest contraction of the tensor train
 };
 

@@ -143,6 +143,7 @@ __global__ void k_init(Item *items, int n_items)
     it.nJ[d] = 1;
     it.n_evals = 0;
     it.mv_iters = 0;
+    for (int q = 0; q < 8; ++q) it.work[q] = 0.0;
     it.capped = 0;
     long long cnt = 1;
     for (int k = d - 1; k >= 1; --k) {
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, i
         else { it.crow[k] = 1; it.ccol[k] = it.nJ[1]; }
         it.n_evals += total;
     }
+    if (e == 0) it.work[TTFP_KERNEL_FIBER] += 16.0 * (double)total;
     if (e >= total) return;
     const int row = (int)(e / s.nc), col = (int)(e % s.nc);
     int idx[MAXD];
@@ -315,6 +317,10 @@ __global__ __launch_bounds__(256) void k_tsqr(Item *items, const int *active, in
     const int ncur = tsqr_count(s.rows, BR, G, level);
     const int blk = blockIdx.x;
     if (blk >= ncur) return;
+    if (level == 0 && blk == 0 && threadIdx.x == 0) {
+        const double m = s.rows, n = nc;
+        it.work[TTFP_KERNEL_TSQR] += 8.0 * m * n * n - 8.0 / 3.0 * n * n * n;
+    }
     const size_t rsz = (size_t)nc * nc;
     cplx *A = lds;
     int nr;
@@ -476,6 +482,7 @@ __global__ __launch_bounds__(256) void k_basis(Item *items, const int *active, i
     if (!s.valid) return;
     const int r = it.rsel, nc = s.nc;
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) it.work[TTFP_KERNEL_BASIS] += 4.0 * (double)s.rows * r * r;
     if (e >= (long long)s.rows * r) return;
     const int row = (int)(e / r), c = (int)(e % r);
     const cplx *f = it.F + (size_t)row * nc;
@@ -748,7 +755,11 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     }
     __syncthreads();
     for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
-    if (threadIdx.x == 0) it.mv_iters += iter;
+    if (threadIdx.x == 0) {
+        it.mv_iters += iter;
+        // B = Y A^-1 (8 m r^2), one rank-one update per swap (8 m r)
+        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * (double)m * r * r + 8.0 * (double)m * r * iter;
+    }
 }
 
 // ------------------------------------------------------------------ index sets and core placement
