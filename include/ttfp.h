@@ -141,6 +141,18 @@ int ttfp_qr_r(ttfp_ctx *ctx, int32_t m, int32_t n, const double *A, double *R);
 int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double delta, int32_t *rows,
                 double *B);
 
+/* Launch tuning of a context (chosen per workload shape by the autotuner in
+ * paper_2203_02804_amd/tuning.py):
+ *  TTFP_TUNE_MAXVOL_THREADS  threads per maxvol workgroup: 256, 512 or 1024 (default 1024)
+ *  TTFP_TUNE_TSQR_LDS_KB     LDS budget of a TSQR workgroup in KiB, 16..152 (default 152):
+ *                            smaller budgets give shorter row blocks and more resident groups
+ *  TTFP_TUNE_GRAPH           1: capture each direction's half sweep in a hipGraph once per
+ *                            batch and replay it (needs a non-null stream); 0: launch eagerly
+ * Returns TTFP_EINVAL for an unknown parameter or value. */
+enum { TTFP_TUNE_MAXVOL_THREADS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2 };
+int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value);
+int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
+
 /* Kernel timing: when enabled, HIP events recorded on the context's stream bracket every
  * launch of each kernel family; ttfp_profile_read returns the number of launches, their
  * summed device time and the algorithmic work they did since the last enable (bytes written

@@ -53,10 +53,11 @@ class _Diag(ctypes.Structure):
 
 EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_eval_integrand",
            "ttfp_tt_values", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
-           "ttfp_profile_enable", "ttfp_profile_read", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
+           "ttfp_profile_enable", "ttfp_profile_read", "ttfp_set_tuning", "ttfp_get_tuning", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
            "ttfp_mlp_last_error"]
 KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract"]
+TUNING = {"maxvol_threads": 0, "tsqr_lds_kb": 1, "graph": 2}
 
 _lib = None
 
@@ -85,6 +86,8 @@ def load():
                                 P(ctypes.c_int32), P(ctypes.c_double)]
     lib.ttfp_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.ttfp_profile_read.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_double)]
+    lib.ttfp_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.ttfp_get_tuning.argtypes = [vp, ctypes.c_int, P(ctypes.c_int)]
     lib.ttfp_strerror.argtypes = [ctypes.c_int]
     lib.ttfp_strerror.restype = ctypes.c_char_p
     lib.ttfp_last_error.argtypes = [vp]
@@ -218,6 +221,19 @@ class Pricer:
             return prices, status
         split = np.cumsum([int(o["d"]) for o in opts])[:-1]
         return prices, np.split(delta, split), np.split(vega, split), status
+
+    def set_tuning(self, **kw):
+        """set_tuning(maxvol_threads=..., tsqr_lds_kb=..., graph=...)"""
+        for k, v in kw.items():
+            self._check(self.lib.ttfp_set_tuning(self.ctx, TUNING[k], int(v)))
+
+    def get_tuning(self):
+        out = {}
+        for k, code in TUNING.items():
+            v = ctypes.c_int(0)
+            self._check(self.lib.ttfp_get_tuning(self.ctx, code, ctypes.byref(v)))
+            out[k] = v.value
+        return out
 
     def profile(self, enable=True):
         """Starts (and resets) or stops per-kernel device timing with HIP events."""

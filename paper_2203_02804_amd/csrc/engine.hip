@@ -16,12 +16,12 @@
 
 namespace ttfp {
 __global__ void k_init(Item *items, int n_items);
-__global__ void k_fiber(Item *items, const int *active, int t, int dir, int mode, int sweep);
+__global__ void k_fiber(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_eval_points(const Item *items, long long npts, const int *idx, cplx *out);
 __global__ void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G);
 __global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G);
 __global__ void k_basis(Item *items, const int *active, int t, int dir);
-__global__ void k_maxvol(Item *items, const int *active, int t, int dir);
+__global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax);
 __global__ void k_finish(Item *items, const int *active, int t, int dir);
 __global__ void k_core_sum(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_contract(Item *items, const int *active);
@@ -47,6 +47,10 @@ struct ttfp_ctx {
     // last single-option call (for ttfp_tt_values)
     std::vector<Item> last_items;
     int last_n_items = 0;
+    // tuning (set by ttfp_set_tuning, chosen by the autotuner)
+    int tune_maxvol_threads = 1024;
+    int tune_tsqr_lds_kb = 152;
+    int tune_graph = 0;
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -76,9 +80,9 @@ struct Launch {
 
 // TSQR geometry: groups of G stacked nc x nc factors fit the LDS budget, and leaf blocks
 // have BR = G * nc rows.
-void tsqr_geometry(int nc, int &BR, int &G)
+void tsqr_geometry(int nc, int &BR, int &G, int lds_kb = LDS_BYTES / 1024)
 {
-    const int cap = LDS_BYTES / (int)sizeof(cplx);
+    const int cap = std::min(lds_kb * 1024, LDS_BYTES) / (int)sizeof(cplx);
     G = std::max(2, std::min(cap / (nc * nc), 512 / nc));
     BR = G * nc;
 }
@@ -92,7 +96,7 @@ int tsqr_levels(int rows, int BR, int G)
 struct ItemSizes {
     size_t bytes;
     size_t off_m, off_C, off_L, off_a, off_kind, off_I, off_J, off_F, off_Rl, off_Ri, off_perm, off_Y, off_W,
-        off_Bt, off_cores, off_M, off_M1, off_M2, off_piv;
+        off_Bt, off_cores, off_M, off_M1, off_M2, off_piv, off_keys;
     int rows_max, nblk_max;
 };
 
@@ -123,6 +127,7 @@ ItemSizes item_sizes(int d, int N, int R, int p, int BR)
     s.off_M1 = take(sizeof(cplx) * (size_t)d * R * R);
     s.off_M2 = take(sizeof(cplx) * (size_t)d * R * R);
     s.off_piv = take(sizeof(int) * R);
+    s.off_keys = take(sizeof(float) * (size_t)s.rows_max * 16);
     s.bytes = o;
     return s;
 }
@@ -176,7 +181,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
         maxN = std::max(maxN, g->N);
     }
     int BR, G;
-    tsqr_geometry(maxnc, BR, G);
+    tsqr_geometry(maxnc, BR, G, ctx->tune_tsqr_lds_kb);
     b.geo = {BR, G, tsqr_levels(maxrows, BR, G), maxd, maxrows, maxnc, maxR, maxN};
     // layout
     std::vector<ItemSizes> sz;
@@ -233,6 +238,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             it.M1 = (cplx *)(dev + s.off_M1);
             it.M2 = (cplx *)(dev + s.off_M2);
             it.piv = (int *)(dev + s.off_piv);
+            it.keys = (float *)(dev + s.off_keys);
             it.rows_max = s.rows_max;
             it.nblk_max = s.nblk_max;
             // static term data: one contiguous host staging block up to off_I
@@ -313,7 +319,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     const unsigned ny = (unsigned)n_items;
     {
         ProfScope ps(ctx, TTFP_KERNEL_FIBER);
-        hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.maxrows * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0, sweep);
+        hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.maxR * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_TSQR);
@@ -330,11 +336,12 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_BASIS);
-        hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir);
+        hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows * ((g.maxR + 3) / 4), 256), ny), dim3(256), 0, st, it, act, t, dir);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
-        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(1024), 0, st, it, act, t, dir);
+        const int rm = std::max(g.maxR, 2);
+        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(ctx->tune_maxvol_threads), (size_t)2 * rm * rm * sizeof(cplx), st, it, act, t, dir, rm);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_FINISH);
@@ -354,7 +361,7 @@ int launch_edge(ttfp_ctx *ctx, const Launch &g, int n_items, int dir, int sweep)
     const unsigned ny = (unsigned)n_items;
     {
         ProfScope ps(ctx, TTFP_KERNEL_FIBER);
-        hipLaunchKernelGGL(k_fiber, dim3(cdivu(g.maxrows, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1, sweep);
+        hipLaunchKernelGGL(k_fiber, dim3(cdivu(g.maxR, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_CORESUM);
@@ -392,15 +399,51 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
     std::vector<double> prev(n_opts, NAN);
     std::vector<int> opt_active(n_opts, 1);
     std::vector<Item> host_items(n_items);
+    // one half sweep: the steps of every core, then the edge core and the contraction
+    auto launch_half = [&](int dir, int sweep) -> int {
+        for (int t = 0; t + 1 < b.geo.maxd; ++t) {
+            int rc = launch_step(ctx, b.geo, n_items, t, dir, sweep);
+            if (rc) return rc;
+        }
+        return launch_edge(ctx, b.geo, n_items, dir, sweep);
+    };
+    // Graph mode: each direction's half sweep is captured once and replayed; the kernels read
+    // their shapes, ranks, activity and random-draw counter from device memory, so one graph
+    // serves every sweep. Capture needs a stream other than the null stream.
+    struct Graphs {
+        hipGraph_t g[2] = {nullptr, nullptr};
+        hipGraphExec_t x[2] = {nullptr, nullptr};
+        ~Graphs()
+        {
+            for (int q = 0; q < 2; ++q) {
+                if (x[q]) (void)hipGraphExecDestroy(x[q]);
+                if (g[q]) (void)hipGraphDestroy(g[q]);
+            }
+        }
+    } graphs;
+    const bool use_graph = ctx->tune_graph && ctx->stream != nullptr;
     int half = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int dir = 0; dir < 2; ++dir, ++half) {
-            for (int t = 0; t + 1 < b.geo.maxd; ++t) {
-                int rc = launch_step(ctx, b.geo, n_items, t, dir, sweep);
+            if (use_graph) {
+                if (!graphs.x[dir]) {
+                    const bool prof_saved = ctx->prof;
+                    ctx->prof = false;                   // no event records inside a capture
+                    HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+                    int rc = launch_half(dir, sweep);
+                    hipGraph_t gr = nullptr;
+                    hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
+                    ctx->prof = prof_saved;
+                    if (rc) return rc;
+                    HIPCHK(e);
+                    graphs.g[dir] = gr;
+                    HIPCHK(hipGraphInstantiate(&graphs.x[dir], gr, nullptr, nullptr, 0));
+                }
+                HIPCHK(hipGraphLaunch(graphs.x[dir], ctx->stream));
+            } else {
+                int rc = launch_half(dir, sweep);
                 if (rc) return rc;
             }
-            int rc = launch_edge(ctx, b.geo, n_items, dir, sweep);
-            if (rc) return rc;
             HIPCHK(hipMemcpyAsync(host_items.data(), ctx->d_items, n_items * sizeof(Item), hipMemcpyDeviceToHost, ctx->stream));
             HIPCHK(hipStreamSynchronize(ctx->stream));
             if (ctx->prof) prof_collect(ctx);
@@ -484,6 +527,16 @@ done:
     if (ctx->prof)
         for (const Item &it : host_items)
             for (int q = 0; q < TTFP_KERNEL_COUNT; ++q) ctx->prof_work[q] += it.work[q];
+#ifdef TTFP_PHASE_TIMING
+    {
+        double ph[12] = {0};
+        for (const Item &it : host_items)
+            for (int q = 0; q < 12; ++q) ph[q] += it.phase[q];
+        std::fprintf(stderr, "phases (us summed over %d items):", n_items);
+        for (int q = 0; q < 12; ++q) std::fprintf(stderr, " %d:%.0f", q, ph[q] * 0.01);
+        std::fprintf(stderr, "\n");
+    }
+#endif
     b.items = host_items;
     return TTFP_OK;
 }
@@ -558,6 +611,40 @@ int ttfp_create(ttfp_ctx **out, int device, void *hip_stream)
     c->stream = (hipStream_t)hip_stream;
     *out = c;
     return TTFP_OK;
+}
+
+int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
+{
+    if (!ctx) return TTFP_EINVAL;
+    switch (param) {
+    case TTFP_TUNE_MAXVOL_THREADS:
+        if (value != 256 && value != 512 && value != 1024) break;
+        ctx->tune_maxvol_threads = value;
+        return TTFP_OK;
+    case TTFP_TUNE_TSQR_LDS_KB:
+        if (value < 16 || value > LDS_BYTES / 1024) break;
+        ctx->tune_tsqr_lds_kb = value;
+        return TTFP_OK;
+    case TTFP_TUNE_GRAPH:
+        if (value != 0 && value != 1) break;
+        ctx->tune_graph = value;
+        return TTFP_OK;
+    default:
+        break;
+    }
+    ctx->last_error = "bad tuning parameter or value";
+    return TTFP_EINVAL;
+}
+
+int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value)
+{
+    if (!ctx || !value) return TTFP_EINVAL;
+    switch (param) {
+    case TTFP_TUNE_MAXVOL_THREADS: *value = ctx->tune_maxvol_threads; return TTFP_OK;
+    case TTFP_TUNE_TSQR_LDS_KB: *value = ctx->tune_tsqr_lds_kb; return TTFP_OK;
+    case TTFP_TUNE_GRAPH: *value = ctx->tune_graph; return TTFP_OK;
+    default: return TTFP_EINVAL;
+    }
 }
 
 int ttfp_profile_enable(ttfp_ctx *ctx, int enable)
@@ -913,7 +1000,8 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
     e = e ? e : hipMemcpy(dit, &it, sizeof(Item), hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(it.Y, A, 16 * (size_t)m * r, hipMemcpyHostToDevice);
     if (!e) {
-        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(1024), 0, ctx->stream, dit, act, 0, 2);
+        const int rm = std::max(r, 2);
+        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(ctx->tune_maxvol_threads), (size_t)2 * rm * rm * sizeof(cplx), ctx->stream, dit, act, 0, 2, rm);
         e = hipGetLastError();
     }
     e = e ? e : hipStreamSynchronize(ctx->stream);

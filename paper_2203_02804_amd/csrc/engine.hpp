@@ -45,15 +45,18 @@ struct Item {
     cplx *M;                   // d slots of R x R: core sums over the node index
     cplx *M1, *M2;             // d slots of R x R: first / second node moments (Greeks)
     int *piv;                  // R pivot rows
+    float *keys;               // rows_max x 16 partial squared row norms of Y (maxvol start)
     int rows_max, nblk_max;
     // ---- dynamic state
     int nI[MAXD + 1], nJ[MAXD + 1];   // sizes of the left / right index sets
     int crow[MAXD], ccol[MAXD];       // core shapes
     int rsel;                         // rank selected in the current step
+    int half;                         // half sweeps completed (counter of the random draws)
     int capped;
     long long n_evals;
     long long mv_iters;               // maxvol swaps performed (diagnostic)
     double work[8];                   // algorithmic work per kernel family (bytes or flops)
+    double phase[12];                 // per-phase device time (ticks), TTFP_PHASE_TIMING builds only
     cplx P;                           // latest contraction of the tensor train
 };
 

@@ -40,6 +40,22 @@ __device__ __forceinline__ cplx cexp_(cplx a)
     return {e * c, e * s};
 }
 
+#ifdef TTFP_PHASE_TIMING
+#define PHASE_MARK(slot)                                                     \
+    do {                                                                     \
+        __syncthreads();                                                     \
+        if (threadIdx.x == 0) {                                              \
+            const long long now_ = wall_clock64();                           \
+            it.phase[slot] += (double)(now_ - t_prev_);                      \
+            t_prev_ = now_;                                                  \
+        }                                                                    \
+    } while (0)
+#define PHASE_START long long t_prev_ = wall_clock64()
+#else
+#define PHASE_MARK(slot) do {} while (0)
+#define PHASE_START do {} while (0)
+#endif
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -142,8 +158,10 @@ __global__ void k_init(Item *items, int n_items)
     it.nI[0] = 1;
     it.nJ[d] = 1;
     it.n_evals = 0;
+    it.half = 0;
     it.mv_iters = 0;
     for (int q = 0; q < 8; ++q) it.work[q] = 0.0;
+    for (int q = 0; q < 12; ++q) it.phase[q] = 0.0;
     it.capped = 0;
     long long cnt = 1;
     for (int k = d - 1; k >= 1; --k) {
@@ -165,47 +183,92 @@ __global__ void k_init(Item *items, int n_items)
 }
 
 // ------------------------------------------------------------------ fiber evaluation
-__global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, int t, int dir, int mode, int sweep)
+// One thread per (row group g, column c) pair, looping over the node index i of core k.
+// Left-to-right: g = left index a, c = right index b, row = a N + i.
+// Right-to-left: g = right index b, c = left index a, row = i nb + b.
+// Everything that does not depend on i is formed once per pair:
+//   E_0 = sum_{l != k} z_l (-i m_l) - 1/2 sum_{l,l' != k} z_l C_ll' z_l',
+//   tau = -sum_{l != k} C_kl z_l,   H = prod_{l != k} h_l(z_l),
+// so that each entry costs one complex multiply-add, one exp and one sincos:
+//   F = exp(E_0 + z_k tau + c_k(i)) H h_k(z_k),  c_k(i) = z_k (-i m_k) - C_kk z_k^2 / 2,
+// with c_k and h_k tabulated per node in LDS.
+__global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, int t, int dir, int mode)
 {
+    __shared__ cplx ctab[MAXN];
+    __shared__ cplx htab[MAXN];
     const int item = blockIdx.y;
     if (!active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, mode);
     if (!s.valid) return;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long total = (long long)s.rows * s.nc;
     const int d = it.d, N = it.N, R = it.R, k = s.k;
-    if (mode == 1 && e == 0) {
-        if (dir == 0) { it.crow[k] = it.nI[k]; it.ccol[k] = 1; }
-        else { it.crow[k] = 1; it.ccol[k] = it.nJ[1]; }
-        it.n_evals += total;
+    const int ng = (dir == 0) ? s.rows / N : it.nJ[k + 1];     // row groups
+    const long long pairs = (long long)ng * s.nc;
+    if ((long long)blockIdx.x * blockDim.x >= pairs) return;
+    const long long total = (long long)s.rows * s.nc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (mode == 1) {
+            if (dir == 0) { it.crow[k] = it.nI[k]; it.ccol[k] = 1; }
+            else { it.crow[k] = 1; it.ccol[k] = it.nJ[1]; }
+            it.n_evals += total;
+        }
+        it.work[TTFP_KERNEL_FIBER] += 16.0 * (double)total;
     }
-    if (e == 0) it.work[TTFP_KERNEL_FIBER] += 16.0 * (double)total;
-    if (e >= total) return;
-    const int row = (int)(e / s.nc), col = (int)(e % s.nc);
-    int idx[MAXD];
-    int a, i, b;
-    if (dir == 0) { a = row / N; i = row % N; b = col; }
-    else { i = row / it.nJ[k + 1]; b = row % it.nJ[k + 1]; a = col; }
-    const uint64_t ctr = ((uint64_t)sweep << 40) ^ ((uint64_t)dir << 32) ^ ((uint64_t)t << 16);
-    // left coordinates 0..k-1
-    if (dir == 1 && a >= s.ncb) {
-        for (int c = 0; c < k; ++c) idx[c] = rand_index(it.seed, 3 + ctr, (uint64_t)(a - s.ncb), (uint64_t)c, N);
-    } else {
-        const int *Ia = it.Iset + ((size_t)k * R + a) * d;
-        for (int c = 0; c < k; ++c) idx[c] = Ia[c];
+    // node tables of coordinate k
+    const double Lk = it.L[k], etak = 2.0 * Lk / N, ak = it.alpha[k], mk = it.m[k], Ckk = it.C[k * d + k];
+    const int kindk = it.kind[k];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const cplx z = {-Lk + (i + 0.5) * etak, ak};
+        const cplx w = {-0.5 * Ckk * z.x, -mk - 0.5 * Ckk * z.y};     // -i m_k - C_kk z / 2
+        ctab[i] = cmul(z, w);
+        htab[i] = factor(kindk, z);
     }
-    idx[k] = i;
-    // right coordinates k+1..d-1
-    if (dir == 0 && b >= s.ncb) {
-        for (int c = k + 1; c < d; ++c) idx[c] = rand_index(it.seed, 4 + ctr, (uint64_t)(b - s.ncb), (uint64_t)c, N);
-    } else {
-        const int *Jb = it.Jset + ((size_t)(k + 1) * R + b) * d;
-        for (int c = k + 1; c < d; ++c) idx[c] = Jb[c];
+    __syncthreads();
+    const long long pidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pidx >= pairs) return;
+    const int g = (int)(pidx / s.nc), c = (int)(pidx % s.nc);
+    const int a = (dir == 0) ? g : c;          // left multi-index
+    const int b = (dir == 0) ? c : g;          // right multi-index
+    const uint64_t ctr = ((uint64_t)it.half << 40) ^ ((uint64_t)dir << 32) ^ ((uint64_t)t << 16);
+    // nodes of every coordinate but k
+    cplx z[MAXD];
+    const double invN = 1.0 / N;
+    for (int l = 0; l < d; ++l) {
+        if (l == k) { z[l] = {0.0, 0.0}; continue; }
+        int ix;
+        if (l < k) {
+            if (dir == 1 && a >= s.ncb) ix = rand_index(it.seed, 3 + ctr, (uint64_t)(a - s.ncb), (uint64_t)l, N);
+            else ix = it.Iset[((size_t)k * R + a) * d + l];
+        } else {
+            if (dir == 0 && b >= s.ncb) ix = rand_index(it.seed, 4 + ctr, (uint64_t)(b - s.ncb), (uint64_t)l, N);
+            else ix = it.Jset[((size_t)(k + 1) * R + b) * d + l];
+        }
+        const double L = it.L[l];
+        z[l] = {-L + (ix + 0.5) * 2.0 * L * invN, it.alpha[l]};
     }
-    cplx v = integrand(it, idx);
+    cplx e0 = {0.0, 0.0}, tau = {0.0, 0.0}, H = {1.0, 0.0};
+    for (int l = 0; l < d; ++l) {
+        if (l == k) continue;
+        const double *Cl = it.C + l * d;
+        cplx q = {0.0, 0.0};
+        for (int l2 = 0; l2 < d; ++l2) {
+            if (l2 == k) continue;
+            q = {q.x + Cl[l2] * z[l2].x, q.y + Cl[l2] * z[l2].y};
+        }
+        const cplx w = {-0.5 * q.x, -it.m[l] - 0.5 * q.y};
+        e0 = cadd(e0, cmul(z[l], w));
+        tau = {tau.x - it.C[k * d + l] * z[l].x, tau.y - it.C[k * d + l] * z[l].y};
+        H = cmul(H, factor(it.kind[l], z[l]));
+    }
     cplx *out = mode == 0 ? it.F : it.cores + (size_t)k * R * N * R;
-    out[(size_t)row * s.nc + col] = v;
+    const int nc = s.nc;
+    for (int i = 0; i < N; ++i) {
+        const cplx zk = {-Lk + (i + 0.5) * etak, ak};
+        const cplx ex = cadd(cadd(e0, cmul(zk, tau)), ctab[i]);
+        const cplx v = cmul(cexp_(ex), cmul(H, htab[i]));
+        const size_t row = (dir == 0) ? (size_t)g * N + i : (size_t)i * ng + g;
+        out[row * nc + c] = v;
+    }
 }
 
 // Integrand at explicit multi-indices (verification entry point).
@@ -222,6 +285,7 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 // Householder reflections H = I - beta v v^H. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
 // Column-major storage makes the lanes of a wave read consecutive 16-byte elements.
 constexpr int TSQR_MAX_ROWS = 512;
+constexpr int TSQR_THREADS = 256;
 
 __device__ void householder_lds(cplx *A, int nr, int nc, cplx *alph, double *sh)
 {
@@ -252,33 +316,42 @@ __device__ void householder_lds(cplx *A, int nr, int nc, cplx *alph, double *sh)
         }
         __syncthreads();
         const double beta = sh[0];
+        // this wave's trailing columns c = j + 1 + wave + u nw, four at a time: the partial dot
+        // products of a group are formed in one pass over the rows and reduced together
+        // (eight independent butterflies), then the group is updated in a second pass
         if (beta != 0.0) {
-            // this lane's part of v stays in registers for every trailing column
-            cplx v[TSQR_MAX_ROWS / 64];
+            const int ncw = (nc - (j + 1 + wave) + nw - 1) / nw;
+            for (int u0 = 0; u0 < ncw; u0 += 4) {
+                const int ng = min(4, ncw - u0);
+                cplx *ac[4];
 #pragma unroll
-            for (int q = 0; q < TSQR_MAX_ROWS / 64; ++q) {
-                const int i = j + lane + 64 * q;
-                v[q] = i < nr ? vj[i] : cplx{0.0, 0.0};
-            }
-            for (int c = j + 1 + wave; c < nc; c += nw) {
-                cplx *ac = A + (size_t)c * nr;
-                double dr = 0.0, di = 0.0;
+                for (int g = 0; g < 4; ++g) ac[g] = A + (size_t)(j + 1 + wave + (u0 + min(g, ng - 1)) * nw) * nr;
+                double dr[4] = {0.0, 0.0, 0.0, 0.0}, di[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int i = j + lane; i < nr; i += 64) {
+                    const cplx vi = vj[i];
 #pragma unroll
-                for (int q = 0; q < TSQR_MAX_ROWS / 64; ++q) {
-                    const int i = j + lane + 64 * q;
-                    if (i < nr) {
-                        cplx p = cmulc(v[q], ac[i]);
-                        dr += p.x;
-                        di += p.y;
+                    for (int g = 0; g < 4; ++g) {
+                        const cplx p = cmulc(vi, ac[g][i]);
+                        dr[g] += p.x;
+                        di[g] += p.y;
                     }
                 }
-                dr = wave_sum(dr);
-                di = wave_sum(di);
-                const cplx f = {beta * dr, beta * di};
 #pragma unroll
-                for (int q = 0; q < TSQR_MAX_ROWS / 64; ++q) {
-                    const int i = j + lane + 64 * q;
-                    if (i < nr) ac[i] = csub(ac[i], cmul(f, v[q]));
+                for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        dr[g] += __shfl_xor(dr[g], o, 64);
+                        di[g] += __shfl_xor(di[g], o, 64);
+                    }
+                }
+                cplx f[4];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) f[g] = {beta * dr[g], beta * di[g]};
+                for (int i = j + lane; i < nr; i += 64) {
+                    const cplx vi = vj[i];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        if (g < ng) ac[g][i] = csub(ac[g][i], cmul(f[g], vi));
                 }
             }
         }
@@ -302,7 +375,7 @@ __device__ __forceinline__ int tsqr_final_level(int rows, int BR, int G)
 
 // One TSQR level: level 0 reduces row blocks of the fiber, level L > 0 groups of G
 // triangular factors of level L-1. Writes nc x nc factors into buffer (level % 2).
-__global__ __launch_bounds__(256) void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G)
+__global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G)
 {
     extern __shared__ cplx lds[];
     __shared__ cplx alph[MAXNC];
@@ -335,13 +408,16 @@ __global__ __launch_bounds__(256) void k_tsqr(Item *items, const int *active, in
         nr = (g1 - g0) * nc;
         src = it.Rlev + (size_t)((level - 1) & 1) * it.nblk_max * rsz + (size_t)g0 * rsz;
     }
+    PHASE_START;
     // coalesced read of nr row-major rows, transposed into column-major LDS
     for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
         const int i = e / nc, c = e % nc;
         A[(size_t)c * nr + i] = src[e];
     }
     __syncthreads();
+    PHASE_MARK(8);
     householder_lds(A, nr, nc, alph, sh);
+    PHASE_MARK(9);
     cplx *dst = it.Rlev + (size_t)(level & 1) * it.nblk_max * rsz + (size_t)blk * rsz;
     const int jmax = nr < nc ? nr : nc;
     for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) {
@@ -473,22 +549,46 @@ __global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, in
 }
 
 // ------------------------------------------------------------------ basis of the kept columns
+// Y = F[:, perm[:r]] R2^{-1}: each thread forms one row times four columns of the triangular
+// inverse (held in LDS), reading each fiber entry once for four outputs.
 __global__ __launch_bounds__(256) void k_basis(Item *items, const int *active, int t, int dir)
 {
+    __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
+    __shared__ int pm[TTFP_MAX_RANK];
     const int item = blockIdx.y;
     if (!active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
     const int r = it.rsel, nc = s.nc;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0) it.work[TTFP_KERNEL_BASIS] += 4.0 * (double)s.rows * r * r;
-    if (e >= (long long)s.rows * r) return;
-    const int row = (int)(e / r), c = (int)(e % r);
+    const int ncg = (r + 3) / 4;
+    const long long tasks = (long long)s.rows * ncg;
+    if ((long long)blockIdx.x * blockDim.x >= tasks) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_BASIS] += 4.0 * (double)s.rows * r * r;
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ri[e] = it.Rinv[e];
+    for (int e = threadIdx.x; e < r; e += blockDim.x) pm[e] = it.perm[e];
+    __syncthreads();
+    const long long task = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (task >= tasks) return;
+    const int row = (int)(task / ncg), c0 = 4 * (int)(task % ncg);
     const cplx *f = it.F + (size_t)row * nc;
-    cplx acc = {0.0, 0.0};
-    for (int l = 0; l <= c; ++l) acc = cadd(acc, cmul(f[it.perm[l]], it.Rinv[l * r + c]));
-    it.Y[(size_t)row * r + c] = acc;
+    cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    const int lend = min(c0 + 3, r - 1);
+    for (int l = 0; l <= lend; ++l) {
+        const cplx fl = f[pm[l]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c0 + u < r && l <= c0 + u) acc[u] = cadd(acc[u], cmul(fl, Ri[l * r + c0 + u]));
+    }
+    cplx *y = it.Y + (size_t)row * r;
+    double nrm = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (c0 + u < r) {
+            y[c0 + u] = acc[u];
+            nrm += cabs2(acc[u]);
+        }
+    it.keys[(size_t)row * 16 + c0 / 4] = (float)nrm;   // partial squared norm of the row
 }
 
 // ------------------------------------------------------------------ maxvol
@@ -531,12 +631,14 @@ __device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
 //     rank-one update B -= B[:,j] (B[i,:] - e_j) / B[i,j]; the next argmax is found in the
 //     same pass. Termination: every swap multiplies |det Y[piv]| by more than 1 + delta, and
 //     the loop is also bounded by 4 r + 16 swaps.
-constexpr int MV_KEYS = (2 * TTFP_MAX_RANK * TTFP_MAX_RANK * (int)sizeof(cplx)) / (int)sizeof(float);
 
-__global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir)
+// Abuf is dynamic LDS of 2 rmax^2 complex entries (rmax: the largest rank of the launch), so
+// that small ranks leave room for several workgroups per CU.
+__global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax)
 {
-    __shared__ cplx Abuf[2 * TTFP_MAX_RANK * TTFP_MAX_RANK];
-    cplx *Ag = Abuf, *Ai = Abuf + TTFP_MAX_RANK * TTFP_MAX_RANK;
+    extern __shared__ cplx Abuf[];
+    const int cap = 2 * rmax * rmax;                 // entries of Abuf
+    cplx *Ag = Abuf, *Ai = Abuf + rmax * rmax;
     __shared__ cplx prow[TTFP_MAX_RANK];
     __shared__ cplx fcol[TTFP_MAX_RANK];
     __shared__ int piv[TTFP_MAX_RANK];
@@ -555,21 +657,31 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     cplx *W = it.W;
     cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
     const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    PHASE_START;
     // ---- 1a. row norms (one key per group of gsz consecutive rows: its largest norm)
-    int K = (2 * TTFP_MAX_RANK * TTFP_MAX_RANK) / r;     // K x r block fits in Abuf
+    int K = cap / r;                                     // K x r block fits in Abuf
     if (K > 256) K = 256;
     if (K > m) K = m;
-    const int gsz = (m + MV_KEYS - 1) / MV_KEYS;        // 1 unless m exceeds the key buffer
+    const int nkeys = cap * (int)(sizeof(cplx) / sizeof(float));
+    const int gsz = (m + nkeys - 1) / nkeys;            // 1 unless m exceeds the key buffer
     const int nk = (m + gsz - 1) / gsz;
     float *key = (float *)Abuf;
     float kmax = 0.0f;
     for (int g = threadIdx.x; g < nk; g += nthr) {
         float best = -1.0f;
         for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
-            const cplx *y = Y + (size_t)i * r;
-            double q = 0.0;
-            for (int c = 0; c < r; ++c) q += cabs2(y[c]);
-            best = fmaxf(best, (float)q);
+            float q;
+            if (dir != 2) {
+                const float *kp = it.keys + (size_t)i * 16;   // partials written by k_basis
+                q = 0.0f;
+                for (int u = 0; u < (r + 3) / 4; ++u) q += kp[u];
+            } else {
+                const cplx *y = Y + (size_t)i * r;
+                double qq = 0.0;
+                for (int c = 0; c < r; ++c) qq += cabs2(y[c]);
+                q = (float)qq;
+            }
+            best = fmaxf(best, q);
         }
         key[g] = best;
         kmax = fmaxf(kmax, best);
@@ -579,6 +691,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         a = block_argmax(a, red);
         kmax = (float)a.v;
     }
+    PHASE_MARK(0);
     // ---- 1b. bisection for a threshold with at least K keys above it
     if (threadIdx.x == 0) { shf[0] = 0.0f; shf[1] = kmax; }
     __syncthreads();
@@ -601,28 +714,36 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         __syncthreads();
     }
     const float thr = shf[0];
-    if (threadIdx.x == 0) shi[2] = 0;
-    __syncthreads();
-    for (int g = threadIdx.x; g < nk; g += nthr)
-        if (key[g] >= thr) {
-            const int slot = atomicAdd(&shi[2], 1);
-            if (slot < K) cand[slot] = g;      // group index; resolved to a row below
-        }
-    __syncthreads();
-    const int Kc = min(K, shi[2]);
-    // the slots above were taken in arrival order: sort them by group index so that the
-    // start, and with it the result, does not depend on the order of the atomics
+    // groups with key >= thr, the first K in increasing group order (a prefix sum over
+    // contiguous chunks, so that the selection does not depend on scheduling)
     {
-        int mine = 0, rank = 0;
-        const bool have = threadIdx.x < Kc;
-        if (have) {
-            mine = cand[threadIdx.x];
-            for (int q = 0; q < Kc; ++q) rank += cand[q] < mine;
+        const int chunk = (nk + nthr - 1) / nthr;
+        const int g0 = threadIdx.x * chunk, g1 = min(nk, g0 + chunk);
+        int cnt = 0;
+        for (int g = g0; g < g1; ++g) cnt += key[g] >= thr;
+        int incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
         }
         __syncthreads();
-        if (have) cand[rank] = mine;
+        if (lane == 63) red[wave].i = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int w = 0; w < (nthr >> 6); ++w) { const int t0 = red[w].i; red[w].i = acc; acc += t0; }
+            shi[2] = acc;
+        }
+        __syncthreads();
+        int pos = red[wave].i + incl - cnt;
+        for (int g = g0; g < g1; ++g)
+            if (key[g] >= thr) {
+                if (pos < K) cand[pos] = g;      // group index; resolved to a row below
+                ++pos;
+            }
         __syncthreads();
     }
+    const int Kc = min(K, shi[2]);
     // resolve groups to their largest-norm row
     for (int q = threadIdx.x; q < Kc; q += nthr) {
         const int g = cand[q];
@@ -637,6 +758,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         cand[q] = bi;
     }
     __syncthreads();
+    PHASE_MARK(1);
     cplx *S = Abuf;                                // Kc x r candidate block
     for (int e = threadIdx.x; e < Kc * r; e += nthr) {
         const int g = e / r, c = e % r;
@@ -676,6 +798,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         }
         __syncthreads();
     }
+    PHASE_MARK(2);
     // ---- 2. inverse of Y[piv] by Gauss-Jordan with partial pivoting
     for (int e = threadIdx.x; e < r * r; e += nthr) {
         const int a = e / r, c = e % r;
@@ -718,47 +841,168 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         }
         __syncthreads();
     }
-    // ---- B = Y Ai and the first candidate
+    PHASE_MARK(3);
+    // ---- B = Y Ai and the first candidate: one row times four columns per task
     ArgMax am = {-1.0, 0x7fffffff};
     const long long tot = (long long)m * r;
-    for (long long e = threadIdx.x; e < tot; e += nthr) {
-        const int i = (int)(e / r), c = (int)(e % r);
-        const cplx *y = Y + (size_t)i * r;
-        cplx acc = {0.0, 0.0};
-        for (int l = 0; l < r; ++l) acc = cadd(acc, cmul(y[l], Ai[l * r + c]));
-        B[e] = acc;
-        am = better(am, ArgMax{cabs2(acc), (int)e});
+    {
+        const int ncg = (r + 3) / 4;
+        const long long tasks = (long long)m * ncg;
+        for (long long q = threadIdx.x; q < tasks; q += nthr) {
+            const int i = (int)(q / ncg), c0 = 4 * (int)(q % ncg);
+            const cplx *y = Y + (size_t)i * r;
+            cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+            for (int l = 0; l < r; ++l) {
+                const cplx yl = y[l];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c0 + u < r) acc[u] = cadd(acc[u], cmul(yl, Ai[l * r + c0 + u]));
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c0 + u < r) {
+                    B[(size_t)i * r + c0 + u] = acc[u];
+                    am = better(am, ArgMax{cabs2(acc[u]), i * r + c0 + u});
+                }
+        }
     }
     am = block_argmax(am, red);
-    // ---- 3. swaps
+    // ---- 3. swaps. Rows whose largest |B_ij| exceeds 1 + delta (the candidates, at most
+    // Cmax, lowest row indices first) are kept in LDS; swaps are made among them and
+    // recorded (row i*, column j, w = B[i*,:] - e_j, b = B[i*,j]); one pass over all rows then
+    // applies the recorded rank-one updates B[i,:] -= B[i,j] / b * w in order, refreshes every
+    // row maximum and finds the next global candidate. A swap always involves the largest
+    // candidate entry, which exceeds 1 + delta, so each one grows |det Y[piv]|.
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     const int maxit = 4 * r + 16;
-    int iter = 0;
-    for (; iter < maxit && am.v > lim; ++iter) {
-        const int is = am.i / r, cs = am.i % r;
-        for (int c = threadIdx.x; c < r; c += nthr) prow[c] = B[(size_t)is * r + c];
-        __syncthreads();
-        const cplx bic = prow[cs];
-        for (int i = threadIdx.x; i < m; i += nthr) W[i] = cdiv(B[(size_t)i * r + cs], bic);
-        __syncthreads();
-        if (threadIdx.x == 0) piv[cs] = is;
-        am = {-1.0, 0x7fffffff};
-        for (long long e = threadIdx.x; e < tot; e += nthr) {
-            const int i = (int)(e / r), c = (int)(e % r);
-            cplx pr = prow[c];
-            if (c == cs) pr.x -= 1.0;
-            const cplx v = csub(B[e], cmul(W[i], pr));
-            B[e] = v;
-            am = better(am, ArgMax{cabs2(v), (int)e});
+    const int nw = nthr >> 6;
+    const int Cmax = min(256, (3 * cap / 4) / r);
+    const int recmax = min(64, (cap / 4) / r);
+    cplx *Cr = Abuf;                         // Cmax x r candidate rows
+    cplx *Rw = Abuf + 3 * cap / 4;           // recmax x r recorded update rows
+    int *cpos = reinterpret_cast<int *>(W);          // m: candidate position + 1, or 0
+    int *viol = cpos + m;                             // m: 1 if the row has |B_ij| > 1 + delta
+    __shared__ int cidx[256];
+    __shared__ int rec_j[64];
+    __shared__ cplx rec_b[64];
+    __shared__ int wsum[17];
+    __shared__ cplx snap[256];
+    __shared__ int nstate[2];                // number of candidates, number of records
+    if (threadIdx.x == 0) { nstate[0] = 0; nstate[1] = 0; }
+    for (int i = threadIdx.x; i < m; i += nthr) cpos[i] = 0;
+    __syncthreads();
+    // flush pass: a wave takes 64 / seg rows at a time (seg lanes per row, lane = column);
+    // candidate rows are written back from LDS, the others get the recorded updates; a
+    // ballot marks rows that still violate, each lane keeps its running argmax
+    const int seg = r <= 32 ? 32 : 64;
+    auto flush = [&](void) -> ArgMax {
+        const int nrec = nstate[1];
+        const int rpw = 64 / seg, c = lane % seg, sub = lane / seg;
+        ArgMax best = {-1.0, 0x7fffffff};
+        for (int i0 = wave * rpw; i0 < m; i0 += nw * rpw) {
+            const int i = i0 + sub;
+            const bool act = i < m && c < r;
+            cplx val = act ? B[(size_t)i * r + c] : cplx{0.0, 0.0};
+            const int cp = (i < m) ? cpos[i] : 0;
+            if (cp > 0 && act) val = Cr[(cp - 1) * r + c];
+            for (int q = 0; q < nrec; ++q) {
+                const int src = sub * seg + rec_j[q];
+                const cplx vj = {__shfl(val.x, src, 64), __shfl(val.y, src, 64)};
+                if (cp == 0 && act) val = csub(val, cmul(cdiv(vj, rec_b[q]), Rw[q * r + c]));
+            }
+            if (act && (cp > 0 || nrec > 0)) B[(size_t)i * r + c] = val;
+            const double a2 = act ? cabs2(val) : -1.0;
+            const unsigned long long mask = __ballot(a2 > lim);
+            const unsigned long long mine = (seg == 64) ? mask : ((mask >> (sub * 32)) & 0xffffffffull);
+            if (c == 0 && i < m) viol[i] = mine != 0ull;
+            if (act) best = better(best, ArgMax{a2, i * r + c});
         }
-        am = block_argmax(am, red);
+        return block_argmax(best, red);
+    };
+    PHASE_MARK(4);
+    am = flush();
+    PHASE_MARK(5);
+    int swaps = 0;
+    while (am.v > lim && swaps < maxit) {
+        // (a) candidates: rows with row maximum above the limit, by increasing index
+        {
+            const int chunk = (m + nthr - 1) / nthr;
+            const int i0 = threadIdx.x * chunk, i1 = min(m, i0 + chunk);
+            int cnt = 0;
+            for (int i = i0; i < i1; ++i) cnt += viol[i];
+            int incl = cnt;                            // inclusive scan within the wave
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            if (lane == 63) wsum[wave] = incl;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int acc = 0;
+                for (int w = 0; w < nw; ++w) { const int t0 = wsum[w]; wsum[w] = acc; acc += t0; }
+                wsum[nw] = acc;
+            }
+            __syncthreads();
+            int pos = wsum[wave] + incl - cnt;
+            for (int i = i0; i < i1; ++i)
+                if (viol[i]) {
+                    if (pos < Cmax) {
+                        cidx[pos] = i;
+                        cpos[i] = pos + 1;
+                    }
+                    ++pos;
+                }
+            if (threadIdx.x == 0) { nstate[0] = min(wsum[nw], Cmax); nstate[1] = 0; }
+            __syncthreads();
+        }
+        const int nC = nstate[0];
+        for (int e = threadIdx.x; e < nC * r; e += nthr) Cr[e] = B[(size_t)cidx[e / r] * r + e % r];
+        __syncthreads();
+        // (b) swaps among the candidates, in LDS
+        int nrec = 0;
+        while (nrec < recmax && swaps < maxit) {
+            ArgMax a = {-1.0, 0x7fffffff};
+            for (int e = threadIdx.x; e < nC * r; e += nthr) a = better(a, ArgMax{cabs2(Cr[e]), e});
+            a = block_argmax(a, red);
+            if (!(a.v > lim)) break;
+            const int ci = a.i / r, cs = a.i % r;
+            for (int c = threadIdx.x; c < r; c += nthr) {
+                cplx w = Cr[ci * r + c];
+                if (c == cs) w.x -= 1.0;
+                Rw[nrec * r + c] = w;
+            }
+            if (threadIdx.x == 0) {
+                rec_j[nrec] = cs;
+                rec_b[nrec] = Cr[ci * r + cs];
+                piv[cs] = cidx[ci];
+            }
+            __syncthreads();
+            // column snapshot of the candidates, then the rank-one update
+            const cplx bq = rec_b[nrec];
+            for (int q = threadIdx.x; q < nC; q += nthr) snap[q] = cdiv(Cr[q * r + cs], bq);
+            __syncthreads();
+            for (int e = threadIdx.x; e < nC * r; e += nthr) {
+                const int q = e / r, c = e % r;
+                Cr[e] = csub(Cr[e], cmul(snap[q], Rw[nrec * r + c]));
+            }
+            __syncthreads();
+            ++nrec;
+            ++swaps;
+        }
+        if (threadIdx.x == 0) nstate[1] = nrec;
+        __syncthreads();
+        // (c) apply the records to every other row and find the next candidate
+        am = flush();
+        for (int q = threadIdx.x; q < nC; q += nthr) cpos[cidx[q]] = 0;
+        __syncthreads();
     }
+    PHASE_MARK(6);
     __syncthreads();
     for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
     if (threadIdx.x == 0) {
-        it.mv_iters += iter;
+        it.mv_iters += swaps;
         // B = Y A^-1 (8 m r^2), one rank-one update per swap (8 m r)
-        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * (double)m * r * r + 8.0 * (double)m * r * iter;
+        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * (double)m * r * r + 8.0 * (double)m * r * swaps;
     }
 }
 
@@ -860,7 +1104,10 @@ __global__ __launch_bounds__(64) void k_contract(Item *items, const int *active)
         for (int b = threadIdx.x; b < b_n; b += blockDim.x) v[b] = w[b];
         __syncthreads();
     }
-    if (threadIdx.x == 0) it.P = v[0];
+    if (threadIdx.x == 0) {
+        it.P = v[0];
+        it.half += 1;
+    }
 }
 
 // ------------------------------------------------------------------ node moments for the Greeks
