@@ -41,7 +41,9 @@ enum {
     TTFP_ENOMEM = -2,     /* device allocation failed */
     TTFP_EDEVICE = -3,    /* HIP runtime error (text in ttfp_last_error) */
     TTFP_ENOTCONV = 1,    /* tolerance not met within max_sweeps or rank capped; price written */
-    TTFP_EPRECISION = 2   /* cancellation factor times machine epsilon exceeds tol; price written */
+    TTFP_EPRECISION = 2   /* cancellation factor times machine epsilon exceeds tol, or a
+                             numerical failure (exactly singular maxvol start, non-finite
+                             price); price written */
 };
 
 /* Payoffs (Sec. II.A uses the call on the minimum, Eq. minpayoff). */
@@ -93,6 +95,8 @@ typedef struct {
     int32_t rank_capped;   /* 1 if some bond hit max_rank (a capped cross also stops once its
                               change stops halving over a full sweep) */
     int32_t converged;     /* 1 if the tolerance was met */
+    int64_t maxvol_full_starts; /* maxvol starts taken by pivoting over all rows because the
+                              block of largest-norm rows was numerically rank deficient */
 } ttfp_diag;
 
 typedef struct ttfp_ctx ttfp_ctx;

@@ -48,7 +48,8 @@ class _Grid(ctypes.Structure):
 class _Diag(ctypes.Structure):
     _fields_ = [("imag_rel", ctypes.c_double), ("kappa", ctypes.c_double), ("last_change", ctypes.c_double),
                 ("n_evals", ctypes.c_int64), ("maxvol_swaps", ctypes.c_int64),
-                ("sweeps", ctypes.c_int32), ("rank_capped", ctypes.c_int32), ("converged", ctypes.c_int32)]
+                ("sweeps", ctypes.c_int32), ("rank_capped", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("maxvol_full_starts", ctypes.c_int64)]
 
 
 EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_eval_integrand",
@@ -195,7 +196,7 @@ class Pricer:
         rc = self._check(self.lib.ttfp_price(self.ctx, ctypes.byref(m.opt), ctypes.byref(m.grid), ctypes.byref(out),
                                              _ip(ranks), ctypes.byref(diag)))
         info = dict(imag_rel=diag.imag_rel, kappa=diag.kappa, last_change=diag.last_change, n_evals=diag.n_evals,
-                    maxvol_swaps=diag.maxvol_swaps,
+                    maxvol_swaps=diag.maxvol_swaps, maxvol_full_starts=diag.maxvol_full_starts,
                     sweeps=diag.sweeps, rank_capped=bool(diag.rank_capped), converged=bool(diag.converged))
         return out.value, ranks.reshape(d, d + 1), info, rc
 

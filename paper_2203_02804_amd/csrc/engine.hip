@@ -378,7 +378,8 @@ int launch_edge(ttfp_ctx *ctx, const Launch &g, int n_items, int dir, int sweep)
 struct OptResult {
     double price = 0, imag = 0, change = INFINITY, kappa = 0;
     int sweeps = 0, capped = 0, converged = 0;
-    long long evals = 0, swaps = 0;
+    long long evals = 0, swaps = 0, full_starts = 0;
+    int singular = 0;
     double hist[64] = {0};                 // relative change after each half sweep
     int code = TTFP_OK;
 };
@@ -448,14 +449,16 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
             HIPCHK(hipStreamSynchronize(ctx->stream));
             if (ctx->prof) prof_collect(ctx);
             std::vector<double> pr(n_opts, 0.0), pi(n_opts, 0.0);
-            std::vector<long long> ev(n_opts, 0), sw(n_opts, 0);
-            std::vector<int> cap(n_opts, 0);
+            std::vector<long long> ev(n_opts, 0), sw(n_opts, 0), fs(n_opts, 0);
+            std::vector<int> cap(n_opts, 0), sing(n_opts, 0);
             for (int i = 0; i < n_items; ++i) {
                 const int o = b.item_opt[i];
                 pr[o] += b.item_scale[i] * host_items[i].P.x;
                 pi[o] += b.item_scale[i] * host_items[i].P.y;
                 ev[o] += host_items[i].n_evals;
                 sw[o] += host_items[i].mv_iters;
+                fs[o] += host_items[i].mv_full;
+                sing[o] |= host_items[i].mv_singular;
                 cap[o] |= host_items[i].capped;
             }
             bool any = false;
@@ -466,6 +469,8 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
                 r.imag = pi[o];
                 r.evals = ev[o];
                 r.swaps = sw[o];
+                r.full_starts = fs[o];
+                r.singular = sing[o];
                 r.capped = cap[o];
                 r.sweeps = half + 1;
                 if (!std::isnan(prev[o])) r.change = std::fabs(pr[o] - prev[o]) / std::max(std::fabs(pr[o]), 1e-300);
@@ -502,6 +507,7 @@ done:
             r.kappa = mass[o] / std::max(std::fabs(r.price), 1e-300);
             r.code = (r.converged && !r.capped) ? TTFP_OK : TTFP_ENOTCONV;
             if (r.code == TTFP_OK && r.kappa * 2.220446049250313e-16 > grids[o]->tol) r.code = TTFP_EPRECISION;
+            if (r.singular || !std::isfinite(r.price)) r.code = TTFP_EPRECISION;
         }
     }
     if (greeks) {
@@ -818,6 +824,7 @@ int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, dou
             diag->last_change = r.change;
             diag->n_evals = r.evals;
             diag->maxvol_swaps = r.swaps;
+            diag->maxvol_full_starts = r.full_starts;
             diag->sweeps = r.sweeps;
             diag->rank_capped = r.capped;
             diag->converged = r.converged;

@@ -55,6 +55,8 @@ struct Item {
     int capped;
     long long n_evals;
     long long mv_iters;               // maxvol swaps performed (diagnostic)
+    long long mv_full;                // maxvol starts taken over all rows (degenerate candidate block)
+    int mv_singular;                  // a maxvol start matrix was exactly singular
     double work[8];                   // algorithmic work per kernel family (bytes or flops)
     double phase[12];                 // per-phase device time (ticks), TTFP_PHASE_TIMING builds only
     cplx P;                           // latest contraction of the tensor train

@@ -160,6 +160,8 @@ __global__ void k_init(Item *items, int n_items)
     it.n_evals = 0;
     it.half = 0;
     it.mv_iters = 0;
+    it.mv_full = 0;
+    it.mv_singular = 0;
     for (int q = 0; q < 8; ++q) it.work[q] = 0.0;
     for (int q = 0; q < 12; ++q) it.phase[q] = 0.0;
     it.capped = 0;
@@ -681,9 +683,10 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
                 for (int c = 0; c < r; ++c) qq += cabs2(y[c]);
                 q = (float)qq;
             }
+            if (!(q >= 0.0f && q <= 3.0e38f)) q = 0.0f;     // a non-finite row is never a pivot
             best = fmaxf(best, q);
         }
-        key[g] = best;
+        key[g] = fmaxf(best, 0.0f);
         kmax = fmaxf(kmax, best);
     }
     {
@@ -766,7 +769,11 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     }
     for (int g = threadIdx.x; g < Kc; g += nthr) chosen[g] = 0;
     __syncthreads();
-    // ---- 1c. partial pivoting on the candidate block
+    // ---- 1c. partial pivoting on the candidate block. A pivot below 1e-6 of the largest row
+    // norm means the block is numerically rank deficient (this happens when many integrand
+    // values underflow to zero and the largest rows share their support): the start is then
+    // taken by partial pivoting over all m rows instead (1d).
+    const double ptol2 = 1e-12 * (double)kmax;
     for (int j = 0; j < r; ++j) {
         if (wave == 0) {
             ArgMax am = {-1.0, 0x7fffffff};
@@ -779,13 +786,17 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
                 am = better(am, b2);
             }
             if (lane == 0) {
-                shi[0] = am.i;
-                chosen[am.i] = 1;
-                piv[j] = cand[am.i];
+                const bool ok = am.i >= 0 && am.i < Kc && am.v > ptol2 && am.v <= 1e300;
+                shi[0] = ok ? am.i : -1;
+                if (ok) {
+                    chosen[am.i] = 1;
+                    piv[j] = cand[am.i];
+                }
             }
         }
         __syncthreads();
         const int p = shi[0];
+        if (p < 0) break;                       // uniform: every thread read the same flag
         const int w = r - j - 1;
         if (w > 0) {
             const cplx pj = S[p * r + j];
@@ -797,6 +808,43 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
             }
         }
         __syncthreads();
+    }
+    // ---- 1d. fallback: partial pivoting over every row of Y, in place in a copy held in W
+    // (the output B, written only after the start, holds one flag per row meanwhile)
+    if (shi[0] < 0) {
+        cplx *Wl = W;
+        int *taken = reinterpret_cast<int *>(B);
+        for (long long e = threadIdx.x; e < (long long)m * r; e += nthr) Wl[e] = Y[e];
+        for (int i = threadIdx.x; i < m; i += nthr) taken[i] = 0;
+        __syncthreads();
+        for (int j = 0; j < r; ++j) {
+            ArgMax a = {-1.0, 0x7fffffff};
+            for (int i = threadIdx.x; i < m; i += nthr)
+                if (!taken[i]) {
+                    const double v = cabs2(Wl[(size_t)i * r + j]);
+                    a = better(a, ArgMax{v <= 1e300 ? v : -0.5, i});     // non-finite ranks last
+                }
+            a = block_argmax(a, red);
+            int p = a.i;
+            if (p < 0 || p >= m) p = 0;        // unreachable: j < r <= m rows remain untaken
+            if (threadIdx.x == 0) {
+                taken[p] = 1;
+                piv[j] = p;
+            }
+            __syncthreads();
+            const cplx pj = Wl[(size_t)p * r + j];
+            const double pa = cabs2(pj);
+            const int w = r - j - 1;
+            if (w > 0 && pa > 0.0 && pa <= 1e300)
+                for (long long e = threadIdx.x; e < (long long)m * w; e += nthr) {
+                    const int i = (int)(e / w), c = j + 1 + (int)(e % w);
+                    if (taken[i]) continue;
+                    const cplx f = cdiv(Wl[(size_t)i * r + j], pj);
+                    Wl[(size_t)i * r + c] = csub(Wl[(size_t)i * r + c], cmul(f, Wl[(size_t)p * r + c]));
+                }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) it.mv_full += 1;
     }
     PHASE_MARK(2);
     // ---- 2. inverse of Y[piv] by Gauss-Jordan with partial pivoting
@@ -824,7 +872,11 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
                 cplx t1 = Ai[j * r + c]; Ai[j * r + c] = Ai[p * r + c]; Ai[p * r + c] = t1;
             }
         __syncthreads();
-        const cplx inv = cdiv({1.0, 0.0}, Ag[j * r + j]);
+        const cplx gjj = Ag[j * r + j];
+        const double gabs = cabs2(gjj);
+        const bool sing = !(gabs > 0.0 && gabs <= 1e300);
+        const cplx inv = sing ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, gjj);
+        if (sing && threadIdx.x == 0) it.mv_singular = 1;   // reported as a numerical failure
         __syncthreads();
         for (int c = threadIdx.x; c < r; c += nthr) {
             Ag[j * r + c] = cmul(Ag[j * r + c], inv);
@@ -1031,7 +1083,7 @@ __global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, 
         const int *Ik = it.Iset + (size_t)k * R * d;
         int *In = it.Iset + (size_t)(k + 1) * R * d;
         for (int q = threadIdx.x; q < r; q += blockDim.x) {
-            const int row = it.piv[q], a = row / N, i = row % N;
+            const int row = min(max(it.piv[q], 0), s.rows - 1), a = row / N, i = row % N;
             for (int c = 0; c < k; ++c) In[q * d + c] = Ik[a * d + c];
             In[q * d + k] = i;
         }
@@ -1046,7 +1098,7 @@ __global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, 
         const int *J1 = it.Jset + (size_t)(k + 1) * R * d;
         int *Jn = it.Jset + (size_t)k * R * d;
         for (int q = threadIdx.x; q < r; q += blockDim.x) {
-            const int row = it.piv[q], i = row / nb, b = row % nb;
+            const int row = min(max(it.piv[q], 0), s.rows - 1), i = row / nb, b = row % nb;
             Jn[q * d + k] = i;
             for (int c = k + 1; c < d; ++c) Jn[q * d + c] = J1[b * d + c];
         }

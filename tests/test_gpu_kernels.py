@@ -87,6 +87,23 @@ def test_maxvol_tiny_against_exhaustive_search(pricer, seed):
     assert abs(np.linalg.det(A[rows])) >= vmax / ((1 + delta) ** r * r ** (r / 2)) - 1e-12
 
 
+def test_maxvol_start_when_largest_rows_are_rank_deficient(pricer):
+    # the 100 largest rows span only the first half of the columns (exact zeros elsewhere, as
+    # when integrand values underflow): the start must still reach a nonsingular, dominant
+    # submatrix
+    rng = np.random.Generator(np.random.PCG64(77))
+    m, r = 600, 8
+    A = 1e-2 * (rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r)))
+    A[:100, : r // 2] = rng.standard_normal((100, r // 2)) + 1j * rng.standard_normal((100, r // 2))
+    A[:100, r // 2:] = 0.0
+    rows, B = pricer.maxvol(A, 1e-2)
+    assert len(set(rows.tolist())) == r and rows.min() >= 0 and rows.max() < m
+    assert np.all(np.isfinite(B))
+    ref = A @ np.linalg.inv(A[rows])
+    assert np.max(np.abs(B - ref)) < 1e-10
+    assert np.max(np.abs(B)) <= 1.01 + 1e-10
+
+
 @pytest.mark.parametrize("m,r", [(64, 8), (1000, 24), (4096, 32), (8192, 64), (300, 1)])
 def test_maxvol_dominance(pricer, m, r):
     rng = np.random.Generator(np.random.PCG64(m + r))
