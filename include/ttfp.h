@@ -136,6 +136,18 @@ int ttfp_eval_integrand(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *
  * npts multi-indices idx[npts*d] (host). out[2*npts] interleaved complex. */
 int ttfp_tt_values(ttfp_ctx *ctx, int32_t term, int64_t npts, const int32_t *idx, double *out);
 
+/* After the last ttfp_price on this context: the tensor train of term `term` (Sec. IV.A)
+ * and the index sets its cross ended with (Sec. IV.B). Host buffers, owned by the caller:
+ *   ranks[d+1]            bond ranks r_0 = 1, r_1, ..., r_d = 1
+ *   cores (nullable)      the d cores one after another, core k as r_k x N x r_{k+1} complex
+ *                         values (interleaved re/im) in index order [a][i][b]
+ *   set_sizes (nullable)  [2(d+1)]: sizes of the left sets I_0..I_d, then of the right sets J_0..J_d
+ *   left, right (nullable) [(d+1) x max_rank x d]: entry (k, a, c) holds coordinate c of the a-th
+ *                         multi-index of I_k (c < k) or of J_k (c >= k); other entries are unused.
+ * TTFP_EINVAL without a previous ttfp_price or for a term out of range. */
+int ttfp_tt_export(ttfp_ctx *ctx, int32_t term, int32_t *ranks, double *cores, int32_t *set_sizes, int32_t *left,
+                   int32_t *right);
+
 /* Kernel-level entry points (same kernels as the pricer, exposed for verification).
  * ttfp_qr_r: upper-triangular factor R (n x n, row-major, interleaved complex) of a QR of
  * the m x n complex matrix A (row-major, interleaved), by the TSQR kernels; n <= 68.
@@ -147,7 +159,8 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
 
 /* Launch tuning of a context (chosen per workload shape by the autotuner in
  * paper_2203_02804_amd/tuning.py):
- *  TTFP_TUNE_MAXVOL_THREADS  threads per maxvol workgroup: 256, 512 or 1024 (default 1024)
+ *  TTFP_TUNE_MAXVOL_THREADS  threads per maxvol workgroup: 256, 512 or 1024, or 0 (default):
+ *                            per launch, the largest size that keeps every item resident at once
  *  TTFP_TUNE_TSQR_LDS_KB     LDS budget of a TSQR workgroup in KiB, 16..152 (default 152):
  *                            smaller budgets give shorter row blocks and more resident groups
  *  TTFP_TUNE_GRAPH           1: capture each direction's half sweep in a hipGraph once per

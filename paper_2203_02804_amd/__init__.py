@@ -53,7 +53,7 @@ class _Diag(ctypes.Structure):
 
 
 EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_eval_integrand",
-           "ttfp_tt_values", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
+           "ttfp_tt_values", "ttfp_tt_export", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
            "ttfp_profile_enable", "ttfp_profile_read", "ttfp_set_tuning", "ttfp_get_tuning", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
            "ttfp_mlp_last_error"]
@@ -82,6 +82,8 @@ def load():
     lib.ttfp_eval_integrand.argtypes = [vp, P(_Option), P(_Grid), ctypes.c_int32, ctypes.c_int64,
                                         P(ctypes.c_int32), P(ctypes.c_double)]
     lib.ttfp_tt_values.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32), P(ctypes.c_double)]
+    lib.ttfp_tt_export.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_int32),
+                                   P(ctypes.c_int32), P(ctypes.c_int32)]
     lib.ttfp_qr_r.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
     lib.ttfp_maxvol.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), ctypes.c_double,
                                 P(ctypes.c_int32), P(ctypes.c_double)]
@@ -265,6 +267,29 @@ class Pricer:
         out = np.zeros(2 * idx.shape[0])
         self._check(self.lib.ttfp_tt_values(self.ctx, int(term), idx.shape[0], _ip(idx), _dp(out)))
         return out[0::2] + 1j * out[1::2]
+
+    def tt_export(self, term, d, max_rank, N):
+        """Tensor train and final index sets of term `term` of the last price() call:
+        dict(ranks, cores[k] (r_k, N, r_k+1), I[k] (|I_k|, k), J[k] (|J_k|, d-k))."""
+        ranks = np.zeros(d + 1, np.int32)
+        sizes = np.zeros(2 * (d + 1), np.int32)
+        left = np.zeros((d + 1) * max_rank * d, np.int32)
+        right = np.zeros((d + 1) * max_rank * d, np.int32)
+        self._check(self.lib.ttfp_tt_export(self.ctx, int(term), _ip(ranks), None, _ip(sizes), _ip(left), _ip(right)))
+        total = sum(int(ranks[k]) * N * int(ranks[k + 1]) for k in range(d))
+        buf = np.zeros(2 * total)
+        self._check(self.lib.ttfp_tt_export(self.ctx, int(term), _ip(ranks), _dp(buf), None, None, None))
+        z = buf[0::2] + 1j * buf[1::2]
+        cores, off = [], 0
+        for k in range(d):
+            n = int(ranks[k]) * N * int(ranks[k + 1])
+            cores.append(z[off:off + n].reshape(int(ranks[k]), N, int(ranks[k + 1])))
+            off += n
+        left = left.reshape(d + 1, max_rank, d)
+        right = right.reshape(d + 1, max_rank, d)
+        I = [left[k, :sizes[k], :k].copy() for k in range(d + 1)]
+        J = [right[k, :sizes[d + 1 + k], k:].copy() for k in range(d + 1)]
+        return dict(ranks=ranks, cores=cores, I=I, J=J)
 
     def qr_r(self, A):
         A = np.ascontiguousarray(A, np.complex128)

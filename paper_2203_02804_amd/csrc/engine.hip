@@ -48,7 +48,8 @@ struct ttfp_ctx {
     std::vector<Item> last_items;
     int last_n_items = 0;
     // tuning (set by ttfp_set_tuning, chosen by the autotuner)
-    int tune_maxvol_threads = 1024;
+    int tune_maxvol_threads = 0;          // 0: chosen per launch from the number of items
+    int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 0;
     // kernel timing
@@ -311,6 +312,20 @@ void prof_collect(ttfp_ctx *ctx)
     ctx->ev_open.clear();
 }
 
+// Threads per maxvol workgroup (one workgroup per item): the largest size whose resident
+// workgroups (at most 2048 threads and 160 KiB of LDS per CU, about 15 KiB of it static) hold
+// every item of the launch at once; 256 when no size does.
+int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
+{
+    if (ctx->tune_maxvol_threads) return ctx->tune_maxvol_threads;
+    const long long by_lds = (long long)(160 * 1024) / (long long)(dyn_lds + 15 * 1024);
+    for (int t : {1024, 512}) {
+        const long long per_cu = std::min<long long>(2048 / t, by_lds);
+        if ((long long)n_items <= per_cu * ctx->n_cu) return t;
+    }
+    return 256;
+}
+
 int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
 {
     hipStream_t st = ctx->stream;
@@ -341,7 +356,8 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     {
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
         const int rm = std::max(g.maxR, 2);
-        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(ctx->tune_maxvol_threads), (size_t)2 * rm * rm * sizeof(cplx), st, it, act, t, dir, rm);
+        const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
+        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(maxvol_threads(ctx, n_items, lds)), lds, st, it, act, t, dir, rm);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_FINISH);
@@ -615,6 +631,8 @@ int ttfp_create(ttfp_ctx **out, int device, void *hip_stream)
     if (!c) return TTFP_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) c->n_cu = cus;
     *out = c;
     return TTFP_OK;
 }
@@ -624,7 +642,7 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
     if (!ctx) return TTFP_EINVAL;
     switch (param) {
     case TTFP_TUNE_MAXVOL_THREADS:
-        if (value != 256 && value != 512 && value != 1024) break;
+        if (value != 0 && value != 256 && value != 512 && value != 1024) break;
         ctx->tune_maxvol_threads = value;
         return TTFP_OK;
     case TTFP_TUNE_TSQR_LDS_KB:
@@ -919,6 +937,37 @@ int ttfp_tt_values(ttfp_ctx *ctx, int32_t term, int64_t npts, const int32_t *idx
     return TTFP_OK;
 }
 
+int ttfp_tt_export(ttfp_ctx *ctx, int32_t term, int32_t *ranks, double *cores, int32_t *set_sizes, int32_t *left,
+                   int32_t *right)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (ctx->last_n_items == 0) { ctx->last_error = "no tensor train available"; return TTFP_EINVAL; }
+    if (term < 0 || term >= ctx->last_n_items) { ctx->last_error = "term out of range"; return TTFP_EINVAL; }
+    if (!ranks) { ctx->last_error = "ranks is required"; return TTFP_EINVAL; }
+    const Item &h = ctx->last_items[term];
+    const int d = h.d, N = h.N, R = h.R;
+    ranks[0] = 1;
+    for (int k = 0; k < d; ++k) ranks[k + 1] = h.ccol[k];
+    if (set_sizes)
+        for (int k = 0; k <= d; ++k) {
+            set_sizes[k] = h.nI[k];
+            set_sizes[d + 1 + k] = h.nJ[k];
+        }
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (cores) {
+        size_t off = 0;
+        for (int k = 0; k < d; ++k) {
+            const size_t n = (size_t)h.crow[k] * N * h.ccol[k];
+            HIPCHK(hipMemcpy(cores + 2 * off, h.cores + (size_t)k * R * N * R, 16 * n, hipMemcpyDeviceToHost));
+            off += n;
+        }
+    }
+    if (left) HIPCHK(hipMemcpy(left, h.Iset, sizeof(int) * (size_t)(d + 1) * R * d, hipMemcpyDeviceToHost));
+    if (right) HIPCHK(hipMemcpy(right, h.Jset, sizeof(int) * (size_t)(d + 1) * R * d, hipMemcpyDeviceToHost));
+    return TTFP_OK;
+}
+
 // Raw-matrix entry points: a single item whose shape comes from nI[0] (rows) / nJ[0] (cols).
 static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, int &BR, int &G)
 {
@@ -1008,7 +1057,8 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
     e = e ? e : hipMemcpy(it.Y, A, 16 * (size_t)m * r, hipMemcpyHostToDevice);
     if (!e) {
         const int rm = std::max(r, 2);
-        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(ctx->tune_maxvol_threads), (size_t)2 * rm * rm * sizeof(cplx), ctx->stream, dit, act, 0, 2, rm);
+        const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
+        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(maxvol_threads(ctx, 1, lds)), lds, ctx->stream, dit, act, 0, 2, rm);
         e = hipGetLastError();
     }
     e = e ? e : hipStreamSynchronize(ctx->stream);

@@ -62,6 +62,57 @@ __device__ __forceinline__ double wave_sum(double v)
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Householder reflector for the column x = (x_j, ..., x_{n-1}) (entry i at x[i * stride]), made by
+// wave 0 of the workgroup. The reflector is H = I - tau w w^H with w_j = 1, chosen so that
+// H x = (alpha, 0, ..., 0) with alpha = -phase(x_j) |x|. Every quantity is formed from the column
+// scaled by its largest entry, so columns of any magnitude (integrand values span hundreds of
+// decades) neither underflow to a spurious zero norm nor overflow the reflector (tau lies in
+// [1, 2]); a column below 1e-280 in magnitude is left as it is (tau = 0). On return x holds w
+// (x_j = 1) and the wave's lane 0 has written alpha to *alpha_out and tau to *tau_out.
+__device__ void make_reflector(cplx *x, int stride, int j, int n, cplx *alpha_out, double *tau_out)
+{
+    const int lane = threadIdx.x & 63;
+    double mx = 0.0;
+    for (int i = j + lane; i < n; i += 64) mx = fmax(mx, fmax(fabs(x[(size_t)i * stride].x), fabs(x[(size_t)i * stride].y)));
+    mx = wave_max(mx);
+    if (!(mx >= 1e-280) || !(mx <= 1e300)) {
+        if (lane == 0) {
+            *alpha_out = x[(size_t)j * stride];
+            *tau_out = 0.0;
+        }
+        return;
+    }
+    const double inv = 1.0 / mx;
+    double sq = 0.0;
+    for (int i = j + 1 + lane; i < n; i += 64) {
+        const cplx v = x[(size_t)i * stride];
+        sq += cabs2(cplx{v.x * inv, v.y * inv});
+    }
+    sq = wave_sum(sq);
+    const cplx x0 = x[(size_t)j * stride];
+    const cplx x0s = {x0.x * inv, x0.y * inv};
+    // |x_j| by hypot: a squared modulus below 1e-308 keeps only a few digits, and a phase
+    // formed from it is not of unit modulus (the reflector would not be unitary)
+    const double a0 = hypot(x0s.x, x0s.y);
+    const double nrm = sqrt(sq + a0 * a0);           // >= 1: the largest entry scales to 1
+    const cplx ph = a0 > 1e-300 ? cplx{x0s.x / a0, x0s.y / a0} : cplx{1.0, 0.0};
+    // w_i = x_i / v_j with v_j = phase (|x_j| + |x|) (in units of mx)
+    const double den = 1.0 / (a0 + nrm);
+    const cplx cf = {ph.x * den * inv, -ph.y * den * inv};
+    for (int i = j + 1 + lane; i < n; i += 64) x[(size_t)i * stride] = cmul(x[(size_t)i * stride], cf);
+    if (lane == 0) {
+        x[(size_t)j * stride] = {1.0, 0.0};
+        *alpha_out = {-ph.x * nrm * mx, -ph.y * nrm * mx};
+        *tau_out = (a0 + nrm) / nrm;
+    }
+}
 
 // ------------------------------------------------------------------ counter-based generator
 // SplitMix64 finaliser (Steele, Lea and Flood, 2014) applied to a counter.
@@ -284,7 +335,8 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 
 // ------------------------------------------------------------------ Householder R in LDS
 // Triangularises A (nr x nc, column-major in LDS with leading dimension nr, nr <= 512) by
-// Householder reflections H = I - beta v v^H. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
+// Householder reflections H = I - tau w w^H (make_reflector). On exit row j of R is
+// (alph[j], A[j, j+1..nc-1]).
 // Column-major storage makes the lanes of a wave read consecutive 16-byte elements.
 constexpr int TSQR_MAX_ROWS = 512;
 constexpr int TSQR_THREADS = 256;
@@ -295,27 +347,7 @@ __device__ void householder_lds(cplx *A, int nr, int nc, cplx *alph, double *sh)
     const int jmax = nr < nc ? nr : nc;
     for (int j = 0; j < jmax; ++j) {
         cplx *vj = A + (size_t)j * nr;
-        if (wave == 0) {
-            double s = 0.0;
-            for (int i = j + 1 + lane; i < nr; i += 64) s += cabs2(vj[i]);
-            s = wave_sum(s);
-            if (lane == 0) {
-                cplx x0 = vj[j];
-                double a0 = sqrt(cabs2(x0));
-                double nrm = sqrt(s + a0 * a0);
-                double beta = 0.0;
-                cplx al = {0.0, 0.0};
-                if (nrm > 0.0) {
-                    cplx ph = a0 > 0.0 ? cplx{x0.x / a0, x0.y / a0} : cplx{1.0, 0.0};
-                    al = {-ph.x * nrm, -ph.y * nrm};
-                    cplx v0 = csub(x0, al);
-                    vj[j] = v0;
-                    beta = 2.0 / (s + cabs2(v0));
-                }
-                alph[j] = al;
-                sh[0] = beta;
-            }
-        }
+        if (wave == 0) make_reflector(vj, 1, j, nr, &alph[j], &sh[0]);
         __syncthreads();
         const double beta = sh[0];
         // this wave's trailing columns c = j + 1 + wave + u nw, four at a time: the partial dot
@@ -454,10 +486,18 @@ __global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, in
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int j = 0; j < nc; ++j) {
+        // trailing column norms, formed from the column scaled by its largest entry so that
+        // tiny columns keep their order instead of underflowing to zero
         for (int c = j + threadIdx.x; c < nc; c += blockDim.x) {
-            double q = 0.0;
-            for (int i = j; i < nc; ++i) q += cabs2(A[i * nc + c]);
-            nrm[c] = q;
+            double mx = 0.0;
+            for (int i = j; i < nc; ++i) mx = fmax(mx, fmax(fabs(A[i * nc + c].x), fabs(A[i * nc + c].y)));
+            double q = 1.0;
+            if (mx >= 1e-280 && mx <= 1e300) {           // else mx itself orders the column
+                const double inv = 1.0 / mx;
+                q = 0.0;
+                for (int i = j; i < nc; ++i) q += cabs2(cplx{A[i * nc + c].x * inv, A[i * nc + c].y * inv});
+            }
+            nrm[c] = mx * sqrt(q);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -477,25 +517,7 @@ __global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, in
             }
         __syncthreads();
         // Householder on column j, rows j..nc-1
-        if (wave == 0) {
-            double q = 0.0;
-            for (int i = j + 1 + lane; i < nc; i += 64) q += cabs2(A[i * nc + j]);
-            q = wave_sum(q);
-            if (lane == 0) {
-                cplx x0 = A[j * nc + j];
-                double a0 = sqrt(cabs2(x0)), nn = sqrt(q + a0 * a0), beta = 0.0;
-                cplx al = {0.0, 0.0};
-                if (nn > 0.0) {
-                    cplx ph = a0 > 0.0 ? cplx{x0.x / a0, x0.y / a0} : cplx{1.0, 0.0};
-                    al = {-ph.x * nn, -ph.y * nn};
-                    cplx v0 = csub(x0, al);
-                    A[j * nc + j] = v0;
-                    beta = 2.0 / (q + cabs2(v0));
-                }
-                alph[j] = al;
-                sh[0] = beta;
-            }
-        }
+        if (wave == 0) make_reflector(A + j, nc, j, nc, &alph[j], &sh[0]);
         __syncthreads();
         const double beta = sh[0];
         if (beta != 0.0)
@@ -515,9 +537,9 @@ __global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, in
     }
     // rank: leading pivots above rank_eps * |R_00|
     if (threadIdx.x == 0) {
-        const double r00 = sqrt(cabs2(alph[0]));
+        const double r00 = hypot(alph[0].x, alph[0].y);
         int r = 0;
-        while (r < nc && r00 > 0.0 && sqrt(cabs2(alph[r])) > it.rank_eps * r00) ++r;
+        while (r < nc && r00 > 0.0 && hypot(alph[r].x, alph[r].y) > it.rank_eps * r00) ++r;
         if (r < 1) r = 1;
         int cap = min(it.R, s.rows);
         if (dir == 2) cap = min(cap, nc);
@@ -769,16 +791,29 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     }
     for (int g = threadIdx.x; g < Kc; g += nthr) chosen[g] = 0;
     __syncthreads();
-    // ---- 1c. partial pivoting on the candidate block. A pivot below 1e-6 of the largest row
-    // norm means the block is numerically rank deficient (this happens when many integrand
-    // values underflow to zero and the largest rows share their support): the start is then
-    // taken by partial pivoting over all m rows instead (1d).
+    // ---- 1c. greedy volume start on the candidate block (pivoted Gram-Schmidt on rows): row j
+    // of the start is the candidate whose component orthogonal to the rows already taken is
+    // largest. A residual below 1e-6 of the largest row norm means the block is numerically rank
+    // deficient (this happens when many integrand values underflow to zero and the largest rows
+    // share their support): the start is then taken the same way over all m rows (1d).
     const double ptol2 = 1e-12 * (double)kmax;
+    __shared__ double rn[256];
+    __shared__ double qn[1];
+    // rows are spread over segments of seg lanes (lane = column), as in the flush pass below
+    const int seg = r <= 32 ? 32 : 64, rpw = 64 / seg, cl = lane % seg, sub = lane / seg;
+    const int nwv = nthr >> 6;
+    for (int g0 = wave * rpw; g0 < Kc; g0 += nwv * rpw) {
+        const int g = g0 + sub;
+        double q = (g < Kc && cl < r) ? cabs2(S[g * r + cl]) : 0.0;
+        for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+        if (g < Kc && cl == 0) rn[g] = q;
+    }
+    __syncthreads();
     for (int j = 0; j < r; ++j) {
         if (wave == 0) {
             ArgMax am = {-1.0, 0x7fffffff};
             for (int g = lane; g < Kc; g += 64)
-                if (!chosen[g]) am = better(am, ArgMax{cabs2(S[g * r + j]), g});
+                if (!chosen[g]) am = better(am, ArgMax{rn[g], g});
             for (int o = 32; o > 0; o >>= 1) {
                 ArgMax b2;
                 b2.v = __shfl_xor(am.v, o, 64);
@@ -791,57 +826,94 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
                 if (ok) {
                     chosen[am.i] = 1;
                     piv[j] = cand[am.i];
+                    qn[0] = am.v;
                 }
             }
         }
         __syncthreads();
         const int p = shi[0];
         if (p < 0) break;                       // uniform: every thread read the same flag
-        const int w = r - j - 1;
-        if (w > 0) {
-            const cplx pj = S[p * r + j];
-            for (int e = threadIdx.x; e < Kc * w; e += nthr) {
-                const int g = e / w, c = j + 1 + e % w;
-                if (chosen[g]) continue;
-                const cplx f = cdiv(S[g * r + j], pj);
-                S[g * r + c] = csub(S[g * r + c], cmul(f, S[p * r + c]));
+        if (j + 1 < r) {
+            const double inv = 1.0 / qn[0];
+            const cplx pc = cl < r ? S[p * r + cl] : cplx{0.0, 0.0};
+            for (int g0 = wave * rpw; g0 < Kc; g0 += nwv * rpw) {
+                const int g = g0 + sub;
+                const bool live = g < Kc && !chosen[g];
+                const bool act = live && cl < r;
+                cplx v = act ? S[g * r + cl] : cplx{0.0, 0.0};
+                cplx dot = cmulc(pc, v);
+                for (int o = seg >> 1; o > 0; o >>= 1) {
+                    dot.x += __shfl_xor(dot.x, o, 64);
+                    dot.y += __shfl_xor(dot.y, o, 64);
+                }
+                const cplx f = {dot.x * inv, dot.y * inv};
+                v = csub(v, cmul(f, pc));
+                double q = act ? cabs2(v) : 0.0;
+                for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+                if (act) S[g * r + cl] = v;
+                if (live && cl == 0) rn[g] = q;
             }
         }
         __syncthreads();
     }
-    // ---- 1d. fallback: partial pivoting over every row of Y, in place in a copy held in W
-    // (the output B, written only after the start, holds one flag per row meanwhile)
+    // ---- 1d. fallback: the same greedy selection over every row of Y, on a copy held in W;
+    // residual norms and row flags live in the output B, written only after the start
     if (shi[0] < 0) {
         cplx *Wl = W;
-        int *taken = reinterpret_cast<int *>(B);
-        for (long long e = threadIdx.x; e < (long long)m * r; e += nthr) Wl[e] = Y[e];
-        for (int i = threadIdx.x; i < m; i += nthr) taken[i] = 0;
+        double *wn = reinterpret_cast<double *>(B);
+        int *taken = reinterpret_cast<int *>(wn + m);
+        const int c = cl, nw = nwv;
+        for (int i0 = wave * rpw; i0 < m; i0 += nw * rpw) {
+            const int i = i0 + sub;
+            const bool act = i < m && c < r;
+            const cplx v = act ? Y[(size_t)i * r + c] : cplx{0.0, 0.0};
+            if (act) Wl[(size_t)i * r + c] = v;
+            double q = cabs2(v);
+            for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+            if (c == 0 && i < m) {
+                wn[i] = q;
+                taken[i] = 0;
+            }
+        }
         __syncthreads();
         for (int j = 0; j < r; ++j) {
             ArgMax a = {-1.0, 0x7fffffff};
             for (int i = threadIdx.x; i < m; i += nthr)
                 if (!taken[i]) {
-                    const double v = cabs2(Wl[(size_t)i * r + j]);
+                    const double v = wn[i];
                     a = better(a, ArgMax{v <= 1e300 ? v : -0.5, i});     // non-finite ranks last
                 }
             a = block_argmax(a, red);
             int p = a.i;
             if (p < 0 || p >= m) p = 0;        // unreachable: j < r <= m rows remain untaken
+            const double pn = (a.v > 0.0 && a.v <= 1e300) ? a.v : 0.0;
             if (threadIdx.x == 0) {
                 taken[p] = 1;
                 piv[j] = p;
             }
+            for (int cc = threadIdx.x; cc < r; cc += nthr) prow[cc] = Wl[(size_t)p * r + cc];
             __syncthreads();
-            const cplx pj = Wl[(size_t)p * r + j];
-            const double pa = cabs2(pj);
-            const int w = r - j - 1;
-            if (w > 0 && pa > 0.0 && pa <= 1e300)
-                for (long long e = threadIdx.x; e < (long long)m * w; e += nthr) {
-                    const int i = (int)(e / w), c = j + 1 + (int)(e % w);
-                    if (taken[i]) continue;
-                    const cplx f = cdiv(Wl[(size_t)i * r + j], pj);
-                    Wl[(size_t)i * r + c] = csub(Wl[(size_t)i * r + c], cmul(f, Wl[(size_t)p * r + c]));
+            if (j + 1 < r && pn > 0.0) {
+                const double inv = 1.0 / pn;
+                for (int i0 = wave * rpw; i0 < m; i0 += nw * rpw) {
+                    const int i = i0 + sub;
+                    const bool live = i < m && !taken[i];
+                    const bool act = live && c < r;
+                    cplx v = act ? Wl[(size_t)i * r + c] : cplx{0.0, 0.0};
+                    const cplx pc = c < r ? prow[c] : cplx{0.0, 0.0};
+                    cplx dot = cmulc(pc, v);
+                    for (int o = seg >> 1; o > 0; o >>= 1) {
+                        dot.x += __shfl_xor(dot.x, o, 64);
+                        dot.y += __shfl_xor(dot.y, o, 64);
+                    }
+                    const cplx f = {dot.x * inv, dot.y * inv};
+                    v = csub(v, cmul(f, pc));
+                    double q = act ? cabs2(v) : 0.0;
+                    for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+                    if (act) Wl[(size_t)i * r + c] = v;
+                    if (live && c == 0) wn[i] = q;
                 }
+            }
             __syncthreads();
         }
         if (threadIdx.x == 0) it.mv_full += 1;
@@ -937,6 +1009,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     __shared__ int cidx[256];
     __shared__ int rec_j[64];
     __shared__ cplx rec_b[64];
+    __shared__ cplx rec_bi[64];              // 1 / rec_b
     __shared__ int wsum[17];
     __shared__ cplx snap[256];
     __shared__ int nstate[2];                // number of candidates, number of records
@@ -946,7 +1019,6 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     // flush pass: a wave takes 64 / seg rows at a time (seg lanes per row, lane = column);
     // candidate rows are written back from LDS, the others get the recorded updates; a
     // ballot marks rows that still violate, each lane keeps its running argmax
-    const int seg = r <= 32 ? 32 : 64;
     auto flush = [&](void) -> ArgMax {
         const int nrec = nstate[1];
         const int rpw = 64 / seg, c = lane % seg, sub = lane / seg;
@@ -960,7 +1032,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
             for (int q = 0; q < nrec; ++q) {
                 const int src = sub * seg + rec_j[q];
                 const cplx vj = {__shfl(val.x, src, 64), __shfl(val.y, src, 64)};
-                if (cp == 0 && act) val = csub(val, cmul(cdiv(vj, rec_b[q]), Rw[q * r + c]));
+                if (cp == 0 && act) val = csub(val, cmul(cmul(vj, rec_bi[q]), Rw[q * r + c]));
             }
             if (act && (cp > 0 || nrec > 0)) B[(size_t)i * r + c] = val;
             const double a2 = act ? cabs2(val) : -1.0;
@@ -1026,6 +1098,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
             if (threadIdx.x == 0) {
                 rec_j[nrec] = cs;
                 rec_b[nrec] = Cr[ci * r + cs];
+                rec_bi[nrec] = cdiv({1.0, 0.0}, Cr[ci * r + cs]);
                 piv[cs] = cidx[ci];
             }
             __syncthreads();

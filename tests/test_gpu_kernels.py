@@ -73,6 +73,26 @@ def test_tsqr_r_factor(pricer, m, n):
         assert np.allclose(R[m:], 0)
 
 
+@pytest.mark.parametrize("m,n", [(256, 36), (7168, 36), (8192, 36), (600, 68)])
+def test_tsqr_rows_spanning_hundreds_of_decades(pricer, m, n):
+    # fibers of the integrand mix rows near its peak with rows deep in its tails (down to
+    # 1e-300 and exact zeros); a leaf block may also hold fewer rows than columns (m=256)
+    rng = np.random.Generator(np.random.PCG64(m + 7 * n))
+    A = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    A *= 10.0 ** (-300.0 * rng.random(m) ** 3)[:, None]
+    A[rng.random(m) < 0.05] = 0.0
+    A[: m // 3] *= 1e-170                      # whole leaf blocks of tiny rows
+    R = pricer.qr_r(A)
+    assert np.all(np.isfinite(R))
+    G0 = A.conj().T @ A
+    assert np.linalg.norm(R.conj().T @ R - G0) <= 1e-13 * np.linalg.norm(G0)
+    # the diagonal agrees with a reference factor wherever it is resolved
+    d0 = np.abs(np.diag(np.linalg.qr(A, mode="r")))
+    dg = np.abs(np.diag(R))
+    big = d0 > 1e-10 * d0.max()
+    assert np.max(np.abs(dg[big] / d0[big] - 1)) < 1e-6
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_maxvol_tiny_against_exhaustive_search(pricer, seed):
     rng = np.random.Generator(np.random.PCG64(100 + seed))
