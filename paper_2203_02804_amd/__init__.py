@@ -57,7 +57,7 @@ EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price
            "ttfp_profile_enable", "ttfp_profile_read", "ttfp_set_tuning", "ttfp_get_tuning", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
            "ttfp_mlp_last_error"]
-KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract"]
+KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract", "interp"]
 TUNING = {"maxvol_threads": 0, "tsqr_lds_kb": 1, "graph": 2}
 
 _lib = None

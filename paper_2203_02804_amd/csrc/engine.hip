@@ -22,6 +22,8 @@ __global__ void k_tsqr(Item *items, const int *active, int t, int dir, int level
 __global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G);
 __global__ void k_basis(Item *items, const int *active, int t, int dir);
 __global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax);
+__global__ void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax);
+__global__ void k_interp(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_finish(Item *items, const int *active, int t, int dir);
 __global__ void k_core_sum(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_contract(Item *items, const int *active);
@@ -97,7 +99,7 @@ int tsqr_levels(int rows, int BR, int G)
 struct ItemSizes {
     size_t bytes;
     size_t off_m, off_C, off_L, off_a, off_kind, off_I, off_J, off_F, off_Rl, off_Ri, off_perm, off_Y, off_W,
-        off_Bt, off_cores, off_M, off_M1, off_M2, off_piv, off_keys;
+        off_Bt, off_cores, off_M, off_M1, off_M2, off_piv, off_keys, off_Ai;
     int rows_max, nblk_max;
 };
 
@@ -129,6 +131,7 @@ ItemSizes item_sizes(int d, int N, int R, int p, int BR)
     s.off_M2 = take(sizeof(cplx) * (size_t)d * R * R);
     s.off_piv = take(sizeof(int) * R);
     s.off_keys = take(sizeof(float) * (size_t)s.rows_max * 16);
+    s.off_Ai = take(sizeof(cplx) * (size_t)R * R);
     s.bytes = o;
     return s;
 }
@@ -240,6 +243,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             it.M2 = (cplx *)(dev + s.off_M2);
             it.piv = (int *)(dev + s.off_piv);
             it.keys = (float *)(dev + s.off_keys);
+            it.Ai = (cplx *)(dev + s.off_Ai);
             it.rows_max = s.rows_max;
             it.nblk_max = s.nblk_max;
             // static term data: one contiguous host staging block up to off_I
@@ -326,6 +330,9 @@ int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
     return 256;
 }
 
+// Refinement rounds of maxvol after its first pass over the candidate block.
+constexpr int MAXVOL_REFINE_ROUNDS = 2;
+
 int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
 {
     hipStream_t st = ctx->stream;
@@ -357,7 +364,22 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
         const int rm = std::max(g.maxR, 2);
         const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
-        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(maxvol_threads(ctx, n_items, lds)), lds, st, it, act, t, dir, rm);
+        const unsigned th = (unsigned)maxvol_threads(ctx, n_items, lds);
+        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(th), lds, st, it, act, t, dir, rm);
+    }
+    // interpolation matrix of every row, then refinement rounds (each returns at once for an
+    // item whose rows all satisfy the dominance bound)
+    const unsigned gi = cdivu((long long)g.maxrows * ((g.maxR + 3) / 4), 256);
+    for (int round = 0; round <= MAXVOL_REFINE_ROUNDS; ++round) {
+        if (round > 0) {
+            ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
+            const int rm = std::max(g.maxR, 2);
+            const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
+            hipLaunchKernelGGL(k_maxvol_refine, dim3(ny), dim3((unsigned)maxvol_threads(ctx, n_items, lds)), lds, st, it, act, t,
+                               dir, rm);
+        }
+        ProfScope ps(ctx, TTFP_KERNEL_INTERP);
+        hipLaunchKernelGGL(k_interp, dim3(gi, ny), dim3(256), 0, st, it, act, t, dir, round > 0 ? 1 : 0);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_FINISH);
@@ -975,7 +997,8 @@ static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, in
     const int nblk = (m + BR - 1) / BR;
     size_t oF = 0, oRl = align_up(oF + 16 * (size_t)m * n), oY = align_up(oRl + 16 * 2 * (size_t)nblk * n * n),
            oW = align_up(oY + 16 * (size_t)m * r), oBt = align_up(oW + 16 * (size_t)m * r), oP = align_up(oBt + 16 * (size_t)m * r),
-           total = align_up(oP + 4 * (size_t)std::max(r, 1));
+           oK = align_up(oP + 4 * (size_t)std::max(r, 1)), oA = align_up(oK + 4 * 16 * (size_t)m),
+           total = align_up(oA + 16 * (size_t)r * r);
     HIPCHK(hipMalloc(&buf, total));
     std::memset(&it, 0, sizeof it);
     it.d = 1;
@@ -987,6 +1010,8 @@ static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, in
     it.W = (cplx *)(buf + oW);
     it.Bt = (cplx *)(buf + oBt);
     it.piv = (int *)(buf + oP);
+    it.keys = (float *)(buf + oK);
+    it.Ai = (cplx *)(buf + oA);
     it.nblk_max = nblk;
     it.rows_max = m;
     it.nI[0] = m;
@@ -1058,7 +1083,15 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
     if (!e) {
         const int rm = std::max(r, 2);
         const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
-        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(maxvol_threads(ctx, 1, lds)), lds, ctx->stream, dit, act, 0, 2, rm);
+        const unsigned th = (unsigned)maxvol_threads(ctx, 1, lds);
+        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
+        // refinement rounds until every row satisfies the dominance bound (each round returns at
+        // once when none violates)
+        const unsigned gi = cdivu((long long)m * ((r + 3) / 4), 256);
+        for (int round = 0; round <= 8; ++round) {
+            if (round > 0) hipLaunchKernelGGL(k_maxvol_refine, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
+            hipLaunchKernelGGL(k_interp, dim3(gi, 1), dim3(256), 0, ctx->stream, dit, act, 0, 2, round > 0 ? 1 : 0);
+        }
         e = hipGetLastError();
     }
     e = e ? e : hipStreamSynchronize(ctx->stream);

@@ -45,6 +45,7 @@ struct Item {
     cplx *M;                   // d slots of R x R: core sums over the node index
     cplx *M1, *M2;             // d slots of R x R: first / second node moments (Greeks)
     int *piv;                  // R pivot rows
+    cplx *Ai;                  // R x R inverse of the pivot rows of Y (maxvol -> k_interp)
     float *keys;               // rows_max x 16 partial squared row norms of Y (maxvol start)
     int rows_max, nblk_max;
     // ---- dynamic state
@@ -57,7 +58,9 @@ struct Item {
     long long mv_iters;               // maxvol swaps performed (diagnostic)
     long long mv_full;                // maxvol starts taken over all rows (degenerate candidate block)
     int mv_singular;                  // a maxvol start matrix was exactly singular
-    double work[8];                   // algorithmic work per kernel family (bytes or flops)
+    int mv_viol;                      // k_interp found rows with |B_ij| > 1 + delta
+    int mv_dirty;                     // the pivots moved since B was last formed
+    double work[12];                  // algorithmic work per kernel family (bytes or flops)
     double phase[12];                 // per-phase device time (ticks), TTFP_PHASE_TIMING builds only
     cplx P;                           // latest contraction of the tensor train
 };

@@ -213,7 +213,9 @@ __global__ void k_init(Item *items, int n_items)
     it.mv_iters = 0;
     it.mv_full = 0;
     it.mv_singular = 0;
-    for (int q = 0; q < 8; ++q) it.work[q] = 0.0;
+    it.mv_viol = 0;
+    it.mv_dirty = 0;
+    for (int q = 0; q < 12; ++q) it.work[q] = 0.0;
     for (int q = 0; q < 12; ++q) it.phase[q] = 0.0;
     it.capped = 0;
     long long cnt = 1;
@@ -646,18 +648,172 @@ __device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
     return scratch[nw];
 }
 
-// Dominant r x r submatrix of Y (rows x r).
-//  1. start: the K rows of largest norm (Y has orthonormal columns, so these are the rows
-//     of largest leverage) are selected by bisection on the norm; Gaussian elimination with
-//     partial pivoting on that K x r block (in LDS) picks r starting rows.
-//  2. B = Y Y[piv]^{-1} (Gauss-Jordan inverse in LDS, one pass over Y).
-//  3. maxvol swaps: while max |B_ij| > 1 + delta, row i replaces pivot j and B takes the
-//     rank-one update B -= B[:,j] (B[i,:] - e_j) / B[i,j]; the next argmax is found in the
-//     same pass. Termination: every swap multiplies |det Y[piv]| by more than 1 + delta, and
-//     the loop is also bounded by 4 r + 16 swaps.
+// Dominant r x r submatrix of Y (rows x r) and the interpolation matrix B = Y Y[piv]^{-1}.
+//
+// k_maxvol works on a block of candidate rows only: the K rows of largest norm (Y has
+// orthonormal columns, so these are the rows of largest leverage), K = min(512, max(4 r, 64)).
+//  1. start: greedy volume selection on the block (pivoted Gram-Schmidt on rows); when the
+//     block is numerically rank deficient, the same selection over all m rows.
+//  2. A^{-1} = Y[piv]^{-1} by Gauss-Jordan with partial pivoting (LDS), and the block's rows of
+//     B, Bc = Y[cand] A^{-1}.
+//  3. maxvol swaps on Bc: while its entry of largest modulus exceeds 1 + delta, that row
+//     replaces the pivot of its column and Bc takes the rank-one update
+//     Bc -= Bc[:,j] (Bc[i,:] - e_j) / Bc[i,j]. Each swap multiplies |det Y[piv]| by more than
+//     1 + delta; at most 4 r + 16 swaps.
+//  4. A^{-1} again from the final pivots, stored for k_interp.
+// k_interp forms B for every row (a tiled product spread over the whole chip) and marks the
+// rows whose largest |B_ij| exceeds 1 + delta. k_maxvol_refine puts the pivots and the worst
+// such rows into a new block and repeats 3-4, after which k_interp runs again; when no row
+// violates, both return at once. The result is dominant over every row once no row violates.
+constexpr int MV_KMAX = 512;
 
-// Abuf is dynamic LDS of 2 rmax^2 complex entries (rmax: the largest rank of the launch), so
-// that small ranks leave room for several workgroups per CU.
+// Up to K indices g < n of largest value v[g * stride] (nonnegative floats, largest vmax), among
+// those of value >= lo0: the first ones in index order among those at or above a threshold
+// found by bisection, so that the choice does not depend on scheduling. Writes out[0..Kc) and
+// returns Kc (same in every thread). Every thread of the workgroup must call it.
+__device__ int select_largest(const float *v, int stride, int n, int K, float lo0, float vmax, int *out, ArgMax *red,
+                              int *shi, float *shf)
+{
+    const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (threadIdx.x == 0) { shf[0] = lo0; shf[1] = fmaxf(vmax, lo0); }
+    __syncthreads();
+    for (int it2 = 0; it2 < 40; ++it2) {
+        const float lo = shf[0], hi = shf[1], mid = 0.5f * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        int cnt = 0;
+        for (int g = threadIdx.x; g < n; g += nthr) cnt += v[(size_t)g * stride] >= mid;
+        double a = (double)cnt;
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        __syncthreads();
+        if (lane == 0) red[wave].v = a;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < (nthr >> 6); ++w) tot += red[w].v;
+            if (tot >= K) shf[0] = mid; else shf[1] = mid;
+        }
+        __syncthreads();
+    }
+    const float thr = shf[0];
+    const int chunk = (n + nthr - 1) / nthr;
+    const int g0 = threadIdx.x * chunk, g1 = min(n, g0 + chunk);
+    int cnt = 0;
+    for (int g = g0; g < g1; ++g) cnt += v[(size_t)g * stride] >= thr;
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int x = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += x;
+    }
+    __syncthreads();
+    if (lane == 63) red[wave].i = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < (nthr >> 6); ++w) { const int t0 = red[w].i; red[w].i = acc; acc += t0; }
+        shi[2] = acc;
+    }
+    __syncthreads();
+    int pos = red[wave].i + incl - cnt;
+    for (int g = g0; g < g1; ++g)
+        if (v[(size_t)g * stride] >= thr) {
+            if (pos < K) out[pos] = g;
+            ++pos;
+        }
+    __syncthreads();
+    return min(K, shi[2]);
+}
+
+// A^{-1} = Y[piv]^{-1} (r x r, row stride r) by Gauss-Jordan with partial pivoting, in LDS.
+// An exactly singular pivot leaves its column at zero and sets it.mv_singular.
+__device__ void gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag, cplx *Ai, cplx *fcol, int *shi, Item &it)
+{
+    const int nthr = blockDim.x;
+    __syncthreads();
+    for (int e = threadIdx.x; e < r * r; e += nthr) {
+        const int a = e / r, c = e % r;
+        Ag[e] = Y[(size_t)min(max(piv[a], 0), m - 1) * r + c];
+        Ai[e] = (a == c) ? cplx{1.0, 0.0} : cplx{0.0, 0.0};
+    }
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        if (threadIdx.x == 0) {
+            int p = j;
+            double best = cabs2(Ag[j * r + j]);
+            for (int a = j + 1; a < r; ++a) {
+                const double v = cabs2(Ag[a * r + j]);
+                if (v > best) { best = v; p = a; }
+            }
+            shi[0] = p;
+        }
+        __syncthreads();
+        const int p = shi[0];
+        if (p != j)
+            for (int c = threadIdx.x; c < r; c += nthr) {
+                cplx t0 = Ag[j * r + c]; Ag[j * r + c] = Ag[p * r + c]; Ag[p * r + c] = t0;
+                cplx t1 = Ai[j * r + c]; Ai[j * r + c] = Ai[p * r + c]; Ai[p * r + c] = t1;
+            }
+        __syncthreads();
+        const cplx gjj = Ag[j * r + j];
+        const bool sing = !(fmax(fabs(gjj.x), fabs(gjj.y)) > 0.0) || !(cabs2(gjj) <= 1e300);
+        const cplx inv = sing ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, gjj);
+        if (sing && threadIdx.x == 0) it.mv_singular = 1;
+        __syncthreads();
+        for (int c = threadIdx.x; c < r; c += nthr) {
+            Ag[j * r + c] = cmul(Ag[j * r + c], inv);
+            Ai[j * r + c] = cmul(Ai[j * r + c], inv);
+        }
+        __syncthreads();
+        for (int a = threadIdx.x; a < r; a += nthr) fcol[a] = Ag[a * r + j];
+        __syncthreads();
+        for (int e = threadIdx.x; e < r * r; e += nthr) {
+            const int a = e / r, c = e % r;
+            if (a == j) continue;
+            Ag[e] = csub(Ag[e], cmul(fcol[a], Ag[j * r + c]));
+            Ai[e] = csub(Ai[e], cmul(fcol[a], Ai[j * r + c]));
+        }
+        __syncthreads();
+    }
+}
+
+// maxvol swaps on the candidate block Bc (Kc x r, global memory, rows cand[0..Kc)); returns the
+// number of swaps (same in every thread).
+__device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, double lim, int maxit, cplx *prow, cplx *colv,
+                          ArgMax *red)
+{
+    const int nthr = blockDim.x;
+    int swaps = 0;
+    const long long tot = (long long)Kc * r;
+    while (swaps < maxit) {
+        ArgMax a = {-1.0, 0x7fffffff};
+        for (long long e = threadIdx.x; e < tot; e += nthr) {
+            const double v = cabs2(Bc[e]);
+            a = better(a, ArgMax{v <= 1e300 ? v : -1.0, (int)e});
+        }
+        a = block_argmax(a, red);
+        if (!(a.v > lim) || a.i < 0 || a.i >= tot) break;
+        const int qs = a.i / r, js = a.i % r;
+        const cplx b = Bc[(size_t)qs * r + js];
+        for (int c = threadIdx.x; c < r; c += nthr) {
+            cplx w = Bc[(size_t)qs * r + c];
+            if (c == js) w.x -= 1.0;
+            prow[c] = w;
+        }
+        for (int q = threadIdx.x; q < Kc; q += nthr) colv[q] = cdiv(Bc[(size_t)q * r + js], b);
+        if (threadIdx.x == 0) piv[js] = cand[qs];
+        __syncthreads();
+        for (long long e = threadIdx.x; e < tot; e += nthr) {
+            const int q = (int)(e / r), c = (int)(e % r);
+            Bc[e] = csub(Bc[e], cmul(colv[q], prow[c]));
+        }
+        __syncthreads();
+        ++swaps;
+    }
+    return swaps;
+}
+
+// Abuf is dynamic LDS of 2 rmax^2 complex entries (rmax: the largest rank of the launch): the
+// key buffer of the start and the two r x r blocks of the Gauss-Jordan inverse.
 __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax)
 {
     extern __shared__ cplx Abuf[];
@@ -666,8 +822,11 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     __shared__ cplx prow[TTFP_MAX_RANK];
     __shared__ cplx fcol[TTFP_MAX_RANK];
     __shared__ int piv[TTFP_MAX_RANK];
-    __shared__ int cand[256];
-    __shared__ int chosen[256];
+    __shared__ int cand[MV_KMAX];
+    __shared__ int chosen[MV_KMAX];
+    __shared__ cplx colv[MV_KMAX];
+    __shared__ double rn[MV_KMAX];
+    __shared__ double qn[1];
     __shared__ ArgMax red[17];
     __shared__ int shi[4];
     __shared__ float shf[2];
@@ -682,22 +841,23 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
     const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     PHASE_START;
-    // ---- 1a. row norms (one key per group of gsz consecutive rows: its largest norm)
-    int K = cap / r;                                     // K x r block fits in Abuf
-    if (K > 256) K = 256;
-    if (K > m) K = m;
+    // ---- 1a. row norms (one key per group of gsz consecutive rows: its largest norm); the first
+    // key slot of every row is then cleared: k_interp records violations there
     const int nkeys = cap * (int)(sizeof(cplx) / sizeof(float));
     const int gsz = (m + nkeys - 1) / nkeys;            // 1 unless m exceeds the key buffer
     const int nk = (m + gsz - 1) / gsz;
+    int K = max(4 * r, 64);
+    K = min(K, MV_KMAX);
+    K = min(K, nk);
     float *key = (float *)Abuf;
     float kmax = 0.0f;
     for (int g = threadIdx.x; g < nk; g += nthr) {
         float best = -1.0f;
         for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
             float q;
+            float *kp = it.keys + (size_t)i * 16;
             if (dir != 2) {
-                const float *kp = it.keys + (size_t)i * 16;   // partials written by k_basis
-                q = 0.0f;
+                q = 0.0f;                                // partials written by k_basis
                 for (int u = 0; u < (r + 3) / 4; ++u) q += kp[u];
             } else {
                 const cplx *y = Y + (size_t)i * r;
@@ -705,11 +865,12 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
                 for (int c = 0; c < r; ++c) qq += cabs2(y[c]);
                 q = (float)qq;
             }
+            kp[0] = 0.0f;
             if (!(q >= 0.0f && q <= 3.0e38f)) q = 0.0f;     // a non-finite row is never a pivot
             best = fmaxf(best, q);
         }
         key[g] = fmaxf(best, 0.0f);
-        kmax = fmaxf(kmax, best);
+        kmax = fmaxf(kmax, key[g]);
     }
     {
         ArgMax a = {(double)kmax, 0};
@@ -717,59 +878,8 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         kmax = (float)a.v;
     }
     PHASE_MARK(0);
-    // ---- 1b. bisection for a threshold with at least K keys above it
-    if (threadIdx.x == 0) { shf[0] = 0.0f; shf[1] = kmax; }
-    __syncthreads();
-    for (int it2 = 0; it2 < 40; ++it2) {
-        const float lo = shf[0], hi = shf[1], mid = 0.5f * (lo + hi);
-        if (!(mid > lo && mid < hi)) break;
-        int cnt = 0;
-        for (int g = threadIdx.x; g < nk; g += nthr) cnt += key[g] >= mid;
-        ArgMax a = {(double)cnt, 0};
-        // block sum through the argmax scratch: reduce counts by waves
-        for (int o = 32; o > 0; o >>= 1) a.v += __shfl_xor(a.v, o, 64);
-        __syncthreads();
-        if (lane == 0) red[wave] = a;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double tot = 0.0;
-            for (int w = 0; w < (nthr >> 6); ++w) tot += red[w].v;
-            if (tot >= K) shf[0] = mid; else shf[1] = mid;
-        }
-        __syncthreads();
-    }
-    const float thr = shf[0];
-    // groups with key >= thr, the first K in increasing group order (a prefix sum over
-    // contiguous chunks, so that the selection does not depend on scheduling)
-    {
-        const int chunk = (nk + nthr - 1) / nthr;
-        const int g0 = threadIdx.x * chunk, g1 = min(nk, g0 + chunk);
-        int cnt = 0;
-        for (int g = g0; g < g1; ++g) cnt += key[g] >= thr;
-        int incl = cnt;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += v;
-        }
-        __syncthreads();
-        if (lane == 63) red[wave].i = incl;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int w = 0; w < (nthr >> 6); ++w) { const int t0 = red[w].i; red[w].i = acc; acc += t0; }
-            shi[2] = acc;
-        }
-        __syncthreads();
-        int pos = red[wave].i + incl - cnt;
-        for (int g = g0; g < g1; ++g)
-            if (key[g] >= thr) {
-                if (pos < K) cand[pos] = g;      // group index; resolved to a row below
-                ++pos;
-            }
-        __syncthreads();
-    }
-    const int Kc = min(K, shi[2]);
-    // resolve groups to their largest-norm row
+    // ---- 1b. the K largest groups, resolved to their largest-norm row
+    const int Kc = select_largest(key, 1, nk, K, 0.0f, kmax, cand, red, shi, shf);
     for (int q = threadIdx.x; q < Kc; q += nthr) {
         const int g = cand[q];
         int bi = g * gsz;
@@ -781,30 +891,25 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
             if (v > best) { best = v; bi = i; }
         }
         cand[q] = bi;
+        chosen[q] = 0;
     }
     __syncthreads();
     PHASE_MARK(1);
-    cplx *S = Abuf;                                // Kc x r candidate block
-    for (int e = threadIdx.x; e < Kc * r; e += nthr) {
-        const int g = e / r, c = e % r;
-        S[e] = Y[(size_t)cand[g] * r + c];
-    }
-    for (int g = threadIdx.x; g < Kc; g += nthr) chosen[g] = 0;
-    __syncthreads();
-    // ---- 1c. greedy volume start on the candidate block (pivoted Gram-Schmidt on rows): row j
-    // of the start is the candidate whose component orthogonal to the rows already taken is
-    // largest. A residual below 1e-6 of the largest row norm means the block is numerically rank
-    // deficient (this happens when many integrand values underflow to zero and the largest rows
-    // share their support): the start is then taken the same way over all m rows (1d).
+    // ---- 1c. greedy volume start on the block S = Y[cand] (a copy in W): row j of the start
+    // is the candidate whose component orthogonal to the rows already taken is largest. A
+    // residual below 1e-6 of the largest row norm means the block is numerically rank deficient
+    // (this happens when many integrand values underflow to zero and the largest rows share
+    // their support): the start is then taken the same way over all m rows (1d).
     const double ptol2 = 1e-12 * (double)kmax;
-    __shared__ double rn[256];
-    __shared__ double qn[1];
-    // rows are spread over segments of seg lanes (lane = column), as in the flush pass below
     const int seg = r <= 32 ? 32 : 64, rpw = 64 / seg, cl = lane % seg, sub = lane / seg;
     const int nwv = nthr >> 6;
+    cplx *S = W;
     for (int g0 = wave * rpw; g0 < Kc; g0 += nwv * rpw) {
         const int g = g0 + sub;
-        double q = (g < Kc && cl < r) ? cabs2(S[g * r + cl]) : 0.0;
+        const bool act = g < Kc && cl < r;
+        const cplx v = act ? Y[(size_t)cand[g] * r + cl] : cplx{0.0, 0.0};
+        if (act) S[(size_t)g * r + cl] = v;
+        double q = cabs2(v);
         for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
         if (g < Kc && cl == 0) rn[g] = q;
     }
@@ -835,12 +940,12 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         if (p < 0) break;                       // uniform: every thread read the same flag
         if (j + 1 < r) {
             const double inv = 1.0 / qn[0];
-            const cplx pc = cl < r ? S[p * r + cl] : cplx{0.0, 0.0};
+            const cplx pc = cl < r ? S[(size_t)p * r + cl] : cplx{0.0, 0.0};
             for (int g0 = wave * rpw; g0 < Kc; g0 += nwv * rpw) {
                 const int g = g0 + sub;
                 const bool live = g < Kc && !chosen[g];
                 const bool act = live && cl < r;
-                cplx v = act ? S[g * r + cl] : cplx{0.0, 0.0};
+                cplx v = act ? S[(size_t)g * r + cl] : cplx{0.0, 0.0};
                 cplx dot = cmulc(pc, v);
                 for (int o = seg >> 1; o > 0; o >>= 1) {
                     dot.x += __shfl_xor(dot.x, o, 64);
@@ -850,27 +955,26 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
                 v = csub(v, cmul(f, pc));
                 double q = act ? cabs2(v) : 0.0;
                 for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
-                if (act) S[g * r + cl] = v;
+                if (act) S[(size_t)g * r + cl] = v;
                 if (live && cl == 0) rn[g] = q;
             }
         }
         __syncthreads();
     }
     // ---- 1d. fallback: the same greedy selection over every row of Y, on a copy held in W;
-    // residual norms and row flags live in the output B, written only after the start
+    // residual norms and row flags live in the output B, written only by k_interp
     if (shi[0] < 0) {
         cplx *Wl = W;
         double *wn = reinterpret_cast<double *>(B);
         int *taken = reinterpret_cast<int *>(wn + m);
-        const int c = cl, nw = nwv;
-        for (int i0 = wave * rpw; i0 < m; i0 += nw * rpw) {
+        for (int i0 = wave * rpw; i0 < m; i0 += nwv * rpw) {
             const int i = i0 + sub;
-            const bool act = i < m && c < r;
-            const cplx v = act ? Y[(size_t)i * r + c] : cplx{0.0, 0.0};
-            if (act) Wl[(size_t)i * r + c] = v;
+            const bool act = i < m && cl < r;
+            const cplx v = act ? Y[(size_t)i * r + cl] : cplx{0.0, 0.0};
+            if (act) Wl[(size_t)i * r + cl] = v;
             double q = cabs2(v);
             for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
-            if (c == 0 && i < m) {
+            if (cl == 0 && i < m) {
                 wn[i] = q;
                 taken[i] = 0;
             }
@@ -895,12 +999,12 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
             __syncthreads();
             if (j + 1 < r && pn > 0.0) {
                 const double inv = 1.0 / pn;
-                for (int i0 = wave * rpw; i0 < m; i0 += nw * rpw) {
+                for (int i0 = wave * rpw; i0 < m; i0 += nwv * rpw) {
                     const int i = i0 + sub;
                     const bool live = i < m && !taken[i];
-                    const bool act = live && c < r;
-                    cplx v = act ? Wl[(size_t)i * r + c] : cplx{0.0, 0.0};
-                    const cplx pc = c < r ? prow[c] : cplx{0.0, 0.0};
+                    const bool act = live && cl < r;
+                    cplx v = act ? Wl[(size_t)i * r + cl] : cplx{0.0, 0.0};
+                    const cplx pc = cl < r ? prow[cl] : cplx{0.0, 0.0};
                     cplx dot = cmulc(pc, v);
                     for (int o = seg >> 1; o > 0; o >>= 1) {
                         dot.x += __shfl_xor(dot.x, o, 64);
@@ -910,8 +1014,8 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
                     v = csub(v, cmul(f, pc));
                     double q = act ? cabs2(v) : 0.0;
                     for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
-                    if (act) Wl[(size_t)i * r + c] = v;
-                    if (live && c == 0) wn[i] = q;
+                    if (act) Wl[(size_t)i * r + cl] = v;
+                    if (live && cl == 0) wn[i] = q;
                 }
             }
             __syncthreads();
@@ -919,62 +1023,15 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         if (threadIdx.x == 0) it.mv_full += 1;
     }
     PHASE_MARK(2);
-    // ---- 2. inverse of Y[piv] by Gauss-Jordan with partial pivoting
-    for (int e = threadIdx.x; e < r * r; e += nthr) {
-        const int a = e / r, c = e % r;
-        Ag[e] = Y[(size_t)piv[a] * r + c];
-        Ai[e] = (a == c) ? cplx{1.0, 0.0} : cplx{0.0, 0.0};
-    }
-    __syncthreads();
-    for (int j = 0; j < r; ++j) {
-        if (threadIdx.x == 0) {
-            int p = j;
-            double best = cabs2(Ag[j * r + j]);
-            for (int a = j + 1; a < r; ++a) {
-                double v = cabs2(Ag[a * r + j]);
-                if (v > best) { best = v; p = a; }
-            }
-            shi[0] = p;
-        }
-        __syncthreads();
-        const int p = shi[0];
-        if (p != j)
-            for (int c = threadIdx.x; c < r; c += nthr) {
-                cplx t0 = Ag[j * r + c]; Ag[j * r + c] = Ag[p * r + c]; Ag[p * r + c] = t0;
-                cplx t1 = Ai[j * r + c]; Ai[j * r + c] = Ai[p * r + c]; Ai[p * r + c] = t1;
-            }
-        __syncthreads();
-        const cplx gjj = Ag[j * r + j];
-        const double gabs = cabs2(gjj);
-        const bool sing = !(gabs > 0.0 && gabs <= 1e300);
-        const cplx inv = sing ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, gjj);
-        if (sing && threadIdx.x == 0) it.mv_singular = 1;   // reported as a numerical failure
-        __syncthreads();
-        for (int c = threadIdx.x; c < r; c += nthr) {
-            Ag[j * r + c] = cmul(Ag[j * r + c], inv);
-            Ai[j * r + c] = cmul(Ai[j * r + c], inv);
-        }
-        __syncthreads();
-        for (int a = threadIdx.x; a < r; a += nthr) fcol[a] = Ag[a * r + j];
-        __syncthreads();
-        for (int e = threadIdx.x; e < r * r; e += nthr) {
-            const int a = e / r, c = e % r;
-            if (a == j) continue;
-            Ag[e] = csub(Ag[e], cmul(fcol[a], Ag[j * r + c]));
-            Ai[e] = csub(Ai[e], cmul(fcol[a], Ai[j * r + c]));
-        }
-        __syncthreads();
-    }
-    PHASE_MARK(3);
-    // ---- B = Y Ai and the first candidate: one row times four columns per task
-    ArgMax am = {-1.0, 0x7fffffff};
-    const long long tot = (long long)m * r;
+    // ---- 2. A^{-1} and the block's rows of B (in W, over the start's copy)
+    gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
+    PHASE_MARK(10);
+    cplx *Bc = W;
     {
         const int ncg = (r + 3) / 4;
-        const long long tasks = (long long)m * ncg;
-        for (long long q = threadIdx.x; q < tasks; q += nthr) {
-            const int i = (int)(q / ncg), c0 = 4 * (int)(q % ncg);
-            const cplx *y = Y + (size_t)i * r;
+        for (int q = threadIdx.x; q < Kc * ncg; q += nthr) {
+            const int g = q / ncg, c0 = 4 * (q % ncg);
+            const cplx *y = Y + (size_t)cand[g] * r;
             cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
             for (int l = 0; l < r; ++l) {
                 const cplx yl = y[l];
@@ -984,150 +1041,143 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (c0 + u < r) {
-                    B[(size_t)i * r + c0 + u] = acc[u];
-                    am = better(am, ArgMax{cabs2(acc[u]), i * r + c0 + u});
-                }
+                if (c0 + u < r) Bc[(size_t)g * r + c0 + u] = acc[u];
         }
     }
-    am = block_argmax(am, red);
-    // ---- 3. swaps. Rows whose largest |B_ij| exceeds 1 + delta (the candidates, at most
-    // Cmax, lowest row indices first) are kept in LDS; swaps are made among them and
-    // recorded (row i*, column j, w = B[i*,:] - e_j, b = B[i*,j]); one pass over all rows then
-    // applies the recorded rank-one updates B[i,:] -= B[i,j] / b * w in order, refreshes every
-    // row maximum and finds the next global candidate. A swap always involves the largest
-    // candidate entry, which exceeds 1 + delta, so each one grows |det Y[piv]|.
+    __syncthreads();
+    PHASE_MARK(3);
+    // ---- 3. swaps within the block, 4. A^{-1} of the final pivots
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
-    const int maxit = 4 * r + 16;
-    const int nw = nthr >> 6;
-    const int Cmax = min(256, (3 * cap / 4) / r);
-    const int recmax = min(64, (cap / 4) / r);
-    cplx *Cr = Abuf;                         // Cmax x r candidate rows
-    cplx *Rw = Abuf + 3 * cap / 4;           // recmax x r recorded update rows
-    int *cpos = reinterpret_cast<int *>(W);          // m: candidate position + 1, or 0
-    int *viol = cpos + m;                             // m: 1 if the row has |B_ij| > 1 + delta
-    __shared__ int cidx[256];
-    __shared__ int rec_j[64];
-    __shared__ cplx rec_b[64];
-    __shared__ cplx rec_bi[64];              // 1 / rec_b
-    __shared__ int wsum[17];
-    __shared__ cplx snap[256];
-    __shared__ int nstate[2];                // number of candidates, number of records
-    if (threadIdx.x == 0) { nstate[0] = 0; nstate[1] = 0; }
-    for (int i = threadIdx.x; i < m; i += nthr) cpos[i] = 0;
+    const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red);
+    if (swaps > 0) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
     __syncthreads();
-    // flush pass: a wave takes 64 / seg rows at a time (seg lanes per row, lane = column);
-    // candidate rows are written back from LDS, the others get the recorded updates; a
-    // ballot marks rows that still violate, each lane keeps its running argmax
-    auto flush = [&](void) -> ArgMax {
-        const int nrec = nstate[1];
-        const int rpw = 64 / seg, c = lane % seg, sub = lane / seg;
-        ArgMax best = {-1.0, 0x7fffffff};
-        for (int i0 = wave * rpw; i0 < m; i0 += nw * rpw) {
-            const int i = i0 + sub;
-            const bool act = i < m && c < r;
-            cplx val = act ? B[(size_t)i * r + c] : cplx{0.0, 0.0};
-            const int cp = (i < m) ? cpos[i] : 0;
-            if (cp > 0 && act) val = Cr[(cp - 1) * r + c];
-            for (int q = 0; q < nrec; ++q) {
-                const int src = sub * seg + rec_j[q];
-                const cplx vj = {__shfl(val.x, src, 64), __shfl(val.y, src, 64)};
-                if (cp == 0 && act) val = csub(val, cmul(cmul(vj, rec_bi[q]), Rw[q * r + c]));
-            }
-            if (act && (cp > 0 || nrec > 0)) B[(size_t)i * r + c] = val;
-            const double a2 = act ? cabs2(val) : -1.0;
-            const unsigned long long mask = __ballot(a2 > lim);
-            const unsigned long long mine = (seg == 64) ? mask : ((mask >> (sub * 32)) & 0xffffffffull);
-            if (c == 0 && i < m) viol[i] = mine != 0ull;
-            if (act) best = better(best, ArgMax{a2, i * r + c});
-        }
-        return block_argmax(best, red);
-    };
-    PHASE_MARK(4);
-    am = flush();
-    PHASE_MARK(5);
-    int swaps = 0;
-    while (am.v > lim && swaps < maxit) {
-        // (a) candidates: rows with row maximum above the limit, by increasing index
-        {
-            const int chunk = (m + nthr - 1) / nthr;
-            const int i0 = threadIdx.x * chunk, i1 = min(m, i0 + chunk);
-            int cnt = 0;
-            for (int i = i0; i < i1; ++i) cnt += viol[i];
-            int incl = cnt;                            // inclusive scan within the wave
-            for (int o = 1; o < 64; o <<= 1) {
-                const int v = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += v;
-            }
-            if (lane == 63) wsum[wave] = incl;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                int acc = 0;
-                for (int w = 0; w < nw; ++w) { const int t0 = wsum[w]; wsum[w] = acc; acc += t0; }
-                wsum[nw] = acc;
-            }
-            __syncthreads();
-            int pos = wsum[wave] + incl - cnt;
-            for (int i = i0; i < i1; ++i)
-                if (viol[i]) {
-                    if (pos < Cmax) {
-                        cidx[pos] = i;
-                        cpos[i] = pos + 1;
-                    }
-                    ++pos;
-                }
-            if (threadIdx.x == 0) { nstate[0] = min(wsum[nw], Cmax); nstate[1] = 0; }
-            __syncthreads();
-        }
-        const int nC = nstate[0];
-        for (int e = threadIdx.x; e < nC * r; e += nthr) Cr[e] = B[(size_t)cidx[e / r] * r + e % r];
-        __syncthreads();
-        // (b) swaps among the candidates, in LDS
-        int nrec = 0;
-        while (nrec < recmax && swaps < maxit) {
-            ArgMax a = {-1.0, 0x7fffffff};
-            for (int e = threadIdx.x; e < nC * r; e += nthr) a = better(a, ArgMax{cabs2(Cr[e]), e});
-            a = block_argmax(a, red);
-            if (!(a.v > lim)) break;
-            const int ci = a.i / r, cs = a.i % r;
-            for (int c = threadIdx.x; c < r; c += nthr) {
-                cplx w = Cr[ci * r + c];
-                if (c == cs) w.x -= 1.0;
-                Rw[nrec * r + c] = w;
-            }
-            if (threadIdx.x == 0) {
-                rec_j[nrec] = cs;
-                rec_b[nrec] = Cr[ci * r + cs];
-                rec_bi[nrec] = cdiv({1.0, 0.0}, Cr[ci * r + cs]);
-                piv[cs] = cidx[ci];
-            }
-            __syncthreads();
-            // column snapshot of the candidates, then the rank-one update
-            const cplx bq = rec_b[nrec];
-            for (int q = threadIdx.x; q < nC; q += nthr) snap[q] = cdiv(Cr[q * r + cs], bq);
-            __syncthreads();
-            for (int e = threadIdx.x; e < nC * r; e += nthr) {
-                const int q = e / r, c = e % r;
-                Cr[e] = csub(Cr[e], cmul(snap[q], Rw[nrec * r + c]));
-            }
-            __syncthreads();
-            ++nrec;
-            ++swaps;
-        }
-        if (threadIdx.x == 0) nstate[1] = nrec;
-        __syncthreads();
-        // (c) apply the records to every other row and find the next candidate
-        am = flush();
-        for (int q = threadIdx.x; q < nC; q += nthr) cpos[cidx[q]] = 0;
-        __syncthreads();
-    }
-    PHASE_MARK(6);
-    __syncthreads();
+    for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
     for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
     if (threadIdx.x == 0) {
         it.mv_iters += swaps;
-        // B = Y A^-1 (8 m r^2), one rank-one update per swap (8 m r)
-        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * (double)m * r * r + 8.0 * (double)m * r * swaps;
+        it.mv_viol = 0;
+        it.mv_dirty = 1;
+        // Bc (8 Kc r^2), one rank-one update of Bc per swap (8 Kc r), Gauss-Jordan (8 r^3 each)
+        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * Kc * (double)r * r + 8.0 * Kc * (double)r * swaps +
+                                       8.0 * (double)r * r * r * (swaps > 0 ? 2 : 1);
+    }
+    PHASE_MARK(6);
+}
+
+// Refinement round: the pivots and up to K - r rows that k_interp found violating (largest first)
+// form the block; swaps as in k_maxvol. Returns at once when no row violated.
+__global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax)
+{
+    extern __shared__ cplx Abuf[];
+    cplx *Ag = Abuf, *Ai = Abuf + rmax * rmax;
+    __shared__ cplx prow[TTFP_MAX_RANK];
+    __shared__ cplx fcol[TTFP_MAX_RANK];
+    __shared__ int piv[TTFP_MAX_RANK];
+    __shared__ int cand[MV_KMAX];
+    __shared__ cplx colv[MV_KMAX];
+    __shared__ ArgMax red[17];
+    __shared__ int shi[4];
+    __shared__ float shf[2];
+    const int item = blockIdx.x;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    if (!it.mv_viol) {
+        if (threadIdx.x == 0) it.mv_dirty = 0;
+        return;
+    }
+    const int m = s.rows, r = it.rsel, nthr = blockDim.x;
+    const cplx *Y = it.Y;
+    cplx *W = it.W;
+    const cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
+    PHASE_START;
+    for (int c = threadIdx.x; c < r; c += nthr) {
+        piv[c] = it.piv[c];
+        cand[c] = piv[c];
+    }
+    float vmax = 0.0f;
+    for (int i = threadIdx.x; i < m; i += nthr) vmax = fmaxf(vmax, it.keys[(size_t)i * 16]);
+    {
+        ArgMax a = {(double)vmax, 0};
+        a = block_argmax(a, red);
+        vmax = (float)a.v;
+    }
+    const int K = min(min(max(4 * r, 64), MV_KMAX), m);
+    // only rows that violated (a positive mark) are candidates
+    const int nv = select_largest(it.keys, 16, m, K - r, 1e-30f, vmax, cand + r, red, shi, shf);
+    const int Kc = r + nv;
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += nthr) it.keys[(size_t)i * 16] = 0.0f;   // for the next k_interp
+    // block rows: the pivots (rows of the identity) and the violating rows of B
+    cplx *Bc = W;
+    for (int e = threadIdx.x; e < Kc * r; e += nthr) {
+        const int q = e / r, c = e % r;
+        Bc[e] = q < r ? cplx{q == c ? 1.0 : 0.0, 0.0} : B[(size_t)cand[q] * r + c];
+    }
+    __syncthreads();
+    PHASE_MARK(4);
+    const double lim = (1.0 + it.delta) * (1.0 + it.delta);
+    const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red);
+    PHASE_MARK(5);
+    if (swaps > 0) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
+    __syncthreads();
+    PHASE_MARK(7);
+    if (swaps > 0) {
+        for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
+        for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
+    }
+    if (threadIdx.x == 0) {
+        it.mv_iters += swaps;
+        it.mv_viol = 0;
+        it.mv_dirty = swaps > 0;
+        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * Kc * (double)r * swaps + (swaps > 0 ? 8.0 * (double)r * r * r : 0.0);
+    }
+}
+
+// B = Y A^{-1} for every row: one row times four columns per thread, A^{-1} in LDS. Rows whose
+// largest |B_ij| exceeds 1 + delta are marked (largest squared modulus in the row's first key
+// slot) and the item is flagged for a refinement round. mode 1: only after a refinement that
+// moved a pivot.
+__global__ __launch_bounds__(256) void k_interp(Item *items, const int *active, int t, int dir, int mode)
+{
+    __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
+    const int item = blockIdx.y;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    if (mode == 1 && !it.mv_dirty) return;
+    const int r = it.rsel, m = s.rows;
+    const int ncg = (r + 3) / 4;
+    const long long tasks = (long long)m * ncg;
+    if ((long long)blockIdx.x * blockDim.x >= tasks) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_INTERP] += 8.0 * (double)m * r * r;
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ai[e] = it.Ai[e];
+    __syncthreads();
+    const long long task = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (task >= tasks) return;
+    const int row = (int)(task / ncg), c0 = 4 * (int)(task % ncg);
+    const cplx *y = it.Y + (size_t)row * r;
+    cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int l = 0; l < r; ++l) {
+        const cplx yl = y[l];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c0 + u < r) acc[u] = cadd(acc[u], cmul(yl, Ai[l * r + c0 + u]));
+    }
+    cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
+    double mx = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (c0 + u < r) {
+            B[(size_t)row * r + c0 + u] = acc[u];
+            mx = fmax(mx, cabs2(acc[u]));
+        }
+    const double lim = (1.0 + it.delta) * (1.0 + it.delta);
+    if (mx > lim && mx <= 1e300) {
+        atomicMax(reinterpret_cast<unsigned int *>(it.keys + (size_t)row * 16), __float_as_uint((float)mx));
+        it.mv_viol = 1;
     }
 }
 
