@@ -771,8 +771,11 @@ int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
                 return rc;
             }
         }
-        // chunk options so that one chunk's workspace stays below a cap
-        const size_t cap_bytes = (size_t)24 << 30;
+        // chunk options so that one chunk's workspace fits in 70% of the device memory that is
+        // free or already held by this context's workspace (at least 4 GiB)
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)24 << 30;
+        const size_t cap_bytes = std::max((size_t)4 << 30, (size_t)(0.7 * (double)(free_b + ctx->arena_bytes)));
         int worst = TTFP_OK;
         size_t greek_off = 0;
         int o0 = 0;

@@ -677,6 +677,21 @@ __device__ int select_largest(const float *v, int stride, int n, int K, float lo
     const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (threadIdx.x == 0) { shf[0] = lo0; shf[1] = fmaxf(vmax, lo0); }
+    {
+        // when at most K values reach lo0, all of them are taken and no bisection is needed
+        int cnt = 0;
+        for (int g = threadIdx.x; g < n; g += nthr) cnt += v[(size_t)g * stride] >= lo0;
+        double a = (double)cnt;
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        __syncthreads();
+        if (lane == 0) red[wave].v = a;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < (nthr >> 6); ++w) tot += red[w].v;
+            if (tot <= K) shf[1] = lo0;        // collapses the bisection interval
+        }
+    }
     __syncthreads();
     for (int it2 = 0; it2 < 40; ++it2) {
         const float lo = shf[0], hi = shf[1], mid = 0.5f * (lo + hi);
@@ -812,6 +827,43 @@ __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, do
     return swaps;
 }
 
+// Start of maxvol by Gaussian elimination with partial pivoting on a block S (n x r, global
+// memory, row g of S is row rowmap[g] of Y, or row g when rowmap is null). chosen[n] flags the
+// rows taken (cleared by the caller). Stops at the first column whose largest remaining entry
+// has squared modulus <= ptol2 and returns its index; returns r when all r pivots were found.
+__device__ int lu_start(cplx *S, int n, int r, const int *rowmap, int *chosen, int *piv, double ptol2, cplx *prow,
+                        ArgMax *red, int *shi)
+{
+    const int nthr = blockDim.x;
+    for (int j = 0; j < r; ++j) {
+        ArgMax a = {-1.0, 0x7fffffff};
+        for (int g = threadIdx.x; g < n; g += nthr)
+            if (!chosen[g]) {
+                const double v = cabs2(S[(size_t)g * r + j]);
+                a = better(a, ArgMax{v <= 1e300 ? v : -1.0, g});
+            }
+        a = block_argmax(a, red);
+        if (!(a.v > ptol2) || a.i < 0 || a.i >= n) return j;      // same decision in every thread
+        const int p = a.i;
+        const cplx pinv = cdiv({1.0, 0.0}, S[(size_t)p * r + j]);
+        for (int c = j + 1 + threadIdx.x; c < r; c += nthr) prow[c] = cmul(S[(size_t)p * r + c], pinv);
+        if (threadIdx.x == 0) {
+            chosen[p] = 1;
+            piv[j] = rowmap ? rowmap[p] : p;
+        }
+        __syncthreads();
+        const int w = r - j - 1;
+        if (w > 0)
+            for (long long e = threadIdx.x; e < (long long)n * w; e += nthr) {
+                const int g = (int)(e / w), c = j + 1 + (int)(e % w);
+                if (chosen[g]) continue;
+                S[(size_t)g * r + c] = csub(S[(size_t)g * r + c], cmul(S[(size_t)g * r + j], prow[c]));
+            }
+        __syncthreads();
+    }
+    return r;
+}
+
 // Abuf is dynamic LDS of 2 rmax^2 complex entries (rmax: the largest rank of the launch): the
 // key buffer of the start and the two r x r blocks of the Gauss-Jordan inverse.
 __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax)
@@ -825,8 +877,6 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     __shared__ int cand[MV_KMAX];
     __shared__ int chosen[MV_KMAX];
     __shared__ cplx colv[MV_KMAX];
-    __shared__ double rn[MV_KMAX];
-    __shared__ double qn[1];
     __shared__ ArgMax red[17];
     __shared__ int shi[4];
     __shared__ float shf[2];
@@ -895,133 +945,76 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     }
     __syncthreads();
     PHASE_MARK(1);
-    // ---- 1c. greedy volume start on the block S = Y[cand] (a copy in W): row j of the start
-    // is the candidate whose component orthogonal to the rows already taken is largest. A
-    // residual below 1e-6 of the largest row norm means the block is numerically rank deficient
+    // ---- 1c. start: elimination with partial pivoting on the block S = Y[cand] (a copy in W).
+    // A pivot below 1e-6 of the largest row norm means the block is numerically rank deficient
     // (this happens when many integrand values underflow to zero and the largest rows share
-    // their support): the start is then taken the same way over all m rows (1d).
+    // their support); the start is then taken on the 2048 largest rows, and failing that on
+    // all m rows (row flags and the larger block's row list live in the output B, which only
+    // k_interp writes).
     const double ptol2 = 1e-12 * (double)kmax;
-    const int seg = r <= 32 ? 32 : 64, rpw = 64 / seg, cl = lane % seg, sub = lane / seg;
-    const int nwv = nthr >> 6;
     cplx *S = W;
-    for (int g0 = wave * rpw; g0 < Kc; g0 += nwv * rpw) {
-        const int g = g0 + sub;
-        const bool act = g < Kc && cl < r;
-        const cplx v = act ? Y[(size_t)cand[g] * r + cl] : cplx{0.0, 0.0};
-        if (act) S[(size_t)g * r + cl] = v;
-        double q = cabs2(v);
-        for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
-        if (g < Kc && cl == 0) rn[g] = q;
-    }
+    for (long long e = threadIdx.x; e < (long long)Kc * r; e += nthr)
+        S[e] = Y[(size_t)cand[e / r] * r + e % r];
     __syncthreads();
-    for (int j = 0; j < r; ++j) {
-        if (wave == 0) {
-            ArgMax am = {-1.0, 0x7fffffff};
-            for (int g = lane; g < Kc; g += 64)
-                if (!chosen[g]) am = better(am, ArgMax{rn[g], g});
-            for (int o = 32; o > 0; o >>= 1) {
-                ArgMax b2;
-                b2.v = __shfl_xor(am.v, o, 64);
-                b2.i = __shfl_xor(am.i, o, 64);
-                am = better(am, b2);
-            }
-            if (lane == 0) {
-                const bool ok = am.i >= 0 && am.i < Kc && am.v > ptol2 && am.v <= 1e300;
-                shi[0] = ok ? am.i : -1;
-                if (ok) {
-                    chosen[am.i] = 1;
-                    piv[j] = cand[am.i];
-                    qn[0] = am.v;
+    int nf = lu_start(S, Kc, r, cand, chosen, piv, ptol2, prow, red, shi);
+    if (nf < r) {
+        int *flag = reinterpret_cast<int *>(B);
+        int *rows2 = flag + m;
+        const int K2 = min(min(2048, m), nk);
+        int n2 = m;
+        const int *map = nullptr;
+        if (K2 < m) {
+            // group keys are still in Abuf: the K2 largest groups, resolved to rows
+            int *grp = rows2;
+            n2 = select_largest(key, 1, nk, K2, 0.0f, kmax, grp, red, shi, shf);
+            for (int q = threadIdx.x; q < n2; q += nthr) {
+                const int g = grp[q];
+                int bi = g * gsz;
+                double best = -1.0;
+                for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
+                    const cplx *y = Y + (size_t)i * r;
+                    double v = 0.0;
+                    for (int c = 0; c < r; ++c) v += cabs2(y[c]);
+                    if (v > best) { best = v; bi = i; }
                 }
+                grp[q] = bi;
             }
-        }
-        __syncthreads();
-        const int p = shi[0];
-        if (p < 0) break;                       // uniform: every thread read the same flag
-        if (j + 1 < r) {
-            const double inv = 1.0 / qn[0];
-            const cplx pc = cl < r ? S[(size_t)p * r + cl] : cplx{0.0, 0.0};
-            for (int g0 = wave * rpw; g0 < Kc; g0 += nwv * rpw) {
-                const int g = g0 + sub;
-                const bool live = g < Kc && !chosen[g];
-                const bool act = live && cl < r;
-                cplx v = act ? S[(size_t)g * r + cl] : cplx{0.0, 0.0};
-                cplx dot = cmulc(pc, v);
-                for (int o = seg >> 1; o > 0; o >>= 1) {
-                    dot.x += __shfl_xor(dot.x, o, 64);
-                    dot.y += __shfl_xor(dot.y, o, 64);
-                }
-                const cplx f = {dot.x * inv, dot.y * inv};
-                v = csub(v, cmul(f, pc));
-                double q = act ? cabs2(v) : 0.0;
-                for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
-                if (act) S[(size_t)g * r + cl] = v;
-                if (live && cl == 0) rn[g] = q;
-            }
-        }
-        __syncthreads();
-    }
-    // ---- 1d. fallback: the same greedy selection over every row of Y, on a copy held in W;
-    // residual norms and row flags live in the output B, written only by k_interp
-    if (shi[0] < 0) {
-        cplx *Wl = W;
-        double *wn = reinterpret_cast<double *>(B);
-        int *taken = reinterpret_cast<int *>(wn + m);
-        for (int i0 = wave * rpw; i0 < m; i0 += nwv * rpw) {
-            const int i = i0 + sub;
-            const bool act = i < m && cl < r;
-            const cplx v = act ? Y[(size_t)i * r + cl] : cplx{0.0, 0.0};
-            if (act) Wl[(size_t)i * r + cl] = v;
-            double q = cabs2(v);
-            for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
-            if (cl == 0 && i < m) {
-                wn[i] = q;
-                taken[i] = 0;
-            }
-        }
-        __syncthreads();
-        for (int j = 0; j < r; ++j) {
-            ArgMax a = {-1.0, 0x7fffffff};
-            for (int i = threadIdx.x; i < m; i += nthr)
-                if (!taken[i]) {
-                    const double v = wn[i];
-                    a = better(a, ArgMax{v <= 1e300 ? v : -0.5, i});     // non-finite ranks last
-                }
-            a = block_argmax(a, red);
-            int p = a.i;
-            if (p < 0 || p >= m) p = 0;        // unreachable: j < r <= m rows remain untaken
-            const double pn = (a.v > 0.0 && a.v <= 1e300) ? a.v : 0.0;
-            if (threadIdx.x == 0) {
-                taken[p] = 1;
-                piv[j] = p;
-            }
-            for (int cc = threadIdx.x; cc < r; cc += nthr) prow[cc] = Wl[(size_t)p * r + cc];
             __syncthreads();
-            if (j + 1 < r && pn > 0.0) {
-                const double inv = 1.0 / pn;
-                for (int i0 = wave * rpw; i0 < m; i0 += nwv * rpw) {
-                    const int i = i0 + sub;
-                    const bool live = i < m && !taken[i];
-                    const bool act = live && cl < r;
-                    cplx v = act ? Wl[(size_t)i * r + cl] : cplx{0.0, 0.0};
-                    const cplx pc = cl < r ? prow[cl] : cplx{0.0, 0.0};
-                    cplx dot = cmulc(pc, v);
-                    for (int o = seg >> 1; o > 0; o >>= 1) {
-                        dot.x += __shfl_xor(dot.x, o, 64);
-                        dot.y += __shfl_xor(dot.y, o, 64);
+            map = rows2;
+        }
+        for (int pass = 0; pass < 2 && nf < r; ++pass) {
+            if (pass == 0 && n2 == m) continue;        // the larger block is all rows already
+            const int nn = pass == 0 ? n2 : m;
+            const int *mp = pass == 0 ? map : nullptr;
+            for (long long e = threadIdx.x; e < (long long)nn * r; e += nthr) {
+                const int g = (int)(e / r);
+                S[e] = Y[(size_t)(mp ? mp[g] : g) * r + e % r];
+            }
+            for (int g = threadIdx.x; g < nn; g += nthr) flag[g] = 0;
+            __syncthreads();
+            nf = lu_start(S, nn, r, mp, flag, piv, pass == 0 ? ptol2 : 0.0, prow, red, shi);
+        }
+        if (nf < r) {
+            // Y itself is rank deficient: the remaining pivots are the lowest untaken rows
+            if (threadIdx.x == 0) {
+                int next = 0;
+                for (int j = nf; j < r; ++j) {
+                    bool used = true;
+                    while (used && next < m) {
+                        used = false;
+                        for (int q = 0; q < j; ++q) used |= piv[q] == next;
+                        if (used) ++next;
                     }
-                    const cplx f = {dot.x * inv, dot.y * inv};
-                    v = csub(v, cmul(f, pc));
-                    double q = act ? cabs2(v) : 0.0;
-                    for (int o = seg >> 1; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
-                    if (act) Wl[(size_t)i * r + cl] = v;
-                    if (live && cl == 0) wn[i] = q;
+                    piv[j] = min(next, m - 1);
+                    ++next;
                 }
+                it.mv_singular = 1;
             }
             __syncthreads();
         }
         if (threadIdx.x == 0) it.mv_full += 1;
     }
+    __syncthreads();
     PHASE_MARK(2);
     // ---- 2. A^{-1} and the block's rows of B (in W, over the start's copy)
     gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
