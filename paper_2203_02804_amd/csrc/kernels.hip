@@ -336,58 +336,133 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 }
 
 // ------------------------------------------------------------------ Householder R in LDS
-// Triangularises A (nr x nc, column-major in LDS with leading dimension nr, nr <= 512) by
-// Householder reflections H = I - tau w w^H (make_reflector). On exit row j of R is
-// (alph[j], A[j, j+1..nc-1]).
-// Column-major storage makes the lanes of a wave read consecutive 16-byte elements.
-constexpr int TSQR_MAX_ROWS = 512;
+// Triangularises A (nr x nc, row-major in LDS with an odd row stride ncp, so that both a row
+// and a column spread over the LDS banks) by Householder reflections H = I - tau w w^H, in
+// panels of TSQR_NB columns. Within a panel each reflector is formed by wave 0 and applied to
+// the panel's later columns by one wave per column; the trailing columns then take the
+// panel's reflectors one after another, each column owned by a group of S adjacent lanes that
+// splits the rows, so a dot product needs an S-lane butterfly only.
+// tri > 0: A stacks tri upper-triangular nc x nc factors (a merge of the reduction tree); the
+// reflector of column j then touches only row j of the first factor and rows 0..j of the
+// others, and only those rows are visited. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
 constexpr int TSQR_THREADS = 256;
+constexpr int TSQR_NB = 4;
 
-__device__ void householder_lds(cplx *A, int nr, int nc, cplx *alph, double *sh)
+__device__ __forceinline__ int hh_len(int j, int nr, int nc, int tri) { return tri ? 1 + (tri - 1) * (j + 1) : nr - j; }
+__device__ __forceinline__ int hh_row(int k, int j, int nc, int tri)
+{
+    if (!tri) return j + k;
+    if (k == 0) return j;
+    const int q = (k - 1) / (j + 1);
+    return nc * (1 + q) + (k - 1 - q * (j + 1));
+}
+
+// reflector of column j over its support rows (wave 0 of the workgroup); see make_reflector
+__device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, int tri, cplx *alpha_out, double *tau_out)
+{
+    const int lane = threadIdx.x & 63;
+    double mx = 0.0;
+    for (int k = lane; k < len; k += 64) {
+        const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
+        mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+    }
+    mx = wave_max(mx);
+    if (!(mx >= 1e-280) || !(mx <= 1e300)) {
+        if (lane == 0) {
+            *alpha_out = A[(size_t)j * ncp + j];
+            *tau_out = 0.0;
+        }
+        return;
+    }
+    const double inv = 1.0 / mx;
+    double sq = 0.0;
+    for (int k = 1 + lane; k < len; k += 64) {
+        const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
+        sq += cabs2(cplx{v.x * inv, v.y * inv});
+    }
+    sq = wave_sum(sq);
+    const cplx x0 = A[(size_t)j * ncp + j];
+    const cplx x0s = {x0.x * inv, x0.y * inv};
+    const double a0 = hypot(x0s.x, x0s.y);
+    const double nrm = sqrt(sq + a0 * a0);
+    const cplx ph = a0 > 1e-300 ? cplx{x0s.x / a0, x0s.y / a0} : cplx{1.0, 0.0};
+    const double den = 1.0 / (a0 + nrm);
+    const cplx cf = {ph.x * den * inv, -ph.y * den * inv};
+    for (int k = 1 + lane; k < len; k += 64) {
+        cplx *p = A + (size_t)hh_row(k, j, nc, tri) * ncp + j;
+        *p = cmul(*p, cf);
+    }
+    if (lane == 0) {
+        A[(size_t)j * ncp + j] = {1.0, 0.0};
+        *alpha_out = {-ph.x * nrm * mx, -ph.y * nrm * mx};
+        *tau_out = (a0 + nrm) / nrm;
+    }
+}
+
+__device__ void householder_lds(cplx *A, int nr, int nc, int ncp, int tri, cplx *alph, double *tau)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int jmax = nr < nc ? nr : nc;
-    for (int j = 0; j < jmax; ++j) {
-        cplx *vj = A + (size_t)j * nr;
-        if (wave == 0) make_reflector(vj, 1, j, nr, &alph[j], &sh[0]);
-        __syncthreads();
-        const double beta = sh[0];
-        // this wave's trailing columns c = j + 1 + wave + u nw, four at a time: the partial dot
-        // products of a group are formed in one pass over the rows and reduced together
-        // (eight independent butterflies), then the group is updated in a second pass
-        if (beta != 0.0) {
-            const int ncw = (nc - (j + 1 + wave) + nw - 1) / nw;
-            for (int u0 = 0; u0 < ncw; u0 += 4) {
-                const int ng = min(4, ncw - u0);
-                cplx *ac[4];
-#pragma unroll
-                for (int g = 0; g < 4; ++g) ac[g] = A + (size_t)(j + 1 + wave + (u0 + min(g, ng - 1)) * nw) * nr;
-                double dr[4] = {0.0, 0.0, 0.0, 0.0}, di[4] = {0.0, 0.0, 0.0, 0.0};
-                for (int i = j + lane; i < nr; i += 64) {
-                    const cplx vi = vj[i];
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const cplx p = cmulc(vi, ac[g][i]);
-                        dr[g] += p.x;
-                        di[g] += p.y;
-                    }
+    for (int j0 = 0; j0 < jmax; j0 += TSQR_NB) {
+        const int jb = min(TSQR_NB, jmax - j0);
+        // ---- panel: reflectors of columns j0..j0+jb-1, each applied to the panel's later columns
+        for (int j = j0; j < j0 + jb; ++j) {
+            if (wave == 0) make_reflector_rows(A, ncp, j, hh_len(j, nr, nc, tri), nc, tri, &alph[j], &tau[j]);
+            __syncthreads();
+            const double tj = tau[j];
+            const int len = hh_len(j, nr, nc, tri);
+            for (int c = j + 1 + wave; c < j0 + jb && c < nc; c += nw) {
+                if (tj == 0.0) break;
+                double dr = 0.0, di = 0.0;
+                for (int k = lane; k < len; k += 64) {
+                    const int i = hh_row(k, j, nc, tri);
+                    const cplx p = cmulc(A[(size_t)i * ncp + j], A[(size_t)i * ncp + c]);
+                    dr += p.x;
+                    di += p.y;
                 }
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        dr[g] += __shfl_xor(dr[g], o, 64);
-                        di[g] += __shfl_xor(di[g], o, 64);
-                    }
+                dr = wave_sum(dr);
+                di = wave_sum(di);
+                const cplx f = {tj * dr, tj * di};
+                for (int k = lane; k < len; k += 64) {
+                    const int i = hh_row(k, j, nc, tri);
+                    A[(size_t)i * ncp + c] = csub(A[(size_t)i * ncp + c], cmul(f, A[(size_t)i * ncp + j]));
                 }
-                cplx f[4];
-#pragma unroll
-                for (int g = 0; g < 4; ++g) f[g] = {beta * dr[g], beta * di[g]};
-                for (int i = j + lane; i < nr; i += 64) {
-                    const cplx vi = vj[i];
-#pragma unroll
-                    for (int g = 0; g < 4; ++g)
-                        if (g < ng) ac[g][i] = csub(ac[g][i], cmul(f[g], vi));
+            }
+            __syncthreads();
+        }
+        // ---- trailing columns: the panel's reflectors in order, S lanes per column
+        const int c0 = j0 + jb, nt = nc - c0;
+        if (nt > 0) {
+            int S = 1;
+            while (S < 16 && 2 * S * nt <= (int)blockDim.x) S *= 2;
+            const int sidx = threadIdx.x % S, per = blockDim.x / S;
+            for (int cb = 0; cb < nt; cb += per) {
+                const int cl = cb + threadIdx.x / S;
+                const bool act = cl < nt;
+                const int c = c0 + (act ? cl : 0);
+                for (int j = j0; j < j0 + jb; ++j) {
+                    const double tj = tau[j];
+                    if (tj == 0.0) continue;                // same for every lane
+                    const int len = hh_len(j, nr, nc, tri);
+                    double dr = 0.0, di = 0.0;
+                    if (act)
+                        for (int k = sidx; k < len; k += S) {
+                            const int i = hh_row(k, j, nc, tri);
+                            const cplx w = A[(size_t)i * ncp + j];
+                            const cplx p = cmulc(w, A[(size_t)i * ncp + c]);
+                            dr += p.x;
+                            di += p.y;
+                        }
+                    for (int o = S >> 1; o > 0; o >>= 1) {
+                        dr += __shfl_xor(dr, o, 64);
+                        di += __shfl_xor(di, o, 64);
+                    }
+                    const cplx f = {tj * dr, tj * di};
+                    if (act)
+                        for (int k = sidx; k < len; k += S) {
+                            const int i = hh_row(k, j, nc, tri);
+                            A[(size_t)i * ncp + c] = csub(A[(size_t)i * ncp + c], cmul(f, A[(size_t)i * ncp + j]));
+                        }
                 }
             }
         }
@@ -415,7 +490,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
 {
     extern __shared__ cplx lds[];
     __shared__ cplx alph[MAXNC];
-    __shared__ double sh[4];
+    __shared__ double tau[MAXNC];
     const int item = blockIdx.y;
     if (!active[item]) return;
     Item &it = items[item];
@@ -431,8 +506,9 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
         it.work[TTFP_KERNEL_TSQR] += 8.0 * m * n * n - 8.0 / 3.0 * n * n * n;
     }
     const size_t rsz = (size_t)nc * nc;
+    const int ncp = nc | 1;                          // odd row stride in LDS
     cplx *A = lds;
-    int nr;
+    int nr, tri = 0;
     const cplx *src;
     if (level == 0) {
         const int r0 = blk * BR;
@@ -442,24 +518,25 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
         const int nprev = tsqr_count(s.rows, BR, G, level - 1);
         const int g0 = blk * G, g1 = min(nprev, g0 + G);
         nr = (g1 - g0) * nc;
+        tri = g1 - g0;                               // stacked triangular factors
         src = it.Rlev + (size_t)((level - 1) & 1) * it.nblk_max * rsz + (size_t)g0 * rsz;
     }
     PHASE_START;
-    // coalesced read of nr row-major rows, transposed into column-major LDS
+    // coalesced read of nr row-major rows into the padded row-major LDS block
     for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
         const int i = e / nc, c = e % nc;
-        A[(size_t)c * nr + i] = src[e];
+        A[(size_t)i * ncp + c] = src[e];
     }
     __syncthreads();
     PHASE_MARK(8);
-    householder_lds(A, nr, nc, alph, sh);
+    householder_lds(A, nr, nc, ncp, tri, alph, tau);
     PHASE_MARK(9);
     cplx *dst = it.Rlev + (size_t)(level & 1) * it.nblk_max * rsz + (size_t)blk * rsz;
     const int jmax = nr < nc ? nr : nc;
     for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) {
         int j = e / nc, c = e % nc;
         cplx v = {0.0, 0.0};
-        if (j < jmax && c >= j) v = (c == j) ? alph[j] : A[(size_t)c * nr + j];
+        if (j < jmax && c >= j) v = (c == j) ? alph[j] : A[(size_t)j * ncp + c];
         dst[e] = v;
     }
 }
