@@ -317,18 +317,23 @@ void prof_collect(ttfp_ctx *ctx)
     ctx->ev_open.clear();
 }
 
-// Threads per maxvol workgroup (one workgroup per item): the largest size whose resident
-// workgroups (at most 2048 threads and 160 KiB of LDS per CU, about 15 KiB of it static) hold
-// every item of the launch at once; 256 when no size does.
+// Threads per maxvol workgroup (one workgroup per item): the size that minimises the number of
+// rounds of resident workgroups (at most 2048 threads and 160 KiB of LDS per CU, about 15 KiB of
+// it static) divided by threads^0.7 (a workgroup's speed grows sublinearly with its size).
 int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
 {
     if (ctx->tune_maxvol_threads) return ctx->tune_maxvol_threads;
-    const long long by_lds = (long long)(160 * 1024) / (long long)(dyn_lds + 15 * 1024);
-    for (int t : {1024, 512}) {
+    const long long by_lds = std::max(1LL, (long long)(160 * 1024) / (long long)(dyn_lds + 15 * 1024));
+    int best = 1024;
+    double best_cost = 1e300;
+    for (int t : {1024, 512, 256}) {
         const long long per_cu = std::min<long long>(2048 / t, by_lds);
-        if ((long long)n_items <= per_cu * ctx->n_cu) return t;
+        const long long slots = per_cu * std::max(ctx->n_cu, 1);
+        const double rounds = (double)((n_items + slots - 1) / slots);
+        const double cost = rounds / std::pow((double)t, 0.7);
+        if (cost < best_cost * (1.0 - 1e-9)) { best_cost = cost; best = t; }
     }
-    return 256;
+    return best;
 }
 
 // Refinement rounds of maxvol after its first pass over the candidate block.
