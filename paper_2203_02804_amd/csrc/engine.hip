@@ -354,7 +354,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
         int n = (g.maxrows + g.BR - 1) / g.BR;
         const size_t lds = tsqr_lds_bytes(g.BR, g.maxnc);
         for (int level = 0; level < g.nlev; ++level) {
-            hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(n, 1), ny), dim3(256), lds, st, it, act, t, dir, level, g.BR, g.G);
+            hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(n, 1), ny), dim3(TSQR_THREADS), lds, st, it, act, t, dir, level, g.BR, g.G);
             n = (n + g.G - 1) / g.G;
         }
     }
@@ -550,7 +550,8 @@ done:
             OptResult &r = res[o];
             r.kappa = mass[o] / std::max(std::fabs(r.price), 1e-300);
             r.code = (r.converged && !r.capped) ? TTFP_OK : TTFP_ENOTCONV;
-            if (r.code == TTFP_OK && r.kappa * 2.220446049250313e-16 > grids[o]->tol) r.code = TTFP_EPRECISION;
+            // cancellation beyond the tolerance makes the price meaningless, converged or not
+            if (r.kappa * 2.220446049250313e-16 > grids[o]->tol) r.code = TTFP_EPRECISION;
             if (r.singular || !std::isfinite(r.price)) r.code = TTFP_EPRECISION;
         }
     }
@@ -1050,7 +1051,7 @@ int ttfp_qr_r(ttfp_ctx *ctx, int32_t m, int32_t n, const double *A, double *R)
     const int nlev = tsqr_levels(m, BR, G);
     int nb = (m + BR - 1) / BR;
     for (int level = 0; !e && level < nlev; ++level) {
-        hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(nb, 1), 1), dim3(256), tsqr_lds_bytes(BR, std::max(n, 4)), ctx->stream, dit, act, 0, 2,
+        hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(nb, 1), 1), dim3(TSQR_THREADS), tsqr_lds_bytes(BR, std::max(n, 4)), ctx->stream, dit, act, 0, 2,
                            level, BR, G);
         e = hipGetLastError();
         nb = (nb + G - 1) / G;

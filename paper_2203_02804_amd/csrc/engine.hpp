@@ -16,6 +16,7 @@ constexpr int MAXD = TTFP_MAX_D;
 constexpr int MAXNC = TTFP_MAX_RANK + 4;     // fiber columns: rank + enrichment
 constexpr int MAXN = 1024;                   // nodes per coordinate
 constexpr int LDS_BYTES = 152 * 1024;        // per-workgroup LDS budget of the QR kernels
+constexpr int TSQR_THREADS = 512;            // threads of a TSQR workgroup
 
 struct cplx { double x, y; };
 

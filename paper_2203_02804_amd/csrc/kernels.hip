@@ -345,7 +345,6 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 // tri > 0: A stacks tri upper-triangular nc x nc factors (a merge of the reduction tree); the
 // reflector of column j then touches only row j of the first factor and rows 0..j of the
 // others, and only those rows are visited. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
-constexpr int TSQR_THREADS = 256;
 constexpr int TSQR_NB = 4;
 
 __device__ __forceinline__ int hh_len(int j, int nr, int nc, int tri) { return tri ? 1 + (tri - 1) * (j + 1) : nr - j; }
