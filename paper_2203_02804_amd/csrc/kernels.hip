@@ -1204,11 +1204,17 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
     }
 }
 
-// B = Y A^{-1} for every row: one row times four columns per thread, A^{-1} in LDS. Rows whose
-// largest |B_ij| exceeds 1 + delta are marked (largest squared modulus in the row's first key
-// slot) and the item is flagged for a refinement round. mode 1: only after a refinement that
-// moved a pivot.
-__global__ __launch_bounds__(256) void k_interp(Item *items, const int *active, int t, int dir, int mode)
+// B = Y A^{-1} for every row on the FP64 matrix cores: a wave forms a 16-row panel of B (all r
+// columns, as up to four 16 x 16 tiles) with v_mfma_f64_16x16x4f64, the complex product as four
+// real ones (re = Yr Ar - Yi Ai, im = Yr Ai + Yi Ar); A^{-1} is held in LDS. Lane l supplies
+// A-operand entry (row l % 16, k l / 16) and B-operand entry (k l / 16, column l % 16), and holds
+// accumulator rows l / 16 + 4 v, column l % 16 (v = 0..3; the layout was checked by a probe
+// against a host product). Rows whose largest |B_ij| exceeds 1 + delta
+// are marked (largest squared modulus in the row's first key slot) and the item is flagged
+// for a refinement round. mode 1: only after a refinement that moved a pivot.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+constexpr int INTERP_WAVES = 4;                  // 16-row panels per workgroup
+__global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const int *active, int t, int dir, int mode)
 {
     __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
     const int item = blockIdx.y;
@@ -1218,35 +1224,60 @@ __global__ __launch_bounds__(256) void k_interp(Item *items, const int *active, 
     if (!s.valid) return;
     if (mode == 1 && !it.mv_dirty) return;
     const int r = it.rsel, m = s.rows;
-    const int ncg = (r + 3) / 4;
-    const long long tasks = (long long)m * ncg;
-    if ((long long)blockIdx.x * blockDim.x >= tasks) return;
+    const int rows_per_wg = 16 * INTERP_WAVES;
+    if (blockIdx.x * rows_per_wg >= m) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_INTERP] += 8.0 * (double)m * r * r;
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ai[e] = it.Ai[e];
     __syncthreads();
-    const long long task = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (task >= tasks) return;
-    const int row = (int)(task / ncg), c0 = 4 * (int)(task % ncg);
-    const cplx *y = it.Y + (size_t)row * r;
-    cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    for (int l = 0; l < r; ++l) {
-        const cplx yl = y[l];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * rows_per_wg + wave * 16;
+    if (row0 >= m) return;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ntile = (r + 15) / 16;
+    const cplx *Y = it.Y;
+    double4_t cre[4], cim[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (c0 + u < r) acc[u] = cadd(acc[u], cmul(yl, Ai[l * r + c0 + u]));
+    for (int q = 0; q < 4; ++q) {
+        cre[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        cim[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
+    const int arow = row0 + li;
+    for (int k0 = 0; k0 < r; k0 += 4) {
+        const int kk = k0 + lk;
+        const cplx a = (arow < m && kk < r) ? Y[(size_t)arow * r + kk] : cplx{0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= ntile) break;
+            const int jj = 16 * q + li;
+            const cplx b = (kk < r && jj < r) ? Ai[kk * r + jj] : cplx{0.0, 0.0};
+            cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cre[q], 0, 0, 0);
+            cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cre[q], 0, 0, 0);
+            cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, cim[q], 0, 0, 0);
+            cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim[q], 0, 0, 0);
+        }
     }
     cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
-    double mx = 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (c0 + u < r) {
-            B[(size_t)row * r + c0 + u] = acc[u];
-            mx = fmax(mx, cabs2(acc[u]));
-        }
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
-    if (mx > lim && mx <= 1e300) {
-        atomicMax(reinterpret_cast<unsigned int *>(it.keys + (size_t)row * 16), __float_as_uint((float)mx));
-        it.mv_viol = 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = row0 + lk + 4 * v;
+        double mx = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= ntile) break;
+            const int col = 16 * q + li;
+            if (row < m && col < r) {
+                const cplx val = {cre[q][v], cim[q][v]};
+                B[(size_t)row * r + col] = val;
+                mx = fmax(mx, cabs2(val));
+            }
+        }
+        // largest entry of the row over the 16 lanes that hold its columns
+        for (int o = 8; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if (li == 0 && row < m && mx > lim && mx <= 1e300) {
+            atomicMax(reinterpret_cast<unsigned int *>(it.keys + (size_t)row * 16), __float_as_uint((float)mx));
+            it.mv_viol = 1;
+        }
     }
 }
 
