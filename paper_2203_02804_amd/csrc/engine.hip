@@ -364,7 +364,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_BASIS);
-        hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows * ((g.maxR + 3) / 4), 256), ny), dim3(256), 0, st, it, act, t, dir);
+        hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows, 64), ny), dim3(256), 0, st, it, act, t, dir);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);

@@ -651,9 +651,13 @@ __global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, in
 }
 
 // ------------------------------------------------------------------ basis of the kept columns
-// Y = F[:, perm[:r]] R2^{-1}: each thread forms one row times four columns of the triangular
-// inverse (held in LDS), reading each fiber entry once for four outputs.
-__global__ __launch_bounds__(256) void k_basis(Item *items, const int *active, int t, int dir)
+// Y = F[:, perm[:r]] R2^{-1} on the FP64 matrix cores, laid out as in k_interp (a wave forms a
+// 16-row panel as up to four 16 x 16 complex tiles, four real MFMA products each); the
+// triangular inverse is held in LDS with its zero lower part. Each row's squared norm is left
+// in four-column partial sums in its key slots (the start of maxvol reads them).
+typedef double double4_t __attribute__((ext_vector_type(4)));
+constexpr int PANEL_WAVES = 4;                   // 16-row panels per workgroup
+__global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const int *active, int t, int dir)
 {
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
     __shared__ int pm[TTFP_MAX_RANK];
@@ -662,35 +666,55 @@ __global__ __launch_bounds__(256) void k_basis(Item *items, const int *active, i
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
-    const int r = it.rsel, nc = s.nc;
-    const int ncg = (r + 3) / 4;
-    const long long tasks = (long long)s.rows * ncg;
-    if ((long long)blockIdx.x * blockDim.x >= tasks) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_BASIS] += 4.0 * (double)s.rows * r * r;
+    const int r = it.rsel, nc = s.nc, m = s.rows;
+    const int rows_per_wg = 16 * PANEL_WAVES;
+    if (blockIdx.x * rows_per_wg >= m) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_BASIS] += 4.0 * (double)m * r * r;
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ri[e] = it.Rinv[e];
     for (int e = threadIdx.x; e < r; e += blockDim.x) pm[e] = it.perm[e];
     __syncthreads();
-    const long long task = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (task >= tasks) return;
-    const int row = (int)(task / ncg), c0 = 4 * (int)(task % ncg);
-    const cplx *f = it.F + (size_t)row * nc;
-    cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    const int lend = min(c0 + 3, r - 1);
-    for (int l = 0; l <= lend; ++l) {
-        const cplx fl = f[pm[l]];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * rows_per_wg + wave * 16;
+    if (row0 >= m) return;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ntile = (r + 15) / 16;
+    double4_t cre[4], cim[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (c0 + u < r && l <= c0 + u) acc[u] = cadd(acc[u], cmul(fl, Ri[l * r + c0 + u]));
+    for (int q = 0; q < 4; ++q) {
+        cre[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        cim[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
-    cplx *y = it.Y + (size_t)row * r;
-    double nrm = 0.0;
+    const int arow = row0 + li;
+    for (int k0 = 0; k0 < r; k0 += 4) {
+        const int kk = k0 + lk;
+        const cplx a = (arow < m && kk < r) ? it.F[(size_t)arow * nc + pm[kk]] : cplx{0.0, 0.0};
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (c0 + u < r) {
-            y[c0 + u] = acc[u];
-            nrm += cabs2(acc[u]);
+        for (int q = 0; q < 4; ++q) {
+            if (q >= ntile) break;
+            const int jj = 16 * q + li;
+            const cplx b = (kk < r && jj < r) ? Ri[kk * r + jj] : cplx{0.0, 0.0};
+            cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cre[q], 0, 0, 0);
+            cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cre[q], 0, 0, 0);
+            cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, cim[q], 0, 0, 0);
+            cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim[q], 0, 0, 0);
         }
-    it.keys[(size_t)row * 16 + c0 / 4] = (float)nrm;   // partial squared norm of the row
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = row0 + lk + 4 * v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= ntile) break;
+            const int col = 16 * q + li;
+            const cplx val = {cre[q][v], cim[q][v]};
+            double nrm = (row < m && col < r) ? cabs2(val) : 0.0;
+            if (row < m && col < r) it.Y[(size_t)row * r + col] = val;
+            // partial squared norm over the four columns 4 (col / 4) .. 4 (col / 4) + 3
+            nrm += __shfl_xor(nrm, 1, 64);
+            nrm += __shfl_xor(nrm, 2, 64);
+            if (row < m && (li & 3) == 0 && col < r) it.keys[(size_t)row * 16 + col / 4] = (float)nrm;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ maxvol
@@ -1212,7 +1236,6 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
 // against a host product). Rows whose largest |B_ij| exceeds 1 + delta
 // are marked (largest squared modulus in the row's first key slot) and the item is flagged
 // for a refinement round. mode 1: only after a refinement that moved a pivot.
-typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int INTERP_WAVES = 4;                  // 16-row panels per workgroup
 __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const int *active, int t, int dir, int mode)
 {
