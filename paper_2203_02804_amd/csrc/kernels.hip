@@ -56,17 +56,47 @@ __device__ __forceinline__ cplx cexp_(cplx a)
 #define PHASE_START do {} while (0)
 #endif
 
+// Cross-lane moves by DPP (row-local permutations that run at VALU speed, unlike the LDS-routed
+// ds_bpermute of a generic shuffle). CTRL: 0xB1 quad_perm [1,0,3,2] (lane ^ 1), 0x4E quad_perm
+// [2,3,0,1] (lane ^ 2), 0x141 row_half_mirror (lane 7 - i within 8), 0x140 row_mirror (lane
+// 15 - i within 16). After the four steps every lane of a row of 16 holds the row's sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// sum over each group of S adjacent lanes (S = 1, 2, 4, 8, 16), left in every lane of the group
+__device__ __forceinline__ double seg_sum(double v, int S)
+{
+    if (S >= 2) v += dpp_move<0xB1>(v);
+    if (S >= 4) v += dpp_move<0x4E>(v);
+    if (S >= 8) v += dpp_move<0x141>(v);
+    if (S >= 16) v += dpp_move<0x140>(v);
+    return v;
+}
+// sum / max over the 64 lanes of a wave (all lanes active), returned in every lane
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v = seg_sum(v, 16);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp_move<0xB1>(v));
+    v = fmax(v, dpp_move<0x4E>(v));
+    v = fmax(v, dpp_move<0x141>(v));
+    v = fmax(v, dpp_move<0x140>(v));
+    return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
 
 // Householder reflector for the column x = (x_j, ..., x_{n-1}) (entry i at x[i * stride]), made by
@@ -452,10 +482,8 @@ __device__ void householder_lds(cplx *A, int nr, int nc, int ncp, int tri, cplx 
                             dr += p.x;
                             di += p.y;
                         }
-                    for (int o = S >> 1; o > 0; o >>= 1) {
-                        dr += __shfl_xor(dr, o, 64);
-                        di += __shfl_xor(di, o, 64);
-                    }
+                    dr = seg_sum(dr, S);
+                    di = seg_sum(di, S);
                     const cplx f = {tj * dr, tj * di};
                     if (act)
                         for (int k = sidx; k < len; k += S) {
