@@ -754,26 +754,32 @@ __device__ __forceinline__ ArgMax better(ArgMax a, ArgMax b)
     return a;
 }
 
-// block-wide argmax (ties: lowest flat index); every thread receives the result
+// block-wide argmax (ties: lowest flat index); every thread receives the result. Within a wave
+// by DPP row permutations and readlanes (better() is a total order on (value, index), so the
+// mirror steps leave every lane of a row with the row's best); across waves through LDS.
+template <int CTRL>
+__device__ __forceinline__ ArgMax dpp_best(ArgMax a)
+{
+    ArgMax b;
+    b.v = dpp_move<CTRL>(a.v);
+    b.i = __builtin_amdgcn_update_dpp(0, a.i, CTRL, 0xF, 0xF, false);
+    return better(a, b);
+}
 __device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
 {
-    for (int o = 32; o > 0; o >>= 1) {
-        ArgMax b;
-        b.v = __shfl_xor(a.v, o, 64);
-        b.i = __shfl_xor(a.i, o, 64);
-        a = better(a, b);
-    }
+    a = dpp_best<0xB1>(a);
+    a = dpp_best<0x4E>(a);
+    a = dpp_best<0x141>(a);
+    a = dpp_best<0x140>(a);
+    for (int l = 16; l < 64; l += 16) a = better(a, ArgMax{read_lane(a.v, l), __builtin_amdgcn_readlane(a.i, l)});
+    a = better(ArgMax{read_lane(a.v, 0), __builtin_amdgcn_readlane(a.i, 0)}, a);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    __syncthreads();
+    __syncthreads();                     // earlier readers of scratch are done
     if (lane == 0) scratch[wave] = a;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        ArgMax m = scratch[0];
-        for (int w = 1; w < nw; ++w) m = better(m, scratch[w]);
-        scratch[nw] = m;
-    }
-    __syncthreads();
-    return scratch[nw];
+    ArgMax m = scratch[0];
+    for (int w = 1; w < nw; ++w) m = better(m, scratch[w]);
+    return m;
 }
 
 // Dominant r x r submatrix of Y (rows x r) and the interpolation matrix B = Y Y[piv]^{-1}.
