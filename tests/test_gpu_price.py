@@ -157,3 +157,37 @@ def test_precision_flag_on_too_coarse_grid(pricer):
     assert det["kappa"] > 500                      # the oracle's own cancellation factor
     assert det["kappa"] / 100 < info["kappa"] < det["kappa"] * 100   # the pricer's estimate
     assert rc != ttfp.TTFP_OK                       # kappa * eps exceeds tol
+
+
+def test_tt_export_matches_tt_values_and_index_sets(pricer):
+    opt = W.random_small_options(1, seed=61, d_choices=(3,))[0]
+    N, R = 32, 24
+    g = W.grid(N, tol=1e-10, max_rank=R)
+    p, ranks, info, rc = pricer.price(opt, g)
+    d = opt["d"]
+    rng = np.random.Generator(np.random.PCG64(9))
+    for t in range(ranks.shape[0]):
+        ex = pricer.tt_export(t, d, R, N)
+        assert ex["ranks"].tolist() == ranks[t].tolist()
+        for k, G in enumerate(ex["cores"]):
+            assert G.shape == (ranks[t][k], N, ranks[t][k + 1])
+        idx = rng.integers(0, N, size=(64, d))
+        vals = np.empty(len(idx), complex)
+        for q, ix in enumerate(idx):
+            v = np.ones(1, complex)
+            for k, G in enumerate(ex["cores"]):
+                v = v @ G[:, ix[k], :]
+            vals[q] = v[0]
+        ref = pricer.tt_values(t, idx)
+        # the two contraction orders round differently; a wrong layout would differ at O(1)
+        assert np.allclose(vals, ref, rtol=1e-8, atol=1e-11 * np.max(np.abs(ref)))
+        # the final index sets: in range, distinct, and nested (I_{k+1} extends I_k, J_k extends J_{k+1})
+        for k in range(1, d):
+            I, J = ex["I"][k], ex["J"][k]
+            assert I.shape[1] == k and J.shape[1] == d - k
+            assert I.size == 0 or (I.min() >= 0 and I.max() < N)
+            assert J.min() >= 0 and J.max() < N
+            assert len(np.unique(J, axis=0)) == len(J)
+            if k + 1 < d:
+                prev = {tuple(row) for row in ex["J"][k + 1]}
+                assert all(tuple(row[1:]) in prev for row in J)
