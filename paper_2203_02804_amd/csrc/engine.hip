@@ -580,11 +580,11 @@ done:
             for (int q = 0; q < TTFP_KERNEL_COUNT; ++q) ctx->prof_work[q] += it.work[q];
 #ifdef TTFP_PHASE_TIMING
     {
-        double ph[12] = {0};
+        double ph[16] = {0};
         for (const Item &it : host_items)
-            for (int q = 0; q < 12; ++q) ph[q] += it.phase[q];
+            for (int q = 0; q < 16; ++q) ph[q] += it.phase[q];
         std::fprintf(stderr, "phases (us summed over %d items):", n_items);
-        for (int q = 0; q < 12; ++q) std::fprintf(stderr, " %d:%.0f", q, ph[q] * 0.01);
+        for (int q = 0; q < 16; ++q) std::fprintf(stderr, " %d:%.0f", q, ph[q] * 0.01);
         std::fprintf(stderr, "\n");
     }
 #endif

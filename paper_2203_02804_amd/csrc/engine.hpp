@@ -62,7 +62,7 @@ struct Item {
     int mv_viol;                      // k_interp found rows with |B_ij| > 1 + delta
     int mv_dirty;                     // the pivots moved since B was last formed
     double work[12];                  // algorithmic work per kernel family (bytes or flops)
-    double phase[12];                 // per-phase device time (ticks), TTFP_PHASE_TIMING builds only
+    double phase[16];                 // per-phase device time (ticks), TTFP_PHASE_TIMING builds only
     cplx P;                           // latest contraction of the tensor train
 };
 

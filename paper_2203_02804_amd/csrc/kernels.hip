@@ -64,8 +64,8 @@ template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double read_lane(double v, int l)
@@ -74,6 +74,25 @@ __device__ __forceinline__ double read_lane(double v, int l)
     const int lo = __builtin_amdgcn_readlane((int)b, l);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Row exchanges of gfx950 (v_permlane16_swap / v_permlane32_swap on two copies of v): every lane
+// gets the values of rows {2q, 2q+1} (16-lane rows, swap16) or of halves {0, 1} (32-lane halves,
+// swap32) that hold it, lower one in lo, upper one in hi, in the same order in every lane.
+__device__ __forceinline__ void swap16(double v, double &lo, double &hi)
+{
+    const long long b = __double_as_longlong(v);
+    const auto l = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    lo = __longlong_as_double(((long long)h[0] << 32) | l[0]);
+    hi = __longlong_as_double(((long long)h[1] << 32) | l[1]);
+}
+__device__ __forceinline__ void swap32(double v, double &lo, double &hi)
+{
+    const long long b = __double_as_longlong(v);
+    const auto l = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    lo = __longlong_as_double(((long long)h[0] << 32) | l[0]);
+    hi = __longlong_as_double(((long long)h[1] << 32) | l[1]);
 }
 // sum over each group of S adjacent lanes (S = 1, 2, 4, 8, 16), left in every lane of the group
 __device__ __forceinline__ double seg_sum(double v, int S)
@@ -84,27 +103,63 @@ __device__ __forceinline__ double seg_sum(double v, int S)
     if (S >= 16) v += dpp_move<0x140>(v);
     return v;
 }
-// sum / max over the 64 lanes of a wave (all lanes active), returned in every lane
+// sum / max over the 64 lanes of a wave (all lanes active), returned in every lane as
+// (row0 + row1) + (row2 + row3), bit-identical across lanes
 __device__ __forceinline__ double wave_sum(double v)
 {
+    double lo, hi;
     v = seg_sum(v, 16);
-    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+    swap16(v, lo, hi);
+    swap32(lo + hi, lo, hi);
+    return lo + hi;
 }
 __device__ __forceinline__ double wave_max(double v)
 {
+    double lo, hi;
     v = fmax(v, dpp_move<0xB1>(v));
     v = fmax(v, dpp_move<0x4E>(v));
     v = fmax(v, dpp_move<0x141>(v));
     v = fmax(v, dpp_move<0x140>(v));
-    return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+    swap16(v, lo, hi);
+    swap32(fmax(lo, hi), lo, hi);
+    return fmax(lo, hi);
+}
+
+// Scalars of a Householder reflector. The column is scaled by s = 2^-e, the power of two that
+// takes its largest magnitude into [0.5, 1) (exact, and cheaper than a division); sqs is the
+// sum of squared moduli of the scaled entries below the leading one, x0 the unscaled leading
+// entry. Returns the factor cf that turns an unscaled entry below the leading one into w_i,
+// alpha = -phase(x0) |x| and tau = (|x0| + |x|) / |x| (in [1, 2]).
+struct ReflScalars {
+    cplx cf, alpha;
+    double tau;
+};
+__device__ __forceinline__ ReflScalars reflector_scalars(cplx x0, double s, int e, double sqs)
+{
+    const cplx x0s = {x0.x * s, x0.y * s};
+    // |x_j|: squares below 1e-300 keep only a few digits, and a phase formed from them is
+    // not of unit modulus (the reflector would not be unitary); hypot then
+    double a0 = sqrt(x0s.x * x0s.x + x0s.y * x0s.y);
+    if (a0 < 1e-150) a0 = hypot(x0s.x, x0s.y);
+    const double nrm = sqrt(sqs + a0 * a0);         // >= 0.5: the largest entry scales to [0.5, 1)
+    const double ra = a0 > 1e-300 ? 1.0 / a0 : 0.0;
+    const cplx ph = a0 > 1e-300 ? cplx{x0s.x * ra, x0s.y * ra} : cplx{1.0, 0.0};
+    // w_i = x_i / v_j with v_j = phase (|x_j| + |x|) (in units of 2^e)
+    const double den = 1.0 / (a0 + nrm);
+    ReflScalars r;
+    r.cf = {ph.x * den * s, -ph.y * den * s};
+    r.alpha = {-ldexp(ph.x * nrm, e), -ldexp(ph.y * nrm, e)};
+    r.tau = (a0 + nrm) / nrm;
+    return r;
 }
 
 // Householder reflector for the column x = (x_j, ..., x_{n-1}) (entry i at x[i * stride]), made by
 // wave 0 of the workgroup. The reflector is H = I - tau w w^H with w_j = 1, chosen so that
 // H x = (alpha, 0, ..., 0) with alpha = -phase(x_j) |x|. Every quantity is formed from the column
-// scaled by its largest entry, so columns of any magnitude (integrand values span hundreds of
-// decades) neither underflow to a spurious zero norm nor overflow the reflector (tau lies in
-// [1, 2]); a column below 1e-280 in magnitude is left as it is (tau = 0). On return x holds w
+// scaled by the power of two that takes its largest entry into [0.5, 1), so columns of any
+// magnitude (integrand values span hundreds of decades) neither underflow to a spurious zero norm
+// nor overflow the reflector (tau lies in [1, 2]); a column below 1e-280 in magnitude is left as
+// it is (tau = 0). On return x holds w
 // (x_j = 1) and the wave's lane 0 has written alpha to *alpha_out and tau to *tau_out.
 __device__ void make_reflector(cplx *x, int stride, int j, int n, cplx *alpha_out, double *tau_out)
 {
@@ -119,28 +174,21 @@ __device__ void make_reflector(cplx *x, int stride, int j, int n, cplx *alpha_ou
         }
         return;
     }
-    const double inv = 1.0 / mx;
+    int e;
+    frexp(mx, &e);
+    const double sc = ldexp(1.0, -e);
     double sq = 0.0;
     for (int i = j + 1 + lane; i < n; i += 64) {
         const cplx v = x[(size_t)i * stride];
-        sq += cabs2(cplx{v.x * inv, v.y * inv});
+        sq += cabs2(cplx{v.x * sc, v.y * sc});
     }
     sq = wave_sum(sq);
-    const cplx x0 = x[(size_t)j * stride];
-    const cplx x0s = {x0.x * inv, x0.y * inv};
-    // |x_j| by hypot: a squared modulus below 1e-308 keeps only a few digits, and a phase
-    // formed from it is not of unit modulus (the reflector would not be unitary)
-    const double a0 = hypot(x0s.x, x0s.y);
-    const double nrm = sqrt(sq + a0 * a0);           // >= 1: the largest entry scales to 1
-    const cplx ph = a0 > 1e-300 ? cplx{x0s.x / a0, x0s.y / a0} : cplx{1.0, 0.0};
-    // w_i = x_i / v_j with v_j = phase (|x_j| + |x|) (in units of mx)
-    const double den = 1.0 / (a0 + nrm);
-    const cplx cf = {ph.x * den * inv, -ph.y * den * inv};
-    for (int i = j + 1 + lane; i < n; i += 64) x[(size_t)i * stride] = cmul(x[(size_t)i * stride], cf);
+    const ReflScalars r = reflector_scalars(x[(size_t)j * stride], sc, e, sq);
+    for (int i = j + 1 + lane; i < n; i += 64) x[(size_t)i * stride] = cmul(x[(size_t)i * stride], r.cf);
     if (lane == 0) {
         x[(size_t)j * stride] = {1.0, 0.0};
-        *alpha_out = {-ph.x * nrm * mx, -ph.y * nrm * mx};
-        *tau_out = (a0 + nrm) / nrm;
+        *alpha_out = r.alpha;
+        *tau_out = r.tau;
     }
 }
 
@@ -246,7 +294,7 @@ __global__ void k_init(Item *items, int n_items)
     it.mv_viol = 0;
     it.mv_dirty = 0;
     for (int q = 0; q < 12; ++q) it.work[q] = 0.0;
-    for (int q = 0; q < 12; ++q) it.phase[q] = 0.0;
+    for (int q = 0; q < 16; ++q) it.phase[q] = 0.0;
     it.capped = 0;
     long long cnt = 1;
     for (int k = d - 1; k >= 1; --k) {
@@ -368,10 +416,8 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 // ------------------------------------------------------------------ Householder R in LDS
 // Triangularises A (nr x nc, row-major in LDS with an odd row stride ncp, so that both a row
 // and a column spread over the LDS banks) by Householder reflections H = I - tau w w^H, in
-// panels of TSQR_NB columns. Within a panel each reflector is formed by wave 0 and applied to
-// the panel's later columns by one wave per column; the trailing columns then take the
-// panel's reflectors one after another, each column owned by a group of S adjacent lanes that
-// splits the rows, so a dot product needs an S-lane butterfly only.
+// panels of TSQR_NB columns. A panel is factored inside one wave (wave 0), one panel ahead of
+// the trailing update that the other waves carry out (see householder_lds).
 // tri > 0: A stacks tri upper-triangular nc x nc factors (a merge of the reduction tree); the
 // reflector of column j then touches only row j of the first factor and rows 0..j of the
 // others, and only those rows are visited. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
@@ -386,115 +432,260 @@ __device__ __forceinline__ int hh_row(int k, int j, int nc, int tri)
     return nc * (1 + q) + (k - 1 - q * (j + 1));
 }
 
-// reflector of column j over its support rows (wave 0 of the workgroup); see make_reflector
+// Orders one wave's LDS accesses across its lanes: a wave's LDS instructions execute in
+// order, so only the compiler has to be kept from moving loads and stores across this point.
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Rows per lane that the single-wave Householder steps keep in registers between their two
+// passes (blocks up to 192 rows, which covers the leaves and merges of wide fibers); further
+// rows are read again from LDS.
+constexpr int HH_SLOTS = 3;
+
+// reflector of column j over its support rows (one wave); see make_reflector. The largest
+// magnitude and the sum of squares come from one pass over the column; only a column whose
+// magnitude lies outside [1e-140, 1e140], where the raw squares could under- or overflow, is
+// summed a second time with the scaled values.
+#ifdef TTFP_PHASE_TIMING
+__shared__ double hh_refl_ticks;                    // time wave 0 spends forming reflectors
+#endif
 __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, int tri, cplx *alpha_out, double *tau_out)
 {
+#ifdef TTFP_PHASE_TIMING
+    const long long t_in = wall_clock64();
+#define REFL_DONE do { if (threadIdx.x == 0) hh_refl_ticks += (double)(wall_clock64() - t_in); } while (0)
+#else
+#define REFL_DONE do {} while (0)
+#endif
     const int lane = threadIdx.x & 63;
-    double mx = 0.0;
-    for (int k = lane; k < len; k += 64) {
+    double mx = 0.0, sq = 0.0;
+    cplx xv[HH_SLOTS];
+    int xi[HH_SLOTS];
+#pragma unroll
+    for (int m = 0; m < HH_SLOTS; ++m) {
+        const int k = lane + 64 * m;
+        xi[m] = k < len ? hh_row(k, j, nc, tri) : 0;
+        xv[m] = k < len ? A[(size_t)xi[m] * ncp + j] : cplx{0.0, 0.0};
+        mx = fmax(mx, fmax(fabs(xv[m].x), fabs(xv[m].y)));
+        if (k > 0) sq += cabs2(xv[m]);
+    }
+    for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
         const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
         mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+        sq += cabs2(v);
     }
     mx = wave_max(mx);
-    if (!(mx >= 1e-280) || !(mx <= 1e300)) {
-        if (lane == 0) {
-            *alpha_out = A[(size_t)j * ncp + j];
-            *tau_out = 0.0;
-        }
-        return;
-    }
-    const double inv = 1.0 / mx;
-    double sq = 0.0;
-    for (int k = 1 + lane; k < len; k += 64) {
-        const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
-        sq += cabs2(cplx{v.x * inv, v.y * inv});
-    }
     sq = wave_sum(sq);
     const cplx x0 = A[(size_t)j * ncp + j];
-    const cplx x0s = {x0.x * inv, x0.y * inv};
-    const double a0 = hypot(x0s.x, x0s.y);
-    const double nrm = sqrt(sq + a0 * a0);
-    const cplx ph = a0 > 1e-300 ? cplx{x0s.x / a0, x0s.y / a0} : cplx{1.0, 0.0};
-    const double den = 1.0 / (a0 + nrm);
-    const cplx cf = {ph.x * den * inv, -ph.y * den * inv};
-    for (int k = 1 + lane; k < len; k += 64) {
+    if (!(mx >= 1e-280) || !(mx <= 1e300)) {
+        if (lane == 0) {
+            *alpha_out = x0;
+            *tau_out = 0.0;
+        }
+        REFL_DONE;
+        return;
+    }
+    int e;
+    frexp(mx, &e);
+    const double sc = ldexp(1.0, -e);
+    if (mx >= 1e-140 && mx <= 1e140) {
+        sq = sq * sc * sc;
+    } else {
+        sq = 0.0;
+#pragma unroll
+        for (int m = 0; m < HH_SLOTS; ++m)
+            if (lane + 64 * m > 0) sq += cabs2(cplx{xv[m].x * sc, xv[m].y * sc});
+        for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
+            const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
+            sq += cabs2(cplx{v.x * sc, v.y * sc});
+        }
+        sq = wave_sum(sq);
+    }
+    const ReflScalars r = reflector_scalars(x0, sc, e, sq);
+#pragma unroll
+    for (int m = 0; m < HH_SLOTS; ++m) {
+        const int k = lane + 64 * m;
+        if (k > 0 && k < len) A[(size_t)xi[m] * ncp + j] = cmul(xv[m], r.cf);
+    }
+    for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
         cplx *p = A + (size_t)hh_row(k, j, nc, tri) * ncp + j;
-        *p = cmul(*p, cf);
+        *p = cmul(*p, r.cf);
     }
     if (lane == 0) {
         A[(size_t)j * ncp + j] = {1.0, 0.0};
-        *alpha_out = {-ph.x * nrm * mx, -ph.y * nrm * mx};
-        *tau_out = (a0 + nrm) / nrm;
+        *alpha_out = r.alpha;
+        *tau_out = r.tau;
     }
+    REFL_DONE;
+#undef REFL_DONE
 }
 
-__device__ void householder_lds(cplx *A, int nr, int nc, int ncp, int tri, cplx *alph, double *tau)
+// Applies reflectors j0..j1-1, in order, to columns [ca, cb). Threads t = 0..T-1 (T a multiple
+// of 64, every one of them calling) form groups of S adjacent lanes, one column per group,
+// which split the column's support rows; a dot product then needs an S-lane butterfly only.
+__device__ void hh_apply_cols(cplx *A, int ncp, int nr, int nc, int tri, const double *tau,
+                              int ca, int cb, int j0, int j1, int t, int T)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int jmax = nr < nc ? nr : nc;
-    for (int j0 = 0; j0 < jmax; j0 += TSQR_NB) {
-        const int jb = min(TSQR_NB, jmax - j0);
-        // ---- panel: reflectors of columns j0..j0+jb-1, each applied to the panel's later columns
-        for (int j = j0; j < j0 + jb; ++j) {
-            if (wave == 0) make_reflector_rows(A, ncp, j, hh_len(j, nr, nc, tri), nc, tri, &alph[j], &tau[j]);
-            __syncthreads();
+    const int nt = cb - ca;
+    if (nt <= 0 || j1 <= j0) return;
+    int S = 1;
+    while (S < 16 && 2 * S * nt <= T) S *= 2;
+    const int sidx = t % S, per = T / S;
+    for (int cq = 0; cq < nt; cq += per) {
+        const int cl = cq + t / S;
+        const bool act = cl < nt;
+        const int c = ca + (act ? cl : 0);
+        for (int j = j0; j < j1; ++j) {
             const double tj = tau[j];
+            if (tj == 0.0) continue;                // same for every lane
             const int len = hh_len(j, nr, nc, tri);
-            for (int c = j + 1 + wave; c < j0 + jb && c < nc; c += nw) {
-                if (tj == 0.0) break;
-                double dr = 0.0, di = 0.0;
-                for (int k = lane; k < len; k += 64) {
+            double dr = 0.0, di = 0.0;
+            if (act)
+                for (int k = sidx; k < len; k += S) {
                     const int i = hh_row(k, j, nc, tri);
                     const cplx p = cmulc(A[(size_t)i * ncp + j], A[(size_t)i * ncp + c]);
                     dr += p.x;
                     di += p.y;
                 }
-                dr = wave_sum(dr);
-                di = wave_sum(di);
-                const cplx f = {tj * dr, tj * di};
-                for (int k = lane; k < len; k += 64) {
+            dr = seg_sum(dr, S);
+            di = seg_sum(di, S);
+            const cplx f = {tj * dr, tj * di};
+            if (act)
+                for (int k = sidx; k < len; k += S) {
                     const int i = hh_row(k, j, nc, tri);
                     A[(size_t)i * ncp + c] = csub(A[(size_t)i * ncp + c], cmul(f, A[(size_t)i * ncp + j]));
                 }
-            }
-            __syncthreads();
         }
-        // ---- trailing columns: the panel's reflectors in order, S lanes per column
-        const int c0 = j0 + jb, nt = nc - c0;
-        if (nt > 0) {
-            int S = 1;
-            while (S < 16 && 2 * S * nt <= (int)blockDim.x) S *= 2;
-            const int sidx = threadIdx.x % S, per = blockDim.x / S;
-            for (int cb = 0; cb < nt; cb += per) {
-                const int cl = cb + threadIdx.x / S;
-                const bool act = cl < nt;
-                const int c = c0 + (act ? cl : 0);
-                for (int j = j0; j < j0 + jb; ++j) {
-                    const double tj = tau[j];
-                    if (tj == 0.0) continue;                // same for every lane
-                    const int len = hh_len(j, nr, nc, tri);
-                    double dr = 0.0, di = 0.0;
-                    if (act)
-                        for (int k = sidx; k < len; k += S) {
-                            const int i = hh_row(k, j, nc, tri);
-                            const cplx w = A[(size_t)i * ncp + j];
-                            const cplx p = cmulc(w, A[(size_t)i * ncp + c]);
-                            dr += p.x;
-                            di += p.y;
-                        }
-                    dr = seg_sum(dr, S);
-                    di = seg_sum(di, S);
-                    const cplx f = {tj * dr, tj * di};
-                    if (act)
-                        for (int k = sidx; k < len; k += S) {
-                            const int i = hh_row(k, j, nc, tri);
-                            A[(size_t)i * ncp + c] = csub(A[(size_t)i * ncp + c], cmul(f, A[(size_t)i * ncp + j]));
-                        }
-                }
-            }
-        }
-        __syncthreads();
     }
+}
+
+// Applies reflectors j0..j1-1, in order, to the n <= TSQR_NB columns ca..ca+n-1, within the
+// calling wave: each lane takes every 64th support row for all n columns, so one pass over the
+// rows forms the n dot products (reduced across the wave together) and a second one updates;
+// the first HH_SLOTS rows of a lane stay in registers between the passes.
+__device__ void hh_apply_wave(cplx *A, int ncp, int nr, int nc, int tri, const double *tau,
+                              int ca, int n, int j0, int j1)
+{
+    if (n <= 0) return;
+    const int lane = threadIdx.x & 63;
+    for (int j = j0; j < j1; ++j) {
+        const double tj = tau[j];
+        if (tj == 0.0) continue;                    // same for every lane
+        const int len = hh_len(j, nr, nc, tri);
+        double dr[TSQR_NB], di[TSQR_NB];
+#pragma unroll
+        for (int q = 0; q < TSQR_NB; ++q) dr[q] = di[q] = 0.0;
+        cplx wv[HH_SLOTS], cv[HH_SLOTS][TSQR_NB];
+        int ri[HH_SLOTS];
+#pragma unroll
+        for (int m = 0; m < HH_SLOTS; ++m) {
+            const int k = lane + 64 * m;
+            const bool in = k < len;
+            ri[m] = in ? hh_row(k, j, nc, tri) : 0;
+            const cplx *row = A + (size_t)ri[m] * ncp;
+            wv[m] = in ? row[j] : cplx{0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < TSQR_NB; ++q) {
+                cv[m][q] = (in && q < n) ? row[ca + q] : cplx{0.0, 0.0};
+                const cplx p = cmulc(wv[m], cv[m][q]);
+                dr[q] += p.x;
+                di[q] += p.y;
+            }
+        }
+        for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
+            const cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
+            const cplx w = row[j];
+#pragma unroll
+            for (int q = 0; q < TSQR_NB; ++q)
+                if (q < n) {
+                    const cplx p = cmulc(w, row[ca + q]);
+                    dr[q] += p.x;
+                    di[q] += p.y;
+                }
+        }
+        cplx f[TSQR_NB];
+#pragma unroll
+        for (int q = 0; q < TSQR_NB; ++q) {
+            f[q] = {0.0, 0.0};
+            if (q < n) f[q] = {tj * wave_sum(dr[q]), tj * wave_sum(di[q])};
+        }
+#pragma unroll
+        for (int m = 0; m < HH_SLOTS; ++m)
+            if (lane + 64 * m < len) {
+                cplx *row = A + (size_t)ri[m] * ncp;
+#pragma unroll
+                for (int q = 0; q < TSQR_NB; ++q)
+                    if (q < n) row[ca + q] = csub(cv[m][q], cmul(f[q], wv[m]));
+            }
+        for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
+            cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
+            const cplx w = row[j];
+#pragma unroll
+            for (int q = 0; q < TSQR_NB; ++q)
+                if (q < n) row[ca + q] = csub(row[ca + q], cmul(f[q], w));
+        }
+        wave_lds_order();                           // reflector j+1 visits other rows per lane
+    }
+}
+
+// Factors the panel of columns c..c+n-1 (n <= TSQR_NB) within the calling wave: each
+// reflector is formed and then applied to the panel's later columns.
+__device__ void hh_factor_panel_wave(cplx *A, int ncp, int nr, int nc, int tri, cplx *alph, double *tau, int c, int n)
+{
+    for (int j = c; j < c + n; ++j) {
+        make_reflector_rows(A, ncp, j, hh_len(j, nr, nc, tri), nc, tri, &alph[j], &tau[j]);
+        wave_lds_order();
+        hh_apply_wave(A, ncp, nr, nc, tri, tau, j + 1, c + n - j - 1, j, j + 1);
+    }
+}
+
+// Triangularises A in panels of TSQR_NB columns with a one-panel look-ahead: while the other
+// waves apply panel P's reflectors to the columns beyond panel P+1, wave 0 applies them to
+// panel P+1's columns and factors panel P+1 by itself. The two parts touch disjoint columns
+// and read panel P's reflectors only, so one barrier per panel separates the steps.
+__device__ void householder_lds(cplx *A, int nr, int nc, int ncp, int tri, cplx *alph, double *tau, double *ph)
+{
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#ifdef TTFP_PHASE_TIMING
+    long long hh_t = wall_clock64();
+    double hh_acc[3] = {0.0, 0.0, 0.0};
+#define HH_MARK(q) do { __syncthreads(); const long long n_ = wall_clock64(); hh_acc[q] += (double)(n_ - hh_t); hh_t = n_; } while (0)
+    // time from the panel's start to where wave 0 (q = 0) or wave 1 (q = 1) is done
+#define HH_PART(q) do { if (threadIdx.x == 64 * (q)) hh_acc[q] += (double)(wall_clock64() - hh_t); } while (0)
+    if (threadIdx.x == 0) hh_refl_ticks = 0.0;
+#else
+#define HH_MARK(q) do {} while (0)
+#define HH_PART(q) do {} while (0)
+#endif
+    const int jmax = nr < nc ? nr : nc;
+    const int t0 = nw > 1 ? 64 : 0;                 // first thread of the trailing update
+    if (jmax > 0 && wave == 0) hh_factor_panel_wave(A, ncp, nr, nc, tri, alph, tau, 0, min(TSQR_NB, jmax));
+    __syncthreads();
+    HH_MARK(2);
+    for (int j0 = 0; j0 < jmax; j0 += TSQR_NB) {
+        const int j1 = min(j0 + TSQR_NB, jmax);     // panel P: reflectors j0..j1-1 are formed
+        const int n1 = min(TSQR_NB, jmax - j1);     // width of panel P+1 (0 at the end)
+        if (wave == 0 && n1 > 0) {
+            hh_apply_wave(A, ncp, nr, nc, tri, tau, j1, n1, j0, j1);
+            hh_factor_panel_wave(A, ncp, nr, nc, tri, alph, tau, j1, n1);
+        }
+        HH_PART(0);
+        if ((int)threadIdx.x >= t0)
+            hh_apply_cols(A, ncp, nr, nc, tri, tau, j1 + n1, nc, j0, j1, threadIdx.x - t0, blockDim.x - t0);
+        HH_PART(1);
+        __syncthreads();
+        HH_MARK(2);
+    }
+#ifdef TTFP_PHASE_TIMING
+    if (threadIdx.x == 0 && ph) { ph[0] += hh_acc[0]; ph[2] += hh_acc[2]; ph[3] += hh_refl_ticks; }
+    if (threadIdx.x == 64 && ph) ph[1] += hh_acc[1];
+#endif
+#undef HH_MARK
+#undef HH_PART
 }
 
 // number of TSQR blocks at a level
@@ -556,7 +747,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
     }
     __syncthreads();
     PHASE_MARK(8);
-    householder_lds(A, nr, nc, ncp, tri, alph, tau);
+    householder_lds(A, nr, nc, ncp, tri, alph, tau, it.phase + 12);
     PHASE_MARK(9);
     cplx *dst = it.Rlev + (size_t)(level & 1) * it.nblk_max * rsz + (size_t)blk * rsz;
     const int jmax = nr < nc ? nr : nc;
