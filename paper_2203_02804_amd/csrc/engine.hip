@@ -131,7 +131,7 @@ ItemSizes item_sizes(int d, int N, int R, int p, int BR)
     s.off_M1 = take(sizeof(cplx) * (size_t)d * R * R);
     s.off_M2 = take(sizeof(cplx) * (size_t)d * R * R);
     s.off_piv = take(sizeof(int) * R);
-    s.off_keys = take(sizeof(float) * (size_t)s.rows_max * 16);
+    s.off_keys = take(sizeof(float) * (size_t)s.rows_max * 17);   // keys, then viol
     s.off_Ai = take(sizeof(cplx) * (size_t)R * R);
     s.bytes = o;
     return s;
@@ -244,6 +244,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             it.M2 = (cplx *)(dev + s.off_M2);
             it.piv = (int *)(dev + s.off_piv);
             it.keys = (float *)(dev + s.off_keys);
+            it.viol = it.keys + (size_t)s.rows_max * 16;
             it.Ai = (cplx *)(dev + s.off_Ai);
             it.rows_max = s.rows_max;
             it.nblk_max = s.nblk_max;
@@ -1007,7 +1008,7 @@ static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, in
     const int nblk = (m + BR - 1) / BR;
     size_t oF = 0, oRl = align_up(oF + 16 * (size_t)m * n), oY = align_up(oRl + 16 * 2 * (size_t)nblk * n * n),
            oW = align_up(oY + 16 * (size_t)m * r), oBt = align_up(oW + 16 * (size_t)m * r), oP = align_up(oBt + 16 * (size_t)m * r),
-           oK = align_up(oP + 4 * (size_t)std::max(r, 1)), oA = align_up(oK + 4 * 16 * (size_t)m),
+           oK = align_up(oP + 4 * (size_t)std::max(r, 1)), oA = align_up(oK + 4 * 17 * (size_t)m),
            total = align_up(oA + 16 * (size_t)r * r);
     HIPCHK(hipMalloc(&buf, total));
     std::memset(&it, 0, sizeof it);
@@ -1021,6 +1022,7 @@ static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, in
     it.Bt = (cplx *)(buf + oBt);
     it.piv = (int *)(buf + oP);
     it.keys = (float *)(buf + oK);
+    it.viol = it.keys + 16 * (size_t)m;
     it.Ai = (cplx *)(buf + oA);
     it.nblk_max = nblk;
     it.rows_max = m;

@@ -48,6 +48,7 @@ struct Item {
     int *piv;                  // R pivot rows
     cplx *Ai;                  // R x R inverse of the pivot rows of Y (maxvol -> k_interp)
     float *keys;               // rows_max x 16 partial squared row norms of Y (maxvol start)
+    float *viol;               // rows_max marks of k_interp: a row's largest |B| above the bound, else 0
     int rows_max, nblk_max;
     // ---- dynamic state
     int nI[MAXD + 1], nJ[MAXD + 1];   // sizes of the left / right index sets

@@ -1216,8 +1216,8 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
     const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     PHASE_START;
-    // ---- 1a. row norms (one key per group of gsz consecutive rows: its largest norm); the first
-    // key slot of every row is then cleared: k_interp records violations there
+    // ---- 1a. row norms (one key per group of gsz consecutive rows: its largest norm); the
+    // violation marks that k_interp records are cleared
     const int nkeys = cap * (int)(sizeof(cplx) / sizeof(float));
     const int gsz = (m + nkeys - 1) / nkeys;            // 1 unless m exceeds the key buffer
     const int nk = (m + gsz - 1) / gsz;
@@ -1240,7 +1240,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
                 for (int c = 0; c < r; ++c) qq += cabs2(y[c]);
                 q = (float)qq;
             }
-            kp[0] = 0.0f;
+            it.viol[i] = 0.0f;
             if (!(q >= 0.0f && q <= 3.0e38f)) q = 0.0f;     // a non-finite row is never a pivot
             best = fmaxf(best, q);
         }
@@ -1415,7 +1415,7 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
         cand[c] = piv[c];
     }
     float vmax = 0.0f;
-    for (int i = threadIdx.x; i < m; i += nthr) vmax = fmaxf(vmax, it.keys[(size_t)i * 16]);
+    for (int i = threadIdx.x; i < m; i += nthr) vmax = fmaxf(vmax, it.viol[i]);
     {
         ArgMax a = {(double)vmax, 0};
         a = block_argmax(a, red);
@@ -1423,10 +1423,10 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
     }
     const int K = min(min(max(4 * r, 64), MV_KMAX), m);
     // only rows that violated (a positive mark) are candidates
-    const int nv = select_largest(it.keys, 16, m, K - r, 1e-30f, vmax, cand + r, red, shi, shf);
+    const int nv = select_largest(it.viol, 1, m, K - r, 1e-30f, vmax, cand + r, red, shi, shf);
     const int Kc = r + nv;
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += nthr) it.keys[(size_t)i * 16] = 0.0f;   // for the next k_interp
+    for (int i = threadIdx.x; i < m; i += nthr) it.viol[i] = 0.0f;   // for the next k_interp
     // block rows: the pivots (rows of the identity) and the violating rows of B
     cplx *Bc = W;
     for (int e = threadIdx.x; e < Kc * r; e += nthr) {
@@ -1523,7 +1523,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
         // largest entry of the row over the 16 lanes that hold its columns
         for (int o = 8; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
         if (li == 0 && row < m && mx > lim && mx <= 1e300) {
-            atomicMax(reinterpret_cast<unsigned int *>(it.keys + (size_t)row * 16), __float_as_uint((float)mx));
+            atomicMax(reinterpret_cast<unsigned int *>(it.viol + row), __float_as_uint((float)mx));
             it.mv_viol = 1;
         }
     }
