@@ -956,14 +956,19 @@ __device__ __forceinline__ ArgMax dpp_best(ArgMax a)
     b.i = __builtin_amdgcn_update_dpp(0, a.i, CTRL, 0xF, 0xF, false);
     return better(a, b);
 }
-__device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
+// best (value, lowest index) over the 64 lanes of a wave, in every lane
+__device__ __forceinline__ ArgMax wave_argmax(ArgMax a)
 {
     a = dpp_best<0xB1>(a);
     a = dpp_best<0x4E>(a);
     a = dpp_best<0x141>(a);
     a = dpp_best<0x140>(a);
     for (int l = 16; l < 64; l += 16) a = better(a, ArgMax{read_lane(a.v, l), __builtin_amdgcn_readlane(a.i, l)});
-    a = better(ArgMax{read_lane(a.v, 0), __builtin_amdgcn_readlane(a.i, 0)}, a);
+    return better(ArgMax{read_lane(a.v, 0), __builtin_amdgcn_readlane(a.i, 0)}, a);
+}
+__device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
+{
+    a = wave_argmax(a);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     __syncthreads();                     // earlier readers of scratch are done
     if (lane == 0) scratch[wave] = a;
@@ -1068,7 +1073,9 @@ __device__ int select_largest(const float *v, int stride, int n, int K, float lo
 // An exactly singular pivot leaves its column at zero and sets it.mv_singular.
 __device__ void gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag, cplx *Ai, cplx *fcol, int *shi, Item &it)
 {
-    const int nthr = blockDim.x;
+    // pivot row of Ag and Ai (scaled) and the old row j of both, for the in-place update
+    __shared__ cplx pa[TTFP_MAX_RANK], pi[TTFP_MAX_RANK], ja[TTFP_MAX_RANK], ji[TTFP_MAX_RANK];
+    const int nthr = blockDim.x, lane = threadIdx.x & 63;
     __syncthreads();
     for (int e = threadIdx.x; e < r * r; e += nthr) {
         const int a = e / r, c = e % r;
@@ -1077,40 +1084,44 @@ __device__ void gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag
     }
     __syncthreads();
     for (int j = 0; j < r; ++j) {
-        if (threadIdx.x == 0) {
-            int p = j;
-            double best = cabs2(Ag[j * r + j]);
-            for (int a = j + 1; a < r; ++a) {
-                const double v = cabs2(Ag[a * r + j]);
-                if (v > best) { best = v; p = a; }
+        // partial pivoting: the first row of the largest modulus in column j (rows j..r-1), by wave 0
+        if (threadIdx.x < 64) {
+            ArgMax b = {-2.0, r};
+            for (int a = j + lane; a < r; a += 64) {
+                double v = cabs2(Ag[a * r + j]);
+                if (!(v >= 0.0)) v = -1.0;              // a non-finite entry ranks below every number
+                b = better(b, ArgMax{v, a});
             }
-            shi[0] = p;
+            b = wave_argmax(b);
+            if (lane == 0) shi[0] = b.i;
         }
         __syncthreads();
         const int p = shi[0];
-        if (p != j)
-            for (int c = threadIdx.x; c < r; c += nthr) {
-                cplx t0 = Ag[j * r + c]; Ag[j * r + c] = Ag[p * r + c]; Ag[p * r + c] = t0;
-                cplx t1 = Ai[j * r + c]; Ai[j * r + c] = Ai[p * r + c]; Ai[p * r + c] = t1;
-            }
-        __syncthreads();
-        const cplx gjj = Ag[j * r + j];
+        const cplx gjj = Ag[p * r + j];
         const bool sing = !(fmax(fabs(gjj.x), fabs(gjj.y)) > 0.0) || !(cabs2(gjj) <= 1e300);
         const cplx inv = sing ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, gjj);
         if (sing && threadIdx.x == 0) it.mv_singular = 1;
-        __syncthreads();
+        // rows j and p trade places; the pivot row is scaled; fcol holds column j of the
+        // swapped matrix (the elimination factors)
         for (int c = threadIdx.x; c < r; c += nthr) {
-            Ag[j * r + c] = cmul(Ag[j * r + c], inv);
-            Ai[j * r + c] = cmul(Ai[j * r + c], inv);
+            pa[c] = cmul(Ag[p * r + c], inv);
+            pi[c] = cmul(Ai[p * r + c], inv);
+            ja[c] = Ag[j * r + c];
+            ji[c] = Ai[j * r + c];
+            fcol[c] = c == p ? Ag[j * r + j] : Ag[c * r + j];
         }
-        __syncthreads();
-        for (int a = threadIdx.x; a < r; a += nthr) fcol[a] = Ag[a * r + j];
         __syncthreads();
         for (int e = threadIdx.x; e < r * r; e += nthr) {
             const int a = e / r, c = e % r;
-            if (a == j) continue;
-            Ag[e] = csub(Ag[e], cmul(fcol[a], Ag[j * r + c]));
-            Ai[e] = csub(Ai[e], cmul(fcol[a], Ai[j * r + c]));
+            if (a == j) {
+                Ag[e] = pa[c];
+                Ai[e] = pi[c];
+            } else {
+                const cplx f = fcol[a];
+                const cplx ga = a == p ? ja[c] : Ag[e], ia = a == p ? ji[c] : Ai[e];
+                Ag[e] = csub(ga, cmul(f, pa[c]));
+                Ai[e] = csub(ia, cmul(f, pi[c]));
+            }
         }
         __syncthreads();
     }
