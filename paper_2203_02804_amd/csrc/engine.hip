@@ -390,7 +390,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_FINISH);
-        hipLaunchKernelGGL(k_finish, dim3(cdivu((long long)g.maxrows * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir);
+        hipLaunchKernelGGL(k_finish, dim3(1, ny), dim3(256), 0, st, it, act, t, dir);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_CORESUM);

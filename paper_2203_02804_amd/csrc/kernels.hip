@@ -5,8 +5,8 @@
 //   k_tsqr     triangular factor of a QR of the fiber, TSQR over LDS-resident row blocks
 //   k_qrcp     column-pivoted QR of that factor: rank by pivot size, inverse of the kept block
 //   k_basis    orthonormal basis of the kept fiber columns
-//   k_maxvol   rows of a dominant submatrix (maxvol) and the interpolating core B
-//   k_finish   next index set, core placement
+//   k_maxvol   rows of a dominant submatrix (maxvol); k_interp the interpolating core B
+//   k_finish   next index set and core shape
 //   k_core_sum core summed over the node index (the quadrature weights are uniform)
 // then k_fiber on the edge core and k_contract (Sec. IV.A inner product with the weights).
 #include <hip/hip_runtime.h>
@@ -1224,7 +1224,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     const int m = s.rows, r = it.rsel;
     const cplx *Y = it.Y;
     cplx *W = it.W;
-    cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
+    cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
     const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     PHASE_START;
     // ---- 1a. row norms (one key per group of gsz consecutive rows: its largest norm); the
@@ -1419,7 +1419,7 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
     const int m = s.rows, r = it.rsel, nthr = blockDim.x;
     const cplx *Y = it.Y;
     cplx *W = it.W;
-    const cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
+    const cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
     PHASE_START;
     for (int c = threadIdx.x; c < r; c += nthr) {
         piv[c] = it.piv[c];
@@ -1442,7 +1442,8 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
     cplx *Bc = W;
     for (int e = threadIdx.x; e < Kc * r; e += nthr) {
         const int q = e / r, c = e % r;
-        Bc[e] = q < r ? cplx{q == c ? 1.0 : 0.0, 0.0} : B[(size_t)cand[q] * r + c];
+        Bc[e] = q < r ? cplx{q == c ? 1.0 : 0.0, 0.0}
+                      : B[dir == 1 ? (size_t)c * m + cand[q] : (size_t)cand[q] * r + c];
     }
     __syncthreads();
     PHASE_MARK(4);
@@ -1469,9 +1470,9 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
 // real ones (re = Yr Ar - Yi Ai, im = Yr Ai + Yi Ar); A^{-1} is held in LDS. Lane l supplies
 // A-operand entry (row l % 16, k l / 16) and B-operand entry (k l / 16, column l % 16), and holds
 // accumulator rows l / 16 + 4 v, column l % 16 (v = 0..3; the layout was checked by a probe
-// against a host product). Rows whose largest |B_ij| exceeds 1 + delta
-// are marked (largest squared modulus in the row's first key slot) and the item is flagged
-// for a refinement round. mode 1: only after a refinement that moved a pivot.
+// against a host product). B goes straight into the core's slot. Rows whose largest |B_ij|
+// exceeds 1 + delta are marked (largest squared modulus in viol) and the item is flagged for a
+// refinement round. mode 1: only after a refinement that moved a pivot.
 constexpr int INTERP_WAVES = 4;                  // 16-row panels per workgroup
 __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const int *active, int t, int dir, int mode)
 {
@@ -1515,7 +1516,10 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
             cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim[q], 0, 0, 0);
         }
     }
-    cplx *B = (dir == 0) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
+    // the core slot holds B itself for a left-to-right step (rows (a, i), columns b: the core's
+    // a x N x b layout) and B transposed for a right-to-left one (rows (i, b), columns a);
+    // the raw entry point's B is row-major in Bt
+    cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1527,7 +1531,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
             const int col = 16 * q + li;
             if (row < m && col < r) {
                 const cplx val = {cre[q][v], cim[q][v]};
-                B[(size_t)row * r + col] = val;
+                B[dir == 1 ? (size_t)col * m + row : (size_t)row * r + col] = val;
                 mx = fmax(mx, cabs2(val));
             }
         }
@@ -1549,18 +1553,6 @@ __global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, 
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
     const int r = it.rsel, d = it.d, N = it.N, R = it.R, k = s.k;
-    if (dir == 1) {
-        const int nb = it.nJ[k + 1];
-        const long long tot = (long long)s.rows * r;
-        cplx *core = it.cores + (size_t)k * R * N * R;
-        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-             e += (long long)gridDim.x * blockDim.x) {
-            const int row = (int)(e / r), a = (int)(e % r);
-            const int i = row / nb, b = row % nb;
-            core[((size_t)a * N + i) * nb + b] = it.Bt[e];
-        }
-    }
-    if (blockIdx.x != 0) return;
     if (dir == 0) {
         const int *Ik = it.Iset + (size_t)k * R * d;
         int *In = it.Iset + (size_t)(k + 1) * R * d;
