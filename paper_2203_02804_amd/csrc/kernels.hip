@@ -904,9 +904,19 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const i
         cim[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int arow = row0 + li;
-    for (int k0 = 0; k0 < r; k0 += 4) {
-        const int kk = k0 + lk;
-        const cplx a = (arow < m && kk < r) ? it.F[(size_t)arow * nc + pm[kk]] : cplx{0.0, 0.0};
+    // the lane's kept fiber entries (columns perm[lk], perm[lk + 4], ...) are loaded first
+    constexpr int KS = TTFP_MAX_RANK / 4;
+    cplx av[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int kk = 4 * ks + lk;
+        av[ks] = (arow < m && kk < r) ? it.F[(size_t)arow * nc + pm[kk]] : cplx{0.0, 0.0};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        if (4 * ks >= r) break;
+        const int kk = 4 * ks + lk;
+        const cplx a = av[ks];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= ntile) break;
@@ -1502,9 +1512,20 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
         cim[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int arow = row0 + li;
-    for (int k0 = 0; k0 < r; k0 += 4) {
-        const int kk = k0 + lk;
-        const cplx a = (arow < m && kk < r) ? Y[(size_t)arow * r + kk] : cplx{0.0, 0.0};
+    // the lane's whole slice of its Y row (entries lk, lk + 4, ...) is loaded before the
+    // products, so the loads are in flight together
+    constexpr int KS = TTFP_MAX_RANK / 4;
+    cplx av[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int kk = 4 * ks + lk;
+        av[ks] = (arow < m && kk < r) ? Y[(size_t)arow * r + kk] : cplx{0.0, 0.0};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        if (4 * ks >= r) break;
+        const int kk = 4 * ks + lk;
+        const cplx a = av[ks];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= ntile) break;
