@@ -113,41 +113,60 @@ __device__ __forceinline__ double wave_sum(double v)
     swap32(lo + hi, lo, hi);
     return lo + hi;
 }
-// Eight sums over the 64 lanes of a wave at once, left in v (the same in every lane): three
-// exchange steps that halve the values a lane carries (partner lane ^ 1, lane ^ 2, then
-// row_ror:4, which keeps bits 0 and 1 of the lane and flips bit 2), row_ror:8 for the rest of the
-// 16-lane row, the row swaps across the wave, and one readlane per value (value k ends in the
-// lanes whose three low bits are k reversed). About half the instructions of eight wave_sums.
-__device__ __forceinline__ void wave_sum8(double (&v)[8])
+// NV = 2, 4 or 8 sums over the 64 lanes of a wave at once, left in v (the same in every lane).
+// Exchange steps halve the values a lane carries (partner lane ^ 1, lane ^ 2, then row_ror:4,
+// which keeps bits 0 and 1 of the lane and flips bit 2), plain steps over the lane bits left
+// (lane ^ 2, row_ror:4, row_ror:8) finish each 16-lane row, the row swaps cross the wave, and
+// one readlane per value broadcasts it (value k ends in the lanes whose low log2(NV) bits are k
+// reversed). For eight values this is about half the instructions of eight wave_sums.
+template <int NV>
+__device__ __forceinline__ void wave_sum_n(double (&v)[NV])
 {
+    static_assert(NV == 2 || NV == 4 || NV == 8, "2, 4 or 8 values");
     const int lane = threadIdx.x & 63;
     const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
-    double u[4], w[2];
+    double x;
+    if constexpr (NV == 8) {
+        double u[4], w[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double send = b0 ? v[k] : v[k + 4], keep = b0 ? v[k + 4] : v[k];
-        u[k] = keep + dpp_move<0xB1>(send);
-    }
+        for (int k = 0; k < 4; ++k) {
+            const double send = b0 ? v[k] : v[k + 4], keep = b0 ? v[k + 4] : v[k];
+            u[k] = keep + dpp_move<0xB1>(send);
+        }
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const double send = b1 ? u[k] : u[k + 2], keep = b1 ? u[k + 2] : u[k];
-        w[k] = keep + dpp_move<0x4E>(send);
+        for (int k = 0; k < 2; ++k) {
+            const double send = b1 ? u[k] : u[k + 2], keep = b1 ? u[k + 2] : u[k];
+            w[k] = keep + dpp_move<0x4E>(send);
+        }
+        const double send = b2 ? w[0] : w[1], keep = b2 ? w[1] : w[0];
+        x = keep + dpp_move<0x124>(send);
+    } else if constexpr (NV == 4) {
+        double u[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const double send = b0 ? v[k] : v[k + 2], keep = b0 ? v[k + 2] : v[k];
+            u[k] = keep + dpp_move<0xB1>(send);
+        }
+        const double send = b1 ? u[0] : u[1], keep = b1 ? u[1] : u[0];
+        x = keep + dpp_move<0x4E>(send);
+        x += dpp_move<0x124>(x);
+    } else {
+        const double send = b0 ? v[0] : v[1], keep = b0 ? v[1] : v[0];
+        x = keep + dpp_move<0xB1>(send);
+        x += dpp_move<0x4E>(x);
+        x += dpp_move<0x124>(x);
     }
-    const double send = b2 ? w[0] : w[1], keep = b2 ? w[1] : w[0];
-    double x = keep + dpp_move<0x124>(send);
     x += dpp_move<0x128>(x);
     double lo, hi;
     swap16(x, lo, hi);
     swap32(lo + hi, lo, hi);
     x = lo + hi;
-    v[0] = read_lane(x, 0);
-    v[1] = read_lane(x, 4);
-    v[2] = read_lane(x, 2);
-    v[3] = read_lane(x, 6);
-    v[4] = read_lane(x, 1);
-    v[5] = read_lane(x, 5);
-    v[6] = read_lane(x, 3);
-    v[7] = read_lane(x, 7);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        // lane holding value k: k's low bits reversed
+        const int l = NV == 8 ? ((k & 1) << 2 | (k & 2) | (k >> 2)) : NV == 4 ? ((k & 1) << 1 | (k >> 1)) : k;
+        v[k] = read_lane(x, l);
+    }
 }
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -599,23 +618,23 @@ __device__ void hh_apply_cols(cplx *A, int ncp, int nr, int nc, int tri, const d
     }
 }
 
-// Applies reflectors j0..j1-1, in order, to the n <= TSQR_NB columns ca..ca+n-1, within the
-// calling wave: each lane takes every 64th support row for all n columns, so one pass over the
-// rows forms the n dot products (reduced across the wave together) and a second one updates;
+// Applies reflectors j0..j1-1, in order, to the NQ <= TSQR_NB columns ca..ca+NQ-1, within the
+// calling wave: each lane takes every 64th support row for all NQ columns, so one pass over the
+// rows forms the NQ dot products (reduced across the wave together) and a second one updates;
 // the first HH_SLOTS rows of a lane stay in registers between the passes.
-__device__ void hh_apply_wave(cplx *A, int ncp, int nr, int nc, int tri, const double *tau,
-                              int ca, int n, int j0, int j1)
+template <int NQ>
+__device__ void hh_apply_wave_n(cplx *A, int ncp, int nr, int nc, int tri, const double *tau, int ca, int j0, int j1)
 {
-    if (n <= 0) return;
+    constexpr int NV = NQ == 3 ? 8 : 2 * NQ;     // sums per reflector (real and imaginary parts)
     const int lane = threadIdx.x & 63;
     for (int j = j0; j < j1; ++j) {
         const double tj = tau[j];
         if (tj == 0.0) continue;                    // same for every lane
         const int len = hh_len(j, nr, nc, tri);
-        double dr[TSQR_NB], di[TSQR_NB];
+        double sums[NV];
 #pragma unroll
-        for (int q = 0; q < TSQR_NB; ++q) dr[q] = di[q] = 0.0;
-        cplx wv[HH_SLOTS], cv[HH_SLOTS][TSQR_NB];
+        for (int q = 0; q < NV; ++q) sums[q] = 0.0;
+        cplx wv[HH_SLOTS], cv[HH_SLOTS][NQ];
         int ri[HH_SLOTS];
 #pragma unroll
         for (int m = 0; m < HH_SLOTS; ++m) {
@@ -625,46 +644,53 @@ __device__ void hh_apply_wave(cplx *A, int ncp, int nr, int nc, int tri, const d
             const cplx *row = A + (size_t)ri[m] * ncp;
             wv[m] = in ? row[j] : cplx{0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < TSQR_NB; ++q) {
-                cv[m][q] = (in && q < n) ? row[ca + q] : cplx{0.0, 0.0};
+            for (int q = 0; q < NQ; ++q) {
+                cv[m][q] = in ? row[ca + q] : cplx{0.0, 0.0};
                 const cplx p = cmulc(wv[m], cv[m][q]);
-                dr[q] += p.x;
-                di[q] += p.y;
+                sums[q] += p.x;
+                sums[NV / 2 + q] += p.y;
             }
         }
         for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
             const cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
             const cplx w = row[j];
 #pragma unroll
-            for (int q = 0; q < TSQR_NB; ++q)
-                if (q < n) {
-                    const cplx p = cmulc(w, row[ca + q]);
-                    dr[q] += p.x;
-                    di[q] += p.y;
-                }
+            for (int q = 0; q < NQ; ++q) {
+                const cplx p = cmulc(w, row[ca + q]);
+                sums[q] += p.x;
+                sums[NV / 2 + q] += p.y;
+            }
         }
-        static_assert(TSQR_NB == 4, "the column sums go through one eight-value wave reduction");
-        double sums[8] = {dr[0], dr[1], dr[2], dr[3], di[0], di[1], di[2], di[3]};
-        wave_sum8(sums);
-        cplx f[TSQR_NB];
+        wave_sum_n<NV>(sums);
+        cplx f[NQ];
 #pragma unroll
-        for (int q = 0; q < TSQR_NB; ++q) f[q] = {tj * sums[q], tj * sums[4 + q]};
+        for (int q = 0; q < NQ; ++q) f[q] = {tj * sums[q], tj * sums[NV / 2 + q]};
 #pragma unroll
         for (int m = 0; m < HH_SLOTS; ++m)
             if (lane + 64 * m < len) {
                 cplx *row = A + (size_t)ri[m] * ncp;
 #pragma unroll
-                for (int q = 0; q < TSQR_NB; ++q)
-                    if (q < n) row[ca + q] = csub(cv[m][q], cmul(f[q], wv[m]));
+                for (int q = 0; q < NQ; ++q) row[ca + q] = csub(cv[m][q], cmul(f[q], wv[m]));
             }
         for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
             cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
             const cplx w = row[j];
 #pragma unroll
-            for (int q = 0; q < TSQR_NB; ++q)
-                if (q < n) row[ca + q] = csub(row[ca + q], cmul(f[q], w));
+            for (int q = 0; q < NQ; ++q) row[ca + q] = csub(row[ca + q], cmul(f[q], w));
         }
         wave_lds_order();                           // reflector j+1 visits other rows per lane
+    }
+}
+__device__ __forceinline__ void hh_apply_wave(cplx *A, int ncp, int nr, int nc, int tri, const double *tau,
+                                              int ca, int n, int j0, int j1)
+{
+    static_assert(TSQR_NB == 4, "column counts 1..4");
+    switch (n) {
+    case 4: hh_apply_wave_n<4>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
+    case 3: hh_apply_wave_n<3>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
+    case 2: hh_apply_wave_n<2>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
+    case 1: hh_apply_wave_n<1>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
+    default: break;
     }
 }
 
