@@ -180,11 +180,12 @@ __device__ __forceinline__ double wave_max(double v)
     return fmax(lo, hi);
 }
 
-// Scalars of a Householder reflector. The column is scaled by s = 2^-e, the power of two that
-// takes its largest magnitude into [0.5, 1) (exact, and cheaper than a division); sqs is the
-// sum of squared moduli of the scaled entries below the leading one, x0 the unscaled leading
-// entry. Returns the factor cf that turns an unscaled entry below the leading one into w_i,
-// alpha = -phase(x0) |x| and tau = (|x0| + |x|) / |x| (in [1, 2]).
+// Scalars of a Householder reflector. The column is scaled by s = 2^-e, a power of two (e = 0 for
+// a column that needs no scaling, else the one that takes its largest magnitude into [0.5, 1):
+// exact, and cheaper than a division); sqs is the sum of squared moduli of the scaled entries
+// below the leading one, x0 the unscaled leading entry. Returns the factor cf that turns an
+// unscaled entry below the leading one into w_i, alpha = -phase(x0) |x| and
+// tau = (|x0| + |x|) / |x| (in [1, 2]).
 struct ReflScalars {
     cplx cf, alpha;
     double tau;
@@ -196,7 +197,7 @@ __device__ __forceinline__ ReflScalars reflector_scalars(cplx x0, double s, int 
     // not of unit modulus (the reflector would not be unitary); hypot then
     double a0 = sqrt(x0s.x * x0s.x + x0s.y * x0s.y);
     if (a0 < 1e-150) a0 = hypot(x0s.x, x0s.y);
-    const double nrm = sqrt(sqs + a0 * a0);         // >= 0.5: the largest entry scales to [0.5, 1)
+    const double nrm = sqrt(sqs + a0 * a0);
     const double ra = a0 > 1e-300 ? 1.0 / a0 : 0.0;
     const cplx ph = a0 > 1e-300 ? cplx{x0s.x * ra, x0s.y * ra} : cplx{1.0, 0.0};
     // w_i = x_i / v_j with v_j = phase (|x_j| + |x|) (in units of 2^e)
@@ -501,10 +502,12 @@ __device__ __forceinline__ void wave_lds_order()
 // rows are read again from LDS.
 constexpr int HH_SLOTS = 3;
 
-// reflector of column j over its support rows (one wave); see make_reflector. The largest
-// magnitude and the sum of squares come from one pass over the column; only a column whose
-// magnitude lies outside [1e-140, 1e140], where the raw squares could under- or overflow, is
-// summed a second time with the scaled values.
+// reflector of column j over its support rows (one wave); see make_reflector. One pass sums the
+// squared moduli of the entries below the leading one; when that sum and |x_j|^2 lie within
+// [1e-290, 1e290] no square has overflowed and those that underflowed are negligible, and the
+// reflector is formed from the unscaled column. Otherwise the largest magnitude is found, and the
+// column is scaled by a power of two as in make_reflector (a column below 1e-280 is left as it
+// is, tau = 0).
 #ifdef TTFP_PHASE_TIMING
 __shared__ double hh_refl_ticks;                    // time wave 0 spends forming reflectors
 #endif
@@ -517,7 +520,7 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
 #define REFL_DONE do {} while (0)
 #endif
     const int lane = threadIdx.x & 63;
-    double mx = 0.0, sq = 0.0;
+    double sq = 0.0;
     cplx xv[HH_SLOTS];
     int xi[HH_SLOTS];
 #pragma unroll
@@ -525,31 +528,35 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
         const int k = lane + 64 * m;
         xi[m] = k < len ? hh_row(k, j, nc, tri) : 0;
         xv[m] = k < len ? A[(size_t)xi[m] * ncp + j] : cplx{0.0, 0.0};
-        mx = fmax(mx, fmax(fabs(xv[m].x), fabs(xv[m].y)));
         if (k > 0) sq += cabs2(xv[m]);
     }
-    for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
-        const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
-        mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
-        sq += cabs2(v);
-    }
-    mx = wave_max(mx);
+    for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) sq += cabs2(A[(size_t)hh_row(k, j, nc, tri) * ncp + j]);
     sq = wave_sum(sq);
     const cplx x0 = A[(size_t)j * ncp + j];
-    if (!(mx >= 1e-280) || !(mx <= 1e300)) {
-        if (lane == 0) {
-            *alpha_out = x0;
-            *tau_out = 0.0;
-        }
-        REFL_DONE;
-        return;
-    }
-    int e;
-    frexp(mx, &e);
-    const double sc = ldexp(1.0, -e);
-    if (mx >= 1e-140 && mx <= 1e140) {
-        sq = sq * sc * sc;
+    const double all = sq + cabs2(x0);
+    ReflScalars r;
+    if (all >= 1e-290 && all <= 1e290) {
+        r = reflector_scalars(x0, 1.0, 0, sq);
     } else {
+        double mx = 0.0;
+#pragma unroll
+        for (int m = 0; m < HH_SLOTS; ++m) mx = fmax(mx, fmax(fabs(xv[m].x), fabs(xv[m].y)));
+        for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
+            const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
+            mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+        }
+        mx = wave_max(mx);
+        if (!(mx >= 1e-280) || !(mx <= 1e300)) {
+            if (lane == 0) {
+                *alpha_out = x0;
+                *tau_out = 0.0;
+            }
+            REFL_DONE;
+            return;
+        }
+        int e;
+        frexp(mx, &e);
+        const double sc = ldexp(1.0, -e);
         sq = 0.0;
 #pragma unroll
         for (int m = 0; m < HH_SLOTS; ++m)
@@ -559,8 +566,8 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
             sq += cabs2(cplx{v.x * sc, v.y * sc});
         }
         sq = wave_sum(sq);
+        r = reflector_scalars(x0, sc, e, sq);
     }
-    const ReflScalars r = reflector_scalars(x0, sc, e, sq);
 #pragma unroll
     for (int m = 0; m < HH_SLOTS; ++m) {
         const int k = lane + 64 * m;
