@@ -473,11 +473,14 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 // Triangularises A (nr x nc, row-major in LDS with an odd row stride ncp, so that both a row
 // and a column spread over the LDS banks) by Householder reflections H = I - tau w w^H, in
 // panels of TSQR_NB columns. A panel is factored inside one wave (wave 0), one panel ahead of
-// the trailing update that the other waves carry out (see householder_lds).
+// the trailing update that the other waves carry out (see householder_lds). Panels of one
+// column measured fastest (47.7 options/s on the d = 5 headline batch, against 46.4, 45.2 and
+// 45.0 for two, three and four): wave 0's chain per column is then one single-column
+// application and one reflector, at the price of a barrier per column.
 // tri > 0: A stacks tri upper-triangular nc x nc factors (a merge of the reduction tree); the
 // reflector of column j then touches only row j of the first factor and rows 0..j of the
 // others, and only those rows are visited. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
-constexpr int TSQR_NB = 4;
+constexpr int TSQR_NB = 1;
 
 __device__ __forceinline__ int hh_len(int j, int nr, int nc, int tri) { return tri ? 1 + (tri - 1) * (j + 1) : nr - j; }
 __device__ __forceinline__ int hh_row(int k, int j, int nc, int tri)
@@ -691,7 +694,7 @@ __device__ void hh_apply_wave_n(cplx *A, int ncp, int nr, int nc, int tri, const
 __device__ __forceinline__ void hh_apply_wave(cplx *A, int ncp, int nr, int nc, int tri, const double *tau,
                                               int ca, int n, int j0, int j1)
 {
-    static_assert(TSQR_NB == 4, "column counts 1..4");
+    static_assert(TSQR_NB >= 1 && TSQR_NB <= 4, "column counts 1..4");
     switch (n) {
     case 4: hh_apply_wave_n<4>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
     case 3: hh_apply_wave_n<3>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
