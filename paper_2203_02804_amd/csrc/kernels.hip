@@ -590,39 +590,49 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
 }
 
 // Applies reflectors j0..j1-1, in order, to columns [ca, cb). Threads t = 0..T-1 (T a multiple
-// of 64, every one of them calling) form groups of S adjacent lanes, one column per group,
-// which split the column's support rows; a dot product then needs an S-lane butterfly only.
+// of 64, every one of them calling) form groups of S adjacent lanes, one pair of adjacent columns
+// per group (w is read once for both), which split the columns' support rows; a dot product then
+// needs an S-lane butterfly only.
 __device__ void hh_apply_cols(cplx *A, int ncp, int nr, int nc, int tri, const double *tau,
                               int ca, int cb, int j0, int j1, int t, int T)
 {
     const int nt = cb - ca;
     if (nt <= 0 || j1 <= j0) return;
+    const int np = (nt + 1) / 2;                    // column pairs
     int S = 1;
-    while (S < 16 && 2 * S * nt <= T) S *= 2;
+    while (S < 16 && 2 * S * np <= T) S *= 2;
     const int sidx = t % S, per = T / S;
-    for (int cq = 0; cq < nt; cq += per) {
-        const int cl = cq + t / S;
-        const bool act = cl < nt;
-        const int c = ca + (act ? cl : 0);
+    for (int cq = 0; cq < np; cq += per) {
+        const int cp = cq + t / S;
+        const bool act = cp < np, hasB = act && 2 * cp + 1 < nt;
+        const int cA = ca + (act ? 2 * cp : 0), cB = hasB ? cA + 1 : cA;
         for (int j = j0; j < j1; ++j) {
             const double tj = tau[j];
             if (tj == 0.0) continue;                // same for every lane
             const int len = hh_len(j, nr, nc, tri);
-            double dr = 0.0, di = 0.0;
+            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
             if (act)
                 for (int k = sidx; k < len; k += S) {
-                    const int i = hh_row(k, j, nc, tri);
-                    const cplx p = cmulc(A[(size_t)i * ncp + j], A[(size_t)i * ncp + c]);
-                    dr += p.x;
-                    di += p.y;
+                    const cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
+                    const cplx w = row[j];
+                    const cplx p = cmulc(w, row[cA]), q = cmulc(w, row[cB]);
+                    ar += p.x;
+                    ai += p.y;
+                    br += q.x;
+                    bi += q.y;
                 }
-            dr = seg_sum(dr, S);
-            di = seg_sum(di, S);
-            const cplx f = {tj * dr, tj * di};
+            ar = seg_sum(ar, S);
+            ai = seg_sum(ai, S);
+            br = seg_sum(br, S);
+            bi = seg_sum(bi, S);
+            const cplx fA = {tj * ar, tj * ai}, fB = {tj * br, tj * bi};
             if (act)
                 for (int k = sidx; k < len; k += S) {
-                    const int i = hh_row(k, j, nc, tri);
-                    A[(size_t)i * ncp + c] = csub(A[(size_t)i * ncp + c], cmul(f, A[(size_t)i * ncp + j]));
+                    cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
+                    const cplx w = row[j];
+                    const cplx x = row[cA], y = row[cB];
+                    row[cA] = csub(x, cmul(fA, w));
+                    if (hasB) row[cB] = csub(y, cmul(fB, w));
                 }
         }
     }
@@ -725,7 +735,7 @@ __device__ void householder_lds(cplx *A, int nr, int nc, int ncp, int tri, cplx 
 #ifdef TTFP_PHASE_TIMING
     long long hh_t = wall_clock64();
     double hh_acc[3] = {0.0, 0.0, 0.0};
-#define HH_MARK(q) do { __syncthreads(); const long long n_ = wall_clock64(); hh_acc[q] += (double)(n_ - hh_t); hh_t = n_; } while (0)
+#define HH_MARK(q) do { const long long n_ = wall_clock64(); hh_acc[q] += (double)(n_ - hh_t); hh_t = n_; } while (0)
     // time from the panel's start to where wave 0 (q = 0) or wave 1 (q = 1) is done
 #define HH_PART(q) do { if (threadIdx.x == 64 * (q)) hh_acc[q] += (double)(wall_clock64() - hh_t); } while (0)
     if (threadIdx.x == 0) hh_refl_ticks = 0.0;
