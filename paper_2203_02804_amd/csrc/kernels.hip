@@ -103,6 +103,15 @@ __device__ __forceinline__ double seg_sum(double v, int S)
     if (S >= 16) v += dpp_move<0x140>(v);
     return v;
 }
+// largest value over each group of S adjacent lanes (S = 1, 2, 4, 8, 16), in every lane of it
+__device__ __forceinline__ double seg_max(double v, int S)
+{
+    if (S >= 2) v = fmax(v, dpp_move<0xB1>(v));
+    if (S >= 4) v = fmax(v, dpp_move<0x4E>(v));
+    if (S >= 8) v = fmax(v, dpp_move<0x141>(v));
+    if (S >= 16) v = fmax(v, dpp_move<0x140>(v));
+    return v;
+}
 // sum / max over the 64 lanes of a wave (all lanes active), returned in every lane as
 // (row0 + row1) + (row2 + row3), bit-identical across lanes
 __device__ __forceinline__ double wave_sum(double v)
@@ -209,6 +218,34 @@ __device__ __forceinline__ ReflScalars reflector_scalars(cplx x0, double s, int 
     return r;
 }
 
+struct ArgMax { double v; int i; };
+
+__device__ __forceinline__ ArgMax better(ArgMax a, ArgMax b)
+{
+    if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
+    return a;
+}
+
+// argmax within a wave (ties: lowest index) by DPP row permutations and readlanes: better() is a
+// total order on (value, index), so the mirror steps leave every lane of a row with the row's best
+template <int CTRL>
+__device__ __forceinline__ ArgMax dpp_best(ArgMax a)
+{
+    ArgMax b;
+    b.v = dpp_move<CTRL>(a.v);
+    b.i = __builtin_amdgcn_update_dpp(0, a.i, CTRL, 0xF, 0xF, false);
+    return better(a, b);
+}
+// best (value, lowest index) over the 64 lanes of a wave, in every lane
+__device__ __forceinline__ ArgMax wave_argmax(ArgMax a)
+{
+    a = dpp_best<0xB1>(a);
+    a = dpp_best<0x4E>(a);
+    a = dpp_best<0x141>(a);
+    a = dpp_best<0x140>(a);
+    for (int l = 16; l < 64; l += 16) a = better(a, ArgMax{read_lane(a.v, l), __builtin_amdgcn_readlane(a.i, l)});
+    return better(ArgMax{read_lane(a.v, 0), __builtin_amdgcn_readlane(a.i, 0)}, a);
+}
 // Householder reflector for the column x = (x_j, ..., x_{n-1}) (entry i at x[i * stride]), made by
 // wave 0 of the workgroup. The reflector is H = I - tau w w^H with w_j = 1, chosen so that
 // H x = (alpha, 0, ..., 0) with alpha = -phase(x_j) |x|. Every quantity is formed from the column
@@ -844,74 +881,79 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
 // ------------------------------------------------------------------ pivoted QR of R, rank, inverse
 __global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G)
 {
-    __shared__ cplx A[MAXNC * MAXNC];
+    __shared__ cplx A[MAXNC * (MAXNC | 1)];
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
     __shared__ double nrm[MAXNC];
+    __shared__ double tauq[MAXNC];
     __shared__ int perm[MAXNC];
     __shared__ cplx alph[MAXNC];
-    __shared__ double sh[4];
     __shared__ int shi[4];
     const int item = blockIdx.x;
     if (!active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
-    const int nc = s.nc;
+    const int nc = s.nc, ncp = nc | 1;              // odd row stride in LDS
+    const int nthr = blockDim.x;
     const size_t rsz = (size_t)nc * nc;
     const int lf = tsqr_final_level(s.rows, BR, G);
     const cplx *src = it.Rlev + (size_t)(lf & 1) * it.nblk_max * rsz;
-    for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) A[e] = src[e];
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) perm[c] = c;
+    for (int e = threadIdx.x; e < nc * nc; e += nthr) A[(e / nc) * ncp + e % nc] = src[e];
+    for (int c = threadIdx.x; c < nc; c += nthr) perm[c] = c;
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int j = 0; j < nc; ++j) {
-        // trailing column norms, formed from the column scaled by its largest entry so that
-        // tiny columns keep their order instead of underflowing to zero
-        for (int c = j + threadIdx.x; c < nc; c += blockDim.x) {
-            double mx = 0.0;
-            for (int i = j; i < nc; ++i) mx = fmax(mx, fmax(fabs(A[i * nc + c].x), fabs(A[i * nc + c].y)));
-            double q = 1.0;
-            if (mx >= 1e-280 && mx <= 1e300) {           // else mx itself orders the column
-                const double inv = 1.0 / mx;
-                q = 0.0;
-                for (int i = j; i < nc; ++i) q += cabs2(cplx{A[i * nc + c].x * inv, A[i * nc + c].y * inv});
+        // trailing column norms over rows j..nc-1, groups of S lanes per column; formed from the
+        // column scaled by its largest entry so that tiny columns keep their order instead of
+        // underflowing to zero (outside [1e-280, 1e300] the largest entry itself orders it)
+        {
+            const int ncol = nc - j;
+            int S = 1;
+            while (S < 16 && 2 * S * ncol <= nthr) S *= 2;
+            const int per = nthr / S, sidx = threadIdx.x % S;
+            for (int cq = 0; cq < ncol; cq += per) {
+                const int cl = cq + threadIdx.x / S;
+                const bool act = cl < ncol;
+                const int c = j + (act ? cl : 0);
+                double mx = 0.0;
+                if (act)
+                    for (int i = j + sidx; i < nc; i += S)
+                        mx = fmax(mx, fmax(fabs(A[i * ncp + c].x), fabs(A[i * ncp + c].y)));
+                mx = seg_max(mx, S);
+                const bool scaled = mx >= 1e-280 && mx <= 1e300;
+                const double inv = scaled ? 1.0 / mx : 0.0;
+                double q = 0.0;
+                if (act)
+                    for (int i = j + sidx; i < nc; i += S)
+                        q += cabs2(cplx{A[i * ncp + c].x * inv, A[i * ncp + c].y * inv});
+                q = seg_sum(q, S);
+                if (act && sidx == 0) nrm[c] = scaled ? mx * sqrt(q) : mx;
             }
-            nrm[c] = mx * sqrt(q);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int p = j;
-            for (int c = j + 1; c < nc; ++c)
-                if (nrm[c] > nrm[p]) p = c;
-            shi[0] = p;
-            if (p != j) { int tmp = perm[j]; perm[j] = perm[p]; perm[p] = tmp; }
-        }
-        __syncthreads();
-        const int p = shi[0];
-        if (p != j)
-            for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-                cplx tmp = A[i * nc + j];
-                A[i * nc + j] = A[i * nc + p];
-                A[i * nc + p] = tmp;
-            }
-        __syncthreads();
-        // Householder on column j, rows j..nc-1
-        if (wave == 0) make_reflector(A + j, nc, j, nc, &alph[j], &sh[0]);
-        __syncthreads();
-        const double beta = sh[0];
-        if (beta != 0.0)
-            for (int c = j + 1 + wave; c < nc; c += nw) {
-                double dr = 0.0, di = 0.0;
-                for (int i = j + lane; i < nc; i += 64) {
-                    cplx pr = cmulc(A[i * nc + j], A[i * nc + c]);
-                    dr += pr.x;
-                    di += pr.y;
+        // pivot (largest norm, lowest index on ties), column swap and reflector: wave 0
+        if (wave == 0) {
+            ArgMax bst = {-1.0, j};
+            for (int c = j + lane; c < nc; c += 64) bst = better(bst, ArgMax{nrm[c], c});
+            bst = wave_argmax(bst);
+            const int p = bst.i;
+            if (p != j) {
+                for (int i = lane; i < nc; i += 64) {
+                    const cplx tmp = A[i * ncp + j];
+                    A[i * ncp + j] = A[i * ncp + p];
+                    A[i * ncp + p] = tmp;
                 }
-                dr = wave_sum(dr);
-                di = wave_sum(di);
-                cplx f = {beta * dr, beta * di};
-                for (int i = j + lane; i < nc; i += 64) A[i * nc + c] = csub(A[i * nc + c], cmul(f, A[i * nc + j]));
+                if (lane == 0) {
+                    const int tp = perm[j];
+                    perm[j] = perm[p];
+                    perm[p] = tp;
+                }
             }
+            wave_lds_order();
+            make_reflector(A + j, ncp, j, nc, &alph[j], &tauq[j]);
+        }
+        __syncthreads();
+        hh_apply_cols(A, ncp, nc, nc, 0, tauq, j + 1, nc, j, j + 1, threadIdx.x, nthr);
         __syncthreads();
     }
     // rank: leading pivots above rank_eps * |R_00|
@@ -937,7 +979,7 @@ __global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, in
         for (int i = c - 1; i >= 0; --i) {
             cplx acc = {0.0, 0.0};
             for (int l = i + 1; l <= c; ++l) {
-                cplx ril = (l == i) ? alph[i] : A[i * nc + l];
+                cplx ril = (l == i) ? alph[i] : A[i * ncp + l];
                 acc = cadd(acc, cmul(ril, Ri[l * r + c]));
             }
             cplx rii = alph[i];
@@ -1029,35 +1071,8 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const i
 }
 
 // ------------------------------------------------------------------ maxvol
-struct ArgMax { double v; int i; };
-
-__device__ __forceinline__ ArgMax better(ArgMax a, ArgMax b)
-{
-    if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
-    return a;
-}
-
-// block-wide argmax (ties: lowest flat index); every thread receives the result. Within a wave
-// by DPP row permutations and readlanes (better() is a total order on (value, index), so the
-// mirror steps leave every lane of a row with the row's best); across waves through LDS.
-template <int CTRL>
-__device__ __forceinline__ ArgMax dpp_best(ArgMax a)
-{
-    ArgMax b;
-    b.v = dpp_move<CTRL>(a.v);
-    b.i = __builtin_amdgcn_update_dpp(0, a.i, CTRL, 0xF, 0xF, false);
-    return better(a, b);
-}
-// best (value, lowest index) over the 64 lanes of a wave, in every lane
-__device__ __forceinline__ ArgMax wave_argmax(ArgMax a)
-{
-    a = dpp_best<0xB1>(a);
-    a = dpp_best<0x4E>(a);
-    a = dpp_best<0x141>(a);
-    a = dpp_best<0x140>(a);
-    for (int l = 16; l < 64; l += 16) a = better(a, ArgMax{read_lane(a.v, l), __builtin_amdgcn_readlane(a.i, l)});
-    return better(ArgMax{read_lane(a.v, 0), __builtin_amdgcn_readlane(a.i, 0)}, a);
-}
+// block-wide argmax (ties: lowest flat index); every thread receives the result: within each wave
+// as above, across waves through LDS
 __device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
 {
     a = wave_argmax(a);
