@@ -117,12 +117,14 @@ def surrogate_leg(pricer, n_train, tt_rate):
             "calibration_factor": sur.factor, "gates": gates}
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "one_factor_config2prime.json")
+
+
 def load_refs(seed, n):
     """One-factor reference prices of config2_batch(n, seed, 'beta') from the stored golden file
     (written by tests/golden/make_one_factor_golden.py from the oracle), or None."""
-    path = os.path.join(ROOT, "tests", "golden", "one_factor_config2prime.json")
     try:
-        with open(path) as f:
+        with open(GOLDEN) as f:
             refs = json.load(f)["batches"].get(str(seed))
     except OSError:
         return None
@@ -156,7 +158,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=64, help="options per step")
+    ap.add_argument("--batch", type=int, default=192,
+                    help="options per step (960 work items: the one-workgroup-per-item kernels fill the CUs)")
     ap.add_argument("--N", type=int, default=256, help="nodes per dimension (headline workload)")
     ap.add_argument("--max-rank", type=int, default=64, help="rank cap (headline workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -171,8 +174,11 @@ def main():
               f"independent, so a multi-GPU run would split the batch by option; it is not measured here",
               file=sys.stderr)
         sys.exit(2)
-    if args.batch > 128 or args.warmup + args.steps > 6:
-        print("the stored references cover 6 batches of at most 128 options", file=sys.stderr)
+    with open(GOLDEN) as f:
+        stored = json.load(f)
+    if args.batch > stored["batch"] or args.warmup + args.steps > len(stored["batches"]):
+        print(f"the stored references cover {len(stored['batches'])} batches of at most {stored['batch']} options",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

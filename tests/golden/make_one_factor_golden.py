@@ -18,7 +18,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import workloads as W  # noqa: E402
 from oracle import closed_forms as CF  # noqa: E402
 
-BATCH = 128
+BATCH = 192
 SEEDS = [2203 + 1000 * s for s in range(6)]     # benchmark batches (warm-up + timed steps)
 
 
