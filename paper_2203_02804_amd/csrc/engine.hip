@@ -365,7 +365,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_BASIS);
-        hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows, 64), ny), dim3(256), 0, st, it, act, t, dir);
+        hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows, MM_ROWS_PER_WG), ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
@@ -376,7 +376,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     // interpolation matrix of every row, then refinement rounds (each returns at once for an
     // item whose rows all satisfy the dominance bound)
-    const unsigned gi = cdivu((long long)g.maxrows, 64);          // 64-row panels (k_interp)
+    const unsigned gi = cdivu((long long)g.maxrows, MM_ROWS_PER_WG);   // row blocks of k_interp
     for (int round = 0; round <= MAXVOL_REFINE_ROUNDS; ++round) {
         if (round > 0) {
             ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
@@ -386,7 +386,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
                                dir, rm);
         }
         ProfScope ps(ctx, TTFP_KERNEL_INTERP);
-        hipLaunchKernelGGL(k_interp, dim3(gi, ny), dim3(256), 0, st, it, act, t, dir, round > 0 ? 1 : 0);
+        hipLaunchKernelGGL(k_interp, dim3(gi, ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir, round > 0 ? 1 : 0);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_FINISH);
@@ -1099,10 +1099,10 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
         hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
         // refinement rounds until every row satisfies the dominance bound (each round returns at
         // once when none violates)
-        const unsigned gi = cdivu((long long)m, 64);
+        const unsigned gi = cdivu((long long)m, MM_ROWS_PER_WG);
         for (int round = 0; round <= 8; ++round) {
             if (round > 0) hipLaunchKernelGGL(k_maxvol_refine, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
-            hipLaunchKernelGGL(k_interp, dim3(gi, 1), dim3(256), 0, ctx->stream, dit, act, 0, 2, round > 0 ? 1 : 0);
+            hipLaunchKernelGGL(k_interp, dim3(gi, 1), dim3(64 * MM_WAVES), 0, ctx->stream, dit, act, 0, 2, round > 0 ? 1 : 0);
         }
         e = hipGetLastError();
     }

@@ -999,7 +999,7 @@ __global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, in
 // triangular inverse is held in LDS with its zero lower part. Each row's squared norm is left
 // in four-column partial sums in its key slots (the start of maxvol reads them).
 typedef double double4_t __attribute__((ext_vector_type(4)));
-constexpr int PANEL_WAVES = 4;                   // 16-row panels per workgroup
+constexpr int PANEL_WAVES = MM_WAVES;            // 16-row panels per workgroup
 __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const int *active, int t, int dir)
 {
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
@@ -1028,19 +1028,9 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const i
         cim[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int arow = row0 + li;
-    // the lane's kept fiber entries (columns perm[lk], perm[lk + 4], ...) are loaded first
-    constexpr int KS = TTFP_MAX_RANK / 4;
-    cplx av[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int kk = 4 * ks + lk;
-        av[ks] = (arow < m && kk < r) ? it.F[(size_t)arow * nc + pm[kk]] : cplx{0.0, 0.0};
-    }
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        if (4 * ks >= r) break;
-        const int kk = 4 * ks + lk;
-        const cplx a = av[ks];
+    for (int k0 = 0; k0 < r; k0 += 4) {
+        const int kk = k0 + lk;
+        const cplx a = (arow < m && kk < r) ? it.F[(size_t)arow * nc + pm[kk]] : cplx{0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= ntile) break;
@@ -1580,7 +1570,7 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
 // against a host product). B goes straight into the core's slot. Rows whose largest |B_ij|
 // exceeds 1 + delta are marked (largest squared modulus in viol) and the item is flagged for a
 // refinement round. mode 1: only after a refinement that moved a pivot.
-constexpr int INTERP_WAVES = 4;                  // 16-row panels per workgroup
+constexpr int INTERP_WAVES = MM_WAVES;           // 16-row panels per workgroup
 __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const int *active, int t, int dir, int mode)
 {
     __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
@@ -1609,20 +1599,9 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
         cim[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int arow = row0 + li;
-    // the lane's whole slice of its Y row (entries lk, lk + 4, ...) is loaded before the
-    // products, so the loads are in flight together
-    constexpr int KS = TTFP_MAX_RANK / 4;
-    cplx av[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int kk = 4 * ks + lk;
-        av[ks] = (arow < m && kk < r) ? Y[(size_t)arow * r + kk] : cplx{0.0, 0.0};
-    }
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        if (4 * ks >= r) break;
-        const int kk = 4 * ks + lk;
-        const cplx a = av[ks];
+    for (int k0 = 0; k0 < r; k0 += 4) {
+        const int kk = k0 + lk;
+        const cplx a = (arow < m && kk < r) ? Y[(size_t)arow * r + kk] : cplx{0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= ntile) break;
