@@ -361,7 +361,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_QRCP);
-        hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(256), 0, st, it, act, t, dir, g.BR, g.G);
+        hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(QRCP_THREADS), 0, st, it, act, t, dir, g.BR, g.G);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_BASIS);

@@ -879,7 +879,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
 }
 
 // ------------------------------------------------------------------ pivoted QR of R, rank, inverse
-__global__ __launch_bounds__(256) void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G)
+__global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G)
 {
     __shared__ cplx A[MAXNC * (MAXNC | 1)];
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
