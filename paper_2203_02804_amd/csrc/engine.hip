@@ -81,15 +81,20 @@ struct Launch {
     int BR, G, nlev, maxd, maxrows, maxnc, maxR, maxN;
 };
 
-// TSQR geometry: groups of G stacked nc x nc factors fit the LDS budget (rows padded to an odd
-// stride nc | 1), and leaf blocks have BR = G * nc rows.
+// TSQR geometry: leaf blocks of BR = Gl nc rows of the fiber, padded row-major (odd stride
+// nc | 1), and merges of G triangular factors packed by rows (nc (nc + 1) / 2 entries each),
+// both within the LDS budget (at nc = 68: two 68-row groups per leaf, four factors per merge).
 void tsqr_geometry(int nc, int &BR, int &G, int lds_kb = LDS_BYTES / 1024)
 {
     const int cap = std::min(lds_kb * 1024, LDS_BYTES) / (int)sizeof(cplx);
-    G = std::max(2, std::min(cap / (nc * (nc | 1)), 512 / nc));
-    BR = G * nc;
+    const int Gl = std::max(2, std::min(cap / (nc * (nc | 1)), 512 / nc));
+    BR = Gl * nc;
+    G = std::max(2, std::min(cap / (nc * (nc + 1) / 2), 8));
 }
-size_t tsqr_lds_bytes(int BR, int maxnc) { return (size_t)BR * (maxnc | 1) * sizeof(cplx); }
+size_t tsqr_lds_bytes(int BR, int G, int maxnc)
+{
+    return std::max((size_t)BR * (maxnc | 1), (size_t)G * maxnc * (maxnc + 1) / 2) * sizeof(cplx);
+}
 int tsqr_levels(int rows, int BR, int G)
 {
     int n = (rows + BR - 1) / BR, l = 1;
@@ -353,7 +358,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     {
         ProfScope ps(ctx, TTFP_KERNEL_TSQR);
         int n = (g.maxrows + g.BR - 1) / g.BR;
-        const size_t lds = tsqr_lds_bytes(g.BR, g.maxnc);
+        const size_t lds = tsqr_lds_bytes(g.BR, g.G, g.maxnc);
         for (int level = 0; level < g.nlev; ++level) {
             hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(n, 1), ny), dim3(TSQR_THREADS), lds, st, it, act, t, dir, level, g.BR, g.G);
             n = (n + g.G - 1) / g.G;
@@ -1053,7 +1058,7 @@ int ttfp_qr_r(ttfp_ctx *ctx, int32_t m, int32_t n, const double *A, double *R)
     const int nlev = tsqr_levels(m, BR, G);
     int nb = (m + BR - 1) / BR;
     for (int level = 0; !e && level < nlev; ++level) {
-        hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(nb, 1), 1), dim3(TSQR_THREADS), tsqr_lds_bytes(BR, std::max(n, 4)), ctx->stream, dit, act, 0, 2,
+        hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(nb, 1), 1), dim3(TSQR_THREADS), tsqr_lds_bytes(BR, G, std::max(n, 4)), ctx->stream, dit, act, 0, 2,
                            level, BR, G);
         e = hipGetLastError();
         nb = (nb + G - 1) / G;

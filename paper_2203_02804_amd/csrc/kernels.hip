@@ -517,6 +517,26 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 // tri > 0: A stacks tri upper-triangular nc x nc factors (a merge of the reduction tree); the
 // reflector of column j then touches only row j of the first factor and rows 0..j of the
 // others, and only those rows are visited. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
+// Row addressing of the block being triangularised: row(r) of a stacked row index r (as from
+// hh_row) is a pointer p with p[c] the entry (r, c).
+struct RowsPadded {                               // row-major, odd row stride ncp
+    cplx *A;
+    int ncp;
+    __device__ __forceinline__ cplx *row(int r) const { return A + (size_t)r * ncp; }
+};
+// Stacked upper-triangular nc x nc factors, each packed by rows (row i holds columns i..nc-1,
+// tp = nc (nc + 1) / 2 entries a factor): a merge of the reduction tree touches only entries
+// (i, c) with c >= i, and four factors of 68 columns fit where two unpacked ones did.
+struct RowsPacked {
+    cplx *A;
+    int nc, tp;
+    __device__ __forceinline__ cplx *row(int r) const
+    {
+        const int b = r / nc, i = r - b * nc;
+        return A + (size_t)b * tp + i * nc - (i * (i - 1)) / 2 - i;
+    }
+};
+
 constexpr int TSQR_NB = 1;
 
 __device__ __forceinline__ int hh_len(int j, int nr, int nc, int tri) { return tri ? 1 + (tri - 1) * (j + 1) : nr - j; }
@@ -551,7 +571,8 @@ constexpr int HH_SLOTS = 3;
 #ifdef TTFP_PHASE_TIMING
 __shared__ double hh_refl_ticks;                    // time wave 0 spends forming reflectors
 #endif
-__device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, int tri, cplx *alpha_out, double *tau_out)
+template <class L>
+__device__ void make_reflector_rows(const L &Lr, int j, int len, int nc, int tri, cplx *alpha_out, double *tau_out)
 {
 #ifdef TTFP_PHASE_TIMING
     const long long t_in = wall_clock64();
@@ -567,12 +588,12 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
     for (int m = 0; m < HH_SLOTS; ++m) {
         const int k = lane + 64 * m;
         xi[m] = k < len ? hh_row(k, j, nc, tri) : 0;
-        xv[m] = k < len ? A[(size_t)xi[m] * ncp + j] : cplx{0.0, 0.0};
+        xv[m] = k < len ? Lr.row(xi[m])[j] : cplx{0.0, 0.0};
         if (k > 0) sq += cabs2(xv[m]);
     }
-    for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) sq += cabs2(A[(size_t)hh_row(k, j, nc, tri) * ncp + j]);
+    for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) sq += cabs2(Lr.row(hh_row(k, j, nc, tri))[j]);
     sq = wave_sum(sq);
-    const cplx x0 = A[(size_t)j * ncp + j];
+    const cplx x0 = Lr.row(j)[j];
     const double all = sq + cabs2(x0);
     ReflScalars r;
     if (all >= 1e-290 && all <= 1e290) {
@@ -582,7 +603,7 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
 #pragma unroll
         for (int m = 0; m < HH_SLOTS; ++m) mx = fmax(mx, fmax(fabs(xv[m].x), fabs(xv[m].y)));
         for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
-            const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
+            const cplx v = Lr.row(hh_row(k, j, nc, tri))[j];
             mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
         }
         mx = wave_max(mx);
@@ -602,7 +623,7 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
         for (int m = 0; m < HH_SLOTS; ++m)
             if (lane + 64 * m > 0) sq += cabs2(cplx{xv[m].x * sc, xv[m].y * sc});
         for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
-            const cplx v = A[(size_t)hh_row(k, j, nc, tri) * ncp + j];
+            const cplx v = Lr.row(hh_row(k, j, nc, tri))[j];
             sq += cabs2(cplx{v.x * sc, v.y * sc});
         }
         sq = wave_sum(sq);
@@ -611,14 +632,14 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
 #pragma unroll
     for (int m = 0; m < HH_SLOTS; ++m) {
         const int k = lane + 64 * m;
-        if (k > 0 && k < len) A[(size_t)xi[m] * ncp + j] = cmul(xv[m], r.cf);
+        if (k > 0 && k < len) Lr.row(xi[m])[j] = cmul(xv[m], r.cf);
     }
     for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
-        cplx *p = A + (size_t)hh_row(k, j, nc, tri) * ncp + j;
+        cplx *p = Lr.row(hh_row(k, j, nc, tri)) + j;
         *p = cmul(*p, r.cf);
     }
     if (lane == 0) {
-        A[(size_t)j * ncp + j] = {1.0, 0.0};
+        Lr.row(j)[j] = {1.0, 0.0};
         *alpha_out = r.alpha;
         *tau_out = r.tau;
     }
@@ -630,7 +651,8 @@ __device__ void make_reflector_rows(cplx *A, int ncp, int j, int len, int nc, in
 // of 64, every one of them calling) form groups of S adjacent lanes, one pair of adjacent columns
 // per group (w is read once for both), which split the columns' support rows; a dot product then
 // needs an S-lane butterfly only.
-__device__ void hh_apply_cols(cplx *A, int ncp, int nr, int nc, int tri, const double *tau,
+template <class L>
+__device__ void hh_apply_cols(const L &Lr, int nr, int nc, int tri, const double *tau,
                               int ca, int cb, int j0, int j1, int t, int T)
 {
     const int nt = cb - ca;
@@ -650,7 +672,7 @@ __device__ void hh_apply_cols(cplx *A, int ncp, int nr, int nc, int tri, const d
             double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
             if (act)
                 for (int k = sidx; k < len; k += S) {
-                    const cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
+                    const cplx *row = Lr.row(hh_row(k, j, nc, tri));
                     const cplx w = row[j];
                     const cplx p = cmulc(w, row[cA]), q = cmulc(w, row[cB]);
                     ar += p.x;
@@ -665,7 +687,7 @@ __device__ void hh_apply_cols(cplx *A, int ncp, int nr, int nc, int tri, const d
             const cplx fA = {tj * ar, tj * ai}, fB = {tj * br, tj * bi};
             if (act)
                 for (int k = sidx; k < len; k += S) {
-                    cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
+                    cplx *row = Lr.row(hh_row(k, j, nc, tri));
                     const cplx w = row[j];
                     const cplx x = row[cA], y = row[cB];
                     row[cA] = csub(x, cmul(fA, w));
@@ -679,8 +701,8 @@ __device__ void hh_apply_cols(cplx *A, int ncp, int nr, int nc, int tri, const d
 // calling wave: each lane takes every 64th support row for all NQ columns, so one pass over the
 // rows forms the NQ dot products (reduced across the wave together) and a second one updates;
 // the first HH_SLOTS rows of a lane stay in registers between the passes.
-template <int NQ>
-__device__ void hh_apply_wave_n(cplx *A, int ncp, int nr, int nc, int tri, const double *tau, int ca, int j0, int j1)
+template <int NQ, class L>
+__device__ void hh_apply_wave_n(const L &Lr, int nr, int nc, int tri, const double *tau, int ca, int j0, int j1)
 {
     constexpr int NV = NQ == 3 ? 8 : 2 * NQ;     // sums per reflector (real and imaginary parts)
     const int lane = threadIdx.x & 63;
@@ -698,7 +720,7 @@ __device__ void hh_apply_wave_n(cplx *A, int ncp, int nr, int nc, int tri, const
             const int k = lane + 64 * m;
             const bool in = k < len;
             ri[m] = in ? hh_row(k, j, nc, tri) : 0;
-            const cplx *row = A + (size_t)ri[m] * ncp;
+            const cplx *row = Lr.row(ri[m]);
             wv[m] = in ? row[j] : cplx{0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -709,7 +731,7 @@ __device__ void hh_apply_wave_n(cplx *A, int ncp, int nr, int nc, int tri, const
             }
         }
         for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
-            const cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
+            const cplx *row = Lr.row(hh_row(k, j, nc, tri));
             const cplx w = row[j];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -725,12 +747,12 @@ __device__ void hh_apply_wave_n(cplx *A, int ncp, int nr, int nc, int tri, const
 #pragma unroll
         for (int m = 0; m < HH_SLOTS; ++m)
             if (lane + 64 * m < len) {
-                cplx *row = A + (size_t)ri[m] * ncp;
+                cplx *row = Lr.row(ri[m]);
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) row[ca + q] = csub(cv[m][q], cmul(f[q], wv[m]));
             }
         for (int k = lane + 64 * HH_SLOTS; k < len; k += 64) {
-            cplx *row = A + (size_t)hh_row(k, j, nc, tri) * ncp;
+            cplx *row = Lr.row(hh_row(k, j, nc, tri));
             const cplx w = row[j];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) row[ca + q] = csub(row[ca + q], cmul(f[q], w));
@@ -738,27 +760,29 @@ __device__ void hh_apply_wave_n(cplx *A, int ncp, int nr, int nc, int tri, const
         wave_lds_order();                           // reflector j+1 visits other rows per lane
     }
 }
-__device__ __forceinline__ void hh_apply_wave(cplx *A, int ncp, int nr, int nc, int tri, const double *tau,
+template <class L>
+__device__ __forceinline__ void hh_apply_wave(const L &Lr, int nr, int nc, int tri, const double *tau,
                                               int ca, int n, int j0, int j1)
 {
     static_assert(TSQR_NB >= 1 && TSQR_NB <= 4, "column counts 1..4");
     switch (n) {
-    case 4: hh_apply_wave_n<4>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
-    case 3: hh_apply_wave_n<3>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
-    case 2: hh_apply_wave_n<2>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
-    case 1: hh_apply_wave_n<1>(A, ncp, nr, nc, tri, tau, ca, j0, j1); break;
+    case 4: hh_apply_wave_n<4>(Lr, nr, nc, tri, tau, ca, j0, j1); break;
+    case 3: hh_apply_wave_n<3>(Lr, nr, nc, tri, tau, ca, j0, j1); break;
+    case 2: hh_apply_wave_n<2>(Lr, nr, nc, tri, tau, ca, j0, j1); break;
+    case 1: hh_apply_wave_n<1>(Lr, nr, nc, tri, tau, ca, j0, j1); break;
     default: break;
     }
 }
 
 // Factors the panel of columns c..c+n-1 (n <= TSQR_NB) within the calling wave: each
 // reflector is formed and then applied to the panel's later columns.
-__device__ void hh_factor_panel_wave(cplx *A, int ncp, int nr, int nc, int tri, cplx *alph, double *tau, int c, int n)
+template <class L>
+__device__ void hh_factor_panel_wave(const L &Lr, int nr, int nc, int tri, cplx *alph, double *tau, int c, int n)
 {
     for (int j = c; j < c + n; ++j) {
-        make_reflector_rows(A, ncp, j, hh_len(j, nr, nc, tri), nc, tri, &alph[j], &tau[j]);
+        make_reflector_rows(Lr, j, hh_len(j, nr, nc, tri), nc, tri, &alph[j], &tau[j]);
         wave_lds_order();
-        hh_apply_wave(A, ncp, nr, nc, tri, tau, j + 1, c + n - j - 1, j, j + 1);
+        hh_apply_wave(Lr, nr, nc, tri, tau, j + 1, c + n - j - 1, j, j + 1);
     }
 }
 
@@ -766,7 +790,8 @@ __device__ void hh_factor_panel_wave(cplx *A, int ncp, int nr, int nc, int tri, 
 // waves apply panel P's reflectors to the columns beyond panel P+1, wave 0 applies them to
 // panel P+1's columns and factors panel P+1 by itself. The two parts touch disjoint columns
 // and read panel P's reflectors only, so one barrier per panel separates the steps.
-__device__ void householder_lds(cplx *A, int nr, int nc, int ncp, int tri, cplx *alph, double *tau, double *ph)
+template <class L>
+__device__ void householder_lds(const L &Lr, int nr, int nc, int tri, cplx *alph, double *tau, double *ph)
 {
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #ifdef TTFP_PHASE_TIMING
@@ -782,19 +807,19 @@ __device__ void householder_lds(cplx *A, int nr, int nc, int ncp, int tri, cplx 
 #endif
     const int jmax = nr < nc ? nr : nc;
     const int t0 = nw > 1 ? 64 : 0;                 // first thread of the trailing update
-    if (jmax > 0 && wave == 0) hh_factor_panel_wave(A, ncp, nr, nc, tri, alph, tau, 0, min(TSQR_NB, jmax));
+    if (jmax > 0 && wave == 0) hh_factor_panel_wave(Lr, nr, nc, tri, alph, tau, 0, min(TSQR_NB, jmax));
     __syncthreads();
     HH_MARK(2);
     for (int j0 = 0; j0 < jmax; j0 += TSQR_NB) {
         const int j1 = min(j0 + TSQR_NB, jmax);     // panel P: reflectors j0..j1-1 are formed
         const int n1 = min(TSQR_NB, jmax - j1);     // width of panel P+1 (0 at the end)
         if (wave == 0 && n1 > 0) {
-            hh_apply_wave(A, ncp, nr, nc, tri, tau, j1, n1, j0, j1);
-            hh_factor_panel_wave(A, ncp, nr, nc, tri, alph, tau, j1, n1);
+            hh_apply_wave(Lr, nr, nc, tri, tau, j1, n1, j0, j1);
+            hh_factor_panel_wave(Lr, nr, nc, tri, alph, tau, j1, n1);
         }
         HH_PART(0);
         if ((int)threadIdx.x >= t0)
-            hh_apply_cols(A, ncp, nr, nc, tri, tau, j1 + n1, nc, j0, j1, threadIdx.x - t0, blockDim.x - t0);
+            hh_apply_cols(Lr, nr, nc, tri, tau, j1 + n1, nc, j0, j1, threadIdx.x - t0, blockDim.x - t0);
         HH_PART(1);
         __syncthreads();
         HH_MARK(2);
@@ -821,8 +846,9 @@ __device__ __forceinline__ int tsqr_final_level(int rows, int BR, int G)
     return l;
 }
 
-// One TSQR level: level 0 reduces row blocks of the fiber, level L > 0 groups of G
-// triangular factors of level L-1. Writes nc x nc factors into buffer (level % 2).
+// One TSQR level: level 0 reduces row blocks of the fiber (BR rows, padded row-major in LDS),
+// level L > 0 groups of G triangular factors of level L-1 (packed by rows in LDS). Writes
+// nc x nc factors into buffer (level % 2).
 __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G)
 {
     extern __shared__ cplx lds[];
@@ -843,7 +869,8 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
         it.work[TTFP_KERNEL_TSQR] += 8.0 * m * n * n - 8.0 / 3.0 * n * n * n;
     }
     const size_t rsz = (size_t)nc * nc;
-    const int ncp = nc | 1;                          // odd row stride in LDS
+    const int ncp = nc | 1;                          // odd row stride of a leaf block in LDS
+    const int tp = nc * (nc + 1) / 2;                // entries of a packed triangular factor
     cplx *A = lds;
     int nr, tri = 0;
     const cplx *src;
@@ -859,21 +886,36 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
         src = it.Rlev + (size_t)((level - 1) & 1) * it.nblk_max * rsz + (size_t)g0 * rsz;
     }
     PHASE_START;
-    // coalesced read of nr row-major rows into the padded row-major LDS block
-    for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
-        const int i = e / nc, c = e % nc;
-        A[(size_t)i * ncp + c] = src[e];
+    if (level == 0) {
+        // coalesced read of nr row-major rows into the padded row-major LDS block
+        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
+            const int i = e / nc, c = e % nc;
+            A[(size_t)i * ncp + c] = src[e];
+        }
+    } else {
+        // the upper triangles of the tri factors, packed by rows
+        for (int e = threadIdx.x; e < tri * (int)rsz; e += blockDim.x) {
+            const int b = e / (int)rsz, w = e - b * (int)rsz, i = w / nc, c = w - i * nc;
+            if (c >= i) A[(size_t)b * tp + i * nc - (i * (i - 1)) / 2 + (c - i)] = src[e];
+        }
     }
     __syncthreads();
     PHASE_MARK(8);
-    householder_lds(A, nr, nc, ncp, tri, alph, tau, it.phase + 12);
+    if (level == 0)
+        householder_lds(RowsPadded{A, ncp}, nr, nc, 0, alph, tau, it.phase + 12);
+    else
+        householder_lds(RowsPacked{A, nc, tp}, nr, nc, tri, alph, tau, it.phase + 12);
     PHASE_MARK(9);
     cplx *dst = it.Rlev + (size_t)(level & 1) * it.nblk_max * rsz + (size_t)blk * rsz;
     const int jmax = nr < nc ? nr : nc;
     for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) {
         int j = e / nc, c = e % nc;
         cplx v = {0.0, 0.0};
-        if (j < jmax && c >= j) v = (c == j) ? alph[j] : A[(size_t)j * ncp + c];
+        if (j < jmax && c >= j) {
+            // row j of R: the first factor's row j
+            const cplx *rowj = level == 0 ? A + (size_t)j * ncp : A + j * nc - (j * (j - 1)) / 2 - j;
+            v = (c == j) ? alph[j] : rowj[c];
+        }
         dst[e] = v;
     }
 }
@@ -953,7 +995,7 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
             make_reflector(A + j, ncp, j, nc, &alph[j], &tauq[j]);
         }
         __syncthreads();
-        hh_apply_cols(A, ncp, nc, nc, 0, tauq, j + 1, nc, j, j + 1, threadIdx.x, nthr);
+        hh_apply_cols(RowsPadded{A, ncp}, nc, nc, 0, tauq, j + 1, nc, j, j + 1, threadIdx.x, nthr);
         __syncthreads();
     }
     // rank: leading pivots above rank_eps * |R_00|
