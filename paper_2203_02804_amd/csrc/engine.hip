@@ -82,14 +82,17 @@ struct Launch {
 };
 
 // TSQR geometry: leaf blocks of BR = Gl nc rows of the fiber, padded row-major (odd stride
-// nc | 1), and merges of G triangular factors packed by rows (nc (nc + 1) / 2 entries each),
-// both within the LDS budget (at nc = 68: two 68-row groups per leaf, four factors per merge).
+// nc | 1), and merges of G <= 3 triangular factors packed by rows (nc (nc + 1) / 2 entries
+// each), both within the LDS budget. Three factors per merge measured fastest at nc = 68 (67.6
+// options/s on the d = 5 headline batch of 192 options against 67.0 with four, and 58.2 against 51.3
+// at 64 options for four against two unpacked): the merges are bound by the serial chain of
+// reflectors, so fewer merges pay, until the longer reflectors cost more than they save.
 void tsqr_geometry(int nc, int &BR, int &G, int lds_kb = LDS_BYTES / 1024)
 {
     const int cap = std::min(lds_kb * 1024, LDS_BYTES) / (int)sizeof(cplx);
     const int Gl = std::max(2, std::min(cap / (nc * (nc | 1)), 512 / nc));
     BR = Gl * nc;
-    G = std::max(2, std::min(cap / (nc * (nc + 1) / 2), 8));
+    G = std::max(2, std::min(cap / (nc * (nc + 1) / 2), 3));
 }
 size_t tsqr_lds_bytes(int BR, int G, int maxnc)
 {
