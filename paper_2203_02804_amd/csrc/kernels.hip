@@ -1037,7 +1037,7 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
 
 // ------------------------------------------------------------------ basis of the kept columns
 // Y = F[:, perm[:r]] R2^{-1} on the FP64 matrix cores, laid out as in k_interp (a wave forms a
-// 16-row panel as up to four 16 x 16 complex tiles, four real MFMA products each); the
+// 16-row panel as up to four 16 x 16 complex tiles, three real MFMA products each); the
 // triangular inverse is held in LDS with its zero lower part. Each row's squared norm is left
 // in four-column partial sums in its key slots (the start of maxvol reads them).
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -1063,11 +1063,14 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const i
     if (row0 >= m) return;
     const int li = lane & 15, lk = lane >> 4;
     const int ntile = (r + 15) / 16;
-    double4_t cre[4], cim[4];
+    // complex products by three real ones (Gauss): prr = Ar Br, pii = Ai Bi, pss = (Ar + Ai)(Br + Bi);
+    // re = prr - pii, im = pss - prr - pii
+    double4_t prr[4], pii[4], pss[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        cre[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-        cim[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        pii[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int arow = row0 + li;
     for (int k0 = 0; k0 < r; k0 += 4) {
@@ -1078,10 +1081,9 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const i
             if (q >= ntile) break;
             const int jj = 16 * q + li;
             const cplx b = (kk < r && jj < r) ? Ri[kk * r + jj] : cplx{0.0, 0.0};
-            cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cre[q], 0, 0, 0);
-            cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cre[q], 0, 0, 0);
-            cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, cim[q], 0, 0, 0);
-            cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim[q], 0, 0, 0);
+            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
+            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
+            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -1091,7 +1093,7 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const i
         for (int q = 0; q < 4; ++q) {
             if (q >= ntile) break;
             const int col = 16 * q + li;
-            const cplx val = {cre[q][v], cim[q][v]};
+            const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
             double nrm = (row < m && col < r) ? cabs2(val) : 0.0;
             if (row < m && col < r) it.Y[(size_t)row * r + col] = val;
             // partial squared norm over the four columns 4 (col / 4) .. 4 (col / 4) + 3
@@ -1605,8 +1607,9 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
 }
 
 // B = Y A^{-1} for every row on the FP64 matrix cores: a wave forms a 16-row panel of B (all r
-// columns, as up to four 16 x 16 tiles) with v_mfma_f64_16x16x4f64, the complex product as four
-// real ones (re = Yr Ar - Yi Ai, im = Yr Ai + Yi Ar); A^{-1} is held in LDS. Lane l supplies
+// columns, as up to four 16 x 16 tiles) with v_mfma_f64_16x16x4f64, the complex product as three
+// real ones (Gauss: re = Yr Ar - Yi Ai, im = (Yr + Yi)(Ar + Ai) - Yr Ar - Yi Ai; the rounding
+// error stays of the order of |Y||A| as with four products); A^{-1} is held in LDS. Lane l supplies
 // A-operand entry (row l % 16, k l / 16) and B-operand entry (k l / 16, column l % 16), and holds
 // accumulator rows l / 16 + 4 v, column l % 16 (v = 0..3; the layout was checked by a probe
 // against a host product). B goes straight into the core's slot. Rows whose largest |B_ij|
@@ -1634,11 +1637,14 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
     const int li = lane & 15, lk = lane >> 4;
     const int ntile = (r + 15) / 16;
     const cplx *Y = it.Y;
-    double4_t cre[4], cim[4];
+    // complex products by three real ones (Gauss): prr = Ar Br, pii = Ai Bi, pss = (Ar + Ai)(Br + Bi);
+    // re = prr - pii, im = pss - prr - pii
+    double4_t prr[4], pii[4], pss[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        cre[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-        cim[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        pii[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int arow = row0 + li;
     for (int k0 = 0; k0 < r; k0 += 4) {
@@ -1649,10 +1655,9 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
             if (q >= ntile) break;
             const int jj = 16 * q + li;
             const cplx b = (kk < r && jj < r) ? Ai[kk * r + jj] : cplx{0.0, 0.0};
-            cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cre[q], 0, 0, 0);
-            cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cre[q], 0, 0, 0);
-            cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, cim[q], 0, 0, 0);
-            cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim[q], 0, 0, 0);
+            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
+            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
+            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
         }
     }
     // the core slot holds B itself for a left-to-right step (rows (a, i), columns b: the core's
@@ -1669,7 +1674,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
             if (q >= ntile) break;
             const int col = 16 * q + li;
             if (row < m && col < r) {
-                const cplx val = {cre[q][v], cim[q][v]};
+                const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
                 B[dir == 1 ? (size_t)col * m + row : (size_t)row * r + col] = val;
                 mx = fmax(mx, cabs2(val));
             }
