@@ -21,7 +21,7 @@ constexpr int MM_ROWS_PER_WG = 16 * MM_WAVES;
 constexpr int QRCP_THREADS = 1024;
 constexpr int MAXN = 1024;                   // nodes per coordinate
 constexpr int LDS_BYTES = 152 * 1024;        // per-workgroup LDS budget of the QR kernels
-constexpr int TSQR_THREADS = 512;            // threads of a TSQR workgroup
+constexpr int TSQR_THREADS = 1024;           // threads of a TSQR workgroup
 
 struct cplx { double x, y; };
 

@@ -765,13 +765,11 @@ __device__ __forceinline__ void hh_apply_wave(const L &Lr, int nr, int nc, int t
                                               int ca, int n, int j0, int j1)
 {
     static_assert(TSQR_NB >= 1 && TSQR_NB <= 4, "column counts 1..4");
-    switch (n) {
-    case 4: hh_apply_wave_n<4>(Lr, nr, nc, tri, tau, ca, j0, j1); break;
-    case 3: hh_apply_wave_n<3>(Lr, nr, nc, tri, tau, ca, j0, j1); break;
-    case 2: hh_apply_wave_n<2>(Lr, nr, nc, tri, tau, ca, j0, j1); break;
-    case 1: hh_apply_wave_n<1>(Lr, nr, nc, tri, tau, ca, j0, j1); break;
-    default: break;
-    }
+    // only the widths a panel of TSQR_NB columns can ask for are instantiated (registers)
+    if constexpr (TSQR_NB >= 4) if (n == 4) hh_apply_wave_n<4>(Lr, nr, nc, tri, tau, ca, j0, j1);
+    if constexpr (TSQR_NB >= 3) if (n == 3) hh_apply_wave_n<3>(Lr, nr, nc, tri, tau, ca, j0, j1);
+    if constexpr (TSQR_NB >= 2) if (n == 2) hh_apply_wave_n<2>(Lr, nr, nc, tri, tau, ca, j0, j1);
+    if (n == 1) hh_apply_wave_n<1>(Lr, nr, nc, tri, tau, ca, j0, j1);
 }
 
 // Factors the panel of columns c..c+n-1 (n <= TSQR_NB) within the calling wave: each
