@@ -510,10 +510,11 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 // Triangularises A (nr x nc, row-major in LDS with an odd row stride ncp, so that both a row
 // and a column spread over the LDS banks) by Householder reflections H = I - tau w w^H, in
 // panels of TSQR_NB columns. A panel is factored inside one wave (wave 0), one panel ahead of
-// the trailing update that the other waves carry out (see householder_lds). Panels of one
-// column measured fastest (47.7 options/s on the d = 5 headline batch, against 46.4, 45.2 and
-// 45.0 for two, three and four): wave 0's chain per column is then one single-column
-// application and one reflector, at the price of a barrier per column.
+// the trailing update that the other waves carry out (see householder_lds). The panel width
+// trades wave 0's chain (narrow panels: fewer column applications per column) against barriers
+// and the trailing update (wide panels). With 16-wave workgroups two columns measured fastest
+// (71.4 options/s on the d = 5 headline batch of 192 options, against 70.7, 70.3 and 67.4 for
+// one, three and four); with 8 waves one column had been (47.7 against 46.4 at 64 options).
 // tri > 0: A stacks tri upper-triangular nc x nc factors (a merge of the reduction tree); the
 // reflector of column j then touches only row j of the first factor and rows 0..j of the
 // others, and only those rows are visited. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
@@ -537,7 +538,7 @@ struct RowsPacked {
     }
 };
 
-constexpr int TSQR_NB = 1;
+constexpr int TSQR_NB = 2;
 
 __device__ __forceinline__ int hh_len(int j, int nr, int nc, int tri) { return tri ? 1 + (tri - 1) * (j + 1) : nr - j; }
 __device__ __forceinline__ int hh_row(int k, int j, int nc, int tri)
@@ -772,92 +773,6 @@ __device__ __forceinline__ void hh_apply_wave(const L &Lr, int nr, int nc, int t
     if (n == 1) hh_apply_wave_n<1>(Lr, nr, nc, tri, tau, ca, j0, j1);
 }
 
-// Leaf blocks (no stacked factors) of at most 64 HH_SLOTS rows, one-column panels: applies
-// reflector j to column j+1 and forms reflector j+1 from the updated column while it is still
-// in registers (the two steps otherwise cost an LDS round trip each). Same arithmetic as
-// hh_apply_wave_n<1> followed by make_reflector_rows, with the rows shared out one lane over.
-template <class L>
-__device__ void hh_apply_reflect_leaf(const L &Lr, int nr, const double *tau, cplx *alph, double *tauo, int j)
-{
-    const int lane = threadIdx.x & 63, c = j + 1, len = nr - j;   // rows j..nr-1 are k = 0..len-1
-    const double tj = tau[j];
-    cplx wv[HH_SLOTS], cv[HH_SLOTS];
-    double dots[2] = {0.0, 0.0};
-#pragma unroll
-    for (int m = 0; m < HH_SLOTS; ++m) {
-        const int k = lane + 64 * m;
-        const cplx *row = Lr.row(j + (k < len ? k : 0));
-        wv[m] = k < len ? row[j] : cplx{0.0, 0.0};
-        cv[m] = k < len ? row[c] : cplx{0.0, 0.0};
-        const cplx p = cmulc(wv[m], cv[m]);
-        dots[0] += p.x;
-        dots[1] += p.y;
-    }
-    if (tj != 0.0) {                                // same for every lane
-        wave_sum_n<2>(dots);
-        const cplx f = {tj * dots[0], tj * dots[1]};
-#pragma unroll
-        for (int m = 0; m < HH_SLOTS; ++m) cv[m] = csub(cv[m], cmul(f, wv[m]));
-    }
-    // reflector j+1: leading entry row j+1 (k = 1: lane 1, slot 0), the rest k >= 2
-    const cplx x0 = {read_lane(cv[0].x, 1), read_lane(cv[0].y, 1)};
-    double sq = 0.0;
-#pragma unroll
-    for (int m = 0; m < HH_SLOTS; ++m) {
-        const int k = lane + 64 * m;
-        if (k >= 2 && k < len) sq += cabs2(cv[m]);
-    }
-    sq = wave_sum(sq);
-    const double all = sq + cabs2(x0);
-    bool keep = false;                              // column left as it is (tau = 0)
-    ReflScalars r;
-    if (all >= 1e-290 && all <= 1e290) {
-        r = reflector_scalars(x0, 1.0, 0, sq);
-    } else {
-        double mx = 0.0;
-#pragma unroll
-        for (int m = 0; m < HH_SLOTS; ++m) {
-            const int k = lane + 64 * m;
-            if (k >= 1 && k < len) mx = fmax(mx, fmax(fabs(cv[m].x), fabs(cv[m].y)));
-        }
-        mx = wave_max(mx);
-        if (!(mx >= 1e-280) || !(mx <= 1e300)) {
-            keep = true;
-            r.alpha = x0;
-            r.tau = 0.0;
-            r.cf = {1.0, 0.0};
-        } else {
-            int e;
-            frexp(mx, &e);
-            const double sc = ldexp(1.0, -e);
-            sq = 0.0;
-#pragma unroll
-            for (int m = 0; m < HH_SLOTS; ++m) {
-                const int k = lane + 64 * m;
-                if (k >= 2 && k < len) sq += cabs2(cplx{cv[m].x * sc, cv[m].y * sc});
-            }
-            sq = wave_sum(sq);
-            r = reflector_scalars(x0, sc, e, sq);
-        }
-    }
-    // row j keeps its R entry, row j+1 becomes w_{j+1} = 1, the rows below w = x cf
-#pragma unroll
-    for (int m = 0; m < HH_SLOTS; ++m) {
-        const int k = lane + 64 * m;
-        if (k < len) {
-            cplx v = cv[m];
-            if (!keep && k == 1) v = {1.0, 0.0};
-            else if (!keep && k >= 2) v = cmul(v, r.cf);
-            Lr.row(j + k)[c] = v;
-        }
-    }
-    if (lane == 0) {
-        alph[c] = r.alpha;
-        tauo[c] = r.tau;
-    }
-    wave_lds_order();
-}
-
 // Factors the panel of columns c..c+n-1 (n <= TSQR_NB) within the calling wave: each
 // reflector is formed and then applied to the panel's later columns.
 template <class L>
@@ -898,12 +813,8 @@ __device__ void householder_lds(const L &Lr, int nr, int nc, int tri, cplx *alph
         const int j1 = min(j0 + TSQR_NB, jmax);     // panel P: reflectors j0..j1-1 are formed
         const int n1 = min(TSQR_NB, jmax - j1);     // width of panel P+1 (0 at the end)
         if (wave == 0 && n1 > 0) {
-            if (TSQR_NB == 1 && tri == 0 && nr - j0 <= 64 * HH_SLOTS && nr - j0 >= 2) {
-                hh_apply_reflect_leaf(Lr, nr, tau, alph, tau, j0);
-            } else {
-                hh_apply_wave(Lr, nr, nc, tri, tau, j1, n1, j0, j1);
-                hh_factor_panel_wave(Lr, nr, nc, tri, alph, tau, j1, n1);
-            }
+            hh_apply_wave(Lr, nr, nc, tri, tau, j1, n1, j0, j1);
+            hh_factor_panel_wave(Lr, nr, nc, tri, alph, tau, j1, n1);
         }
         HH_PART(0);
         if ((int)threadIdx.x >= t0)
