@@ -162,7 +162,9 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
  *  TTFP_TUNE_MAXVOL_THREADS  threads per maxvol workgroup: 256, 512 or 1024, or 0 (default):
  *                            per launch, the largest size that keeps every item resident at once
  *  TTFP_TUNE_TSQR_LDS_KB     LDS budget of a TSQR workgroup in KiB, 16..152 (default 152):
- *                            smaller budgets give shorter row blocks and more resident groups
+ *                            smaller budgets give shorter leaf blocks and merges of fewer
+ *                            factors (a leaf keeps at least two groups of nc rows and a merge
+ *                            at least two factors, whatever the budget)
  *  TTFP_TUNE_GRAPH           1: capture each direction's half sweep in a hipGraph once per
  *                            batch and replay it (needs a non-null stream); 0: launch eagerly
  * Returns TTFP_EINVAL for an unknown parameter or value. */
