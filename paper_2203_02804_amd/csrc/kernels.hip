@@ -1130,7 +1130,9 @@ __device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
 //     replaces the pivot of its column and Bc takes the rank-one update
 //     Bc -= Bc[:,j] (Bc[i,:] - e_j) / Bc[i,j]. Each swap multiplies |det Y[piv]| by more than
 //     1 + delta; at most 4 r + 16 swaps.
-//  4. A^{-1} again from the final pivots, stored for k_interp.
+//  4. A^{-1} of the final pivots, stored for k_interp: the inverse of step 2 carried through
+//     the swaps by the same rank-one updates (Sherman-Morrison), or recomputed by Gauss-Jordan
+//     after more than MV_SM_MAX swaps.
 // k_interp forms B for every row (a tiled product spread over the whole chip) and marks the
 // rows whose largest |B_ij| exceeds 1 + delta. k_maxvol_refine puts the pivots and the worst
 // such rows into a new block and repeats 3-4, after which k_interp runs again; when no row
@@ -1268,9 +1270,12 @@ __device__ void gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag
 }
 
 // maxvol swaps on the candidate block Bc (Kc x r, global memory, rows cand[0..Kc)); returns the
-// number of swaps (same in every thread).
+// number of swaps (same in every thread). A swap that puts candidate row q in place of pivot js
+// changes one row of A = Y[piv]: B = Y A^{-1} and, when Ai is given (r x r, LDS), A^{-1} itself
+// take the same rank-one update (Sherman-Morrison: A'^{-1} = A^{-1} - A^{-1} e_js (B_q - e_js) / B_q,js).
+constexpr int MV_SM_MAX = 32;                   // more swaps than this: a fresh Gauss-Jordan inverse
 __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, double lim, int maxit, cplx *prow, cplx *colv,
-                          ArgMax *red)
+                          ArgMax *red, cplx *Ai = nullptr, cplx *acol = nullptr)
 {
     const int nthr = blockDim.x;
     int swaps = 0;
@@ -1291,12 +1296,16 @@ __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, do
             prow[c] = w;
         }
         for (int q = threadIdx.x; q < Kc; q += nthr) colv[q] = cdiv(Bc[(size_t)q * r + js], b);
+        if (Ai)
+            for (int i = threadIdx.x; i < r; i += nthr) acol[i] = cdiv(Ai[i * r + js], b);
         if (threadIdx.x == 0) piv[js] = cand[qs];
         __syncthreads();
         for (long long e = threadIdx.x; e < tot; e += nthr) {
             const int q = (int)(e / r), c = (int)(e % r);
             Bc[e] = csub(Bc[e], cmul(colv[q], prow[c]));
         }
+        if (Ai)
+            for (int e = threadIdx.x; e < r * r; e += nthr) Ai[e] = csub(Ai[e], cmul(acol[e / r], prow[e % r]));
         __syncthreads();
         ++swaps;
     }
@@ -1517,8 +1526,8 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     PHASE_MARK(3);
     // ---- 3. swaps within the block, 4. A^{-1} of the final pivots
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
-    const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red);
-    if (swaps > 0) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
+    const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red, Ai, fcol);
+    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
     __syncthreads();
     for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
     for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
@@ -1526,9 +1535,10 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         it.mv_iters += swaps;
         it.mv_viol = 0;
         it.mv_dirty = 1;
-        // Bc (8 Kc r^2), one rank-one update of Bc per swap (8 Kc r), Gauss-Jordan (8 r^3 each)
-        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * Kc * (double)r * r + 8.0 * Kc * (double)r * swaps +
-                                       8.0 * (double)r * r * r * (swaps > 0 ? 2 : 1);
+        // Bc (8 Kc r^2), one rank-one update of Bc and A^{-1} per swap (8 (Kc + r) r),
+        // Gauss-Jordan (8 r^3 each)
+        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * Kc * (double)r * r + 8.0 * (Kc + r) * (double)r * swaps +
+                                       8.0 * (double)r * r * r * (swaps > MV_SM_MAX ? 2 : 1);
     }
     PHASE_MARK(6);
 }
@@ -1586,11 +1596,13 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
                       : B[dir == 1 ? (size_t)c * m + cand[q] : (size_t)cand[q] * r + c];
     }
     __syncthreads();
+    for (int e = threadIdx.x; e < r * r; e += nthr) Ai[e] = it.Ai[e];
+    __syncthreads();
     PHASE_MARK(4);
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
-    const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red);
+    const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red, Ai, fcol);
     PHASE_MARK(5);
-    if (swaps > 0) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
+    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
     __syncthreads();
     PHASE_MARK(7);
     if (swaps > 0) {
@@ -1601,7 +1613,7 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
         it.mv_iters += swaps;
         it.mv_viol = 0;
         it.mv_dirty = swaps > 0;
-        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * Kc * (double)r * swaps + (swaps > 0 ? 8.0 * (double)r * r * r : 0.0);
+        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * (Kc + r) * (double)r * swaps + (swaps > MV_SM_MAX ? 8.0 * (double)r * r * r : 0.0);
     }
 }
 
