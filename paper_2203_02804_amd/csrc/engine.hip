@@ -348,9 +348,11 @@ int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
 // Refinement rounds of maxvol after the block start: each marks the rows of B beyond 1 + delta
 // and swaps them in. More rounds give interpolation nearer to dominant, hence crosses that need
 // fewer sweeps and land nearer the exact price: on the d = 5 headline batch of 192 options
-// (within 1e-6 / options/s) 2 rounds 339/576 at 71.3, 3: 380 at 72.2, 4: 412 at 71.9, 6: 400 at
-// 67.3, 10: 406 at 67.4 (one box); a round with no violating row costs one early-exit launch.
-constexpr int MAXVOL_REFINE_ROUNDS = 4;
+// (within 1e-6 / options/s), with blocks of the pivots and 192 violators: 2 rounds 339/576 at
+// 71.3, 3: 380 at 72.2, 4: 412 at 71.9, 6: 400 at 67.3, 10: 406 at 67.4; with blocks of up to
+// 448 violators: 3 rounds 413 at 75.5, 4: 404 at 73.1 (one box). A round with no violating row
+// costs one early-exit launch.
+constexpr int MAXVOL_REFINE_ROUNDS = 3;
 
 int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
 {

@@ -1543,8 +1543,8 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     PHASE_MARK(6);
 }
 
-// Refinement round: the pivots and up to K - r rows that k_interp found violating (largest first)
-// form the block; swaps as in k_maxvol. Returns at once when no row violated.
+// Refinement round: the pivots and up to MV_KMAX - r rows that k_interp found violating (largest
+// first) form the block; swaps as in k_maxvol. Returns at once when no row violated.
 __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax)
 {
     extern __shared__ cplx Abuf[];
@@ -1582,7 +1582,9 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
         a = block_argmax(a, red);
         vmax = (float)a.v;
     }
-    const int K = min(min(max(4 * r, 64), MV_KMAX), m);
+    // the pivots and up to MV_KMAX - r of the worst violators (a larger block than the start's:
+    // more swaps per round, so fewer rounds reach the same dominance)
+    const int K = min(MV_KMAX, m);
     // only rows that violated (a positive mark) are candidates
     const int nv = select_largest(it.viol, 1, m, K - r, 1e-30f, vmax, cand + r, red, shi, shf);
     const int Kc = r + nv;
