@@ -1381,8 +1381,10 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     const int nkeys = cap * (int)(sizeof(cplx) / sizeof(float));
     const int gsz = (m + nkeys - 1) / nkeys;            // 1 unless m exceeds the key buffer
     const int nk = (m + gsz - 1) / gsz;
-    int K = max(4 * r, 64);
-    K = min(K, MV_KMAX);
+    // the start's candidate block: the MV_KMAX rows of largest leverage (a larger block gives a
+    // start nearer to dominant and fewer swaps and refinement rounds after it: 79.3 options/s on
+    // the d = 5 headline batch of 192 options against 75.3 with max(4 r, 64) rows, one box)
+    int K = MV_KMAX;
     K = min(K, nk);
     float *key = (float *)Abuf;
     float kmax = 0.0f;
