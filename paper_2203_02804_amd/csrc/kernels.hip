@@ -507,17 +507,20 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 }
 
 // ------------------------------------------------------------------ Householder R in LDS
-// Triangularises A (nr x nc, row-major in LDS with an odd row stride ncp, so that both a row
-// and a column spread over the LDS banks) by Householder reflections H = I - tau w w^H, in
-// panels of TSQR_NB columns. A panel is factored inside one wave (wave 0), one panel ahead of
+// Triangularises an nr x nc block in LDS (a leaf block row-major with an odd row stride ncp, so
+// that both a row and a column spread over the LDS banks; a merge's stacked factors packed by
+// rows; both reached through a row-layout object) by Householder reflections
+// H = I - tau w w^H, in panels of TSQR_NB columns. A panel is factored inside one wave (wave 0), one panel ahead of
 // the trailing update that the other waves carry out (see householder_lds). The panel width
 // trades wave 0's chain (narrow panels: fewer column applications per column) against barriers
 // and the trailing update (wide panels). With 16-wave workgroups two columns measured fastest
 // (71.4 options/s on the d = 5 headline batch of 192 options, against 70.7, 70.3 and 67.4 for
 // one, three and four); with 8 waves one column had been (47.7 against 46.4 at 64 options).
-// tri > 0: A stacks tri upper-triangular nc x nc factors (a merge of the reduction tree); the
-// reflector of column j then touches only row j of the first factor and rows 0..j of the
-// others, and only those rows are visited. On exit row j of R is (alph[j], A[j, j+1..nc-1]).
+// tri > 0: the block stacks tri upper-triangular nc x nc factors (a merge of the reduction
+// tree); the reflector of column j then touches only row j of the first factor and rows 0..j of
+// the others, and only those rows are visited. On exit row j of R is (alph[j], entries j+1..nc-1
+// of row j).
+
 // Row addressing of the block being triangularised: row(r) of a stacked row index r (as from
 // hh_row) is a pointer p with p[c] the entry (r, c).
 struct RowsPadded {                               // row-major, odd row stride ncp
@@ -527,7 +530,7 @@ struct RowsPadded {                               // row-major, odd row stride n
 };
 // Stacked upper-triangular nc x nc factors, each packed by rows (row i holds columns i..nc-1,
 // tp = nc (nc + 1) / 2 entries a factor): a merge of the reduction tree touches only entries
-// (i, c) with c >= i, and four factors of 68 columns fit where two unpacked ones did.
+// (i, c) with c >= i, and up to four factors of 68 columns fit where two unpacked ones did.
 struct RowsPacked {
     cplx *A;
     int nc, tp;
