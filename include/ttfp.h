@@ -176,8 +176,9 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
  * launch of each kernel family; ttfp_profile_read returns the number of launches, their
  * summed device time and the algorithmic work they did since the last enable (bytes written
  * for the fiber kernel: 16 per complex entry; FP64 flops for TSQR (8 m n^2 - 8 n^3 / 3),
- * basis (4 m r^2), maxvol on its candidate block of K rows (8 K r^2 + 8 K r per swap + 8 r^3 per
- * inverse) and the interpolation matrix (8 m r^2); 0 where not counted). */
+ * basis (4 m r^2), maxvol on its candidate block of K rows (8 K r^2 for the block, 8 (K + r) r
+ * per swap for the rank-one updates of the block and of A^{-1}, 8 r^3 per Gauss-Jordan inverse)
+ * and the interpolation matrix (8 m r^2); 0 where not counted). */
 enum {
     TTFP_KERNEL_FIBER = 0, TTFP_KERNEL_TSQR = 1, TTFP_KERNEL_QRCP = 2, TTFP_KERNEL_BASIS = 3,
     TTFP_KERNEL_MAXVOL = 4, TTFP_KERNEL_FINISH = 5, TTFP_KERNEL_CORESUM = 6, TTFP_KERNEL_CONTRACT = 7,
