@@ -19,7 +19,7 @@ import workloads as W  # noqa: E402
 from oracle import closed_forms as CF  # noqa: E402
 
 BATCH = 192
-SEEDS = [2203 + 1000 * s for s in range(6)]     # benchmark batches (warm-up + timed steps)
+SEEDS = [2203 + 1000 * s for s in range(32)]    # benchmark batches (warm-up + timed steps)
 
 
 def main():

@@ -24,7 +24,7 @@ def stored():
 
 def test_layout(stored):
     assert stored["batch"] == 192
-    assert len(stored["batches"]) == 6
+    assert len(stored["batches"]) == 32
     assert all(len(v) == 192 for v in stored["batches"].values())
     assert abs(stored["rho"] - 0.5 / 1.5) < 1e-15
 
