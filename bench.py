@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-literal", action="store_true", help="skip the literal Wishart N=128 R=32 line")
     ap.add_argument("--surrogate-train", type=int, default=4096, help="TT-priced training options")
+    ap.add_argument("--qr", choices=["cholqr", "tsqr"], default="cholqr",
+                    help="triangular factor of the fibers: shifted Cholesky QR (matrix cores) or Householder TSQR")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of a known size (scales the HBM byte counters of a profiler)")
     args = ap.parse_args()
@@ -213,6 +215,7 @@ def main():
     batches = [W.config2_batch(B, seed=sd, corr_kind="beta") for sd in seeds]
     refs = np.concatenate([load_refs(sd, B) for sd in seeds[args.warmup:]])
     pricer = ttfp.Pricer(0)
+    pricer.set_tuning(qr=0 if args.qr == "cholqr" else 1)
     log(f"bench: d=5 Sigma(0.5) N={args.N} R={args.max_rank} batch={B} warmup={args.warmup} steps={args.steps}")
     prices, status, elapsed, prof = time_batches(pricer, batches, grid, args.warmup, not args.no_profile)
     n_opt = B * args.steps

@@ -74,7 +74,16 @@ typedef struct {
  *  rank_tol     relative pivot threshold for rank truncation; <= 0 means 0.1 tol / sqrt(d-1)
  *  max_rank     TT rank cap (<= TTFP_MAX_RANK); n_enrich random columns are added per step
  *  max_sweeps   at most this many forward+backward sweeps
- *  seed         seeds the counter-based generator for index sets and enrichment          */
+ *  seed         seeds the counter-based generator for index sets and enrichment
+ *  n_err_samples random grid points of the sampled error estimate of Sec. IV.B (the relative
+ *               1-norm error of the tensor trains against the integrand), shared among the
+ *               option's terms: > 0 that many, 0 the paper's 50 000, < 0 none (err_est NaN).
+ *               Term t of an option with n_terms terms gets ceil(n / n_terms) points; coordinate
+ *               k of its point s is the grid index rand(seed_t, 7, s, k, N), where
+ *               rand(q, a, b, c, n) = ((h >> 32) * n) >> 32 with h = f(f(f(q ^ a) ^ b) ^ c), f the
+ *               SplitMix64 finaliser (Steele, Lea and Flood 2014: add 0x9E3779B97F4A7C15, then
+ *               xor-shift-multiply by 0xBF58476D1CE4E5B9 (30), 0x94D049BB133111EB (27), xor-shift 31),
+ *               and seed_t = seed * 0x100000001B3 + t * 0x9E3779B97F4A7C15 + 1 (mod 2^64)        */
 typedef struct {
     int32_t N;
     double L, alpha;
@@ -82,6 +91,7 @@ typedef struct {
     double tol, rank_tol;
     int32_t max_rank, max_sweeps, n_enrich;
     uint64_t seed;
+    int32_t n_err_samples;
 } ttfp_grid;
 
 /* Per-option diagnostics. */
@@ -97,6 +107,11 @@ typedef struct {
     int32_t converged;     /* 1 if the tolerance was met */
     int64_t maxvol_full_starts; /* maxvol starts taken by pivoting over all rows because the
                               block of largest-norm rows was numerically rank deficient */
+    double err_est;        /* the convergence measure of Sec. IV.B on the final tensor trains:
+                              sum_t s_t sum_p |TT_t(x_p) - A_t(x_p)| / sum_t s_t sum_p |A_t(x_p)|
+                              over the sample points of every term t (A_t its integrand, s_t > 0 its
+                              quadrature scale K e^{-rT} prod_k eta_k / 2 pi); NaN without samples */
+    int64_t err_samples;   /* sample points behind err_est (over all terms) */
 } ttfp_diag;
 
 typedef struct ttfp_ctx ttfp_ctx;
@@ -125,6 +140,10 @@ int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, dou
  * (nullable) receives each option's return code. Returns the worst code. */
 int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids,
                      double *prices, double *delta, double *vega, int32_t *status);
+
+/* Diagnostics of option i of the last ttfp_price_batch call on this context (the same fields
+ * ttfp_price fills). TTFP_EINVAL when there is no such option. */
+int ttfp_batch_diag(ttfp_ctx *ctx, int32_t i, ttfp_diag *diag);
 
 /* The integrand of term `term` of an option at npts grid multi-indices idx[npts*d]
  * (host, 0-based), evaluated by the GPU fiber kernel's device function. out[2*npts]
@@ -167,8 +186,11 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
  *                            at least two factors, whatever the budget)
  *  TTFP_TUNE_GRAPH           1: capture each direction's half sweep in a hipGraph once per
  *                            batch and replay it (needs a non-null stream); 0: launch eagerly
+ *  TTFP_TUNE_QR              the fiber's triangular factor: 0 (default) three passes of shifted
+ *                            Cholesky QR with the Gram and transform products on the FP64 matrix
+ *                            cores; 1 Householder TSQR over LDS-resident row blocks
  * Returns TTFP_EINVAL for an unknown parameter or value. */
-enum { TTFP_TUNE_MAXVOL_THREADS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2 };
+enum { TTFP_TUNE_MAXVOL_THREADS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2, TTFP_TUNE_QR = 3 };
 int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value);
 int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
 
@@ -182,7 +204,8 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
 enum {
     TTFP_KERNEL_FIBER = 0, TTFP_KERNEL_TSQR = 1, TTFP_KERNEL_QRCP = 2, TTFP_KERNEL_BASIS = 3,
     TTFP_KERNEL_MAXVOL = 4, TTFP_KERNEL_FINISH = 5, TTFP_KERNEL_CORESUM = 6, TTFP_KERNEL_CONTRACT = 7,
-    TTFP_KERNEL_INTERP = 8, TTFP_KERNEL_COUNT = 9
+    TTFP_KERNEL_INTERP = 8, TTFP_KERNEL_ERREST = 9, TTFP_KERNEL_GRAM = 10, TTFP_KERNEL_CHOL = 11,
+    TTFP_KERNEL_COUNT = 12
 };
 int ttfp_profile_enable(ttfp_ctx *ctx, int enable);
 int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms, double *work);

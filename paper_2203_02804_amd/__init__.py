@@ -42,23 +42,24 @@ class _Grid(ctypes.Structure):
                 ("L_k", ctypes.POINTER(ctypes.c_double)), ("alpha_k", ctypes.POINTER(ctypes.c_double)),
                 ("tol", ctypes.c_double), ("rank_tol", ctypes.c_double),
                 ("max_rank", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("n_enrich", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("n_err_samples", ctypes.c_int32)]
 
 
 class _Diag(ctypes.Structure):
     _fields_ = [("imag_rel", ctypes.c_double), ("kappa", ctypes.c_double), ("last_change", ctypes.c_double),
                 ("n_evals", ctypes.c_int64), ("maxvol_swaps", ctypes.c_int64),
                 ("sweeps", ctypes.c_int32), ("rank_capped", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("maxvol_full_starts", ctypes.c_int64)]
+                ("maxvol_full_starts", ctypes.c_int64), ("err_est", ctypes.c_double), ("err_samples", ctypes.c_int64)]
 
 
-EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_eval_integrand",
+EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_batch_diag", "ttfp_eval_integrand",
            "ttfp_tt_values", "ttfp_tt_export", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
            "ttfp_profile_enable", "ttfp_profile_read", "ttfp_set_tuning", "ttfp_get_tuning", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
            "ttfp_mlp_last_error"]
-KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract", "interp"]
-TUNING = {"maxvol_threads": 0, "tsqr_lds_kb": 1, "graph": 2}
+KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract", "interp", "err_est",
+           "gram", "chol"]
+TUNING = {"maxvol_threads": 0, "tsqr_lds_kb": 1, "graph": 2, "qr": 3}
 
 _lib = None
 
@@ -79,6 +80,7 @@ def load():
     lib.ttfp_price.argtypes = [vp, P(_Option), P(_Grid), P(ctypes.c_double), P(ctypes.c_int32), P(_Diag)]
     lib.ttfp_price_batch.argtypes = [vp, ctypes.c_int32, P(_Option), P(_Grid), P(ctypes.c_double),
                                      P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
+    lib.ttfp_batch_diag.argtypes = [vp, ctypes.c_int32, P(_Diag)]
     lib.ttfp_eval_integrand.argtypes = [vp, P(_Option), P(_Grid), ctypes.c_int32, ctypes.c_int64,
                                         P(ctypes.c_int32), P(ctypes.c_double)]
     lib.ttfp_tt_values.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32), P(ctypes.c_double)]
@@ -136,7 +138,8 @@ class _Marshal:
                           _dp(self.Ak) if self.Ak is not None else null,
                           float(grid.get("tol", 1e-8)), float(grid.get("rank_tol", 0.0)),
                           int(grid.get("max_rank", 32)), int(grid.get("max_sweeps", 6)),
-                          int(grid.get("n_enrich", 4)), int(grid.get("seed", 0)) & ((1 << 64) - 1))
+                          int(grid.get("n_enrich", 4)), int(grid.get("seed", 0)) & ((1 << 64) - 1),
+                          int(grid.get("n_err_samples", 0)))
 
 
 def plan(opt, grid):
@@ -152,6 +155,13 @@ def plan(opt, grid):
         raise TTFPError(rc, lib.ttfp_strerror(rc).decode())
     n = nt.value
     return L[: n * d].reshape(n, d), A[: n * d].reshape(n, d)
+
+
+def _diag_dict(diag):
+    return dict(imag_rel=diag.imag_rel, kappa=diag.kappa, last_change=diag.last_change, n_evals=diag.n_evals,
+                maxvol_swaps=diag.maxvol_swaps, maxvol_full_starts=diag.maxvol_full_starts,
+                sweeps=diag.sweeps, rank_capped=bool(diag.rank_capped), converged=bool(diag.converged),
+                err_est=diag.err_est, err_samples=diag.err_samples)
 
 
 class Pricer:
@@ -197,10 +207,13 @@ class Pricer:
         diag = _Diag()
         rc = self._check(self.lib.ttfp_price(self.ctx, ctypes.byref(m.opt), ctypes.byref(m.grid), ctypes.byref(out),
                                              _ip(ranks), ctypes.byref(diag)))
-        info = dict(imag_rel=diag.imag_rel, kappa=diag.kappa, last_change=diag.last_change, n_evals=diag.n_evals,
-                    maxvol_swaps=diag.maxvol_swaps, maxvol_full_starts=diag.maxvol_full_starts,
-                    sweeps=diag.sweeps, rank_capped=bool(diag.rank_capped), converged=bool(diag.converged))
-        return out.value, ranks.reshape(d, d + 1), info, rc
+        return out.value, ranks.reshape(d, d + 1), _diag_dict(diag), rc
+
+    def batch_diag(self, i):
+        """Diagnostics dict of option i of the last price_batch call."""
+        diag = _Diag()
+        self._check(self.lib.ttfp_batch_diag(self.ctx, int(i), ctypes.byref(diag)))
+        return _diag_dict(diag)
 
     def price_batch(self, opts, grids, greeks=False):
         """Prices a list of options in one batched pass. grids: one dict or a list.

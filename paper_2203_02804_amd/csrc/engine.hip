@@ -20,6 +20,9 @@ __global__ void k_fiber(Item *items, const int *active, int t, int dir, int mode
 __global__ void k_eval_points(const Item *items, long long npts, const int *idx, cplx *out);
 __global__ void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G);
 __global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G);
+__global__ void k_gram(Item *items, const int *active, int t, int dir, int pass);
+__global__ void k_chol(Item *items, const int *active, int t, int dir, int pass);
+__global__ void k_xform(Item *items, const int *active, int t, int dir, int pass);
 __global__ void k_basis(Item *items, const int *active, int t, int dir);
 __global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax);
 __global__ void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax);
@@ -30,6 +33,7 @@ __global__ void k_contract(Item *items, const int *active);
 __global__ void k_core_moments(Item *items, const int *active);
 __global__ void k_moments(Item *items, const int *active, cplx *out, int stride);
 __global__ void k_tt_values(const Item *items, int item, long long npts, const int *idx, cplx *out);
+__global__ void k_err_est(Item *items, const int *active);
 }  // namespace ttfp
 
 using namespace ttfp;
@@ -48,12 +52,15 @@ struct ttfp_ctx {
     size_t moments_cap = 0;
     // last single-option call (for ttfp_tt_values)
     std::vector<Item> last_items;
+    // diagnostics of the options of the last batch call (ttfp_batch_diag)
+    std::vector<ttfp_diag> last_batch_diag;
     int last_n_items = 0;
     // tuning (set by ttfp_set_tuning, chosen by the autotuner)
     int tune_maxvol_threads = 0;          // 0: chosen per launch from the number of items
     int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 0;
+    int tune_qr = 0;                      // 0: shifted Cholesky QR on the matrix cores; 1: Householder TSQR
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -66,6 +73,7 @@ struct ttfp_ctx {
 namespace {
 
 const size_t ALIGN = 256;
+constexpr int GRAM_ROWS_HOST = 256;          // fiber rows per Gram workgroup (k_gram)
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 #define HIPCHK(expr)                                                                     \
@@ -108,7 +116,7 @@ int tsqr_levels(int rows, int BR, int G)
 struct ItemSizes {
     size_t bytes;
     size_t off_m, off_C, off_L, off_a, off_kind, off_I, off_J, off_F, off_Rl, off_Ri, off_perm, off_Y, off_W,
-        off_Bt, off_cores, off_M, off_M1, off_M2, off_piv, off_keys, off_Ai;
+        off_Bt, off_cores, off_M, off_M1, off_M2, off_piv, off_keys, off_Ai, off_Qb, off_Gp, off_Ge, off_Xf, off_Rf;
     int rows_max, nblk_max;
 };
 
@@ -141,11 +149,19 @@ ItemSizes item_sizes(int d, int N, int R, int p, int BR)
     s.off_piv = take(sizeof(int) * R);
     s.off_keys = take(sizeof(float) * (size_t)s.rows_max * 17);   // keys, then viol
     s.off_Ai = take(sizeof(cplx) * (size_t)R * R);
+    const size_t gblk = (size_t)(s.rows_max + GRAM_ROWS_HOST - 1) / GRAM_ROWS_HOST;
+    s.off_Qb = take(sizeof(cplx) * (size_t)s.rows_max * nc);
+    s.off_Gp = take(sizeof(cplx) * gblk * nc * nc);
+    s.off_Ge = take(sizeof(int) * gblk);
+    s.off_Xf = take(sizeof(cplx) * (size_t)nc * nc);
+    s.off_Rf = take(sizeof(cplx) * (size_t)nc * nc);
     s.bytes = o;
     return s;
 }
 
-int ensure_arena(ttfp_ctx *ctx, size_t bytes, size_t n_items)
+// Device workspace of a chunk: the item arena (bytes) and the item array and activity flags
+// (n_items); the Greeks' moment buffer (moment_elems complex values) is allocated on first use.
+int ensure_arena(ttfp_ctx *ctx, size_t bytes, size_t n_items, size_t moment_elems)
 {
     if (bytes > ctx->arena_bytes) {
         if (ctx->arena) HIPCHK(hipFree(ctx->arena));
@@ -209,7 +225,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
         }
     }
     const size_t n_items = sz.size();
-    int rc = ensure_arena(ctx, total, n_items);
+    int rc = ensure_arena(ctx, total, n_items, n_items * (size_t)(maxd + maxd * maxd));
     if (rc) return rc;
     // fill items and upload the static term data
     std::vector<char> host(0);
@@ -231,6 +247,11 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             it.term = (int)t;
             it.rank_eps = g->rank_tol > 0 ? g->rank_tol : 0.1 * g->tol / std::sqrt((double)std::max(P.d - 1, 1));
             it.delta = 5e-2;
+            {
+                const long long per_opt = g->n_err_samples > 0 ? g->n_err_samples : (g->n_err_samples == 0 ? 50000 : 0);
+                const long long nt = (long long)P.terms.size();
+                it.n_samp = (int)((per_opt + nt - 1) / nt);
+            }
             it.seed = g->seed * 0x100000001B3ull + (uint64_t)t * 0x9E3779B97F4A7C15ull + 1;
             it.m = (const double *)(dev + s.off_m);
             it.C = (const double *)(dev + s.off_C);
@@ -254,6 +275,11 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             it.keys = (float *)(dev + s.off_keys);
             it.viol = it.keys + (size_t)s.rows_max * 16;
             it.Ai = (cplx *)(dev + s.off_Ai);
+            it.Qb = (cplx *)(dev + s.off_Qb);
+            it.Gp = (cplx *)(dev + s.off_Gp);
+            it.Ge = (int *)(dev + s.off_Ge);
+            it.Xf = (cplx *)(dev + s.off_Xf);
+            it.Rf = (cplx *)(dev + s.off_Rf);
             it.rows_max = s.rows_max;
             it.nblk_max = s.nblk_max;
             // static term data: one contiguous host staging block up to off_I
@@ -354,6 +380,24 @@ int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
 // costs one early-exit launch.
 constexpr int MAXVOL_REFINE_ROUNDS = 3;
 
+// The fiber's triangular factor by three passes of shifted Cholesky QR (k_gram, k_chol, k_xform).
+void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int maxrows, unsigned ny, int t, int dir)
+{
+    const unsigned gb = cdivu(maxrows, GRAM_ROWS_HOST), gx = cdivu(maxrows, MM_ROWS_PER_WG);
+    for (int pass = 0; pass < 3; ++pass) {
+        if (pass > 0) {
+            ProfScope ps(ctx, TTFP_KERNEL_GRAM);
+            hipLaunchKernelGGL(k_xform, dim3(gx, ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir, pass);
+        }
+        {
+            ProfScope ps(ctx, TTFP_KERNEL_GRAM);
+            hipLaunchKernelGGL(k_gram, dim3(gb, ny), dim3(256), 0, st, it, act, t, dir, pass);
+        }
+        ProfScope ps(ctx, TTFP_KERNEL_CHOL);
+        hipLaunchKernelGGL(k_chol, dim3(ny), dim3(256), 0, st, it, act, t, dir, pass);
+    }
+}
+
 int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
 {
     hipStream_t st = ctx->stream;
@@ -364,7 +408,9 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
         ProfScope ps(ctx, TTFP_KERNEL_FIBER);
         hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.maxR * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
     }
-    {
+    if (ctx->tune_qr == 0) {
+        launch_cholqr(ctx, st, it, act, g.maxrows, ny, t, dir);
+    } else {
         ProfScope ps(ctx, TTFP_KERNEL_TSQR);
         int n = (g.maxrows + g.BR - 1) / g.BR;
         const size_t lds = tsqr_lds_bytes(g.BR, g.G, g.maxnc);
@@ -375,7 +421,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_QRCP);
-        hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(QRCP_THREADS), 0, st, it, act, t, dir, g.BR, g.G);
+        hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(QRCP_THREADS), 0, st, it, act, t, dir, ctx->tune_qr == 0 ? 0 : g.BR, g.G);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_BASIS);
@@ -436,12 +482,29 @@ int launch_edge(ttfp_ctx *ctx, const Launch &g, int n_items, int dir, int sweep)
 
 struct OptResult {
     double price = 0, imag = 0, change = INFINITY, kappa = 0;
+    double err_est = NAN;
+    long long err_samples = 0;
     int sweeps = 0, capped = 0, converged = 0;
     long long evals = 0, swaps = 0, full_starts = 0;
     int singular = 0;
     double hist[64] = {0};                 // relative change after each half sweep
     int code = TTFP_OK;
 };
+
+void fill_diag(const OptResult &r, ttfp_diag *diag)
+{
+    diag->imag_rel = std::fabs(r.imag) / std::max(std::fabs(r.price), 1e-300);
+    diag->kappa = r.kappa;
+    diag->last_change = r.change;
+    diag->n_evals = r.evals;
+    diag->maxvol_swaps = r.swaps;
+    diag->maxvol_full_starts = r.full_starts;
+    diag->sweeps = r.sweeps;
+    diag->rank_capped = r.capped;
+    diag->converged = r.converged;
+    diag->err_est = r.err_est;
+    diag->err_samples = r.err_samples;
+}
 
 // Runs TT-cross on every item of the batch until each option's price is stable.
 int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &grids, std::vector<OptResult> &res,
@@ -570,9 +633,17 @@ done:
             if (r.singular || !std::isfinite(r.price)) r.code = TTFP_EPRECISION;
         }
     }
+    // every item takes part in the sampled error estimate and the Greeks
+    std::fill(active.begin(), active.end(), 1);
+    HIPCHK(hipMemcpyAsync(ctx->d_active, active.data(), n_items * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    bool any_samples = false;
+    for (const Item &it : b.items) any_samples |= it.n_samp > 0;
+    if (any_samples) {
+        ProfScope ps(ctx, TTFP_KERNEL_ERREST);
+        hipLaunchKernelGGL(k_err_est, dim3(n_items), dim3(1024), 0, ctx->stream, ctx->d_items, ctx->d_active);
+        HIPCHK(hipGetLastError());
+    }
     if (greeks) {
-        std::fill(active.begin(), active.end(), 1);
-        HIPCHK(hipMemcpyAsync(ctx->d_active, active.data(), n_items * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
         mstride = b.geo.maxd + b.geo.maxd * b.geo.maxd;
         size_t need = (size_t)n_items * mstride;
         if (need > ctx->moments_cap) {
@@ -590,19 +661,27 @@ done:
     }
     HIPCHK(hipMemcpyAsync(host_items.data(), ctx->d_items, n_items * sizeof(Item), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->prof) prof_collect(ctx);
+    {
+        // Sec. IV.B convergence measure over the option's terms, each term's sums weighted by its
+        // (positive) quadrature scale
+        std::vector<double> ea(n_opts, 0.0), ef(n_opts, 0.0);
+        std::vector<long long> ns(n_opts, 0);
+        for (int i = 0; i < n_items; ++i) {
+            const int o = b.item_opt[i];
+            if (host_items[i].n_samp <= 0) continue;
+            ea[o] += b.item_scale[i] * host_items[i].err_abs;
+            ef[o] += b.item_scale[i] * host_items[i].err_ref;
+            ns[o] += host_items[i].n_samp;
+        }
+        for (int o = 0; o < n_opts; ++o) {
+            res[o].err_samples = ns[o];
+            res[o].err_est = ns[o] > 0 ? (ef[o] > 0.0 ? ea[o] / ef[o] : (ea[o] > 0.0 ? INFINITY : 0.0)) : NAN;
+        }
+    }
     if (ctx->prof)
         for (const Item &it : host_items)
             for (int q = 0; q < TTFP_KERNEL_COUNT; ++q) ctx->prof_work[q] += it.work[q];
-#ifdef TTFP_PHASE_TIMING
-    {
-        double ph[16] = {0};
-        for (const Item &it : host_items)
-            for (int q = 0; q < 16; ++q) ph[q] += it.phase[q];
-        std::fprintf(stderr, "phases (us summed over %d items):", n_items);
-        for (int q = 0; q < 16; ++q) std::fprintf(stderr, " %d:%.0f", q, ph[q] * 0.01);
-        std::fprintf(stderr, "\n");
-    }
-#endif
     b.items = host_items;
     return TTFP_OK;
 }
@@ -697,6 +776,10 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
         if (value != 0 && value != 1) break;
         ctx->tune_graph = value;
         return TTFP_OK;
+    case TTFP_TUNE_QR:
+        if (value != 0 && value != 1) break;
+        ctx->tune_qr = value;
+        return TTFP_OK;
     default:
         break;
     }
@@ -711,6 +794,7 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value)
     case TTFP_TUNE_MAXVOL_THREADS: *value = ctx->tune_maxvol_threads; return TTFP_OK;
     case TTFP_TUNE_TSQR_LDS_KB: *value = ctx->tune_tsqr_lds_kb; return TTFP_OK;
     case TTFP_TUNE_GRAPH: *value = ctx->tune_graph; return TTFP_OK;
+    case TTFP_TUNE_QR: *value = ctx->tune_qr; return TTFP_OK;
     default: return TTFP_EINVAL;
     }
 }
@@ -773,10 +857,14 @@ int ttfp_plan(const ttfp_option *opt, const ttfp_grid *grid, int32_t *n_terms, d
     }
 }
 
-int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids, double *prices,
+}  // extern "C"
+
+namespace {
+
+// The batched pricer behind ttfp_price_batch.
+int price_batch_impl(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids, double *prices,
                      double *delta, double *vega, int32_t *status)
 {
-    if (!ctx) return TTFP_EINVAL;
     if (n < 0 || (n > 0 && (!opts || !grids || !prices))) {
         ctx->last_error = "bad batch arguments";
         return TTFP_EINVAL;
@@ -799,6 +887,7 @@ int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)24 << 30;
         const size_t cap_bytes = std::max((size_t)4 << 30, (size_t)(0.7 * (double)(free_b + ctx->arena_bytes)));
         int worst = TTFP_OK;
+        ctx->last_batch_diag.assign(n, ttfp_diag());
         size_t greek_off = 0;
         int o0 = 0;
         while (o0 < n) {
@@ -830,6 +919,7 @@ int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
             int first_item = 0;
             for (int o = o0; o < o1; ++o) {
                 const OptResult &r = res[o - o0];
+                fill_diag(r, &ctx->last_batch_diag[o]);
                 prices[o] = r.price;
                 if (status) status[o] = r.code;
                 worst = (r.code < 0 || worst < 0) ? std::min(worst, r.code) : std::max(worst, r.code);
@@ -851,6 +941,28 @@ int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
         ctx->last_error = e.what();
         return TTFP_EINVAL;
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids, double *prices,
+                     double *delta, double *vega, int32_t *status)
+{
+    if (!ctx) return TTFP_EINVAL;
+    return price_batch_impl(ctx, n, opts, grids, prices, delta, vega, status);
+}
+
+int ttfp_batch_diag(ttfp_ctx *ctx, int32_t i, ttfp_diag *diag)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (!diag || i < 0 || (size_t)i >= ctx->last_batch_diag.size()) {
+        ctx->last_error = "no such option in the last batch";
+        return TTFP_EINVAL;
+    }
+    *diag = ctx->last_batch_diag[i];
+    return TTFP_OK;
 }
 
 int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, double *price, int32_t *ranks, ttfp_diag *diag)
@@ -883,17 +995,7 @@ int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, dou
                 for (int k = 0; k < P.d; ++k) rk[k + 1] = it.ccol[k];
             }
         }
-        if (diag) {
-            diag->imag_rel = std::fabs(r.imag) / std::max(std::fabs(r.price), 1e-300);
-            diag->kappa = r.kappa;
-            diag->last_change = r.change;
-            diag->n_evals = r.evals;
-            diag->maxvol_swaps = r.swaps;
-            diag->maxvol_full_starts = r.full_starts;
-            diag->sweeps = r.sweeps;
-            diag->rank_capped = r.capped;
-            diag->converged = r.converged;
-        }
+        if (diag) fill_diag(r, diag);
         ctx->last_items = b.items;
         ctx->last_n_items = (int)b.items.size();
         return r.code;
@@ -1023,7 +1125,9 @@ static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, in
     size_t oF = 0, oRl = align_up(oF + 16 * (size_t)m * n), oY = align_up(oRl + 16 * 2 * (size_t)nblk * n * n),
            oW = align_up(oY + 16 * (size_t)m * r), oBt = align_up(oW + 16 * (size_t)m * r), oP = align_up(oBt + 16 * (size_t)m * r),
            oK = align_up(oP + 4 * (size_t)std::max(r, 1)), oA = align_up(oK + 4 * 17 * (size_t)m),
-           total = align_up(oA + 16 * (size_t)r * r);
+           gblk = (size_t)(m + GRAM_ROWS_HOST - 1) / GRAM_ROWS_HOST, oQ = align_up(oA + 16 * (size_t)r * r),
+           oGp = align_up(oQ + 16 * (size_t)m * n), oGe = align_up(oGp + 16 * gblk * n * n), oXf = align_up(oGe + 4 * gblk),
+           oRf = align_up(oXf + 16 * (size_t)n * n), total = align_up(oRf + 16 * (size_t)n * n);
     HIPCHK(hipMalloc(&buf, total));
     std::memset(&it, 0, sizeof it);
     it.d = 1;
@@ -1038,6 +1142,11 @@ static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, in
     it.keys = (float *)(buf + oK);
     it.viol = it.keys + 16 * (size_t)m;
     it.Ai = (cplx *)(buf + oA);
+    it.Qb = (cplx *)(buf + oQ);
+    it.Gp = (cplx *)(buf + oGp);
+    it.Ge = (int *)(buf + oGe);
+    it.Xf = (cplx *)(buf + oXf);
+    it.Rf = (cplx *)(buf + oRf);
     it.nblk_max = nblk;
     it.rows_max = m;
     it.nI[0] = m;
@@ -1064,19 +1173,28 @@ int ttfp_qr_r(ttfp_ctx *ctx, int32_t m, int32_t n, const double *A, double *R)
     e = e ? e : hipMemcpy(act, &one, sizeof(int), hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(dit, &it, sizeof(Item), hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(it.F, A, 16 * (size_t)m * n, hipMemcpyHostToDevice);
-    const int nlev = tsqr_levels(m, BR, G);
-    int nb = (m + BR - 1) / BR;
-    for (int level = 0; !e && level < nlev; ++level) {
-        hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(nb, 1), 1), dim3(TSQR_THREADS), tsqr_lds_bytes(BR, G, std::max(n, 4)), ctx->stream, dit, act, 0, 2,
-                           level, BR, G);
-        e = hipGetLastError();
-        nb = (nb + G - 1) / G;
+    const cplx *rsrc = it.Rf;
+    if (ctx->tune_qr == 0) {
+        if (!e) {
+            launch_cholqr(ctx, ctx->stream, dit, act, m, 1, 0, 2);
+            e = hipGetLastError();
+        }
+    } else {
+        const int nlev = tsqr_levels(m, BR, G);
+        int nb = (m + BR - 1) / BR;
+        for (int level = 0; !e && level < nlev; ++level) {
+            hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(nb, 1), 1), dim3(TSQR_THREADS), tsqr_lds_bytes(BR, G, std::max(n, 4)),
+                               ctx->stream, dit, act, 0, 2, level, BR, G);
+            e = hipGetLastError();
+            nb = (nb + G - 1) / G;
+        }
+        // final level
+        int cnt = (m + BR - 1) / BR, lf = 0;
+        while (cnt > 1) { cnt = (cnt + G - 1) / G; ++lf; }
+        rsrc = it.Rlev + (size_t)(lf & 1) * it.nblk_max * n * n;
     }
     e = e ? e : hipStreamSynchronize(ctx->stream);
-    // final level
-    int cnt = (m + BR - 1) / BR, lf = 0;
-    while (cnt > 1) { cnt = (cnt + G - 1) / G; ++lf; }
-    e = e ? e : hipMemcpy(R, it.Rlev + (size_t)(lf & 1) * it.nblk_max * n * n, 16 * (size_t)n * n, hipMemcpyDeviceToHost);
+    e = e ? e : hipMemcpy(R, rsrc, 16 * (size_t)n * n, hipMemcpyDeviceToHost);
     (void)hipFree(buf);
     (void)hipFree(act);
     (void)hipFree(dit);

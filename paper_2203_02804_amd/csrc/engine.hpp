@@ -32,6 +32,7 @@ struct Item {
     double rank_eps;           // relative pivot threshold for truncation
     double delta;              // maxvol dominance threshold
     uint64_t seed;
+    int n_samp;                // random grid points of the sampled error estimate
     const double *m;           // [d]    mean of w
     const double *C;           // [d*d]  covariance of w
     const double *L;           // [d]    half-widths
@@ -54,11 +55,17 @@ struct Item {
     cplx *Ai;                  // R x R inverse of the pivot rows of Y (maxvol -> k_interp)
     float *keys;               // rows_max x 16 partial squared row norms of Y (maxvol start)
     float *viol;               // rows_max marks of k_interp: a row's largest |B| above the bound, else 0
+    cplx *Qb;                  // rows_max x nc_max: the Cholesky QR's transformed fiber
+    cplx *Gp;                  // gram_blocks(rows_max) x nc x nc partial Gram matrices
+    int *Ge;                   // gram_blocks(rows_max) power-of-two exponents of the partials
+    cplx *Xf;                  // nc x nc inverse of the last Cholesky factor
+    cplx *Rf;                  // nc x nc running triangular factor (the fiber's R after the last pass)
     int rows_max, nblk_max;
     // ---- dynamic state
     int nI[MAXD + 1], nJ[MAXD + 1];   // sizes of the left / right index sets
     int crow[MAXD], ccol[MAXD];       // core shapes
     int rsel;                         // rank selected in the current step
+    int gram_e;                       // exponent of the power-of-two scaling of the fiber's Gram
     int half;                         // half sweeps completed (counter of the random draws)
     int capped;
     long long n_evals;
@@ -68,8 +75,8 @@ struct Item {
     int mv_viol;                      // k_interp found rows with |B_ij| > 1 + delta
     int mv_dirty;                     // the pivots moved since B was last formed
     double work[12];                  // algorithmic work per kernel family (bytes or flops)
-    double phase[16];                 // per-phase device time (ticks), TTFP_PHASE_TIMING builds only
     cplx P;                           // latest contraction of the tensor train
+    double err_abs, err_ref;          // sampled error: sum |TT - A| and sum |A| over n_samp points
 };
 
 // Step addressing: dir 0 = left-to-right (core k = t), dir 1 = right-to-left (core k = d-1-t).

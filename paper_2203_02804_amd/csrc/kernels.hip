@@ -40,21 +40,6 @@ __device__ __forceinline__ cplx cexp_(cplx a)
     return {e * c, e * s};
 }
 
-#ifdef TTFP_PHASE_TIMING
-#define PHASE_MARK(slot)                                                     \
-    do {                                                                     \
-        __syncthreads();                                                     \
-        if (threadIdx.x == 0) {                                              \
-            const long long now_ = wall_clock64();                           \
-            it.phase[slot] += (double)(now_ - t_prev_);                      \
-            t_prev_ = now_;                                                  \
-        }                                                                    \
-    } while (0)
-#define PHASE_START long long t_prev_ = wall_clock64()
-#else
-#define PHASE_MARK(slot) do {} while (0)
-#define PHASE_START do {} while (0)
-#endif
 
 // Cross-lane moves by DPP (row-local permutations that run at VALU speed, unlike the LDS-routed
 // ds_bpermute of a generic shuffle). CTRL: 0xB1 quad_perm [1,0,3,2] (lane ^ 1), 0x4E quad_perm
@@ -387,7 +372,6 @@ __global__ void k_init(Item *items, int n_items)
     it.mv_viol = 0;
     it.mv_dirty = 0;
     for (int q = 0; q < 12; ++q) it.work[q] = 0.0;
-    for (int q = 0; q < 16; ++q) it.phase[q] = 0.0;
     it.capped = 0;
     long long cnt = 1;
     for (int k = d - 1; k >= 1; --k) {
@@ -572,18 +556,9 @@ constexpr int HH_SLOTS = 3;
 // reflector is formed from the unscaled column. Otherwise the largest magnitude is found, and the
 // column is scaled by a power of two as in make_reflector (a column below 1e-280 is left as it
 // is, tau = 0).
-#ifdef TTFP_PHASE_TIMING
-__shared__ double hh_refl_ticks;                    // time wave 0 spends forming reflectors
-#endif
 template <class L>
 __device__ void make_reflector_rows(const L &Lr, int j, int len, int nc, int tri, cplx *alpha_out, double *tau_out)
 {
-#ifdef TTFP_PHASE_TIMING
-    const long long t_in = wall_clock64();
-#define REFL_DONE do { if (threadIdx.x == 0) hh_refl_ticks += (double)(wall_clock64() - t_in); } while (0)
-#else
-#define REFL_DONE do {} while (0)
-#endif
     const int lane = threadIdx.x & 63;
     double sq = 0.0;
     cplx xv[HH_SLOTS];
@@ -616,7 +591,6 @@ __device__ void make_reflector_rows(const L &Lr, int j, int len, int nc, int tri
                 *alpha_out = x0;
                 *tau_out = 0.0;
             }
-            REFL_DONE;
             return;
         }
         int e;
@@ -647,8 +621,6 @@ __device__ void make_reflector_rows(const L &Lr, int j, int len, int nc, int tri
         *alpha_out = r.alpha;
         *tau_out = r.tau;
     }
-    REFL_DONE;
-#undef REFL_DONE
 }
 
 // Applies reflectors j0..j1-1, in order, to columns [ca, cb). Threads t = 0..T-1 (T a multiple
@@ -793,25 +765,13 @@ __device__ void hh_factor_panel_wave(const L &Lr, int nr, int nc, int tri, cplx 
 // panel P+1's columns and factors panel P+1 by itself. The two parts touch disjoint columns
 // and read panel P's reflectors only, so one barrier per panel separates the steps.
 template <class L>
-__device__ void householder_lds(const L &Lr, int nr, int nc, int tri, cplx *alph, double *tau, double *ph)
+__device__ void householder_lds(const L &Lr, int nr, int nc, int tri, cplx *alph, double *tau)
 {
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#ifdef TTFP_PHASE_TIMING
-    long long hh_t = wall_clock64();
-    double hh_acc[3] = {0.0, 0.0, 0.0};
-#define HH_MARK(q) do { const long long n_ = wall_clock64(); hh_acc[q] += (double)(n_ - hh_t); hh_t = n_; } while (0)
-    // time from the panel's start to where wave 0 (q = 0) or wave 1 (q = 1) is done
-#define HH_PART(q) do { if (threadIdx.x == 64 * (q)) hh_acc[q] += (double)(wall_clock64() - hh_t); } while (0)
-    if (threadIdx.x == 0) hh_refl_ticks = 0.0;
-#else
-#define HH_MARK(q) do {} while (0)
-#define HH_PART(q) do {} while (0)
-#endif
     const int jmax = nr < nc ? nr : nc;
     const int t0 = nw > 1 ? 64 : 0;                 // first thread of the trailing update
     if (jmax > 0 && wave == 0) hh_factor_panel_wave(Lr, nr, nc, tri, alph, tau, 0, min(TSQR_NB, jmax));
     __syncthreads();
-    HH_MARK(2);
     for (int j0 = 0; j0 < jmax; j0 += TSQR_NB) {
         const int j1 = min(j0 + TSQR_NB, jmax);     // panel P: reflectors j0..j1-1 are formed
         const int n1 = min(TSQR_NB, jmax - j1);     // width of panel P+1 (0 at the end)
@@ -819,19 +779,10 @@ __device__ void householder_lds(const L &Lr, int nr, int nc, int tri, cplx *alph
             hh_apply_wave(Lr, nr, nc, tri, tau, j1, n1, j0, j1);
             hh_factor_panel_wave(Lr, nr, nc, tri, alph, tau, j1, n1);
         }
-        HH_PART(0);
         if ((int)threadIdx.x >= t0)
             hh_apply_cols(Lr, nr, nc, tri, tau, j1 + n1, nc, j0, j1, threadIdx.x - t0, blockDim.x - t0);
-        HH_PART(1);
         __syncthreads();
-        HH_MARK(2);
     }
-#ifdef TTFP_PHASE_TIMING
-    if (threadIdx.x == 0 && ph) { ph[0] += hh_acc[0]; ph[2] += hh_acc[2]; ph[3] += hh_refl_ticks; }
-    if (threadIdx.x == 64 && ph) ph[1] += hh_acc[1];
-#endif
-#undef HH_MARK
-#undef HH_PART
 }
 
 // number of TSQR blocks at a level
@@ -887,7 +838,6 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
         tri = g1 - g0;                               // stacked triangular factors
         src = it.Rlev + (size_t)((level - 1) & 1) * it.nblk_max * rsz + (size_t)g0 * rsz;
     }
-    PHASE_START;
     if (level == 0) {
         // coalesced read of nr row-major rows into the padded row-major LDS block
         for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
@@ -902,12 +852,10 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
         }
     }
     __syncthreads();
-    PHASE_MARK(8);
     if (level == 0)
-        householder_lds(RowsPadded{A, ncp}, nr, nc, 0, alph, tau, it.phase + 12);
+        householder_lds(RowsPadded{A, ncp}, nr, nc, 0, alph, tau);
     else
-        householder_lds(RowsPacked{A, nc, tp}, nr, nc, tri, alph, tau, it.phase + 12);
-    PHASE_MARK(9);
+        householder_lds(RowsPacked{A, nc, tp}, nr, nc, tri, alph, tau);
     cplx *dst = it.Rlev + (size_t)(level & 1) * it.nblk_max * rsz + (size_t)blk * rsz;
     const int jmax = nr < nc ? nr : nc;
     for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) {
@@ -919,6 +867,333 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
             v = (c == j) ? alph[j] : rowj[c];
         }
         dst[e] = v;
+    }
+}
+
+// ------------------------------------------------------------------ Cholesky QR on the matrix cores
+// The triangular factor of the fiber F (m x nc) by three passes of shifted Cholesky QR (Fukaya,
+// Kannan, Nakatsukasa, Yamamoto and Yanagisawa, "Shifted Cholesky QR for computing the QR
+// factorization of ill-conditioned matrices", 2020):
+//   pass 0: G = (sF)^H (sF) with s = 2^-e (e from the largest entry), R0 = chol(G + shift I)
+//   pass 1: Q = sF R0^{-1},  R1 = chol(Q^H Q + shift I)
+//   pass 2: Q <- Q R1^{-1},  R2 = chol(Q^H Q + shift I);   R = R2 R1 R0 / s.
+// A pass resolves the singular values that stand above the square root of its shift; the next
+// pass sees them relative to what is left, so three passes resolve the spectrum well below the
+// rank threshold while R^H R = F^H F holds to about the shift (10 nc u relative, with the Gram
+// accumulated in FP64). Rank-deficient fibers (exact zero columns, saturated ranks) are covered
+// by the shift of every pass; a Cholesky that still meets a non-positive pivot is redone with a
+// hundred times the shift. The Gram products and the triangular transforms are dense
+// contractions over the fiber's rows and run on the FP64 matrix cores (v_mfma_f64_16x16x4f64);
+// the nc x nc Cholesky, inverse and factor product are one small workgroup per item.
+constexpr int GRAM_ROWS = 256;                     // fiber rows per Gram workgroup
+constexpr int GRAM_CHUNK = 32;                     // rows staged in LDS at a time
+constexpr int NCPAD = (MAXNC + 15) / 16 * 16;      // columns rounded up to whole 16-wide tiles
+constexpr int GRAM_NOSCALE = -100000;              // block exponent of a block of zeros
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int gram_blocks(int rows) { return (rows + GRAM_ROWS - 1) / GRAM_ROWS; }
+
+// Partial Gram of one block of GRAM_ROWS fiber rows: P = X^H X over the block's rows, upper
+// 16 x 16 tiles only, written to it.Gp[block] (nc x nc, row-major). Pass 0 reads F and scales
+// it on the fly by 2^-e_blk, e_blk the exponent of the block's largest entry (the accumulators
+// are rescaled exactly when a later chunk raises it; e_blk goes to it.Ge[block]); passes 1 and 2
+// read Q unscaled. Complex products by three real ones: with X = Xr + i Xi, Y = Yr + i Yi,
+// X^H Y = (t1 + t2) + i (t3 - t1 + t2), t1 = Xr^T Yr, t2 = Xi^T Yi, t3 = (Xr - Xi)^T (Yr + Yi).
+__global__ __launch_bounds__(256) void k_gram(Item *items, const int *active, int t, int dir, int pass)
+{
+    __shared__ cplx chunk[GRAM_CHUNK][NCPAD + 1];
+    __shared__ double wmax[4];
+    const int item = blockIdx.y;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    const int m = s.rows, nc = s.nc, blk = blockIdx.x;
+    if (blk >= gram_blocks(m)) return;
+    if (blk == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_GRAM] += 4.0 * m * (double)nc * nc;
+    const cplx *src = pass == 0 ? it.F : it.Qb;
+    const int T = (nc + 15) / 16, ntiles = T * (T + 1) / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    // this wave's tiles: q = wave, wave + 4, ... in the order (0,0) (0,1) .. (0,T-1) (1,1) ..
+    int tI[4], tJ[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        int q = wave + 4 * u, I = 0;
+        while (I < T && q >= T - I) { q -= T - I; ++I; }
+        tI[u] = I;
+        tJ[u] = I + q;
+    }
+    const int nt = ntiles > wave ? (ntiles - wave + 3) / 4 : 0;
+    double4_t p1[4], p2[4], p3[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        p1[u] = double4_t{0.0, 0.0, 0.0, 0.0};
+        p2[u] = p1[u];
+        p3[u] = p1[u];
+    }
+    int e_blk = GRAM_NOSCALE;
+    double sc = 1.0;
+    const int r0 = blk * GRAM_ROWS, r1 = min(m, r0 + GRAM_ROWS);
+    for (int c0 = r0; c0 < r1; c0 += GRAM_CHUNK) {
+        const int nr = min(GRAM_CHUNK, r1 - c0);
+        __syncthreads();
+        // rows c0 .. c0 + nr - 1 are contiguous in the fiber: one coalesced sweep
+        double mx = 0.0;
+        const cplx *g = src + (size_t)c0 * nc;
+        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
+            const cplx v = g[e];
+            mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+            chunk[e / nc][e % nc] = v;
+        }
+        // zero padding: columns nc .. 16T - 1 of the rows read, all columns of rows nr .. GRAM_CHUNK - 1
+        for (int e = threadIdx.x; e < GRAM_CHUNK * 16 * T; e += blockDim.x) {
+            const int i = e / (16 * T), c = e % (16 * T);
+            if (i >= nr || c >= nc) chunk[i][c] = {0.0, 0.0};
+        }
+        if (pass == 0) {
+            mx = wave_max(mx);
+            if (lane == 0) wmax[wave] = mx;
+            __syncthreads();
+            mx = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+            if (mx > 0.0) {
+                int e;
+                frexp(mx, &e);
+                if (e > e_blk) {
+                    if (e_blk != GRAM_NOSCALE) {
+                        const double f = ldexp(1.0, 2 * (e_blk - e));
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            p1[u] *= f;
+                            p2[u] *= f;
+                            p3[u] *= f;
+                        }
+                    }
+                    e_blk = e;
+                    sc = ldexp(1.0, -e);
+                }
+            }
+        } else {
+            __syncthreads();
+        }
+        const int nks = (nr + 3) / 4;
+        for (int ks = 0; ks < nks; ++ks) {
+            const int row = 4 * ks + lk;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u >= nt) break;
+                const cplx x = chunk[row][16 * tI[u] + li], y = chunk[row][16 * tJ[u] + li];
+                const double xr = x.x * sc, xi = x.y * sc, yr = y.x * sc, yi = y.y * sc;
+                p1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr, p1[u], 0, 0, 0);
+                p2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi, p2[u], 0, 0, 0);
+                p3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr - xi, yr + yi, p3[u], 0, 0, 0);
+            }
+        }
+    }
+    cplx *P = it.Gp + (size_t)blk * nc * nc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (u >= nt) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * tI[u] + lk + 4 * v, j = 16 * tJ[u] + li;
+            if (i < nc && j < nc && i <= j) P[(size_t)i * nc + j] = {p1[u][v] + p2[u][v], p3[u][v] - p1[u][v] + p2[u][v]};
+        }
+    }
+    if (threadIdx.x == 0) it.Ge[blk] = pass == 0 ? e_blk : 0;
+}
+
+// Packed upper-triangular storage of an n x n matrix: row i starts at i n - i (i - 1) / 2.
+__device__ __forceinline__ int up_off(int i, int n) { return i * n - (i * (i - 1)) / 2; }
+
+// Sums the partial Grams (scaled to the largest block exponent), factors G + shift I = R^H R
+// (upper, real positive diagonal), forms X = R^{-1} for the next transform (it.Xf, nc x nc
+// row-major with zeros below the diagonal) and the running factor it.Rf: R in pass 0, R Rf after.
+// The last pass leaves Rf / s = the triangular factor of F (nc x nc, row-major), which the
+// column-pivoted QR reads.
+__global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, int t, int dir, int pass)
+{
+    __shared__ cplx Rp[MAXNC * (MAXNC + 1) / 2];   // G, then its Cholesky factor (packed upper)
+    __shared__ cplx Xp[MAXNC * (MAXNC + 1) / 2];   // R^{-1}, then the factor product (packed upper)
+    __shared__ double red[256 / 64];
+    __shared__ int sh_fail;
+    const int item = blockIdx.x;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    const int m = s.rows, nc = s.nc, nb = gram_blocks(m);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nthr = blockDim.x;
+    const int np = nc * (nc + 1) / 2;
+    // common exponent of the partials (pass 0), then their sum in block order
+    int emax = GRAM_NOSCALE;
+    if (pass == 0)
+        for (int b = 0; b < nb; ++b) emax = max(emax, it.Ge[b]);
+    else
+        emax = 0;
+    double tr = 0.0;
+    for (int e = threadIdx.x; e < np; e += nthr) {
+        int i = 0;
+        while (e >= up_off(i + 1, nc)) ++i;
+        const int j = i + (e - up_off(i, nc));
+        cplx acc = {0.0, 0.0};
+        if (emax != GRAM_NOSCALE)
+            for (int b = 0; b < nb; ++b) {
+                const int eb = it.Ge[b];
+                if (eb == GRAM_NOSCALE) continue;
+                const double f = ldexp(1.0, 2 * (eb - emax));
+                const cplx g = it.Gp[(size_t)b * nc * nc + (size_t)i * nc + j];
+                acc = {acc.x + f * g.x, acc.y + f * g.y};
+            }
+        Xp[e] = acc;                               // G kept here for retries
+        if (i == j) tr += acc.x;
+    }
+    tr = wave_sum(tr);
+    if (lane == 0) red[wave] = tr;
+    __syncthreads();
+    tr = 0.0;
+    for (int w = 0; w < nthr / 64; ++w) tr += red[w];
+    double shift = 10.0 * nc * 2.220446049250313e-16 * tr;
+    // Cholesky of G + shift I by wave 0 (right-looking, packed rows), redone with a larger shift
+    // after a non-positive pivot
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        for (int e = threadIdx.x; e < np; e += nthr) Rp[e] = Xp[e];
+        __syncthreads();
+        for (int i = threadIdx.x; i < nc; i += nthr) Rp[up_off(i, nc)].x += shift;
+        __syncthreads();
+        if (wave == 0) {
+            int fail = 0;
+            for (int j = 0; j < nc && !fail; ++j) {
+                const int oj = up_off(j, nc);
+                const double dj = Rp[oj].x;
+                if (!(dj > 0.0) || !(dj < INFINITY)) { fail = 1; break; }
+                const double rjj = sqrt(dj), inv = 1.0 / rjj;
+                wave_lds_order();
+                for (int k = j + 1 + lane; k < nc; k += 64) Rp[oj + k - j] = {Rp[oj + k - j].x * inv, Rp[oj + k - j].y * inv};
+                if (lane == 0) Rp[oj] = {rjj, 0.0};
+                wave_lds_order();
+                // trailing update of rows i > j: R_ik -= conj(R_ji) R_jk, k >= i
+                const int n2 = nc - j - 1;
+                for (int e = lane; e < n2 * n2; e += 64) {
+                    const int ii = j + 1 + e / n2, kk = j + 1 + e % n2;
+                    if (kk < ii) continue;
+                    const cplx rji = Rp[oj + ii - j], rjk = Rp[oj + kk - j];
+                    cplx &w = Rp[up_off(ii, nc) + kk - ii];
+                    w = csub(w, cmulc(rji, rjk));
+                }
+                wave_lds_order();
+            }
+            if (lane == 0) sh_fail = fail;
+        }
+        __syncthreads();
+        if (!sh_fail) break;
+        if (tr <= 0.0 || !(tr < INFINITY)) break;
+        shift = shift > 0.0 ? 100.0 * shift : 1e-300;
+        __syncthreads();
+    }
+    if (sh_fail || !(tr > 0.0)) {
+        // a zero (or non-finite) fiber: factor zero, transform zero
+        for (int e = threadIdx.x; e < np; e += nthr) Rp[e] = {0.0, 0.0};
+        __syncthreads();
+    }
+    // X = R^{-1}: column c by back substitution (one thread per column)
+    for (int c = threadIdx.x; c < nc; c += nthr) {
+        const cplx rcc = Rp[up_off(c, nc)];
+        const bool zero = rcc.x == 0.0;
+        Xp[up_off(c, nc)] = zero ? cplx{0.0, 0.0} : cplx{1.0 / rcc.x, 0.0};
+        for (int i = c - 1; i >= 0; --i) {
+            const int oi = up_off(i, nc);
+            cplx acc = {0.0, 0.0};
+            for (int l = i + 1; l <= c; ++l) acc = cadd(acc, cmul(Rp[oi + l - i], Xp[up_off(l, nc) + c - l]));
+            const double rii = Rp[oi].x;
+            Xp[oi + c - i] = (rii == 0.0 || zero) ? cplx{0.0, 0.0} : cplx{-acc.x / rii, -acc.y / rii};
+        }
+    }
+    __syncthreads();
+    if (pass < 2)
+        for (int e = threadIdx.x; e < nc * nc; e += nthr) {
+            const int i = e / nc, j = e % nc;
+            it.Xf[e] = j >= i ? Xp[up_off(i, nc) + j - i] : cplx{0.0, 0.0};
+        }
+    __syncthreads();
+    // running factor: Rf <- R (pass 0) or R Rf; the last pass also undoes the scaling
+    const double unscale = pass == 2 ? ldexp(1.0, it.gram_e == GRAM_NOSCALE ? 0 : it.gram_e) : 1.0;
+    for (int e = threadIdx.x; e < np; e += nthr) {
+        int i = 0;
+        while (e >= up_off(i + 1, nc)) ++i;
+        const int j = i + (e - up_off(i, nc));
+        cplx acc;
+        if (pass == 0) {
+            acc = Rp[e];
+        } else {
+            acc = {0.0, 0.0};
+            for (int l = i; l <= j; ++l) acc = cadd(acc, cmul(Rp[up_off(i, nc) + l - i], it.Rf[(size_t)l * nc + j]));
+        }
+        Xp[e] = {acc.x * unscale, acc.y * unscale};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * nc; e += nthr) {
+        const int i = e / nc, j = e % nc;
+        it.Rf[e] = j >= i ? Xp[up_off(i, nc) + j - i] : cplx{0.0, 0.0};
+    }
+    if (pass == 0 && threadIdx.x == 0) it.gram_e = emax;
+}
+
+// Q = X_src Xf for every fiber row, in 16-row panels per wave on the FP64 matrix cores (as in the
+// basis product below): pass 1 reads F scaled by 2^-gram_e and writes Q; pass 2 transforms Q in
+// place (a wave owns its panel, and every load of the panel precedes the panel's stores). Xf is
+// upper triangular, so output column tile J takes only k < 16 (J + 1).
+__global__ __launch_bounds__(64 * MM_WAVES) void k_xform(Item *items, const int *active, int t, int dir, int pass)
+{
+    __shared__ cplx Xs[MAXNC * MAXNC];
+    const int item = blockIdx.y;
+    if (!active[item]) return;
+    Item &it = items[item];
+    StepShape s = step_shape(it, t, dir, 0);
+    if (!s.valid) return;
+    const int nc = s.nc, m = s.rows;
+    if (blockIdx.x * MM_ROWS_PER_WG >= m) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_GRAM] += 4.0 * m * (double)nc * nc;
+    for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) Xs[e] = it.Xf[e];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int row0 = blockIdx.x * MM_ROWS_PER_WG + wave * 16;
+    if (row0 >= m) return;
+    const cplx *src = pass == 1 ? it.F : it.Qb;
+    const double sc = pass == 1 ? ldexp(1.0, it.gram_e == GRAM_NOSCALE ? 0 : -it.gram_e) : 1.0;
+    const int T = (nc + 15) / 16;
+    double4_t prr[NCPAD / 16], pii[NCPAD / 16], pss[NCPAD / 16];
+#pragma unroll
+    for (int q = 0; q < NCPAD / 16; ++q) {
+        prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        pii[q] = prr[q];
+        pss[q] = prr[q];
+    }
+    const int arow = row0 + li;
+    for (int k0 = 0; k0 < nc; k0 += 4) {
+        const int kk = k0 + lk;
+        cplx a = (arow < m && kk < nc) ? src[(size_t)arow * nc + kk] : cplx{0.0, 0.0};
+        a = {a.x * sc, a.y * sc};
+#pragma unroll
+        for (int q = 0; q < NCPAD / 16; ++q) {
+            if (q >= T) break;
+            if (k0 >= 16 * (q + 1)) continue;     // rows of X below the diagonal block are zero
+            const int jj = 16 * q + li;
+            const cplx b = (kk < nc && jj < nc) ? Xs[kk * nc + jj] : cplx{0.0, 0.0};
+            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
+            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
+            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = row0 + lk + 4 * v;
+#pragma unroll
+        for (int q = 0; q < NCPAD / 16; ++q) {
+            if (q >= T) break;
+            const int col = 16 * q + li;
+            if (row < m && col < nc)
+                it.Qb[(size_t)row * nc + col] = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
+        }
     }
 }
 
@@ -940,8 +1215,8 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
     const int nc = s.nc, ncp = nc | 1;              // odd row stride in LDS
     const int nthr = blockDim.x;
     const size_t rsz = (size_t)nc * nc;
-    const int lf = tsqr_final_level(s.rows, BR, G);
-    const cplx *src = it.Rlev + (size_t)(lf & 1) * it.nblk_max * rsz;
+    // the fiber's triangular factor: from the Cholesky QR (BR == 0) or the last TSQR level
+    const cplx *src = BR == 0 ? it.Rf : it.Rlev + (size_t)(tsqr_final_level(s.rows, BR, G) & 1) * it.nblk_max * rsz;
     for (int e = threadIdx.x; e < nc * nc; e += nthr) A[(e / nc) * ncp + e % nc] = src[e];
     for (int c = threadIdx.x; c < nc; c += nthr) perm[c] = c;
     __syncthreads();
@@ -1042,7 +1317,6 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
 // 16-row panel as up to four 16 x 16 complex tiles, three real MFMA products each); the
 // triangular inverse is held in LDS with its zero lower part. Each row's squared norm is left
 // in four-column partial sums in its key slots (the start of maxvol reads them).
-typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int PANEL_WAVES = MM_WAVES;            // 16-row panels per workgroup
 __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const int *active, int t, int dir)
 {
@@ -1378,7 +1652,6 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     cplx *W = it.W;
     cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
     const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    PHASE_START;
     // ---- 1a. row norms (one key per group of gsz consecutive rows: its largest norm); the
     // violation marks that k_interp records are cleared
     const int nkeys = cap * (int)(sizeof(cplx) / sizeof(float));
@@ -1417,7 +1690,6 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         a = block_argmax(a, red);
         kmax = (float)a.v;
     }
-    PHASE_MARK(0);
     // ---- 1b. the K largest groups, resolved to their largest-norm row
     const int Kc = select_largest(key, 1, nk, K, 0.0f, kmax, cand, red, shi, shf);
     for (int q = threadIdx.x; q < Kc; q += nthr) {
@@ -1434,7 +1706,6 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         chosen[q] = 0;
     }
     __syncthreads();
-    PHASE_MARK(1);
     // ---- 1c. start: elimination with partial pivoting on the block S = Y[cand] (a copy in W).
     // A pivot below 1e-6 of the largest row norm means the block is numerically rank deficient
     // (this happens when many integrand values underflow to zero and the largest rows share
@@ -1505,10 +1776,8 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         if (threadIdx.x == 0) it.mv_full += 1;
     }
     __syncthreads();
-    PHASE_MARK(2);
     // ---- 2. A^{-1} and the block's rows of B (in W, over the start's copy)
     gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
-    PHASE_MARK(10);
     cplx *Bc = W;
     {
         const int ncg = (r + 3) / 4;
@@ -1528,7 +1797,6 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         }
     }
     __syncthreads();
-    PHASE_MARK(3);
     // ---- 3. swaps within the block, 4. A^{-1} of the final pivots
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red, Ai, fcol);
@@ -1545,7 +1813,6 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         it.work[TTFP_KERNEL_MAXVOL] += 8.0 * Kc * (double)r * r + 8.0 * (Kc + r) * (double)r * swaps +
                                        8.0 * (double)r * r * r * (swaps > MV_SM_MAX ? 2 : 1);
     }
-    PHASE_MARK(6);
 }
 
 // Refinement round: the pivots and up to MV_KMAX - r rows that k_interp found violating (largest
@@ -1575,7 +1842,6 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
     const cplx *Y = it.Y;
     cplx *W = it.W;
     const cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
-    PHASE_START;
     for (int c = threadIdx.x; c < r; c += nthr) {
         piv[c] = it.piv[c];
         cand[c] = piv[c];
@@ -1605,13 +1871,10 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
     __syncthreads();
     for (int e = threadIdx.x; e < r * r; e += nthr) Ai[e] = it.Ai[e];
     __syncthreads();
-    PHASE_MARK(4);
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red, Ai, fcol);
-    PHASE_MARK(5);
     if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
     __syncthreads();
-    PHASE_MARK(7);
     if (swaps > 0) {
         for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
         for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
@@ -1943,6 +2206,69 @@ __global__ __launch_bounds__(64) void k_tt_values(const Item *items, int item, l
         __syncthreads();
     }
     if (threadIdx.x == 0) out[p] = v[0];
+}
+
+// ------------------------------------------------------------------ sampled error (convergence measure)
+// The tensor train of an item against the integrand at n_samp uniformly drawn grid points
+// (Sec. IV.B measures the convergence of the cross by the relative 1-norm error on random
+// points): err_abs = sum_s |TT(x_s) - A(x_s)|, err_ref = sum_s |A(x_s)|. Coordinate k of point s
+// is rand_index(seed, 7, s, k, N). One wave per point: lane b holds entry b of the running row
+// vector, which is advanced through core k by a loop over its rows (one coalesced load of a core
+// row per step). Sums are formed per wave in point order and reduced across waves in wave order,
+// so the result does not depend on scheduling.
+__global__ __launch_bounds__(1024) void k_err_est(Item *items, const int *active)
+{
+    __shared__ cplx vbuf[1024 / 64][TTFP_MAX_RANK];
+    __shared__ double part[1024 / 64][2];
+    const int item = blockIdx.x;
+    if (!active[item]) return;
+    Item &it = items[item];
+    const int ns = it.n_samp;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int d = it.d, N = it.N, R = it.R;
+    cplx *v = vbuf[wave];
+    double sa = 0.0, sf = 0.0;
+    for (int smp = wave; smp < ns; smp += nw) {
+        for (int k = 0; k < d; ++k) {
+            const int a_n = it.crow[k], b_n = it.ccol[k];
+            const int i = rand_index(it.seed, 7, (uint64_t)smp, (uint64_t)k, N);
+            const cplx *core = it.cores + (size_t)k * R * N * R;
+            cplx acc = {0.0, 0.0};
+            if (lane < b_n) {
+                if (k == 0) {
+                    acc = core[(size_t)i * b_n + lane];                 // a_n == 1
+                } else {
+                    for (int a = 0; a < a_n; ++a) acc = cadd(acc, cmul(v[a], core[((size_t)a * N + i) * b_n + lane]));
+                }
+            }
+            wave_lds_order();
+            if (lane < b_n) v[lane] = acc;
+            wave_lds_order();
+        }
+        if (lane == 0) {
+            int idx[MAXD];
+            for (int k = 0; k < d; ++k) idx[k] = rand_index(it.seed, 7, (uint64_t)smp, (uint64_t)k, N);
+            const cplx f = integrand(it, idx);
+            const cplx tt = v[0];
+            sa += hypot(tt.x - f.x, tt.y - f.y);
+            sf += hypot(f.x, f.y);
+        }
+        wave_lds_order();
+    }
+    if (lane == 0) {
+        part[wave][0] = sa;
+        part[wave][1] = sf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, f = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            a += part[w][0];
+            f += part[w][1];
+        }
+        it.err_abs = a;
+        it.err_ref = f;
+    }
 }
 
 }  // namespace ttfp

@@ -112,6 +112,7 @@ int check_cross_settings(const ttfp_grid *g, std::string &err)
     if (!(g->tol > 0.0) || !finite(g->tol)) { err = "tol must be positive"; return TTFP_EINVAL; }
     if (!finite(g->rank_tol)) { err = "rank_tol must be finite"; return TTFP_EINVAL; }
     if (g->max_sweeps < 1 || g->max_sweeps > 64) { err = "max_sweeps must be in [1, 64]"; return TTFP_EINVAL; }
+    if (g->n_err_samples > (1 << 24)) { err = "n_err_samples must be at most 2^24"; return TTFP_EINVAL; }
     return TTFP_OK;
 }
 
