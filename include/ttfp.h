@@ -145,6 +145,24 @@ int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
  * ttfp_price fills). TTFP_EINVAL when there is no such option. */
 int ttfp_batch_diag(ttfp_ctx *ctx, int32_t i, ttfp_diag *diag);
 
+/* Allocation-free variant of ttfp_price_batch, for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc). Same arguments, outputs and return
+ * codes as ttfp_price_batch, computed by the same kernels; it calls no hipMalloc / hipFree and
+ * creates no events or graphs (like ttfp_price_batch it synchronises its stream between half
+ * sweeps, so it cannot itself be captured into a graph). Its whole device workspace
+ * (work-item array, activity flags, Greeks moments and every item's buffers) lives in one
+ * static device array of TTFP_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs
+ * on holds until the process ends. The batch is priced as one chunk; a batch whose workspace
+ * exceeds that size returns TTFP_EINVAL before any kernel is launched, with the sizes in
+ * ttfp_last_error. Every call on a GPU shares that GPU's array and the array keeps the last
+ * call's contents (each call initialises what it reads): calls that overlap on one GPU, from
+ * any context or stream, race and must not be made. The context's own buffers are untouched;
+ * ttfp_tt_values / ttfp_tt_export do not see the tensor trains of this call. Returns
+ * TTFP_EDEVICE when the array's device address could not be obtained at ttfp_create. */
+#define TTFP_NOALLOC_SCRATCH_BYTES (128u << 20)
+int ttfp_price_batch_noalloc(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids,
+                             double *prices, double *delta, double *vega, int32_t *status);
+
 /* The integrand of term `term` of an option at npts grid multi-indices idx[npts*d]
  * (host, 0-based), evaluated by the GPU fiber kernel's device function. out[2*npts]
  * receives interleaved real/imaginary parts. */

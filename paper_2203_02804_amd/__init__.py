@@ -52,7 +52,7 @@ class _Diag(ctypes.Structure):
                 ("maxvol_full_starts", ctypes.c_int64), ("err_est", ctypes.c_double), ("err_samples", ctypes.c_int64)]
 
 
-EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_batch_diag", "ttfp_eval_integrand",
+EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_batch_diag", "ttfp_price_batch_noalloc", "ttfp_eval_integrand",
            "ttfp_tt_values", "ttfp_tt_export", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
            "ttfp_profile_enable", "ttfp_profile_read", "ttfp_set_tuning", "ttfp_get_tuning", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
@@ -80,6 +80,7 @@ def load():
     lib.ttfp_price.argtypes = [vp, P(_Option), P(_Grid), P(ctypes.c_double), P(ctypes.c_int32), P(_Diag)]
     lib.ttfp_price_batch.argtypes = [vp, ctypes.c_int32, P(_Option), P(_Grid), P(ctypes.c_double),
                                      P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
+    lib.ttfp_price_batch_noalloc.argtypes = lib.ttfp_price_batch.argtypes
     lib.ttfp_batch_diag.argtypes = [vp, ctypes.c_int32, P(_Diag)]
     lib.ttfp_eval_integrand.argtypes = [vp, P(_Option), P(_Grid), ctypes.c_int32, ctypes.c_int64,
                                         P(ctypes.c_int32), P(ctypes.c_double)]
@@ -215,9 +216,11 @@ class Pricer:
         self._check(self.lib.ttfp_batch_diag(self.ctx, int(i), ctypes.byref(diag)))
         return _diag_dict(diag)
 
-    def price_batch(self, opts, grids, greeks=False):
+    def price_batch(self, opts, grids, greeks=False, noalloc=False):
         """Prices a list of options in one batched pass. grids: one dict or a list.
-        Returns prices[n] (and delta, vega lists of per-option arrays when greeks=True), status[n]."""
+        Returns prices[n] (and delta, vega lists of per-option arrays when greeks=True), status[n].
+        noalloc=True calls the allocation-free entry point (workspace in the library's static
+        per-GPU scratch array; batches that do not fit raise TTFPError with TTFP_EINVAL)."""
         n = len(opts)
         if isinstance(grids, dict):
             grids = [grids] * n
@@ -230,9 +233,9 @@ class Pricer:
         delta = np.zeros(tot) if greeks else None
         vega = np.zeros(tot) if greeks else None
         null = ctypes.POINTER(ctypes.c_double)()
-        self._check(self.lib.ttfp_price_batch(self.ctx, n, copts, cgrids, _dp(prices),
-                                              _dp(delta) if greeks else null, _dp(vega) if greeks else null,
-                                              _ip(status)))
+        fn = self.lib.ttfp_price_batch_noalloc if noalloc else self.lib.ttfp_price_batch
+        self._check(fn(self.ctx, n, copts, cgrids, _dp(prices), _dp(delta) if greeks else null,
+                       _dp(vega) if greeks else null, _ip(status)))
         if not greeks:
             return prices, status
         split = np.cumsum([int(o["d"]) for o in opts])[:-1]

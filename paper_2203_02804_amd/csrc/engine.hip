@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,9 @@ struct ttfp_ctx {
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 0;
     int tune_qr = 0;                      // 0: shifted Cholesky QR on the matrix cores; 1: Householder TSQR
+    // allocation-free mode (ttfp_price_batch_noalloc): this device's static scratch array
+    char *scratch = nullptr;
+    bool noalloc = false;
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -159,10 +163,56 @@ ItemSizes item_sizes(int d, int N, int R, int p, int BR)
     return s;
 }
 
-// Device workspace of a chunk: the item arena (bytes) and the item array and activity flags
-// (n_items); the Greeks' moment buffer (moment_elems complex values) is allocated on first use.
+// The allocation-free entry point's workspace: one static array per GPU, held until the process
+// ends. Host code never uses this name as an address: the device address comes from
+// hipGetSymbolAddress (once per device, in ttfp_create) and is kept in g_scratch.
+static __device__ __align__(256) char scratch[TTFP_NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[MAX_DEVICES] = {nullptr};
+
+// Device address of `device`'s scratch array (the device must be current); nullptr on failure.
+char *scratch_address(int device, std::string &err)
+{
+    if (device < 0 || device >= MAX_DEVICES) { err = "device index beyond the scratch table"; return nullptr; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch[device] = (char *)ptr;
+    }
+    return g_scratch[device];
+}
+
+// Device workspace of a chunk: the item arena (bytes), the item array and activity flags
+// (n_items) and, in allocation-free mode, the Greeks' moment buffer (moment_elems complex values,
+// allocated on first use otherwise). Allocation-free mode carves all of it from the scratch array
+// and fails with TTFP_EINVAL when it does not fit.
 int ensure_arena(ttfp_ctx *ctx, size_t bytes, size_t n_items, size_t moment_elems)
 {
+    if (ctx->noalloc) {
+        const size_t o_items = 0, o_act = align_up(n_items * sizeof(Item)),
+                     o_mom = align_up(o_act + n_items * sizeof(int)), o_arena = align_up(o_mom + moment_elems * sizeof(cplx)),
+                     need = o_arena + bytes;
+        if (need > (size_t)TTFP_NOALLOC_SCRATCH_BYTES) {
+            ctx->last_error = "the batch needs " + std::to_string(need) + " bytes of device workspace; the allocation-free "
+                              "entry point has " + std::to_string((size_t)TTFP_NOALLOC_SCRATCH_BYTES);
+            return TTFP_EINVAL;
+        }
+        ctx->d_items = (Item *)(ctx->scratch + o_items);
+        ctx->items_cap = n_items;
+        ctx->d_active = (int *)(ctx->scratch + o_act);
+        ctx->d_moments = (cplx *)(ctx->scratch + o_mom);
+        ctx->moments_cap = moment_elems;
+        ctx->arena = ctx->scratch + o_arena;
+        ctx->arena_bytes = (size_t)TTFP_NOALLOC_SCRATCH_BYTES - o_arena;
+        return TTFP_OK;
+    }
     if (bytes > ctx->arena_bytes) {
         if (ctx->arena) HIPCHK(hipFree(ctx->arena));
         ctx->arena = nullptr;
@@ -544,7 +594,7 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
             }
         }
     } graphs;
-    const bool use_graph = ctx->tune_graph && ctx->stream != nullptr;
+    const bool use_graph = ctx->tune_graph && ctx->stream != nullptr && !ctx->noalloc;
     int half = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int dir = 0; dir < 2; ++dir, ++half) {
@@ -647,6 +697,7 @@ done:
         mstride = b.geo.maxd + b.geo.maxd * b.geo.maxd;
         size_t need = (size_t)n_items * mstride;
         if (need > ctx->moments_cap) {
+            if (ctx->noalloc) { ctx->last_error = "moment buffer beyond the scratch layout"; return TTFP_EINVAL; }
             if (ctx->d_moments) HIPCHK(hipFree(ctx->d_moments));
             HIPCHK(hipMalloc(&ctx->d_moments, need * sizeof(cplx)));
             ctx->moments_cap = need;
@@ -756,6 +807,11 @@ int ttfp_create(ttfp_ctx **out, int device, void *hip_stream)
     c->stream = (hipStream_t)hip_stream;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) c->n_cu = cus;
+    // the allocation-free entry point's scratch array on this device (its address is looked up
+    // once per device; a failure only disables that entry point)
+    std::string err;
+    c->scratch = scratch_address(device, err);
+    if (!c->scratch) c->last_error = err;
     *out = c;
     return TTFP_OK;
 }
@@ -861,7 +917,8 @@ int ttfp_plan(const ttfp_option *opt, const ttfp_grid *grid, int32_t *n_terms, d
 
 namespace {
 
-// The batched pricer behind ttfp_price_batch.
+// The batched pricer behind ttfp_price_batch and ttfp_price_batch_noalloc. With ctx->noalloc the
+// whole batch is one chunk whose workspace comes from the scratch array.
 int price_batch_impl(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids, double *prices,
                      double *delta, double *vega, int32_t *status)
 {
@@ -884,8 +941,9 @@ int price_batch_impl(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
         // chunk options so that one chunk's workspace fits in 70% of the device memory that is
         // free or already held by this context's workspace (at least 4 GiB)
         size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)24 << 30;
-        const size_t cap_bytes = std::max((size_t)4 << 30, (size_t)(0.7 * (double)(free_b + ctx->arena_bytes)));
+        if (ctx->noalloc || hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)24 << 30;
+        const size_t cap_bytes = ctx->noalloc ? SIZE_MAX
+                                              : std::max((size_t)4 << 30, (size_t)(0.7 * (double)(free_b + ctx->arena_bytes)));
         int worst = TTFP_OK;
         ctx->last_batch_diag.assign(n, ttfp_diag());
         size_t greek_off = 0;
@@ -900,7 +958,7 @@ int price_batch_impl(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
                 int nc = g.max_rank + g.n_enrich, BR, G;
                 tsqr_geometry(std::max(nc, 4), BR, G);
                 size_t b1 = item_sizes(plans[o1].d, g.N, g.max_rank, g.n_enrich, std::min(BR, 64)).bytes * plans[o1].terms.size();
-                if (o1 > o0 && (bytes + b1 > cap_bytes || items + plans[o1].terms.size() > 60000)) break;
+                if (o1 > o0 && !ctx->noalloc && (bytes + b1 > cap_bytes || items + plans[o1].terms.size() > 60000)) break;
                 bytes += b1;
                 items += plans[o1].terms.size();
                 cp.push_back(&plans[o1]);
@@ -943,6 +1001,47 @@ int price_batch_impl(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
     }
 }
 
+// Points a context's workspace at its device's scratch array for one call and restores its own
+// buffers afterwards; timing events and graph capture (both allocate) are off meanwhile.
+struct NoAllocScope {
+    ttfp_ctx *c;
+    char *arena;
+    size_t arena_bytes, items_cap, moments_cap;
+    Item *items;
+    int *active;
+    cplx *moments;
+    bool prof;
+    explicit NoAllocScope(ttfp_ctx *ctx)
+        : c(ctx), arena(ctx->arena), arena_bytes(ctx->arena_bytes), items_cap(ctx->items_cap),
+          moments_cap(ctx->moments_cap), items(ctx->d_items), active(ctx->d_active), moments(ctx->d_moments), prof(ctx->prof)
+    {
+        c->noalloc = true;
+        c->prof = false;
+        c->arena = nullptr;
+        c->arena_bytes = 0;
+        c->d_items = nullptr;
+        c->items_cap = 0;
+        c->d_active = nullptr;
+        c->d_moments = nullptr;
+        c->moments_cap = 0;
+    }
+    ~NoAllocScope()
+    {
+        c->noalloc = false;
+        c->prof = prof;
+        c->arena = arena;
+        c->arena_bytes = arena_bytes;
+        c->d_items = items;
+        c->items_cap = items_cap;
+        c->d_active = active;
+        c->d_moments = moments;
+        c->moments_cap = moments_cap;
+        // a later ttfp_tt_values / ttfp_tt_export must not read the scratch array
+        c->last_items.clear();
+        c->last_n_items = 0;
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -963,6 +1062,19 @@ int ttfp_batch_diag(ttfp_ctx *ctx, int32_t i, ttfp_diag *diag)
     }
     *diag = ctx->last_batch_diag[i];
     return TTFP_OK;
+}
+
+int ttfp_price_batch_noalloc(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids, double *prices,
+                             double *delta, double *vega, int32_t *status)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (!ctx->scratch) {
+        ctx->last_error = "the scratch array of this device is unavailable: " + ctx->last_error;
+        return TTFP_EDEVICE;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) { ctx->last_error = "hipSetDevice failed"; return TTFP_EDEVICE; }
+    NoAllocScope scope(ctx);
+    return price_batch_impl(ctx, n, opts, grids, prices, delta, vega, status);
 }
 
 int ttfp_price(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, double *price, int32_t *ranks, ttfp_diag *diag)
