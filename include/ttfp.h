@@ -46,8 +46,14 @@ enum {
                              price); price written */
 };
 
-/* Payoffs (Sec. II.A uses the call on the minimum, Eq. minpayoff). */
-typedef enum { TTFP_CALL_MAX = 0, TTFP_PUT_MAX = 1, TTFP_CALL_MIN = 2 } ttfp_payoff;
+/* Payoffs (Sec. II.A uses the call on the minimum, Eq. minpayoff). The first three are priced
+ * as d separable terms (see above). TTFP_CALL_MIN_STRIP is the call on the minimum in the
+ * paper's own form (Sec. III.C, the min transform under Eq. main): one term in the asset
+ * coordinates x with the joint transform (-1)^(d+1) / ((1 + i sum_k z_k) prod_k (i z_k)) on
+ * Im z_k > 0, sum_k Im z_k > 1 (the transform as direct integration gives it; the printed one
+ * differs by the phase i^(d-2)). Its automatic contour is alpha_k = a_k + 1/d (a_k the aliasing
+ * distance); a scalar grid alpha puts +alpha on every coordinate (the paper uses 5/d). */
+typedef enum { TTFP_CALL_MAX = 0, TTFP_PUT_MAX = 1, TTFP_CALL_MIN = 2, TTFP_CALL_MIN_STRIP = 3 } ttfp_payoff;
 
 #define TTFP_MAX_D 32      /* largest number of assets */
 #define TTFP_MAX_RANK 64   /* largest TT rank (plus enrichment columns <= 68) */
@@ -67,7 +73,8 @@ typedef struct {
  *  L            > 0: the same half-width on every coordinate of every term; <= 0: automatic
  *  alpha        > 0: |contour shift| on every coordinate, signed by the coordinate's strip
  *               (call coordinate +alpha, which must exceed 1; put coordinate -alpha;
- *               max indicators -alpha; min indicators +alpha); <= 0: automatic
+ *               max indicators -alpha; min indicators +alpha; TTFP_CALL_MIN_STRIP +alpha,
+ *               with d alpha > 1); <= 0: automatic
  *  L_k, alpha_k optional [n_terms*d] per-term, per-coordinate values (alpha_k signed),
  *               overriding L / alpha when non-NULL (n_terms = d, or 1 when d = 1)
  *  tol          stop when the relative price change over a half sweep is <= tol
@@ -215,7 +222,9 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
 /* Kernel timing: when enabled, HIP events recorded on the context's stream bracket every
  * launch of each kernel family; ttfp_profile_read returns the number of launches, their
  * summed device time and the algorithmic work they did since the last enable (bytes written
- * for the fiber kernel: 16 per complex entry; FP64 flops for TSQR (8 m n^2 - 8 n^3 / 3),
+ * for the fiber kernel: 16 per complex entry; FP64 flops for TSQR (8 m n^2 - 8 n^3 / 3), the
+ * Cholesky QR's Gram products (4 m n^2 per pass: the Hermitian half of X^H X, m fiber rows,
+ * n columns) and triangular transforms (4 m n^2 per pass: X R^{-1} with R^{-1} triangular),
  * basis (4 m r^2), maxvol on its candidate block of K rows (8 K r^2 for the block, 8 (K + r) r
  * per swap for the rank-one updates of the block and of A^{-1}, 8 r^3 per Gauss-Jordan inverse)
  * and the interpolation matrix (8 m r^2); 0 where not counted). */
@@ -223,7 +232,7 @@ enum {
     TTFP_KERNEL_FIBER = 0, TTFP_KERNEL_TSQR = 1, TTFP_KERNEL_QRCP = 2, TTFP_KERNEL_BASIS = 3,
     TTFP_KERNEL_MAXVOL = 4, TTFP_KERNEL_FINISH = 5, TTFP_KERNEL_CORESUM = 6, TTFP_KERNEL_CONTRACT = 7,
     TTFP_KERNEL_INTERP = 8, TTFP_KERNEL_ERREST = 9, TTFP_KERNEL_GRAM = 10, TTFP_KERNEL_CHOL = 11,
-    TTFP_KERNEL_COUNT = 12
+    TTFP_KERNEL_XFORM = 12, TTFP_KERNEL_COUNT = 13
 };
 int ttfp_profile_enable(ttfp_ctx *ctx, int enable);
 int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms, double *work);

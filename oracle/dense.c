@@ -18,6 +18,11 @@
  * payoff factor (kind 0: (e^w - 1)^+ or (1 - e^w)^+, both 1/(iz(1+iz)) on their
  * own strips; kind 1: 1{w<0}, 1/(iz); kind 2: 1{w>0}, -1/(iz)).
  *
+ * Kind 3 (every coordinate, asset coordinates w = x) is the call on the minimum with the
+ * single-strip transform of Sec. III.C written in the form that direct integration gives:
+ * the product of factors is replaced by the joint transform
+ *   (-1)^(d+1) / ((1 + i sum_k z_k) prod_k (i z_k)),   Im z_k > 0, sum_k Im z_k > 1.
+ *
  * Every point evaluates the full quadratic form from scratch: O(d^2) per point,
  * deliberately without any reuse between points. The sum over the last index is
  * accumulated into a row sum, and row sums are accumulated with Kahan
@@ -53,6 +58,15 @@ static double complex integrand(int d, const double complex *z, const double *m,
         for (int l = 0; l < d; ++l) q += z[k] * C[k * d + l] * z[l];
     e -= 0.5 * q;
     double complex h = 1.0;
+    if (kind[0] == 3) {
+        double complex sz = 0.0;
+        for (int k = 0; k < d; ++k) {
+            sz += z[k];
+            h *= I * z[k];
+        }
+        h = ((d % 2) ? 1.0 : -1.0) / ((1.0 + I * sz) * h);
+        return cexp(e) * h;
+    }
     for (int k = 0; k < d; ++k) h *= payoff_factor(kind[k], z[k]);
     return cexp(e) * h;
 }

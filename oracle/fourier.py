@@ -28,6 +28,13 @@ Payoff factor transforms, derived by direct integration of int e^{i z w} f(w) dw
   1{w < 0}     -> 1/(iz),        Im z < 0
   1{w > 0}     -> -1/(iz),       Im z > 0
 
+The paper's own formulation of the call on the minimum (Sec. III.C, the min transform with
+Eq. main) keeps the asset coordinates and one term ("call_min_strip"): with
+(min_j e^{x_j} - 1)^+ = int_0^inf e^y prod_j 1{x_j > y} dy, direct integration gives the joint
+transform (-1)^(d+1) / ((1 + i sum_j z_j) prod_j (i z_j)) on Im z_j > 0, sum_j Im z_j > 1 (the
+printed formula differs from this by the phase i^(d-2); at d = 1 the form here is the call
+transform above).
+
 Readings of the paper taken here: the maturity multiplies the quadratic term of the
 characteristic function; the d-dimensional normalisation is (2 pi)^{-d}; the sum
 uses N midpoint nodes u_i = -L + (i + 1/2) 2L/N (a symmetric grid); the bilinear
@@ -58,7 +65,7 @@ import numpy as np
 
 from . import build as _build
 
-KIND_CALL, KIND_LT, KIND_GT = 0, 1, 2
+KIND_CALL, KIND_LT, KIND_GT, KIND_STRIP = 0, 1, 2, 3
 DEFAULT_TOL = 1e-12
 
 
@@ -113,6 +120,8 @@ def terms(opt):
     d = opt["d"]
     m, C = log_moments(opt)
     pay = opt["payoff"]
+    if pay == "call_min_strip":
+        return [dict(P=np.eye(d), m=m, C=C, kind=np.full(d, KIND_STRIP, dtype=np.int32), sign=np.ones(d))]
     out = []
     for j in range(d):
         P = np.zeros((d, d))
@@ -153,6 +162,8 @@ def _rule_at(term, N, tau, prec):
     for k in range(len(L)):
         if term["kind"][k] == KIND_CALL and term["sign"][k] > 0:
             alpha[k] = 1.0 + a[k]
+        elif term["kind"][k] == KIND_STRIP:
+            alpha[k] = a[k] + 1.0 / len(L)       # distance a_k from z_k = 0, sum a_k from sum z = i
         else:
             alpha[k] = term["sign"][k] * a[k]
     phi = float(alpha @ term["m"] + 0.5 * alpha @ term["C"] @ alpha)
@@ -198,6 +209,7 @@ def term_grids(opt, N, L=None, alpha=None, tol=DEFAULT_TOL):
                 eta = 2.0 * Lt / N
                 a = grid_tau(tol) * eta / (2.0 * math.pi)
                 At = np.where((term["kind"] == KIND_CALL) & (term["sign"] > 0), 1.0 + a, term["sign"] * a)
+                At = np.where(term["kind"] == KIND_STRIP, a + 1.0 / opt["d"], At)
         elif np.isscalar(alpha):
             At = term["sign"] * float(alpha)
         else:
@@ -289,6 +301,14 @@ def payoff_factor(kind, z):
     if kind == KIND_LT:
         return 1.0 / iz
     return -1.0 / iz
+
+
+def min_strip_transform(z):
+    """Joint transform of (min_j e^{w_j} - 1)^+ (K = 1) at complex z[d] with Im z_j > 0 and
+    sum_j Im z_j > 1: (-1)^(d+1) / ((1 + i sum z) prod (i z_j)) (NumPy version for tests)."""
+    z = np.asarray(z, complex)
+    d = z.shape[-1]
+    return (-1.0) ** (d + 1) / ((1.0 + 1j * z.sum(axis=-1)) * np.prod(1j * z, axis=-1))
 
 
 def paper_min_transform(z, K=1.0):

@@ -22,7 +22,7 @@ def payoff(payoff_kind, ST, K):
         return np.maximum(ST.max(axis=1) - K, 0.0)
     if payoff_kind == "put_max":
         return np.maximum(K - ST.max(axis=1), 0.0)
-    if payoff_kind == "call_min":
+    if payoff_kind in ("call_min", "call_min_strip"):
         return np.maximum(ST.min(axis=1) - K, 0.0)
     raise ValueError(payoff_kind)
 

@@ -19,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libttfp.so")
 
-PAYOFF_CODES = {"call_max": 0, "put_max": 1, "call_min": 2}
+PAYOFF_CODES = {"call_max": 0, "put_max": 1, "call_min": 2, "call_min_strip": 3}
 TTFP_OK, TTFP_EINVAL, TTFP_ENOMEM, TTFP_EDEVICE, TTFP_ENOTCONV, TTFP_EPRECISION = 0, -1, -2, -3, 1, 2
 MAX_RANK = 64
 
@@ -58,7 +58,7 @@ EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
            "ttfp_mlp_last_error"]
 KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract", "interp", "err_est",
-           "gram", "chol"]
+           "gram", "chol", "xform"]
 TUNING = {"maxvol_threads": 0, "tsqr_lds_kb": 1, "graph": 2, "qr": 3}
 
 _lib = None
@@ -200,7 +200,8 @@ class Pricer:
         return rc
 
     def price(self, opt, grid):
-        """Returns (price, ranks[n_terms, d+1], diag dict, return code)."""
+        """Returns (price, ranks[n_terms, d+1], diag dict, return code); n_terms is d for the
+        max/min payoffs (one term per asset, 1 when d = 1) and 1 for call_min_strip."""
         m = _Marshal(opt, grid)
         d = int(opt["d"])
         out = ctypes.c_double(0.0)
@@ -208,7 +209,8 @@ class Pricer:
         diag = _Diag()
         rc = self._check(self.lib.ttfp_price(self.ctx, ctypes.byref(m.opt), ctypes.byref(m.grid), ctypes.byref(out),
                                              _ip(ranks), ctypes.byref(diag)))
-        return out.value, ranks.reshape(d, d + 1), _diag_dict(diag), rc
+        n_terms = 1 if (d == 1 or opt.get("payoff") == "call_min_strip") else d
+        return out.value, ranks[: n_terms * (d + 1)].reshape(n_terms, d + 1), _diag_dict(diag), rc
 
     def batch_diag(self, i):
         """Diagnostics dict of option i of the last price_batch call."""

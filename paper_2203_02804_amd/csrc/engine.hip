@@ -77,7 +77,8 @@ struct ttfp_ctx {
 namespace {
 
 const size_t ALIGN = 256;
-constexpr int GRAM_ROWS_HOST = 256;          // fiber rows per Gram workgroup (k_gram)
+constexpr int GRAM_ROWS_HOST = 1024;         // fiber rows per Gram workgroup (k_gram)
+constexpr int XF_WAVES_HOST = 12;            // 16-row panels per triangular-transform workgroup (k_xform)
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 #define HIPCHK(expr)                                                                     \
@@ -433,15 +434,15 @@ constexpr int MAXVOL_REFINE_ROUNDS = 3;
 // The fiber's triangular factor by three passes of shifted Cholesky QR (k_gram, k_chol, k_xform).
 void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int maxrows, unsigned ny, int t, int dir)
 {
-    const unsigned gb = cdivu(maxrows, GRAM_ROWS_HOST), gx = cdivu(maxrows, MM_ROWS_PER_WG);
+    const unsigned gb = cdivu(maxrows, GRAM_ROWS_HOST), gx = cdivu(maxrows, 16 * XF_WAVES_HOST);
     for (int pass = 0; pass < 3; ++pass) {
         if (pass > 0) {
-            ProfScope ps(ctx, TTFP_KERNEL_GRAM);
-            hipLaunchKernelGGL(k_xform, dim3(gx, ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir, pass);
+            ProfScope ps(ctx, TTFP_KERNEL_XFORM);
+            hipLaunchKernelGGL(k_xform, dim3(gx, ny), dim3(64 * XF_WAVES_HOST), 0, st, it, act, t, dir, pass);
         }
         {
             ProfScope ps(ctx, TTFP_KERNEL_GRAM);
-            hipLaunchKernelGGL(k_gram, dim3(gb, ny), dim3(256), 0, st, it, act, t, dir, pass);
+            hipLaunchKernelGGL(k_gram, dim3(gb, ny), dim3(512), 0, st, it, act, t, dir, pass);
         }
         ProfScope ps(ctx, TTFP_KERNEL_CHOL);
         hipLaunchKernelGGL(k_chol, dim3(ny), dim3(256), 0, st, it, act, t, dir, pass);
@@ -690,7 +691,7 @@ done:
     for (const Item &it : b.items) any_samples |= it.n_samp > 0;
     if (any_samples) {
         ProfScope ps(ctx, TTFP_KERNEL_ERREST);
-        hipLaunchKernelGGL(k_err_est, dim3(n_items), dim3(1024), 0, ctx->stream, ctx->d_items, ctx->d_active);
+        hipLaunchKernelGGL(k_err_est, dim3(n_items), dim3(512), 0, ctx->stream, ctx->d_items, ctx->d_active);
         HIPCHK(hipGetLastError());
     }
     if (greeks) {

@@ -288,12 +288,20 @@ __device__ __forceinline__ int rand_index(uint64_t seed, uint64_t a, uint64_t b,
 // ------------------------------------------------------------------ integrand (one entry)
 // exp(-i z.m - z^T C z / 2) * prod_k h_k(z_k),  z_k = -L_k + (i_k + 1/2) 2L_k/N + i alpha_k:
 // the Gaussian characteristic function at -z (Sec. III.C) times the payoff factor transforms.
+// Kinds: 0 call/put factor 1/(iz(1+iz)); 1 indicator w < 0, 1/(iz); 2 indicator w > 0, -1/(iz);
+// 3 coordinate of the single-strip call on the minimum, 1/(iz), whose term also carries the
+// joint factor (-1)^(d+1) / (1 + i sum_k z_k) (strip_joint).
 __device__ __forceinline__ cplx factor(int kind, cplx z)
 {
     cplx iz = {-z.y, z.x};
     if (kind == 0) return cdiv({1.0, 0.0}, cmul(iz, {1.0 + iz.x, iz.y}));
     cplx v = cdiv({1.0, 0.0}, iz);
-    return kind == 1 ? v : cplx{-v.x, -v.y};
+    return kind == 2 ? cplx{-v.x, -v.y} : v;
+}
+// (-1)^(d+1) / (1 + i s), s = sum_k z_k
+__device__ __forceinline__ cplx strip_joint(int d, cplx s)
+{
+    return cdiv({(d & 1) ? 1.0 : -1.0, 0.0}, {1.0 - s.y, s.x});
 }
 
 __device__ cplx integrand(const Item &it, const int *idx)
@@ -305,7 +313,7 @@ __device__ cplx integrand(const Item &it, const int *idx)
         double L = it.L[k];
         z[k] = {-L + (idx[k] + 0.5) * 2.0 * L * invN, it.alpha[k]};
     }
-    cplx e = {0.0, 0.0}, h = {1.0, 0.0};
+    cplx e = {0.0, 0.0}, h = {1.0, 0.0}, zs = {0.0, 0.0};
     for (int k = 0; k < d; ++k) {
         const double *Ck = it.C + k * d;
         cplx q = {0.0, 0.0};
@@ -314,7 +322,9 @@ __device__ cplx integrand(const Item &it, const int *idx)
         cplx w = {-0.5 * q.x, -it.m[k] - 0.5 * q.y};
         e = cadd(e, cmul(z[k], w));
         h = cmul(h, factor(it.kind[k], z[k]));
+        zs = cadd(zs, z[k]);
     }
+    if (it.kind[0] == 3) h = cmul(h, strip_joint(d, zs));
     return cmul(cexp_(e), h);
 }
 
@@ -371,7 +381,7 @@ __global__ void k_init(Item *items, int n_items)
     it.mv_singular = 0;
     it.mv_viol = 0;
     it.mv_dirty = 0;
-    for (int q = 0; q < 12; ++q) it.work[q] = 0.0;
+    for (int q = 0; q < TTFP_KERNEL_COUNT; ++q) it.work[q] = 0.0;
     it.capped = 0;
     long long cnt = 1;
     for (int k = d - 1; k >= 1; --k) {
@@ -456,9 +466,11 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, i
         const double L = it.L[l];
         z[l] = {-L + (ix + 0.5) * 2.0 * L * invN, it.alpha[l]};
     }
-    cplx e0 = {0.0, 0.0}, tau = {0.0, 0.0}, H = {1.0, 0.0};
+    cplx e0 = {0.0, 0.0}, tau = {0.0, 0.0}, H = {1.0, 0.0}, zrest = {0.0, 0.0};
+    const bool strip = it.kind[0] == 3;
     for (int l = 0; l < d; ++l) {
         if (l == k) continue;
+        zrest = cadd(zrest, z[l]);
         const double *Cl = it.C + l * d;
         cplx q = {0.0, 0.0};
         for (int l2 = 0; l2 < d; ++l2) {
@@ -475,7 +487,8 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, i
     for (int i = 0; i < N; ++i) {
         const cplx zk = {-Lk + (i + 0.5) * etak, ak};
         const cplx ex = cadd(cadd(e0, cmul(zk, tau)), ctab[i]);
-        const cplx v = cmul(cexp_(ex), cmul(H, htab[i]));
+        cplx v = cmul(cexp_(ex), cmul(H, htab[i]));
+        if (strip) v = cmul(v, strip_joint(d, cadd(zrest, zk)));
         const size_t row = (dir == 0) ? (size_t)g * N + i : (size_t)i * ng + g;
         out[row * nc + c] = v;
     }
@@ -885,7 +898,7 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
 // hundred times the shift. The Gram products and the triangular transforms are dense
 // contractions over the fiber's rows and run on the FP64 matrix cores (v_mfma_f64_16x16x4f64);
 // the nc x nc Cholesky, inverse and factor product are one small workgroup per item.
-constexpr int GRAM_ROWS = 256;                     // fiber rows per Gram workgroup
+constexpr int GRAM_ROWS = 1024;                    // fiber rows per Gram workgroup
 constexpr int GRAM_CHUNK = 32;                     // rows staged in LDS at a time
 constexpr int NCPAD = (MAXNC + 15) / 16 * 16;      // columns rounded up to whole 16-wide tiles
 constexpr int GRAM_NOSCALE = -100000;              // block exponent of a block of zeros
@@ -895,14 +908,21 @@ __device__ __forceinline__ int gram_blocks(int rows) { return (rows + GRAM_ROWS 
 
 // Partial Gram of one block of GRAM_ROWS fiber rows: P = X^H X over the block's rows, upper
 // 16 x 16 tiles only, written to it.Gp[block] (nc x nc, row-major). Pass 0 reads F and scales
-// it on the fly by 2^-e_blk, e_blk the exponent of the block's largest entry (the accumulators
-// are rescaled exactly when a later chunk raises it; e_blk goes to it.Ge[block]); passes 1 and 2
-// read Q unscaled. Complex products by three real ones: with X = Xr + i Xi, Y = Yr + i Yi,
-// X^H Y = (t1 + t2) + i (t3 - t1 + t2), t1 = Xr^T Yr, t2 = Xi^T Yi, t3 = (Xr - Xi)^T (Yr + Yi).
-__global__ __launch_bounds__(256) void k_gram(Item *items, const int *active, int t, int dir, int pass)
+// it by 2^-e_blk, e_blk the exponent of the largest entry seen so far in the block (the
+// accumulators are rescaled exactly when a later chunk raises it; e_blk goes to it.Ge[block]);
+// passes 1 and 2 read Q unscaled. A chunk of rows is staged in LDS as separate real and
+// imaginary planes whose row stride (NCPAD doubles, 32 banks mod 64) lets the two rows a half
+// wave reads fall on disjoint banks; the next chunk is loaded into registers meanwhile. Eight
+// waves take two tiles each. Complex products by three real ones (Gauss): with X = Xr + i Xi,
+// Y = Yr + i Yi, X^H Y = (t1 + t2) + i (t3 - t1 + t2), t1 = Xr^T Yr, t2 = Xi^T Yi,
+// t3 = (Xr - Xi)^T (Yr + Yi): three independent accumulators per tile.
+constexpr int GRAM_THREADS = 512;
+__global__ __launch_bounds__(GRAM_THREADS) void k_gram(Item *items, const int *active, int t, int dir, int pass)
 {
-    __shared__ cplx chunk[GRAM_CHUNK][NCPAD + 1];
-    __shared__ double wmax[4];
+    constexpr int PER = (GRAM_CHUNK * MAXNC + GRAM_THREADS - 1) / GRAM_THREADS;   // chunk entries per thread
+    constexpr int NW = GRAM_THREADS / 64, TPW = 2;                                 // waves, tiles per wave
+    __shared__ double cre[GRAM_CHUNK][NCPAD], cim[GRAM_CHUNK][NCPAD];
+    __shared__ double wmax[NW];
     const int item = blockIdx.y;
     if (!active[item]) return;
     Item &it = items[item];
@@ -913,20 +933,37 @@ __global__ __launch_bounds__(256) void k_gram(Item *items, const int *active, in
     if (blk == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_GRAM] += 4.0 * m * (double)nc * nc;
     const cplx *src = pass == 0 ? it.F : it.Qb;
     const int T = (nc + 15) / 16, ntiles = T * (T + 1) / 2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
-    // this wave's tiles: q = wave, wave + 4, ... in the order (0,0) (0,1) .. (0,T-1) (1,1) ..
-    int tI[4], tJ[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    // this wave's tiles: q = wave, wave + NW in the order (0,0) (0,1) .. (0,T-1) (1,1) ..
+    int tI[TPW], tJ[TPW];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        int q = wave + 4 * u, I = 0;
+    for (int u = 0; u < TPW; ++u) {
+        int q = wave + NW * u, I = 0;
         while (I < T && q >= T - I) { q -= T - I; ++I; }
         tI[u] = I;
         tJ[u] = I + q;
     }
-    const int nt = ntiles > wave ? (ntiles - wave + 3) / 4 : 0;
-    double4_t p1[4], p2[4], p3[4];
+    const int nt = ntiles > wave ? min(TPW, (ntiles - wave + NW - 1) / NW) : 0;
+    // entry e = tid + GRAM_THREADS q of a chunk is row e / nc, column e % nc (rows of a chunk are
+    // contiguous in the fiber, so a chunk is one coalesced sweep)
+    int er[PER], ec[PER];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + GRAM_THREADS * q;
+        er[q] = e / nc;
+        ec[q] = e - er[q] * nc;
+    }
+    // padding columns nc .. 16 T - 1 stay zero for every chunk
+    for (int e = tid; e < GRAM_CHUNK * 16 * T; e += GRAM_THREADS) {
+        const int c = e % (16 * T);
+        if (c >= nc) {
+            cre[e / (16 * T)][c] = 0.0;
+            cim[e / (16 * T)][c] = 0.0;
+        }
+    }
+    double4_t p1[TPW], p2[TPW], p3[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
         p1[u] = double4_t{0.0, 0.0, 0.0, 0.0};
         p2[u] = p1[u];
         p3[u] = p1[u];
@@ -934,27 +971,30 @@ __global__ __launch_bounds__(256) void k_gram(Item *items, const int *active, in
     int e_blk = GRAM_NOSCALE;
     double sc = 1.0;
     const int r0 = blk * GRAM_ROWS, r1 = min(m, r0 + GRAM_ROWS);
+    cplx pre[PER];
+    auto fetch = [&](int c0) {
+        const int n = min(GRAM_CHUNK, r1 - c0) * nc;
+        const cplx *g = src + (size_t)c0 * nc;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + GRAM_THREADS * q;
+            pre[q] = e < n ? g[e] : cplx{0.0, 0.0};
+        }
+    };
+    fetch(r0);
     for (int c0 = r0; c0 < r1; c0 += GRAM_CHUNK) {
         const int nr = min(GRAM_CHUNK, r1 - c0);
-        __syncthreads();
-        // rows c0 .. c0 + nr - 1 are contiguous in the fiber: one coalesced sweep
-        double mx = 0.0;
-        const cplx *g = src + (size_t)c0 * nc;
-        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
-            const cplx v = g[e];
-            mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
-            chunk[e / nc][e % nc] = v;
-        }
-        // zero padding: columns nc .. 16T - 1 of the rows read, all columns of rows nr .. GRAM_CHUNK - 1
-        for (int e = threadIdx.x; e < GRAM_CHUNK * 16 * T; e += blockDim.x) {
-            const int i = e / (16 * T), c = e % (16 * T);
-            if (i >= nr || c >= nc) chunk[i][c] = {0.0, 0.0};
-        }
         if (pass == 0) {
+            double mx = 0.0;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) mx = fmax(mx, fmax(fabs(pre[q].x), fabs(pre[q].y)));
             mx = wave_max(mx);
             if (lane == 0) wmax[wave] = mx;
-            __syncthreads();
-            mx = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        }
+        __syncthreads();                         // the previous chunk has been multiplied
+        if (pass == 0) {
+            double mx = 0.0;
+            for (int w = 0; w < NW; ++w) mx = fmax(mx, wmax[w]);
             if (mx > 0.0) {
                 int e;
                 frexp(mx, &e);
@@ -962,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_gram(Item *items, const int *active, in
                     if (e_blk != GRAM_NOSCALE) {
                         const double f = ldexp(1.0, 2 * (e_blk - e));
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
+                        for (int u = 0; u < TPW; ++u) {
                             p1[u] *= f;
                             p2[u] *= f;
                             p3[u] *= f;
@@ -972,17 +1012,23 @@ __global__ __launch_bounds__(256) void k_gram(Item *items, const int *active, in
                     sc = ldexp(1.0, -e);
                 }
             }
-        } else {
-            __syncthreads();
         }
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (er[q] < GRAM_CHUNK) {                // rows past nr were loaded as zeros
+                cre[er[q]][ec[q]] = pre[q].x * sc;
+                cim[er[q]][ec[q]] = pre[q].y * sc;
+            }
+        __syncthreads();
+        if (c0 + GRAM_CHUNK < r1) fetch(c0 + GRAM_CHUNK);
         const int nks = (nr + 3) / 4;
         for (int ks = 0; ks < nks; ++ks) {
             const int row = 4 * ks + lk;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < TPW; ++u) {
                 if (u >= nt) break;
-                const cplx x = chunk[row][16 * tI[u] + li], y = chunk[row][16 * tJ[u] + li];
-                const double xr = x.x * sc, xi = x.y * sc, yr = y.x * sc, yi = y.y * sc;
+                const double xr = cre[row][16 * tI[u] + li], xi = cim[row][16 * tI[u] + li];
+                const double yr = cre[row][16 * tJ[u] + li], yi = cim[row][16 * tJ[u] + li];
                 p1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr, p1[u], 0, 0, 0);
                 p2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi, p2[u], 0, 0, 0);
                 p3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr - xi, yr + yi, p3[u], 0, 0, 0);
@@ -991,7 +1037,7 @@ __global__ __launch_bounds__(256) void k_gram(Item *items, const int *active, in
     }
     cplx *P = it.Gp + (size_t)blk * nc * nc;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < TPW; ++u) {
         if (u >= nt) break;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -999,11 +1045,21 @@ __global__ __launch_bounds__(256) void k_gram(Item *items, const int *active, in
             if (i < nc && j < nc && i <= j) P[(size_t)i * nc + j] = {p1[u][v] + p2[u][v], p3[u][v] - p1[u][v] + p2[u][v]};
         }
     }
-    if (threadIdx.x == 0) it.Ge[blk] = pass == 0 ? e_blk : 0;
+    if (tid == 0) it.Ge[blk] = pass == 0 ? e_blk : 0;
 }
 
 // Packed upper-triangular storage of an n x n matrix: row i starts at i n - i (i - 1) / 2.
 __device__ __forceinline__ int up_off(int i, int n) { return i * n - (i * (i - 1)) / 2; }
+// row of packed entry e: the largest i with up_off(i) <= e (from the quadratic, then corrected)
+__device__ __forceinline__ int up_row(int e, int n)
+{
+    const double b = 2.0 * n + 1.0;
+    int i = (int)(0.5 * (b - sqrt(b * b - 8.0 * e)));
+    i = max(0, min(i, n - 1));
+    while (i > 0 && up_off(i, n) > e) --i;
+    while (i + 1 < n && up_off(i + 1, n) <= e) ++i;
+    return i;
+}
 
 // Sums the partial Grams (scaled to the largest block exponent), factors G + shift I = R^H R
 // (upper, real positive diagonal), forms X = R^{-1} for the next transform (it.Xf, nc x nc
@@ -1032,9 +1088,7 @@ __global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, in
         emax = 0;
     double tr = 0.0;
     for (int e = threadIdx.x; e < np; e += nthr) {
-        int i = 0;
-        while (e >= up_off(i + 1, nc)) ++i;
-        const int j = i + (e - up_off(i, nc));
+        const int i = up_row(e, nc), j = i + (e - up_off(i, nc));
         cplx acc = {0.0, 0.0};
         if (emax != GRAM_NOSCALE)
             for (int b = 0; b < nb; ++b) {
@@ -1114,53 +1168,78 @@ __global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, in
             const int i = e / nc, j = e % nc;
             it.Xf[e] = j >= i ? Xp[up_off(i, nc) + j - i] : cplx{0.0, 0.0};
         }
-    __syncthreads();
-    // running factor: Rf <- R (pass 0) or R Rf; the last pass also undoes the scaling
+    // running factor: Rf <- R (pass 0) or R Rf (the previous Rf staged in Xp, packed); the last
+    // pass also undoes the scaling
     const double unscale = pass == 2 ? ldexp(1.0, it.gram_e == GRAM_NOSCALE ? 0 : it.gram_e) : 1.0;
-    for (int e = threadIdx.x; e < np; e += nthr) {
-        int i = 0;
-        while (e >= up_off(i + 1, nc)) ++i;
-        const int j = i + (e - up_off(i, nc));
+    constexpr int PER = (MAXNC * (MAXNC + 1) / 2 + 255) / 256;
+    cplx res[PER];
+    if (pass > 0) {
+        __syncthreads();                           // Xf written from Xp
+        for (int e = threadIdx.x; e < np; e += nthr) {
+            const int i = up_row(e, nc), j = i + (e - up_off(i, nc));
+            Xp[e] = it.Rf[(size_t)i * nc + j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e >= np) break;
+        const int i = up_row(e, nc), j = i + (e - up_off(i, nc)), oi = up_off(i, nc);
         cplx acc;
         if (pass == 0) {
             acc = Rp[e];
         } else {
             acc = {0.0, 0.0};
-            for (int l = i; l <= j; ++l) acc = cadd(acc, cmul(Rp[up_off(i, nc) + l - i], it.Rf[(size_t)l * nc + j]));
+            for (int l = i; l <= j; ++l) acc = cadd(acc, cmul(Rp[oi + l - i], Xp[up_off(l, nc) + j - l]));
         }
-        Xp[e] = {acc.x * unscale, acc.y * unscale};
+        res[q] = {acc.x * unscale, acc.y * unscale};
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e >= np) break;
+        const int i = up_row(e, nc), j = i + (e - up_off(i, nc));
+        it.Rf[(size_t)i * nc + j] = res[q];
+    }
     for (int e = threadIdx.x; e < nc * nc; e += nthr) {
         const int i = e / nc, j = e % nc;
-        it.Rf[e] = j >= i ? Xp[up_off(i, nc) + j - i] : cplx{0.0, 0.0};
+        if (j < i) it.Rf[e] = {0.0, 0.0};
     }
     if (pass == 0 && threadIdx.x == 0) it.gram_e = emax;
 }
 
-// Q = X_src Xf for every fiber row, in 16-row panels per wave on the FP64 matrix cores (as in the
-// basis product below): pass 1 reads F scaled by 2^-gram_e and writes Q; pass 2 transforms Q in
-// place (a wave owns its panel, and every load of the panel precedes the panel's stores). Xf is
-// upper triangular, so output column tile J takes only k < 16 (J + 1).
-__global__ __launch_bounds__(64 * MM_WAVES) void k_xform(Item *items, const int *active, int t, int dir, int pass)
+// Q = X_src Xf for every fiber row, in 16-row panels per wave on the FP64 matrix cores: pass 1
+// reads F scaled by 2^-gram_e and writes Q; pass 2 transforms Q in place (a wave owns its panel,
+// and every load of the panel precedes the panel's stores). Xf is upper triangular, so output
+// column tile J takes only k < 16 (J + 1). Xf sits in LDS as real and imaginary planes with a row
+// stride of NCPAD doubles (the two k-rows a half wave reads fall on disjoint banks); complex
+// products by three real ones (Gauss) into three independent accumulators per tile.
+constexpr int XF_WAVES = 12;                       // 16-row panels per workgroup
+__global__ __launch_bounds__(64 * XF_WAVES) void k_xform(Item *items, const int *active, int t, int dir, int pass)
 {
-    __shared__ cplx Xs[MAXNC * MAXNC];
+    __shared__ double Xr[MAXNC][NCPAD], Xi[MAXNC][NCPAD];
     const int item = blockIdx.y;
     if (!active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
     const int nc = s.nc, m = s.rows;
-    if (blockIdx.x * MM_ROWS_PER_WG >= m) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_GRAM] += 4.0 * m * (double)nc * nc;
-    for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) Xs[e] = it.Xf[e];
+    if (blockIdx.x * 16 * XF_WAVES >= m) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_XFORM] += 4.0 * m * (double)nc * nc;
+    const int T = (nc + 15) / 16;
+    for (int e = threadIdx.x; e < nc * 16 * T; e += blockDim.x) {
+        const int k = e / (16 * T), c = e - k * 16 * T;
+        const cplx x = c < nc ? it.Xf[(size_t)k * nc + c] : cplx{0.0, 0.0};
+        Xr[k][c] = x.x;
+        Xi[k][c] = x.y;
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
-    const int row0 = blockIdx.x * MM_ROWS_PER_WG + wave * 16;
+    const int row0 = blockIdx.x * 16 * XF_WAVES + wave * 16;
     if (row0 >= m) return;
     const cplx *src = pass == 1 ? it.F : it.Qb;
     const double sc = pass == 1 ? ldexp(1.0, it.gram_e == GRAM_NOSCALE ? 0 : -it.gram_e) : 1.0;
-    const int T = (nc + 15) / 16;
     double4_t prr[NCPAD / 16], pii[NCPAD / 16], pss[NCPAD / 16];
 #pragma unroll
     for (int q = 0; q < NCPAD / 16; ++q) {
@@ -1171,17 +1250,18 @@ __global__ __launch_bounds__(64 * MM_WAVES) void k_xform(Item *items, const int 
     const int arow = row0 + li;
     for (int k0 = 0; k0 < nc; k0 += 4) {
         const int kk = k0 + lk;
-        cplx a = (arow < m && kk < nc) ? src[(size_t)arow * nc + kk] : cplx{0.0, 0.0};
-        a = {a.x * sc, a.y * sc};
+        const bool in = arow < m && kk < nc;
+        const cplx a = in ? src[(size_t)arow * nc + kk] : cplx{0.0, 0.0};
+        const double ar = a.x * sc, ai = a.y * sc, as = ar + ai;
+        const int kr = kk < nc ? kk : 0;           // rows of Xf past nc: the operand is zero anyway
 #pragma unroll
         for (int q = 0; q < NCPAD / 16; ++q) {
             if (q >= T) break;
             if (k0 >= 16 * (q + 1)) continue;     // rows of X below the diagonal block are zero
-            const int jj = 16 * q + li;
-            const cplx b = (kk < nc && jj < nc) ? Xs[kk * nc + jj] : cplx{0.0, 0.0};
-            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
-            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
-            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+            const double br = Xr[kr][16 * q + li], bi = Xi[kr][16 * q + li];
+            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, prr[q], 0, 0, 0);
+            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, pii[q], 0, 0, 0);
+            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, br + bi, pss[q], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -2212,55 +2292,138 @@ __global__ __launch_bounds__(64) void k_tt_values(const Item *items, int item, l
 // The tensor train of an item against the integrand at n_samp uniformly drawn grid points
 // (Sec. IV.B measures the convergence of the cross by the relative 1-norm error on random
 // points): err_abs = sum_s |TT(x_s) - A(x_s)|, err_ref = sum_s |A(x_s)|. Coordinate k of point s
-// is rand_index(seed, 7, s, k, N). One wave per point: lane b holds entry b of the running row
-// vector, which is advanced through core k by a loop over its rows (one coalesced load of a core
-// row per step). Sums are formed per wave in point order and reduced across waves in wave order,
-// so the result does not depend on scheduling.
-__global__ __launch_bounds__(1024) void k_err_est(Item *items, const int *active)
+// is rand_index(seed, 7, s, k, N). One workgroup per item carries the row vectors v_s of a chunk
+// of points through the cores, v_s <- v_s G_k(:, i_k(s), :): the points are bucketed by their
+// node i_k (counting sort in LDS), and each bucket is one small product against the core slice
+// G_k(:, i, :) on the FP64 matrix cores, so a slice is read once per 16 points of its bucket
+// instead of once per point. The row vectors live in the item's fiber buffers (idle once the
+// sweep has ended). Each point's value does not depend on the order inside its bucket, and the
+// sums are formed per thread over a fixed set of points and reduced in thread order, so the
+// result does not depend on scheduling.
+constexpr int ERR_THREADS = 512;
+constexpr int ERR_CHUNK = 8192;                    // points per pass through the cores
+__global__ __launch_bounds__(ERR_THREADS) void k_err_est(Item *items, const int *active)
 {
-    __shared__ cplx vbuf[1024 / 64][TTFP_MAX_RANK];
-    __shared__ double part[1024 / 64][2];
+    __shared__ int cnt[MAXN + 1];
+    __shared__ int cur[MAXN];
+    __shared__ int perm[ERR_CHUNK];
+    __shared__ double part[ERR_THREADS / 64][2];
     const int item = blockIdx.x;
     if (!active[item]) return;
     Item &it = items[item];
     const int ns = it.n_samp;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (ns <= 0) return;
     const int d = it.d, N = it.N, R = it.R;
-    cplx *v = vbuf[wave];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = ERR_THREADS / 64;
+    const int li = lane & 15, lk = lane >> 4;
+    // points per chunk: the row vectors (chunk x R complex, twice) fit the fiber buffers
+    const long long cap = (long long)it.rows_max * (R + it.p) / R;
+    const int SC = (int)min((long long)ERR_CHUNK, cap);
     double sa = 0.0, sf = 0.0;
-    for (int smp = wave; smp < ns; smp += nw) {
-        for (int k = 0; k < d; ++k) {
+    for (int s0 = 0; s0 < ns; s0 += SC) {
+        const int nsc = min(SC, ns - s0);
+        cplx *V = it.F, *Wv = it.Qb;
+        {
+            const int b_n = it.ccol[0];
+            const cplx *core = it.cores;
+            for (int e = tid; e < nsc * b_n; e += ERR_THREADS) {
+                const int jj = e / b_n, b = e - jj * b_n;
+                const int i0 = rand_index(it.seed, 7, (uint64_t)(s0 + jj), 0, N);
+                V[(size_t)jj * R + b] = core[(size_t)i0 * b_n + b];      // r_0 = 1
+            }
+        }
+        __syncthreads();
+        for (int k = 1; k < d; ++k) {
             const int a_n = it.crow[k], b_n = it.ccol[k];
-            const int i = rand_index(it.seed, 7, (uint64_t)smp, (uint64_t)k, N);
             const cplx *core = it.cores + (size_t)k * R * N * R;
-            cplx acc = {0.0, 0.0};
-            if (lane < b_n) {
-                if (k == 0) {
-                    acc = core[(size_t)i * b_n + lane];                 // a_n == 1
-                } else {
-                    for (int a = 0; a < a_n; ++a) acc = cadd(acc, cmul(v[a], core[((size_t)a * N + i) * b_n + lane]));
+            // bucket the chunk's points by node i_k
+            for (int q = tid; q <= N; q += ERR_THREADS) cnt[q] = 0;
+            __syncthreads();
+            for (int jj = tid; jj < nsc; jj += ERR_THREADS)
+                atomicAdd(&cnt[rand_index(it.seed, 7, (uint64_t)(s0 + jj), (uint64_t)k, N)], 1);
+            __syncthreads();
+            if (tid == 0) {
+                int acc = 0;
+                for (int q = 0; q < N; ++q) {
+                    const int c = cnt[q];
+                    cnt[q] = acc;
+                    cur[q] = acc;
+                    acc += c;
+                }
+                cnt[N] = acc;
+            }
+            __syncthreads();
+            for (int jj = tid; jj < nsc; jj += ERR_THREADS) {
+                const int i = rand_index(it.seed, 7, (uint64_t)(s0 + jj), (uint64_t)k, N);
+                perm[atomicAdd(&cur[i], 1)] = jj;
+            }
+            __syncthreads();
+            // bucket i: W[rows] = V[rows] G_k(:, i, :), 16 points per panel, one wave per bucket
+            const int ntile = (b_n + 15) / 16;
+            for (int i = wave; i < N; i += nw) {
+                const int off = cnt[i], c = cnt[i + 1] - off;
+                for (int p0 = 0; p0 < c; p0 += 16) {
+                    double4_t prr[4], pii[4], pss[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+                        pii[q] = prr[q];
+                        pss[q] = prr[q];
+                    }
+                    const int rj = p0 + li < c ? perm[off + p0 + li] : -1;
+                    for (int k0 = 0; k0 < a_n; k0 += 4) {
+                        const int kk = k0 + lk;
+                        const cplx a = (rj >= 0 && kk < a_n) ? V[(size_t)rj * R + kk] : cplx{0.0, 0.0};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            if (q >= ntile) break;
+                            const int cb = 16 * q + li;
+                            const cplx b = (kk < a_n && cb < b_n) ? core[((size_t)kk * N + i) * b_n + cb] : cplx{0.0, 0.0};
+                            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
+                            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
+                            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int rp = p0 + lk + 4 * v;
+                        if (rp >= c) continue;
+                        const int jj = perm[off + rp];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            if (q >= ntile) break;
+                            const int cb = 16 * q + li;
+                            if (cb < b_n)
+                                Wv[(size_t)jj * R + cb] = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
+                        }
+                    }
                 }
             }
-            wave_lds_order();
-            if (lane < b_n) v[lane] = acc;
-            wave_lds_order();
+            __syncthreads();
+            cplx *tmp = V;
+            V = Wv;
+            Wv = tmp;
         }
-        if (lane == 0) {
+        // v_s is now the tensor train's value at x_s (r_d = 1)
+        for (int jj = tid; jj < nsc; jj += ERR_THREADS) {
             int idx[MAXD];
-            for (int k = 0; k < d; ++k) idx[k] = rand_index(it.seed, 7, (uint64_t)smp, (uint64_t)k, N);
+            for (int k = 0; k < d; ++k) idx[k] = rand_index(it.seed, 7, (uint64_t)(s0 + jj), (uint64_t)k, N);
             const cplx f = integrand(it, idx);
-            const cplx tt = v[0];
+            const cplx tt = V[(size_t)jj * R];
             sa += hypot(tt.x - f.x, tt.y - f.y);
             sf += hypot(f.x, f.y);
         }
-        wave_lds_order();
+        __syncthreads();
     }
+    // thread partials in thread order
+    sa = wave_sum(sa);
+    sf = wave_sum(sf);
     if (lane == 0) {
         part[wave][0] = sa;
         part[wave][1] = sf;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double a = 0.0, f = 0.0;
         for (int w = 0; w < nw; ++w) {
             a += part[w][0];

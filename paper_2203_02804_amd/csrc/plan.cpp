@@ -12,6 +12,8 @@
 //   1{w < 0}                   : 1/(iz)        (Im z < 0)
 //   1{w > 0}                   : -1/(iz)       (Im z > 0).
 // Put-on-max swaps the call factor's strip; call-on-min uses 1{w > 0}.
+// The single-strip call on the minimum (the paper's form) is one term with w = x and the
+// joint transform (-1)^(d+1) / ((1 + i sum_k z_k) prod_k (i z_k)), Im z_k > 0, sum Im z_k > 1.
 //
 // Grid (Sec. III.D): N midpoint nodes on [-L_k, L_k] per coordinate. Automatic choice:
 // L_k = sqrt(2 tau (C_w^{-1})_kk) -- the marginal of exp(-u^T C_w u / 2) along u_k has
@@ -47,7 +49,8 @@ static double rule_at(const TermPlan &tp, int N, double tau, const std::vector<d
     for (int k = 0; k < d; ++k) {
         L[k] = std::sqrt(2.0 * tau * prec[k]);
         const double dist = tau * (2.0 * L[k] / N) / TWO_PI;
-        alpha[k] = (tp.kind[k] == KIND_CALL && tp.sign[k] > 0) ? 1.0 + dist : tp.sign[k] * dist;
+        if (tp.kind[k] == KIND_STRIP) alpha[k] = dist + 1.0 / d;   // sum_k dist from the joint pole too
+        else alpha[k] = (tp.kind[k] == KIND_CALL && tp.sign[k] > 0) ? 1.0 + dist : tp.sign[k] * dist;
     }
     double phi = 0.0;
     for (int a = 0; a < d; ++a) {
@@ -122,7 +125,7 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
     if (!g) { err = "grid is NULL"; return TTFP_EINVAL; }
     const int d = o->d;
     if (d < 1 || d > TTFP_MAX_D) { err = "d must be in [1, 32]"; return TTFP_EINVAL; }
-    if (o->payoff < 0 || o->payoff > 2) { err = "unknown payoff"; return TTFP_EINVAL; }
+    if (o->payoff < 0 || o->payoff > 3) { err = "unknown payoff"; return TTFP_EINVAL; }
     if (!o->S0 || !o->sigma || !o->corr) { err = "S0, sigma and corr must be non-NULL"; return TTFP_EINVAL; }
     if (!(o->K > 0) || !(o->T > 0) || !finite(o->K) || !finite(o->T) || !finite(o->r)) {
         err = "K and T must be positive and finite, r finite";
@@ -160,7 +163,8 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
         for (int j = 0; j < d; ++j)
             Cx[(size_t)i * d + j] = out.T * out.sigma[i] * out.sigma[j] * out.corr[(size_t)i * d + j];
 
-    const int n_terms = d;   // d == 1 gives one term as well
+    const bool strip = o->payoff == TTFP_CALL_MIN_STRIP;
+    const int n_terms = strip ? 1 : d;   // d == 1 gives one term as well
     const int N = g->N;
     const double tau = grid_tau(g->tol > 0 ? g->tol : 1e-12);
     for (int t = 0; t < n_terms; ++t) {
@@ -168,13 +172,17 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
         tp.d = d;
         tp.N = N;
         tp.P.assign((size_t)d * d, 0.0);
-        tp.P[(size_t)0 * d + t] = 1.0;
-        int row = 1;
-        for (int l = 0; l < d; ++l) {
-            if (l == t) continue;
-            tp.P[(size_t)row * d + l] = 1.0;
-            tp.P[(size_t)row * d + t] = -1.0;
-            ++row;
+        if (strip) {
+            for (int l = 0; l < d; ++l) tp.P[(size_t)l * d + l] = 1.0;
+        } else {
+            tp.P[(size_t)0 * d + t] = 1.0;
+            int row = 1;
+            for (int l = 0; l < d; ++l) {
+                if (l == t) continue;
+                tp.P[(size_t)row * d + l] = 1.0;
+                tp.P[(size_t)row * d + t] = -1.0;
+                ++row;
+            }
         }
         tp.m.assign(d, 0.0);
         tp.C.assign((size_t)d * d, 0.0);
@@ -195,10 +203,14 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
             }
         tp.kind.assign(d, KIND_CALL);
         tp.sign.assign(d, 1);
-        tp.sign[0] = (o->payoff == TTFP_PUT_MAX) ? -1 : 1;
-        for (int k = 1; k < d; ++k) {
-            tp.kind[k] = (o->payoff == TTFP_CALL_MIN) ? KIND_GT : KIND_LT;
-            tp.sign[k] = (o->payoff == TTFP_CALL_MIN) ? 1 : -1;
+        if (strip) {
+            tp.kind.assign(d, KIND_STRIP);
+        } else {
+            tp.sign[0] = (o->payoff == TTFP_PUT_MAX) ? -1 : 1;
+            for (int k = 1; k < d; ++k) {
+                tp.kind[k] = (o->payoff == TTFP_CALL_MIN) ? KIND_GT : KIND_LT;
+                tp.sign[k] = (o->payoff == TTFP_CALL_MIN) ? 1 : -1;
+            }
         }
         // ---- grid
         bool ok = true;
@@ -237,7 +249,8 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
             } else {
                 double eta = 2.0 * L / N;
                 double dist = tau * eta / TWO_PI;
-                a = (tp.kind[k] == KIND_CALL && tp.sign[k] > 0) ? 1.0 + dist : tp.sign[k] * dist;
+                if (tp.kind[k] == KIND_STRIP) a = dist + 1.0 / d;
+                else a = (tp.kind[k] == KIND_CALL && tp.sign[k] > 0) ? 1.0 + dist : tp.sign[k] * dist;
             }
             // strip check
             bool inside;
@@ -250,6 +263,16 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
                 return TTFP_EINVAL;
             }
             tp.alpha[k] = a;
+        }
+        if (strip) {
+            double sa = 0.0;
+            for (int k = 0; k < d; ++k) sa += tp.alpha[k];
+            if (!(sa > 1.0)) {
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "contour shifts sum to %g: the single-strip transform needs more than 1", sa);
+                err = buf;
+                return TTFP_EINVAL;
+            }
         }
         double sc = out.K * std::exp(-out.r * out.T);
         for (int k = 0; k < d; ++k) sc *= (2.0 * tp.L[k] / N) / TWO_PI;
@@ -268,12 +291,15 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
         double logdet = 0.0;
         for (int k = 0; k < d; ++k) logdet += 2.0 * std::log(Lw[(size_t)k * d + k]);
         double lmass = expo + 0.5 * d * std::log(TWO_PI) - 0.5 * logdet;
+        double asum = 0.0;
         for (int k = 0; k < d; ++k) {
             const double v = tp.alpha[k];
+            asum += v;
             double h = 1.0 / std::fabs(v);                       // |1/(i z)| at z = i v
             if (tp.kind[k] == KIND_CALL) h /= std::fabs(1.0 - v);   // |1/(1 + i z)|
             lmass += std::log(h) - std::log(2.0 * tp.L[k] / N);
         }
+        if (strip) lmass -= std::log(std::fabs(1.0 - asum));      // |1/(1 + i sum z)| at z = i alpha
         double mass = std::exp(std::min(lmass, 700.0));
         tp.absmass = sc * mass;
         out.terms.push_back(std::move(tp));

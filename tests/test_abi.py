@@ -47,6 +47,25 @@ def test_plan_matches_oracle_grid_rule(seed):
                     assert np.allclose(A[t], At, rtol=1e-12)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_plan_single_strip_min_matches_oracle(d):
+    rng = np.random.Generator(np.random.PCG64(40 + d))
+    opt = W.option(d, rng.uniform(85, 115, d), 100.0, 0.9, 0.02, rng.uniform(0.15, 0.35, d),
+                   W.sigma_beta(d, 0.5) if d > 1 else [[1.0]], "call_min_strip")
+    for N in (50, 128):
+        L, A = ttfp.plan(opt, W.grid(N, tol=1e-8))
+        _, grids = F.term_grids(opt, N, tol=1e-8)
+        assert L.shape == (1, d) and len(grids) == 1
+        assert np.allclose(L[0], grids[0][0], rtol=1e-12) and np.allclose(A[0], grids[0][1], rtol=1e-12)
+        assert np.all(A > 0) and A.sum() > 1
+        # the paper's contour: +5/d on every coordinate
+        L, A = ttfp.plan(opt, W.grid(N, tol=1e-8, alpha=5.0 / d))
+        assert np.allclose(A, 5.0 / d)
+    if d > 1:
+        with pytest.raises(ttfp.TTFPError):      # sum of the shifts not above 1
+            ttfp.plan(opt, W.grid(64, alpha=0.9 / d))
+
+
 def test_plan_scalar_grid_signs():
     opt, g = W.config1()
     L, A = ttfp.plan(opt, g)

@@ -191,3 +191,47 @@ def test_tt_export_matches_tt_values_and_index_sets(pricer):
             if k + 1 < d:
                 prev = {tuple(row) for row in ex["J"][k + 1]}
                 assert all(tuple(row[1:]) in prev for row in J)
+
+
+# ---- the call on the minimum in the paper's own form: one term in asset coordinates with the
+# joint single-strip transform (Sec. III.C min transform under Eq. main)
+
+def test_min_strip_integrand_entries(pricer):
+    opt = W.option(3, [95.0, 102.0, 108.0], 100.0, 0.8, 0.02, [0.25, 0.2, 0.3], W.sigma_beta(3, 0.5),
+                   "call_min_strip")
+    N = 50
+    ts, grids = F.term_grids(opt, N, alpha=5.0 / 3)
+    Ls, As = np.array([g[0] for g in grids]), np.array([g[1] for g in grids])
+    rng = np.random.Generator(np.random.PCG64(8))
+    idx = rng.integers(0, N, size=(500, 3))
+    gpu = pricer.eval_integrand(opt, dict(W.grid(N), L=Ls, alpha=As), 0, idx)
+    ref = F.integrand_at(ts[0], N, Ls[0], As[0], idx)
+    assert np.max(np.abs(gpu - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("d,N", [(2, 64), (3, 48)])
+def test_min_strip_against_dense(pricer, d, N):
+    if d == 2:
+        opt, _ = W.config1("call_min_strip")
+    else:
+        opt = W.option(3, [95.0, 102.0, 108.0], 100.0, 0.8, 0.02, [0.25, 0.2, 0.3], W.sigma_beta(3, 0.5),
+                       "call_min_strip")
+    Ls, As = oracle_grid(opt, N)
+    g = dict(W.grid(N, tol=1e-11, max_rank=48, max_sweeps=6), L=Ls, alpha=As)
+    p, ranks, info, rc = pricer.price(opt, g)
+    ref = F.dense_price(opt, N, Ls, As)
+    print(f"min strip d={d} N={N}: rel {p / ref - 1:+.2e} status {rc} ranks {ranks.tolist()}", flush=True)
+    assert ranks.shape == (1, d + 1)
+    assert abs(p / ref - 1) < 1e-8
+
+
+def test_min_strip_one_factor_d5(pricer):
+    opt = W.config2_batch(1, seed=77, corr_kind="beta")[0]
+    opt = dict(opt, payoff="call_min_strip")
+    ref = CF.one_factor_price(opt["S0"], opt["K"], opt["T"], opt["r"], opt["sigma"], 0.5 / 1.5, "call_min")
+    p, ranks, info, rc = pricer.price(opt, W.grid(128, tol=1e-8, max_rank=48, max_sweeps=6))
+    print(f"min strip d=5 N=128: rel {p / ref - 1:+.2e} status {rc} max rank {ranks.max()} err_est {info['err_est']:.1e}",
+          flush=True)
+    assert abs(p / ref - 1) < 1e-4
+    if rc == 0:
+        assert abs(p / ref - 1) < 1e-6

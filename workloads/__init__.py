@@ -14,7 +14,8 @@ An option is a plain dict:
     r        continuously compounded risk-free rate
     sigma    volatilities, list of d floats
     corr     correlation matrix, d x d nested list (symmetric, unit diagonal, SPD)
-    payoff   "call_max" | "put_max" | "call_min"
+    payoff   "call_max" | "put_max" | "call_min" | "call_min_strip" (the call on the minimum
+             priced in the paper's own form: one term in asset coordinates)
 
 A grid setting is a dict with N (nodes per dimension), L and alpha (None means
 "let the pricer choose"), tol, max_rank, max_sweeps and seed.
@@ -28,6 +29,9 @@ from __future__ import annotations
 import numpy as np
 
 PAYOFFS = ("call_max", "put_max", "call_min")
+# the call on the minimum in the paper's own form: asset coordinates, one term, the joint
+# single-strip transform (not drawn by the random generators, whose streams stay as they were)
+ALL_PAYOFFS = PAYOFFS + ("call_min_strip",)
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -62,7 +66,7 @@ def wishart_correlation(rng: np.random.Generator, d: int, dof: int, lam_floor: f
 
 
 def option(d, S0, K, T, r, sigma, corr, payoff="call_max") -> dict:
-    if payoff not in PAYOFFS:
+    if payoff not in ALL_PAYOFFS:
         raise ValueError(payoff)
     return dict(d=int(d), S0=[float(x) for x in S0], K=float(K), T=float(T), r=float(r),
                 sigma=[float(x) for x in sigma], corr=[[float(x) for x in row] for row in corr],
