@@ -67,6 +67,75 @@ def cpu_baseline(opt, grid, budget_s=12.0):
                       f"{N}^{d} points"}
 
 
+def host_cpu():
+    """Model name and logical core count of the host (from /proc/cpuinfo)."""
+    model, n = None, 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    n += 1
+                    model = model or line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return {"model": model, "logical_cores": n or os.cpu_count()}
+
+
+def cpu_ttcross(opt, grid):
+    """The same method on the CPU: the oracle's NumPy TT-cross (plain loops around LAPACK / BLAS)
+    pricing one option of the workload completely (every term, to its own convergence), with the
+    grid, tolerance and rank cap of the GPU run. Its integrand calls go to the oracle's C code."""
+    from oracle import fourier as F
+    from oracle import ttcross as TT
+
+    N = grid["N"]
+    ts, grids = F.term_grids(opt, N, tol=grid["tol"])
+    t0 = time.perf_counter()
+    total = 0j
+    for t, (term, (L, A)) in enumerate(zip(ts, grids)):
+        fun = lambda idx, term=term, L=L, A=A: F.integrand_at(term, N, L, A, idx)
+        cores, _ = TT.tt_cross(fun, opt["d"], N, max_rank=grid["max_rank"], tol=grid["tol"],
+                               max_sweeps=grid["max_sweeps"], seed=t)
+        total += F.term_scale(opt, L, N) * TT.tt_contract(cores)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "options/s", "seconds": dt, "price": total.real,
+            "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "sample": f"one option, all {len(ts)} terms, N={N}, tol {grid['tol']}, max rank {grid['max_rank']}"}
+
+
+def book_leg(pricer, n, seed_refs):
+    """A slice of the batched book (first n options of the 8 192-option book: d ~ U{2..10}, N in
+    {64, 128, 256}, rank cap 32, tol 1e-8) priced with deltas and vegas in one batched call."""
+    import numpy as np
+
+    import workloads as W
+
+    book, Ns = W.config4()
+    opts = book[:n]
+    grids = [W.grid(N, tol=1e-8, max_rank=32, max_sweeps=6) for N in Ns[:n]]
+    # the stored oracle references of the book's first options with d <= 4 (their own grids)
+    refs = {}
+    with open(seed_refs) as f:
+        for c in json.load(f)["cases"]:
+            if c["corr"] == "wishart" and c["index"] < n:
+                refs[c["index"]] = c
+                grids[c["index"]] = dict(grids[c["index"]], L=np.array(c["L"]), alpha=np.array(c["alpha"]))
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prices, delta, vega, status = pricer.price_batch(opts, grids, greeks=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rel = {i: abs(prices[i] / c["price"] - 1) for i, c in refs.items()}
+    return {"workload": f"first {n} options of the batched book (seed 22030), rank cap 32, tol 1e-8, "
+                        f"prices with deltas and vegas",
+            "options_per_s": n / dt, "seconds": dt,
+            "status_counts": {str(k): int(np.sum(status == k)) for k in sorted(set(status.tolist()))},
+            "spot_checks_vs_dense_oracle": {"options": len(rel), "within_1e-6": int(sum(v <= 1e-6 for v in rel.values())),
+                                            "max_rel_err_converged": max([rel[i] for i in rel if status[i] == 0],
+                                                                         default=None)}}
+
+
 def surrogate_leg(pricer, n_train, tt_rate):
     """Trains the BF16 surrogate ensemble on TT prices (outside any timed region), then times
     its inference on a batch of 65 536 options and reports its gate statistics. Labels: the
@@ -90,18 +159,16 @@ def surrogate_leg(pricer, n_train, tt_rate):
     log(f"bench: surrogate labels {t_label:.1f} s, training {t_fit:.1f} s, "
         f"holdout median rel err {np.median(info['holdout_rel_err']):.2e}")
     infer = W.config5_options(65536, seed=55, corr_kind="beta")
-    X = sur._x(infer)
-    for m in range(sur.n_models):
-        sur.net.forward(m, X)
+    X, cv, scale = sur._device_inputs(infer)
+    sur.net.predict(X, cv, scale, sur.factor, 1e-4)
     torch.cuda.synchronize()
-    reps = 5
+    reps = 10
     t0 = time.perf_counter()
     for _ in range(reps):
-        for m in range(sur.n_models):
-            sur.net.forward(m, X)
+        mean, spread, _ = sur.net.predict(X, cv, scale, sur.factor, 1e-4)   # fused ensemble + gate
     torch.cuda.synchronize()
     t_inf = (time.perf_counter() - t0) / reps
-    mean, spread = sur.predict(infer)
+    mean, spread = mean.double().cpu().numpy(), spread.double().cpu().numpy()
     est = sur.factor * spread / np.abs(mean)
     rate = len(infer) / t_inf
     gates = {}
@@ -131,6 +198,28 @@ def copy_calibration(nbytes=1 << 30, reps=3):
 
 
 GOLDEN = os.path.join(ROOT, "tests", "golden", "one_factor_config2prime.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def kernels_digest():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2203_02804_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary (two rocprofv3 --pmc
+    runs, FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain copy of known size),
+    or None when there is none for this kernel or the kernel source has changed since."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = t.get("kernels", {}).get(kernel)
+    if entry is None or t.get("kernels_sha256") != kernels_digest():
+        return None
+    return entry["bytes_per_launch"]
 
 
 def load_refs(seed, n):
@@ -181,8 +270,12 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-literal", action="store_true", help="skip the literal Wishart N=128 R=32 line")
     ap.add_argument("--surrogate-train", type=int, default=4096, help="TT-priced training options")
-    ap.add_argument("--qr", choices=["cholqr", "tsqr"], default="cholqr",
-                    help="triangular factor of the fibers: shifted Cholesky QR (matrix cores) or Householder TSQR")
+    ap.add_argument("--no-book", action="store_true", help="skip the batched-book leg")
+    ap.add_argument("--book", type=int, default=1024, help="options of the batched book in its leg")
+    ap.add_argument("--no-cpu-ttcross", action="store_true", help="skip the CPU TT-cross timing")
+    ap.add_argument("--qr", choices=["cholqr", "tsqr", "cholqr2", "cholqr3"], default="cholqr",
+                    help="triangular factor of the fibers: shifted Cholesky QR on the matrix cores with passes "
+                         "chosen by the rank threshold, Householder TSQR, or two / three Cholesky QR passes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of a known size (scales the HBM byte counters of a profiler)")
     args = ap.parse_args()
@@ -215,7 +308,7 @@ def main():
     batches = [W.config2_batch(B, seed=sd, corr_kind="beta") for sd in seeds]
     refs = np.concatenate([load_refs(sd, B) for sd in seeds[args.warmup:]])
     pricer = ttfp.Pricer(0)
-    pricer.set_tuning(qr=0 if args.qr == "cholqr" else 1)
+    pricer.set_tuning(qr={"cholqr": 0, "tsqr": 1, "cholqr2": 2, "cholqr3": 3}[args.qr])
     log(f"bench: d=5 Sigma(0.5) N={args.N} R={args.max_rank} batch={B} warmup={args.warmup} steps={args.steps}")
     prices, status, elapsed, prof = time_batches(pricer, batches, grid, args.warmup, not args.no_profile)
     n_opt = B * args.steps
@@ -247,7 +340,7 @@ def main():
         roofline = {"kernel": "k_" + dom, "bound": rr["bound"] if rr else None,
                     "achieved": rr["achieved"] if rr else None, "peak": rr["peak"] if rr else None,
                     "unit": rr["unit"] if rr else None, "frac": rr["achieved"] / rr["peak"] if rr else None,
-                    "traffic": None, "avg_launch_ms": ms / max(n_l, 1), "launches": n_l,
+                    "traffic": measured_traffic("k_" + dom), "avg_launch_ms": ms / max(n_l, 1), "launches": n_l,
                     "work_per_launch": work / max(n_l, 1)}
 
     # per-option diagnostics of two options (outside the timed region)
@@ -290,10 +383,19 @@ def main():
     if not args.no_surrogate:
         surrogate = surrogate_leg(pricer, args.surrogate_train, n_opt / elapsed)
 
+    book = None
+    if not args.no_book:
+        book = book_leg(pricer, args.book, os.path.join(ROOT, "tests", "golden", "book_slice.json"))
+        log(f"bench: book slice {book['options_per_s']:.1f} options/s with Greeks, status {book['status_counts']}")
+
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(batches[args.warmup][0], grid)
+        base["host_cpu"] = host_cpu()
         log(f"bench: cpu baseline {base['value']:.3g} options/s ({base['sample']})")
+        if not args.no_cpu_ttcross:
+            base["same_method_cpu"] = cpu_ttcross(batches[args.warmup][0], grid)
+            log(f"bench: cpu TT-cross {base['same_method_cpu']['seconds']:.1f} s per option")
 
     out = {
         "metric": METRIC,
@@ -323,6 +425,7 @@ def main():
                      "sample_diagnostics": diag},
         "plain": plain,
         "literal_config2": literal,
+        "book": book,
         "surrogate": surrogate,
         "kernel_ms": breakdown,
     }

@@ -209,11 +209,18 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
  *                            smaller budgets give shorter leaf blocks and merges of fewer
  *                            factors (a leaf keeps at least two groups of nc rows and a merge
  *                            at least two factors, whatever the budget)
- *  TTFP_TUNE_GRAPH           1: capture each direction's half sweep in a hipGraph once per
- *                            batch and replay it (needs a non-null stream); 0: launch eagerly
- *  TTFP_TUNE_QR              the fiber's triangular factor: 0 (default) three passes of shifted
- *                            Cholesky QR with the Gram and transform products on the FP64 matrix
- *                            cores; 1 Householder TSQR over LDS-resident row blocks
+ *  TTFP_TUNE_GRAPH           1 (default): capture each direction's half sweep (its kernels and
+ *                            the on-device convergence test) in a hipGraph once per batch and
+ *                            replay it, when the context's stream is not the null stream and
+ *                            kernel timing is off; 0: launch eagerly. Either way the host only
+ *                            reads one flag per half sweep, one half sweep behind the device
+ *  TTFP_TUNE_QR              the fiber's triangular factor: shifted Cholesky QR with the Gram
+ *                            and transform products on the FP64 matrix cores, 0 (default) with
+ *                            two passes when every item's relative rank threshold is at least
+ *                            1e-10 and three otherwise, 2 always two passes (singular values
+ *                            resolved down to about 1e-12 of the largest, to 1e-5 relative above
+ *                            1e-10), 3 always three (down to about 1e-16; ttfp_qr_r uses three
+ *                            unless 2 is set); 1 Householder TSQR over LDS-resident row blocks
  * Returns TTFP_EINVAL for an unknown parameter or value. */
 enum { TTFP_TUNE_MAXVOL_THREADS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2, TTFP_TUNE_QR = 3 };
 int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value);
@@ -262,6 +269,19 @@ int ttfp_mlp_grad(ttfp_mlp *m, int model, int batch, const float *x_dev, const f
 /* one Adam step (beta 0.9 / 0.999) on the mean squared error; loss (host, nullable) before the step */
 int ttfp_mlp_train_step(ttfp_mlp *m, int model, int batch, const float *x_dev, const float *t_dev,
                         float lr, float *loss);
+/* Ensemble inference in one fused kernel (all layers of every model, activations in LDS) with
+ * the gate on the device: for row b, price_m = cv_dev[b] + scale_dev[b] * y_m(x_b); mean_dev[b]
+ * and spread_dev[b] receive the ensemble mean and standard deviation (ddof 1) of price_m, and
+ * ok_dev[b] = (factor * spread <= gate * |mean|). All arrays are device arrays of `batch`
+ * entries (x_dev: batch x n_in, FP32). Needs width <= 256, a multiple of 32. Asynchronous on the
+ * model's stream; batch is not limited by max_batch. */
+int ttfp_mlp_predict(ttfp_mlp *m, int batch, const float *x_dev, const float *cv_dev, const float *scale_dev,
+                     float factor, float gate, float *mean_dev, float *spread_dev, int32_t *ok_dev);
+/* The surrogate's control variate for the call on the maximum, max_j of the single-asset
+ * Black-Scholes calls (Sec. II, Eq. BSexact), on the device: S0_dev, sigma_dev batch x d
+ * row-major, K_dev, T_dev, r_dev [batch]; cv_dev [batch] receives it. */
+int ttfp_mlp_control_variate(ttfp_mlp *m, int batch, int d, const float *S0_dev, const float *sigma_dev,
+                             const float *K_dev, const float *T_dev, const float *r_dev, float *cv_dev);
 const char *ttfp_mlp_last_error(const ttfp_mlp *m);
 
 const char *ttfp_strerror(int code);

@@ -9,7 +9,7 @@ unbumped parameters and reused, so the derivative is that of the fixed-grid
 quadrature (the quantity the GPU adjoint differentiates).
 
 Parity: at d = 1 these reduce to the Black-Scholes delta N(d1) and vega
-S0 phi(d1) sqrt(T) (Sec. II, Eq. BSexact), checked in tests/test_oracle_greeks.py.
+S0 phi(d1) sqrt(T) (Sec. II, Eq. BSexact), checked in tests/test_oracle_ttcross.py.
 """
 from __future__ import annotations
 

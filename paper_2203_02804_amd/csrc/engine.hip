@@ -22,7 +22,7 @@ __global__ void k_eval_points(const Item *items, long long npts, const int *idx,
 __global__ void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G);
 __global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G);
 __global__ void k_gram(Item *items, const int *active, int t, int dir, int pass);
-__global__ void k_chol(Item *items, const int *active, int t, int dir, int pass);
+__global__ void k_chol(Item *items, const int *active, int t, int dir, int pass, int last);
 __global__ void k_xform(Item *items, const int *active, int t, int dir, int pass);
 __global__ void k_basis(Item *items, const int *active, int t, int dir);
 __global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax);
@@ -35,6 +35,7 @@ __global__ void k_core_moments(Item *items, const int *active);
 __global__ void k_moments(Item *items, const int *active, cplx *out, int stride);
 __global__ void k_tt_values(const Item *items, int item, long long npts, const int *idx, cplx *out);
 __global__ void k_err_est(Item *items, const int *active);
+__global__ void k_converge(const Item *items, int *active, OptState *os, int n_opts, const double *item_scale, int *flags);
 }  // namespace ttfp
 
 using namespace ttfp;
@@ -60,8 +61,11 @@ struct ttfp_ctx {
     int tune_maxvol_threads = 0;          // 0: chosen per launch from the number of items
     int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
-    int tune_graph = 0;
-    int tune_qr = 0;                      // 0: shifted Cholesky QR on the matrix cores; 1: Householder TSQR
+    int tune_graph = 1;                   // graph replay whenever the stream is not the null stream
+    int tune_qr = 0;                      // 0: Cholesky QR, passes by the rank threshold; 2 / 3: two / three passes; 1: TSQR
+    // the half-sweep flags of the device-side convergence test, read one half sweep behind
+    int *h_flags = nullptr;               // pinned host memory, MAX_HALF + 1 ints
+    hipEvent_t ev_flag[2] = {nullptr, nullptr};
     // allocation-free mode (ttfp_price_batch_noalloc): this device's static scratch array
     char *scratch = nullptr;
     bool noalloc = false;
@@ -92,6 +96,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Launch {
     int BR, G, nlev, maxd, maxrows, maxnc, maxR, maxN;
+    double min_rank_eps;       // smallest relative rank threshold of the batch's items
 };
 
 // TSQR geometry: leaf blocks of BR = Gl nc rows of the fiber, padded row-major (odd stride
@@ -245,6 +250,10 @@ struct Batch {
     std::vector<double> item_scale, item_mass;
     std::vector<const TermPlan *> item_term;
     Launch geo;
+    // device-side convergence state: per option, per item scale, half-sweep flags (+ counter)
+    OptState *d_os = nullptr;
+    double *d_scale = nullptr;
+    int *d_flags = nullptr;
 };
 
 int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, const std::vector<const ttfp_grid *> &grids,
@@ -262,7 +271,13 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
     }
     int BR, G;
     tsqr_geometry(maxnc, BR, G, ctx->tune_tsqr_lds_kb);
-    b.geo = {BR, G, tsqr_levels(maxrows, BR, G), maxd, maxrows, maxnc, maxR, maxN};
+    double min_eps = 1.0;
+    for (size_t o = 0; o < plans.size(); ++o) {
+        const ttfp_grid *g = grids[o];
+        const double eps = g->rank_tol > 0 ? g->rank_tol : 0.1 * g->tol / std::sqrt((double)std::max(plans[o]->d - 1, 1));
+        min_eps = std::min(min_eps, eps);
+    }
+    b.geo = {BR, G, tsqr_levels(maxrows, BR, G), maxd, maxrows, maxnc, maxR, maxN, min_eps};
     // layout
     std::vector<ItemSizes> sz;
     size_t total = 0;
@@ -276,8 +291,13 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
         }
     }
     const size_t n_items = sz.size();
-    int rc = ensure_arena(ctx, total, n_items, n_items * (size_t)(maxd + maxd * maxd));
+    const size_t o_os = total, o_scale = align_up(o_os + plans.size() * sizeof(OptState)),
+                 o_flags = align_up(o_scale + n_items * sizeof(double)), aux_end = align_up(o_flags + (MAX_HALF + 1) * sizeof(int));
+    int rc = ensure_arena(ctx, aux_end, n_items, n_items * (size_t)(maxd + maxd * maxd));
     if (rc) return rc;
+    b.d_os = (OptState *)(ctx->arena + o_os);
+    b.d_scale = (double *)(ctx->arena + o_scale);
+    b.d_flags = (int *)(ctx->arena + o_flags);
     // fill items and upload the static term data
     std::vector<char> host(0);
     size_t base = 0, idx = 0;
@@ -353,6 +373,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
         }
     }
     HIPCHK(hipMemcpyAsync(ctx->d_items, b.items.data(), n_items * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(b.d_scale, b.item_scale.data(), n_items * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     return TTFP_OK;
 }
 
@@ -431,11 +452,23 @@ int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
 // costs one early-exit launch.
 constexpr int MAXVOL_REFINE_ROUNDS = 3;
 
-// The fiber's triangular factor by three passes of shifted Cholesky QR (k_gram, k_chol, k_xform).
-void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int maxrows, unsigned ny, int t, int dir)
+// Passes of shifted Cholesky QR for a relative rank threshold eps. Each pass resolves the
+// singular values above about the square root of its shift (~1e-6 of the largest), relative to
+// what the earlier passes left: two passes resolve down to ~1e-12 (with relative errors of 1e-2
+// near that floor and below 1e-5 above 1e-10), three down to ~1e-16 (R^H R = F^H F to about the
+// shift). TTFP_TUNE_QR 0 takes two passes when every threshold is at least 1e-10, else three.
+int cholqr_passes(const ttfp_ctx *ctx, double eps)
+{
+    if (ctx->tune_qr == 2) return 2;
+    if (ctx->tune_qr == 3) return 3;
+    return eps >= 1e-10 ? 2 : 3;
+}
+
+// The fiber's triangular factor by passes of shifted Cholesky QR (k_gram, k_chol, k_xform).
+void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int maxrows, unsigned ny, int t, int dir, int npass)
 {
     const unsigned gb = cdivu(maxrows, GRAM_ROWS_HOST), gx = cdivu(maxrows, 16 * XF_WAVES_HOST);
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < npass; ++pass) {
         if (pass > 0) {
             ProfScope ps(ctx, TTFP_KERNEL_XFORM);
             hipLaunchKernelGGL(k_xform, dim3(gx, ny), dim3(64 * XF_WAVES_HOST), 0, st, it, act, t, dir, pass);
@@ -445,7 +478,7 @@ void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int 
             hipLaunchKernelGGL(k_gram, dim3(gb, ny), dim3(512), 0, st, it, act, t, dir, pass);
         }
         ProfScope ps(ctx, TTFP_KERNEL_CHOL);
-        hipLaunchKernelGGL(k_chol, dim3(ny), dim3(256), 0, st, it, act, t, dir, pass);
+        hipLaunchKernelGGL(k_chol, dim3(ny), dim3(256), 0, st, it, act, t, dir, pass, pass == npass - 1 ? 1 : 0);
     }
 }
 
@@ -459,8 +492,8 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
         ProfScope ps(ctx, TTFP_KERNEL_FIBER);
         hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.maxR * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
     }
-    if (ctx->tune_qr == 0) {
-        launch_cholqr(ctx, st, it, act, g.maxrows, ny, t, dir);
+    if (ctx->tune_qr != 1) {
+        launch_cholqr(ctx, st, it, act, g.maxrows, ny, t, dir, cholqr_passes(ctx, g.min_rank_eps));
     } else {
         ProfScope ps(ctx, TTFP_KERNEL_TSQR);
         int n = (g.maxrows + g.BR - 1) / g.BR;
@@ -472,7 +505,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_QRCP);
-        hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(QRCP_THREADS), 0, st, it, act, t, dir, ctx->tune_qr == 0 ? 0 : g.BR, g.G);
+        hipLaunchKernelGGL(k_qrcp, dim3(ny), dim3(QRCP_THREADS), 0, st, it, act, t, dir, ctx->tune_qr != 1 ? 0 : g.BR, g.G);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_BASIS);
@@ -570,20 +603,46 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
     HIPCHK(hipGetLastError());
     int max_sweeps = 1;
     for (auto *g : grids) max_sweeps = std::max(max_sweeps, g->max_sweeps);
-    std::vector<double> prev(n_opts, NAN);
-    std::vector<int> opt_active(n_opts, 1);
+    const int max_half = std::min(2 * max_sweeps, MAX_HALF);
+    // the options' convergence state and the half-sweep flags, on the device
+    {
+        std::vector<OptState> os(n_opts);
+        int first = 0;
+        for (int o = 0; o < n_opts; ++o) {
+            OptState &st = os[o];
+            std::memset(&st, 0, sizeof st);
+            st.first = first;
+            while (first < n_items && b.item_opt[first] == o) ++first;
+            st.count = first - st.first;
+            st.max_half = 2 * grids[o]->max_sweeps;
+            st.active = 1;
+            st.tol = grids[o]->tol;
+            st.prev = NAN;
+            st.change = INFINITY;
+        }
+        std::vector<int> flags(MAX_HALF + 1, 0);
+        HIPCHK(hipMemcpyAsync(b.d_os, os.data(), n_opts * sizeof(OptState), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(b.d_flags, flags.data(), flags.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));    // the staging vectors go out of scope
+    }
     std::vector<Item> host_items(n_items);
-    // one half sweep: the steps of every core, then the edge core and the contraction
+    // one half sweep: the steps of every core, the edge core and the contraction, then the
+    // convergence test that switches off the items of finished options
     auto launch_half = [&](int dir, int sweep) -> int {
         for (int t = 0; t + 1 < b.geo.maxd; ++t) {
             int rc = launch_step(ctx, b.geo, n_items, t, dir, sweep);
             if (rc) return rc;
         }
-        return launch_edge(ctx, b.geo, n_items, dir, sweep);
+        int rc = launch_edge(ctx, b.geo, n_items, dir, sweep);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, ctx->stream, ctx->d_items, ctx->d_active, b.d_os, n_opts, b.d_scale,
+                           b.d_flags);
+        HIPCHK(hipGetLastError());
+        return TTFP_OK;
     };
     // Graph mode: each direction's half sweep is captured once and replayed; the kernels read
-    // their shapes, ranks, activity and random-draw counter from device memory, so one graph
-    // serves every sweep. Capture needs a stream other than the null stream.
+    // their shapes, ranks, activity and counters from device memory, so one graph serves every
+    // sweep. Capture needs a stream other than the null stream.
     struct Graphs {
         hipGraph_t g[2] = {nullptr, nullptr};
         hipGraphExec_t x[2] = {nullptr, nullptr};
@@ -595,93 +654,49 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
             }
         }
     } graphs;
-    const bool use_graph = ctx->tune_graph && ctx->stream != nullptr && !ctx->noalloc;
-    int half = 0;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        for (int dir = 0; dir < 2; ++dir, ++half) {
-            if (use_graph) {
-                if (!graphs.x[dir]) {
-                    const bool prof_saved = ctx->prof;
-                    ctx->prof = false;                   // no event records inside a capture
-                    HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-                    int rc = launch_half(dir, sweep);
-                    hipGraph_t gr = nullptr;
-                    hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
-                    ctx->prof = prof_saved;
-                    if (rc) return rc;
-                    HIPCHK(e);
-                    graphs.g[dir] = gr;
-                    HIPCHK(hipGraphInstantiate(&graphs.x[dir], gr, nullptr, nullptr, 0));
-                }
-                HIPCHK(hipGraphLaunch(graphs.x[dir], ctx->stream));
-            } else {
+    const bool use_graph = ctx->tune_graph && ctx->stream != nullptr && !ctx->noalloc && !ctx->prof;
+    // Half sweeps are queued back to back; after queueing half h the host waits for the flag
+    // of half h - 1 (copied into pinned memory behind it), so one half sweep stays queued while
+    // the host decides, and the run ends when no option was active after a half sweep.
+    for (int h = 0; h < max_half; ++h) {
+        const int dir = h & 1, sweep = h >> 1;
+        if (use_graph) {
+            if (!graphs.x[dir]) {
+                HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
                 int rc = launch_half(dir, sweep);
+                hipGraph_t gr = nullptr;
+                hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
                 if (rc) return rc;
+                HIPCHK(e);
+                graphs.g[dir] = gr;
+                HIPCHK(hipGraphInstantiate(&graphs.x[dir], gr, nullptr, nullptr, 0));
             }
-            HIPCHK(hipMemcpyAsync(host_items.data(), ctx->d_items, n_items * sizeof(Item), hipMemcpyDeviceToHost, ctx->stream));
-            HIPCHK(hipStreamSynchronize(ctx->stream));
-            if (ctx->prof) prof_collect(ctx);
-            std::vector<double> pr(n_opts, 0.0), pi(n_opts, 0.0);
-            std::vector<long long> ev(n_opts, 0), sw(n_opts, 0), fs(n_opts, 0);
-            std::vector<int> cap(n_opts, 0), sing(n_opts, 0);
-            for (int i = 0; i < n_items; ++i) {
-                const int o = b.item_opt[i];
-                pr[o] += b.item_scale[i] * host_items[i].P.x;
-                pi[o] += b.item_scale[i] * host_items[i].P.y;
-                ev[o] += host_items[i].n_evals;
-                sw[o] += host_items[i].mv_iters;
-                fs[o] += host_items[i].mv_full;
-                sing[o] |= host_items[i].mv_singular;
-                cap[o] |= host_items[i].capped;
-            }
-            bool any = false;
-            for (int o = 0; o < n_opts; ++o) {
-                if (!opt_active[o]) continue;
-                OptResult &r = res[o];
-                r.price = pr[o];
-                r.imag = pi[o];
-                r.evals = ev[o];
-                r.swaps = sw[o];
-                r.full_starts = fs[o];
-                r.singular = sing[o];
-                r.capped = cap[o];
-                r.sweeps = half + 1;
-                if (!std::isnan(prev[o])) r.change = std::fabs(pr[o] - prev[o]) / std::max(std::fabs(pr[o]), 1e-300);
-                prev[o] = pr[o];
-                if (half < 64) r.hist[half] = r.change;
-                const bool last = (sweep == grids[o]->max_sweeps - 1 && dir == 1);
-                // a rank-capped cross whose change no longer halves over a full sweep has stagnated
-                const bool stalled = r.capped && half >= 3 && half < 64 && r.change > 0.5 * r.hist[half - 2];
-                if (half >= 1 && r.change <= grids[o]->tol) {
-                    r.converged = 1;
-                    opt_active[o] = 0;
-                } else if (last || stalled) {
-                    opt_active[o] = 0;
-                } else {
-                    any = true;
-                }
-            }
-            bool changed = false;
-            for (int i = 0; i < n_items; ++i) {
-                int a = opt_active[b.item_opt[i]];
-                if (a != active[i]) { active[i] = a; changed = true; }
-            }
-            if (changed)
-                HIPCHK(hipMemcpyAsync(ctx->d_active, active.data(), n_items * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-            if (!any) goto done;
+            HIPCHK(hipGraphLaunch(graphs.x[dir], ctx->stream));
+        } else {
+            int rc = launch_half(dir, sweep);
+            if (rc) return rc;
+        }
+        HIPCHK(hipMemcpyAsync(ctx->h_flags + h, b.d_flags + h, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipEventRecord(ctx->ev_flag[h & 1], ctx->stream));
+        if (h >= 1) {
+            HIPCHK(hipEventSynchronize(ctx->ev_flag[(h - 1) & 1]));
+            if (!ctx->h_flags[h - 1]) break;
         }
     }
-done:
     {
-        std::vector<double> mass(n_opts, 0.0);
-        for (int i = 0; i < n_items; ++i) mass[b.item_opt[i]] += b.item_mass[i];
+        std::vector<OptState> os(n_opts);
+        HIPCHK(hipMemcpyAsync(os.data(), b.d_os, n_opts * sizeof(OptState), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
         for (int o = 0; o < n_opts; ++o) {
             OptResult &r = res[o];
-            r.kappa = mass[o] / std::max(std::fabs(r.price), 1e-300);
-            r.code = (r.converged && !r.capped) ? TTFP_OK : TTFP_ENOTCONV;
-            // cancellation beyond the tolerance makes the price meaningless, converged or not
-            if (r.kappa * 2.220446049250313e-16 > grids[o]->tol) r.code = TTFP_EPRECISION;
-            if (r.singular || !std::isfinite(r.price)) r.code = TTFP_EPRECISION;
+            const OptState &st = os[o];
+            r.price = st.price;
+            r.imag = st.imag;
+            r.change = st.change;
+            r.converged = st.converged;
+            r.capped = st.capped;
+            r.sweeps = st.half;
+            for (int q = 0; q < std::min(st.half, 64); ++q) r.hist[q] = st.hist[q];
         }
     }
     // every item takes part in the sampled error estimate and the Greeks
@@ -714,6 +729,26 @@ done:
     HIPCHK(hipMemcpyAsync(host_items.data(), ctx->d_items, n_items * sizeof(Item), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->prof) prof_collect(ctx);
+    {
+        // per-option diagnostics from the items, cancellation factor and return code
+        std::vector<double> mass(n_opts, 0.0);
+        for (int i = 0; i < n_items; ++i) {
+            const int o = b.item_opt[i];
+            mass[o] += b.item_mass[i];
+            res[o].evals += host_items[i].n_evals;
+            res[o].swaps += host_items[i].mv_iters;
+            res[o].full_starts += host_items[i].mv_full;
+            res[o].singular |= host_items[i].mv_singular;
+        }
+        for (int o = 0; o < n_opts; ++o) {
+            OptResult &r = res[o];
+            r.kappa = mass[o] / std::max(std::fabs(r.price), 1e-300);
+            r.code = (r.converged && !r.capped) ? TTFP_OK : TTFP_ENOTCONV;
+            // cancellation beyond the tolerance makes the price meaningless, converged or not
+            if (r.kappa * 2.220446049250313e-16 > grids[o]->tol) r.code = TTFP_EPRECISION;
+            if (r.singular || !std::isfinite(r.price)) r.code = TTFP_EPRECISION;
+        }
+    }
     {
         // Sec. IV.B convergence measure over the option's terms, each term's sums weighted by its
         // (positive) quadrature scale
@@ -808,6 +843,16 @@ int ttfp_create(ttfp_ctx **out, int device, void *hip_stream)
     c->stream = (hipStream_t)hip_stream;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) c->n_cu = cus;
+    if (hipHostMalloc((void **)&c->h_flags, (MAX_HALF + 1) * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_flag[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_flag[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->h_flags) (void)hipHostFree(c->h_flags);
+        for (auto e : c->ev_flag)
+            if (e) (void)hipEventDestroy(e);
+        delete c;
+        return TTFP_EDEVICE;
+    }
     // the allocation-free entry point's scratch array on this device (its address is looked up
     // once per device; a failure only disables that entry point)
     std::string err;
@@ -834,7 +879,7 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
         ctx->tune_graph = value;
         return TTFP_OK;
     case TTFP_TUNE_QR:
-        if (value != 0 && value != 1) break;
+        if (value < 0 || value > 3) break;
         ctx->tune_qr = value;
         return TTFP_OK;
     default:
@@ -887,6 +932,9 @@ int ttfp_destroy(ttfp_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (!ctx->ev_open.empty()) { (void)hipStreamSynchronize(ctx->stream); prof_collect(ctx); }
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto e : ctx->ev_flag)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->d_items) (void)hipFree(ctx->d_items);
     if (ctx->d_active) (void)hipFree(ctx->d_active);
@@ -1287,9 +1335,9 @@ int ttfp_qr_r(ttfp_ctx *ctx, int32_t m, int32_t n, const double *A, double *R)
     e = e ? e : hipMemcpy(dit, &it, sizeof(Item), hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(it.F, A, 16 * (size_t)m * n, hipMemcpyHostToDevice);
     const cplx *rsrc = it.Rf;
-    if (ctx->tune_qr == 0) {
+    if (ctx->tune_qr != 1) {
         if (!e) {
-            launch_cholqr(ctx, ctx->stream, dit, act, m, 1, 0, 2);
+            launch_cholqr(ctx, ctx->stream, dit, act, m, 1, 0, 2, ctx->tune_qr == 2 ? 2 : 3);
             e = hipGetLastError();
         }
     } else {

@@ -79,6 +79,19 @@ struct Item {
     double err_abs, err_ref;          // sampled error: sum |TT - A| and sum |A| over n_samp points
 };
 
+// Convergence state of one option, kept on the device so that the host does not read the items
+// between half sweeps (k_converge updates it after every half sweep).
+constexpr int MAX_HALF = 128;                 // half sweeps (max_sweeps <= 64)
+struct OptState {
+    int first, count;                 // the option's items (contiguous)
+    int max_half;                     // 2 max_sweeps
+    int active, converged, capped, half;
+    double tol;
+    double prev;                      // price after the previous half sweep (NaN before the first)
+    double price, imag, change;       // latest contraction and relative change
+    double hist[64];                  // relative change after each half sweep
+};
+
 // Step addressing: dir 0 = left-to-right (core k = t), dir 1 = right-to-left (core k = d-1-t).
 __host__ __device__ inline int step_core(const Item &it, int t, int dir) { return dir == 0 ? t : it.d - 1 - t; }
 

@@ -889,7 +889,8 @@ __global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *a
 // factorization of ill-conditioned matrices", 2020):
 //   pass 0: G = (sF)^H (sF) with s = 2^-e (e from the largest entry), R0 = chol(G + shift I)
 //   pass 1: Q = sF R0^{-1},  R1 = chol(Q^H Q + shift I)
-//   pass 2: Q <- Q R1^{-1},  R2 = chol(Q^H Q + shift I);   R = R2 R1 R0 / s.
+//   pass 2: Q <- Q R1^{-1},  R2 = chol(Q^H Q + shift I);   R = R2 R1 R0 / s
+// (or two passes, R = R1 R0 / s, a tuning choice).
 // A pass resolves the singular values that stand above the square root of its shift; the next
 // pass sees them relative to what is left, so three passes resolve the spectrum well below the
 // rank threshold while R^H R = F^H F holds to about the shift (10 nc u relative, with the Gram
@@ -1066,7 +1067,7 @@ __device__ __forceinline__ int up_row(int e, int n)
 // row-major with zeros below the diagonal) and the running factor it.Rf: R in pass 0, R Rf after.
 // The last pass leaves Rf / s = the triangular factor of F (nc x nc, row-major), which the
 // column-pivoted QR reads.
-__global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, int t, int dir, int pass)
+__global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, int t, int dir, int pass, int last)
 {
     __shared__ cplx Rp[MAXNC * (MAXNC + 1) / 2];   // G, then its Cholesky factor (packed upper)
     __shared__ cplx Xp[MAXNC * (MAXNC + 1) / 2];   // R^{-1}, then the factor product (packed upper)
@@ -1163,14 +1164,14 @@ __global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, in
         }
     }
     __syncthreads();
-    if (pass < 2)
+    if (!last)
         for (int e = threadIdx.x; e < nc * nc; e += nthr) {
             const int i = e / nc, j = e % nc;
             it.Xf[e] = j >= i ? Xp[up_off(i, nc) + j - i] : cplx{0.0, 0.0};
         }
     // running factor: Rf <- R (pass 0) or R Rf (the previous Rf staged in Xp, packed); the last
     // pass also undoes the scaling
-    const double unscale = pass == 2 ? ldexp(1.0, it.gram_e == GRAM_NOSCALE ? 0 : it.gram_e) : 1.0;
+    const double unscale = last ? ldexp(1.0, it.gram_e == GRAM_NOSCALE ? 0 : it.gram_e) : 1.0;
     constexpr int PER = (MAXNC * (MAXNC + 1) / 2 + 255) / 256;
     cplx res[PER];
     if (pass > 0) {
@@ -2138,6 +2139,63 @@ __global__ __launch_bounds__(64) void k_contract(Item *items, const int *active)
     if (threadIdx.x == 0) {
         it.P = v[0];
         it.half += 1;
+    }
+}
+
+// ------------------------------------------------------------------ convergence test on the device
+// After a half sweep: each option's price is the scaled sum of its items' contractions; its
+// relative change against the previous half sweep decides whether it stays active (the rule
+// of the sweep driver: converged when the change is at most tol after the first half sweep;
+// stopped at its last half sweep, or when a rank-capped cross's change no longer halves over a
+// full sweep). The items of stopped options are switched off for the kernels that follow.
+// flags[c] (c = the launch's half-sweep counter, flags[MAX_HALF]) is set when an option is
+// still active, and the host reads it one half sweep later.
+__global__ __launch_bounds__(256) void k_converge(const Item *items, int *active, OptState *os, int n_opts,
+                                                  const double *item_scale, int *flags)
+{
+    __shared__ int any;
+    const int c = flags[MAX_HALF];
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int o = threadIdx.x; o < n_opts; o += blockDim.x) {
+        OptState &st = os[o];
+        if (!st.active) continue;
+        double pr = 0.0, pi = 0.0;
+        int cap = 0;
+        for (int i = st.first; i < st.first + st.count; ++i) {
+            pr += item_scale[i] * items[i].P.x;
+            pi += item_scale[i] * items[i].P.y;
+            cap |= items[i].capped;
+        }
+        const int h = st.half;
+        double change = INFINITY;
+        if (h > 0) change = fabs(pr - st.prev) / fmax(fabs(pr), 1e-300);
+        if (h < 64) st.hist[h] = change;
+        const bool last = h == st.max_half - 1;
+        const bool stalled = cap && h >= 3 && h < 64 && change > 0.5 * st.hist[h - 2];
+        int act = 1;
+        if (h >= 1 && change <= st.tol) {
+            st.converged = 1;
+            act = 0;
+        } else if (last || stalled) {
+            act = 0;
+        }
+        st.prev = pr;
+        st.price = pr;
+        st.imag = pi;
+        st.change = change;
+        st.capped = cap;
+        st.half = h + 1;
+        st.active = act;
+        if (!act)
+            for (int i = st.first; i < st.first + st.count; ++i) active[i] = 0;
+        else
+            any = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (c < MAX_HALF) flags[c] = any;
+        flags[MAX_HALF] = c + 1;
     }
 }
 

@@ -231,6 +231,119 @@ __global__ void k_cast_weights(int out, int in, int kin, const float *w, bf16 *b
     bt[(size_t)k * out + o] = v;           // kin x out
 }
 
+// ------------------------------------------------------------------ fused ensemble inference
+// All layers of every model of the ensemble for 64 rows of the batch in one workgroup: the
+// activations stay in LDS (bf16, ping-pong), wave w computes output columns [64 w, 64 w + 64)
+// of a layer as 4 x 4 MFMA 16x16x32 tiles (its slice of W streamed from L2 once per workgroup),
+// the head is a per-row dot product, and the models' prices (control variate + scale * y) give
+// the ensemble mean, spread (standard deviation) and the gate factor * spread <= gate * |mean|.
+constexpr int ENS_ROWS = 64;
+constexpr int ENS_MAXW = 256;
+struct EnsembleDesc {
+    int n_in, kin, width, depth, n_models;
+    const bf16 *bw[16];                 // per model: bf16 weights (layers one after another)
+    const float *p[16];                 // per model: FP32 parameters (biases, head bias)
+    long long bw_off[17], b_off[17];    // per layer
+};
+__global__ __launch_bounds__(256) void k_mlp_ensemble(EnsembleDesc D, int Bn, const float *x, const float *cv, const float *scale,
+                                                      float factor, float gate, float *mean, float *spread, int *ok)
+{
+    __shared__ bf16 act[2][ENS_ROWS][ENS_MAXW + 8];
+    __shared__ float ys[16][ENS_ROWS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r16 = lane & 15, kb = lane >> 4;
+    const int row0 = blockIdx.x * ENS_ROWS;
+    const int W = D.width;
+    for (int m = 0; m < D.n_models; ++m) {
+        // input rows, bf16, zero padded to kin features
+        for (int e = tid; e < ENS_ROWS * D.kin; e += 256) {
+            const int r = e / D.kin, k = e % D.kin;
+            const int b = row0 + r;
+            act[0][r][k] = (bf16)((b < Bn && k < D.n_in) ? x[(size_t)b * D.n_in + k] : 0.0f);
+        }
+        __syncthreads();
+        int cur = 0;
+        for (int l = 0; l < D.depth; ++l) {
+            const int K = l == 0 ? D.kin : W;
+            const bf16 *Wl = D.bw[m] + D.bw_off[l];                 // W x K row-major
+            const float *bl = D.p[m] + D.b_off[l];
+            f32x4 acc[4][4];
+            for (int a = 0; a < 4; ++a)
+                for (int c = 0; c < 4; ++c) acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const int c0 = wave * 64;
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                const int kk = k0 + kb * 8;
+                bf16x8 fa[4], fb[4];
+                for (int a = 0; a < 4; ++a) fa[a] = *reinterpret_cast<const bf16x8 *>(&act[cur][16 * a + r16][kk]);
+                for (int c = 0; c < 4; ++c) {
+                    const int col = c0 + 16 * c + r16;
+                    if (col < W) fb[c] = *reinterpret_cast<const bf16x8 *>(Wl + (size_t)col * K + kk);
+                    else
+                        for (int j = 0; j < 8; ++j) fb[c][j] = (bf16)0.0f;
+                }
+                for (int a = 0; a < 4; ++a)
+                    for (int c = 0; c < 4; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[c], acc[a][c], 0, 0, 0);
+            }
+            for (int a = 0; a < 4; ++a)
+                for (int c = 0; c < 4; ++c)
+                    for (int j = 0; j < 4; ++j) {
+                        const int r = 16 * a + 4 * kb + j, col = c0 + 16 * c + r16;
+                        if (col < W) act[cur ^ 1][r][col] = (bf16)silu(acc[a][c][j] + bl[col]);
+                    }
+            __syncthreads();
+            cur ^= 1;
+        }
+        // head: y = A . w_h + b_h, four threads per row
+        {
+            const bf16 *wh = D.bw[m] + D.bw_off[D.depth];
+            const float bh = D.p[m][D.b_off[D.depth]];
+            const int r = tid >> 2, part = tid & 3;
+            float sacc = 0.f;
+            for (int k = part; k < W; k += 4) sacc += (float)act[cur][r][k] * (float)wh[k];
+            sacc += __shfl_xor(sacc, 1, 64);
+            sacc += __shfl_xor(sacc, 2, 64);
+            if (part == 0) ys[m][r] = sacc + bh;
+        }
+        __syncthreads();
+    }
+    // ensemble statistics and the gate
+    if (tid < ENS_ROWS) {
+        const int b = row0 + tid;
+        if (b < Bn) {
+            const float c = cv[b], sc = scale[b];
+            float mu = 0.f;
+            for (int m = 0; m < D.n_models; ++m) mu += c + sc * ys[m][tid];
+            mu /= (float)D.n_models;
+            float var = 0.f;
+            for (int m = 0; m < D.n_models; ++m) {
+                const float dv = c + sc * ys[m][tid] - mu;
+                var += dv * dv;
+            }
+            const float sd = D.n_models > 1 ? sqrtf(var / (float)(D.n_models - 1)) : 0.f;
+            mean[b] = mu;
+            spread[b] = sd;
+            ok[b] = factor * sd <= gate * fabsf(mu) ? 1 : 0;
+        }
+    }
+}
+
+// Control variate of the call on the maximum: max_j of the single-asset Black-Scholes calls
+// (a lower bound of the price). One thread per option; S0 and sigma are B x d row-major.
+__global__ void k_bs_max_call(int Bn, int d, const float *S0, const float *sigma, const float *K, const float *T,
+                              const float *r, float *out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Bn) return;
+    const double k = K[b], t = T[b], rr = r[b], disc = exp(-rr * t);
+    double best = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double s = S0[(size_t)b * d + j], v = sigma[(size_t)b * d + j] * sqrt(t);
+        const double d1 = (log(s / k) + (rr + 0.5 * sigma[(size_t)b * d + j] * sigma[(size_t)b * d + j]) * t) / v;
+        const double c = s * 0.5 * erfc(-d1 * 0.7071067811865476) - k * disc * 0.5 * erfc(-(d1 - v) * 0.7071067811865476);
+        best = fmax(best, c);
+    }
+    out[b] = (float)best;
+}
+
 }  // namespace
 
 // =================================================================================== host
@@ -563,6 +676,48 @@ int ttfp_mlp_train_step(ttfp_mlp *m, int model, int batch, const float *x_dev, c
         MCHK(hipStreamSynchronize(m->stream));
         *loss = l / batch;
     }
+    return TTFP_OK;
+}
+
+int ttfp_mlp_predict(ttfp_mlp *m, int batch, const float *x_dev, const float *cv_dev, const float *scale_dev, float factor,
+                     float gate, float *mean_dev, float *spread_dev, int32_t *ok_dev)
+{
+    if (!m || !x_dev || !cv_dev || !scale_dev || !mean_dev || !spread_dev || !ok_dev) return TTFP_EINVAL;
+    if (batch < 1) { m->err = "batch out of range"; return TTFP_EINVAL; }
+    if (m->width > ENS_MAXW || m->kin > ENS_MAXW || (m->width % 32)) {
+        m->err = "the fused ensemble kernel needs width <= 256, a multiple of 32";
+        return TTFP_EINVAL;
+    }
+    MCHK(hipSetDevice(m->device));
+    EnsembleDesc D;
+    std::memset(&D, 0, sizeof D);
+    D.n_in = m->n_in;
+    D.kin = m->kin;
+    D.width = m->width;
+    D.depth = m->depth;
+    D.n_models = m->n_models;
+    for (int md = 0; md < m->n_models; ++md) {
+        D.bw[md] = m->BW[md];
+        D.p[md] = m->P[md];
+    }
+    for (int l = 0; l <= m->depth; ++l) {
+        D.bw_off[l] = (long long)m->layers[l].bw_off;
+        D.b_off[l] = (long long)m->layers[l].b_off;
+    }
+    hipLaunchKernelGGL(k_mlp_ensemble, dim3(cdivu(batch, ENS_ROWS)), dim3(256), 0, m->stream, D, batch, x_dev, cv_dev, scale_dev,
+                       factor, gate, mean_dev, spread_dev, (int *)ok_dev);
+    MCHK(hipGetLastError());
+    return TTFP_OK;
+}
+
+int ttfp_mlp_control_variate(ttfp_mlp *m, int batch, int d, const float *S0_dev, const float *sigma_dev, const float *K_dev,
+                             const float *T_dev, const float *r_dev, float *cv_dev)
+{
+    if (!m || !S0_dev || !sigma_dev || !K_dev || !T_dev || !r_dev || !cv_dev || batch < 1 || d < 1) return TTFP_EINVAL;
+    MCHK(hipSetDevice(m->device));
+    hipLaunchKernelGGL(k_bs_max_call, dim3(cdivu(batch, 256)), dim3(256), 0, m->stream, batch, d, S0_dev, sigma_dev, K_dev, T_dev,
+                       r_dev, cv_dev);
+    MCHK(hipGetLastError());
     return TTFP_OK;
 }
 

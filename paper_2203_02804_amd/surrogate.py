@@ -4,9 +4,11 @@ An ensemble of MLPs (22 inputs -> 4 x 256 SiLU -> 1, BF16 weights and activation
 accumulation, FP32 master weights, Adam) runs on the library's own HIP kernels
 (ttfp_mlp_*). It learns the residual of the price over a closed-form control variate
 (the largest single-asset Black-Scholes call), from prices the TT path generates.
-At inference the ensemble spread, scaled by a factor calibrated on held-out TT prices,
-estimates each row's error; rows whose estimate exceeds the relative gate are re-priced
-by the TT path (the fallback, which also serves as the judge of the surrogate's error).
+At inference one fused kernel runs every model on a block of rows and forms, on the device,
+the ensemble mean, its spread, and the gate: the spread scaled by a factor calibrated on
+held-out TT prices estimates each row's error, and rows whose estimate exceeds the relative
+gate are re-priced by the TT path (the fallback, which also judges the surrogate's error).
+The host only prepares the input features and reads the gate's mask to pick the fallback rows.
 
 Inputs for d assets: log(S0/K) (d), sigma (d), strictly lower Cholesky entries of the
 correlation (d(d-1)/2), T, r -- 22 numbers for d = 5.
@@ -17,7 +19,6 @@ import ctypes
 import math
 
 import numpy as np
-from scipy import special
 
 from . import TTFPError, load
 
@@ -31,19 +32,6 @@ def features(options):
         rows.append(np.concatenate([np.log(np.asarray(o["S0"]) / o["K"]), np.asarray(o["sigma"]), low,
                                     [o["T"], o["r"]]]))
     return np.asarray(rows, np.float64)
-
-
-def control_variate(options):
-    """max_j of the single-asset Black-Scholes calls (a lower bound of the call on the max)."""
-    out = np.empty(len(options))
-    for n, o in enumerate(options):
-        S = np.asarray(o["S0"], float)
-        s = np.asarray(o["sigma"], float)
-        K, T, r = o["K"], o["T"], o["r"]
-        v = s * math.sqrt(T)
-        d1 = (np.log(S / K) + (r + 0.5 * s * s) * T) / v
-        out[n] = np.max(S * special.ndtr(d1) - K * math.exp(-r * T) * special.ndtr(d1 - v))
-    return out
 
 
 class MLP:
@@ -65,6 +53,8 @@ class MLP:
         lib.ttfp_mlp_forward.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
         lib.ttfp_mlp_grad.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, P(ctypes.c_float), P(ctypes.c_float)]
         lib.ttfp_mlp_train_step.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_float, P(ctypes.c_float)]
+        lib.ttfp_mlp_predict.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp]
+        lib.ttfp_mlp_control_variate.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp]
         lib.ttfp_mlp_last_error.argtypes = [vp]
         lib.ttfp_mlp_last_error.restype = ctypes.c_char_p
         if stream is None:
@@ -118,6 +108,27 @@ class MLP:
         self._check(self.lib.ttfp_mlp_forward(self.h, model, x.shape[0], self._dev(x), self._dev(y)))
         return y
 
+    def predict(self, x, cv, scale, factor, gate):
+        """Fused ensemble inference with the gate on the device: device tensors (mean, spread, ok)
+        of price_m = cv + scale * y_m over the models (see ttfp_mlp_predict)."""
+        import torch
+        B = x.shape[0]
+        mean = torch.empty(B, dtype=torch.float32, device=x.device)
+        spread = torch.empty_like(mean)
+        ok = torch.empty(B, dtype=torch.int32, device=x.device)
+        self._check(self.lib.ttfp_mlp_predict(self.h, B, self._dev(x), self._dev(cv), self._dev(scale), float(factor),
+                                              float(gate), self._dev(mean), self._dev(spread), ctypes.c_void_p(ok.data_ptr())))
+        return mean, spread, ok
+
+    def control_variate(self, S0, sigma, K, T, r):
+        """max_j of the single-asset Black-Scholes calls on the device (device FP32 tensors)."""
+        import torch
+        B, d = S0.shape
+        cv = torch.empty(B, dtype=torch.float32, device=S0.device)
+        self._check(self.lib.ttfp_mlp_control_variate(self.h, B, d, self._dev(S0), self._dev(sigma), self._dev(K),
+                                                      self._dev(T), self._dev(r), self._dev(cv)))
+        return cv
+
     def grad(self, model, x, t):
         g = np.zeros(self.n_params, np.float32)
         loss = ctypes.c_float(0.0)
@@ -155,9 +166,27 @@ class Surrogate:
             self.sd = f.std(axis=0) + 1e-12
         return torch.tensor((f - self.mu) / self.sd, dtype=torch.float32, device=f"cuda:{self.device}").contiguous()
 
+    def _device_inputs(self, options):
+        """Normalised features, control variate and price scale of each row, on the device."""
+        import torch
+        dev = f"cuda:{self.device}"
+        X = self._x(options)
+        f32 = lambda a: torch.tensor(np.asarray(a, np.float64), dtype=torch.float32, device=dev).contiguous()
+        S0 = f32([o["S0"] for o in options])
+        sig = f32([o["sigma"] for o in options])
+        K = f32([o["K"] for o in options])
+        cv = self.net.control_variate(S0, sig, K, f32([o["T"] for o in options]), f32([o["r"] for o in options]))
+        return X, cv, (K * self.tscale).contiguous()
+
     def _target(self, options, prices):
+        import torch
+        dev = f"cuda:{self.device}"
+        f32 = lambda a: torch.tensor(np.asarray(a, np.float64), dtype=torch.float32, device=dev).contiguous()
+        cv = self.net.control_variate(f32([o["S0"] for o in options]), f32([o["sigma"] for o in options]),
+                                      f32([o["K"] for o in options]), f32([o["T"] for o in options]),
+                                      f32([o["r"] for o in options])).double().cpu().numpy()
         K = np.array([o["K"] for o in options])
-        return (np.asarray(prices) - control_variate(options)) / K
+        return (np.asarray(prices) - cv) / K
 
     def fit(self, options, prices, steps=2000, batch=1024, lr=1e-3, holdout=0.1, seed=0, log_every=0):
         """Trains every ensemble member on the TT prices (each with its own shuffle), then
@@ -196,25 +225,24 @@ class Surrogate:
         return dict(history=hist, holdout_rel_err=err / np.abs(np.asarray(prices)[hold]), factor=self.factor)
 
     def predict(self, options):
-        """Ensemble mean price and ensemble spread (standard deviation), both in price units."""
-        X = self._x(options)
-        K = np.array([o["K"] for o in options])
-        cv = control_variate(options)
-        outs = []
-        for m in range(self.n_models):
-            yp = self.net.forward(m, X).double().cpu().numpy()
-            outs.append(cv + K * yp * self.tscale)
-        outs = np.stack(outs)
-        return outs.mean(axis=0), outs.std(axis=0, ddof=1) if self.n_models > 1 else np.zeros(len(options))
+        """Ensemble mean price and ensemble spread (standard deviation), both in price units,
+        from the fused ensemble kernel (host arrays)."""
+        X, cv, scale = self._device_inputs(options)
+        mean, spread, _ = self.net.predict(X, cv, scale, self.factor, 0.0)
+        return mean.double().cpu().numpy(), spread.double().cpu().numpy()
 
     def price(self, options, pricer, grid, rel_gate=1e-4):
-        """Surrogate prices where factor * spread <= rel_gate * |price|, TT prices elsewhere.
-        Returns (prices, served_by_surrogate mask)."""
-        mean, spread = self.predict(options)
-        ok = self.factor * spread <= rel_gate * np.abs(mean)
-        out = mean.copy()
+        """Surrogate prices where factor * spread <= rel_gate * |price| (decided on the device),
+        TT prices elsewhere. Returns (prices, served_by_surrogate mask, status): status holds the
+        TT return code of every fallback row and 0 for the rows the surrogate served."""
+        X, cv, scale = self._device_inputs(options)
+        mean, spread, okd = self.net.predict(X, cv, scale, self.factor, rel_gate)
+        ok = okd.cpu().numpy().astype(bool)
+        out = mean.double().cpu().numpy()
+        status = np.zeros(len(options), np.int32)
         fb = np.nonzero(~ok)[0]
         if len(fb):
-            p, _ = pricer.price_batch([options[i] for i in fb], grid)
+            p, st = pricer.price_batch([options[i] for i in fb], grid)
             out[fb] = p
-        return out, ok
+            status[fb] = st
+        return out, ok, status

@@ -29,13 +29,13 @@ def test_gradient_against_finite_differences():
     rng = np.random.Generator(np.random.PCG64(2))
     x = rng.standard_normal((17, n_in))
     t = rng.standard_normal(17)
-    g = M.grad(p, x, t, n_in, width, depth, rounding=False)
+    g = M.grad(p, x, t, n_in, width, depth, round_weights=False)
     h = 1e-6
     for idx in rng.choice(p.size, 40, replace=False):
         e = np.zeros_like(p)
         e[idx] = h
-        fd = (M.loss(p + e, x, t, n_in, width, depth, rounding=False)
-              - M.loss(p - e, x, t, n_in, width, depth, rounding=False)) / (2 * h)
+        fd = (M.loss(p + e, x, t, n_in, width, depth, round_weights=False)
+              - M.loss(p - e, x, t, n_in, width, depth, round_weights=False)) / (2 * h)
         assert abs(fd - g[idx]) <= 1e-7 * max(1.0, abs(fd)), (idx, fd, g[idx])
 
 
@@ -48,3 +48,28 @@ def test_adam_first_step_moves_by_lr():
     g = np.array([0.5, -3.0])
     q, m1, m2 = M.adam_step(p, g, np.zeros(2), np.zeros(2), 1, 0.01)
     assert np.allclose(q, p - 0.01 * np.sign(g), atol=1e-9)
+
+
+def test_rounding_spread_covers_the_kernels_rounding_points():
+    # the kernels' rounding (bfloat16 input, activations, dZ; float32 sums), imitated in NumPy,
+    # stays within 8 standard deviations of the rounding spread, element by element; the
+    # tolerance is small against the values; a planted mistake is far outside it
+    n_in, width, depth = 22, 64, 4
+    p = _params(n_in, width, depth, 3)
+    rng = np.random.Generator(np.random.PCG64(4))
+    x = rng.standard_normal((300, n_in))
+    t = np.sin(x[:, :5].sum(axis=1))
+    y, gsim = M.simulate_kernel_rounding(p, x, t, n_in, width, depth)
+    y0 = M.forward(p, x, n_in, width, depth)
+    g0 = M.grad(p, x, t, n_in, width, depth)
+    sy, sg, acc = M.rounding_spread(p, x, t, n_in, width, depth, draws=16, seed=5)
+    ty, tg = 8 * sy + 1e-6 * np.abs(y0).max(), 8 * sg + acc
+    assert np.all(np.abs(y - y0) <= ty)
+    assert np.all(np.abs(gsim - g0) <= tg)
+    assert np.median(ty) < 1e-2 * np.abs(y0).max()
+    assert np.median(tg) < 1e-2 * np.abs(g0).max()
+    q = p.copy()
+    q[:n_in], q[n_in:2 * n_in] = p[n_in:2 * n_in].copy(), p[:n_in].copy()
+    assert np.mean(np.abs(M.forward(q, x, n_in, width, depth) - y0) > ty) > 0.5
+    gq = M.grad(q, x, t, n_in, width, depth)
+    assert np.mean(np.abs(gq - g0) > tg) > 0.3
