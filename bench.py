@@ -202,9 +202,13 @@ TRAFFIC = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
 def kernels_digest():
+    """SHA-256 over the kernel source and the host code that picks the launch shapes."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2203_02804_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_2203_02804_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
@@ -271,7 +275,7 @@ def main():
     ap.add_argument("--no-literal", action="store_true", help="skip the literal Wishart N=128 R=32 line")
     ap.add_argument("--surrogate-train", type=int, default=4096, help="TT-priced training options")
     ap.add_argument("--no-book", action="store_true", help="skip the batched-book leg")
-    ap.add_argument("--book", type=int, default=1024, help="options of the batched book in its leg")
+    ap.add_argument("--book", type=int, default=8192, help="options of the batched book in its leg")
     ap.add_argument("--no-cpu-ttcross", action="store_true", help="skip the CPU TT-cross timing")
     ap.add_argument("--qr", choices=["cholqr", "tsqr", "cholqr2", "cholqr3"], default="cholqr",
                     help="triangular factor of the fibers: shifted Cholesky QR on the matrix cores with passes "

@@ -90,7 +90,13 @@ typedef struct {
  *               rand(q, a, b, c, n) = ((h >> 32) * n) >> 32 with h = f(f(f(q ^ a) ^ b) ^ c), f the
  *               SplitMix64 finaliser (Steele, Lea and Flood 2014: add 0x9E3779B97F4A7C15, then
  *               xor-shift-multiply by 0xBF58476D1CE4E5B9 (30), 0x94D049BB133111EB (27), xor-shift 31),
- *               and seed_t = seed * 0x100000001B3 + t * 0x9E3779B97F4A7C15 + 1 (mod 2^64)        */
+ *               and seed_t = seed * 0x100000001B3 + t * 0x9E3779B97F4A7C15 + 1 (mod 2^64)
+ *  certify      0: TTFP_OK means the half-sweep criterion above was met with no rank cap hit.
+ *               1: TTFP_OK also needs err_est * kappa <= tol. The price is a positively weighted
+ *               sum of the integrand over the grid, so |price error| / |price| <= (sum |TT - A|)
+ *               / (sum |A|) * kappa, and err_est estimates that ratio from the samples: the
+ *               product is a sampled bound on the price's relative error. An option that fails
+ *               it returns TTFP_ENOTCONV (needs n_err_samples >= 0).                         */
 typedef struct {
     int32_t N;
     double L, alpha;
@@ -99,6 +105,7 @@ typedef struct {
     int32_t max_rank, max_sweeps, n_enrich;
     uint64_t seed;
     int32_t n_err_samples;
+    int32_t certify;
 } ttfp_grid;
 
 /* Per-option diagnostics. */

@@ -42,7 +42,8 @@ class _Grid(ctypes.Structure):
                 ("L_k", ctypes.POINTER(ctypes.c_double)), ("alpha_k", ctypes.POINTER(ctypes.c_double)),
                 ("tol", ctypes.c_double), ("rank_tol", ctypes.c_double),
                 ("max_rank", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("n_enrich", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("n_err_samples", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("n_err_samples", ctypes.c_int32),
+                ("certify", ctypes.c_int32)]
 
 
 class _Diag(ctypes.Structure):
@@ -140,7 +141,7 @@ class _Marshal:
                           float(grid.get("tol", 1e-8)), float(grid.get("rank_tol", 0.0)),
                           int(grid.get("max_rank", 32)), int(grid.get("max_sweeps", 6)),
                           int(grid.get("n_enrich", 4)), int(grid.get("seed", 0)) & ((1 << 64) - 1),
-                          int(grid.get("n_err_samples", 0)))
+                          int(grid.get("n_err_samples", 0)), int(grid.get("certify", 0)))
 
 
 def plan(opt, grid):

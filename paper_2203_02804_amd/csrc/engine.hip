@@ -764,6 +764,9 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
         for (int o = 0; o < n_opts; ++o) {
             res[o].err_samples = ns[o];
             res[o].err_est = ns[o] > 0 ? (ef[o] > 0.0 ? ea[o] / ef[o] : (ea[o] > 0.0 ? INFINITY : 0.0)) : NAN;
+            // sampled bound on the price's relative error, required when the grid asks for it
+            if (grids[o]->certify && res[o].code == TTFP_OK && !(res[o].err_est * res[o].kappa <= grids[o]->tol))
+                res[o].code = TTFP_ENOTCONV;
         }
     }
     if (ctx->prof)

@@ -116,6 +116,8 @@ int check_cross_settings(const ttfp_grid *g, std::string &err)
     if (!finite(g->rank_tol)) { err = "rank_tol must be finite"; return TTFP_EINVAL; }
     if (g->max_sweeps < 1 || g->max_sweeps > 64) { err = "max_sweeps must be in [1, 64]"; return TTFP_EINVAL; }
     if (g->n_err_samples > (1 << 24)) { err = "n_err_samples must be at most 2^24"; return TTFP_EINVAL; }
+    if (g->certify != 0 && g->certify != 1) { err = "certify must be 0 or 1"; return TTFP_EINVAL; }
+    if (g->certify && g->n_err_samples < 0) { err = "certify needs the sampled error estimate (n_err_samples >= 0)"; return TTFP_EINVAL; }
     return TTFP_OK;
 }
 

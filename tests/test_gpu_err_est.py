@@ -85,3 +85,36 @@ def test_err_est_off_and_batch_diag(pricer):
         assert p1 == prices[i]
         assert 0.0 <= dg["err_est"] < 1.0
         assert abs(dg["err_est"] - info1["err_est"]) <= 1e-12 * info1["err_est"]
+
+
+def test_certified_status(pricer):
+    # certify = 1 keeps TTFP_OK only where the sampled bound err_est * kappa meets tol; every
+    # other code is unchanged, and a certified price is within tol of the dense-grid oracle. At
+    # N = 16 and a rank cap above N the trains can be exact (d <= 3), so the bound can be met;
+    # at N = 64 with rank 8 it is not, and converged options are demoted.
+    import paper_2203_02804_amd as ttfp
+    opts = ([W.config1()[0]] + W.random_small_options(2, seed=3, d_choices=(1,))
+            + W.random_small_options(3, seed=31, d_choices=(2, 3)))
+    n_cert = 0
+    for N, R in ((16, 20), (64, 8)):
+        g = dict(W.grid(N, tol=1e-6, max_rank=R), n_err_samples=4000)
+        # the oracle's grid, handed to both sides
+        grids = [np.array(v) for v in (F.term_grids(o, N, tol=g["tol"])[1] for o in opts)]
+        gl = [dict(g, L=G[:, 0], alpha=G[:, 1]) for G in grids]
+        p0, s0 = pricer.price_batch(opts, gl)
+        p1, s1 = pricer.price_batch(opts, [dict(x, certify=1) for x in gl])
+        assert np.array_equal(p0, p1)
+        for i, o in enumerate(opts):
+            dg = pricer.batch_diag(i)
+            bound = dg["err_est"] * dg["kappa"]
+            want = s0[i] if s0[i] != 0 or bound <= g["tol"] else 1
+            print(f"  N={N} R={R} option {i} d={o['d']} status {s0[i]} -> {s1[i]} bound {bound:.2e}", flush=True)
+            assert s1[i] == want
+            if s1[i] == 0:
+                n_cert += 1
+                ref = F.dense_price(o, N, grids[i][:, 0], grids[i][:, 1])
+                assert abs(p1[i] / ref - 1) <= g["tol"]
+    assert n_cert > 0
+    for bad in (dict(g, certify=2), dict(g, certify=1, n_err_samples=-1)):
+        with pytest.raises(ttfp.TTFPError):
+            pricer.price_batch(opts[:1], bad)
