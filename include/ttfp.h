@@ -210,8 +210,11 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
 
 /* Launch tuning of a context (chosen per workload shape by the autotuner in
  * paper_2203_02804_amd/tuning.py):
- *  TTFP_TUNE_MAXVOL_THREADS  threads per maxvol workgroup: 256, 512 or 1024, or 0 (default):
- *                            per launch, the largest size that keeps every item resident at once
+ *  TTFP_TUNE_MAXVOL_ROUNDS   refinement rounds of maxvol after its block start, 0..8 (default
+ *                            3): each round swaps the rows of B beyond the dominance bound into
+ *                            a new block and forms B again; more rounds give interpolation
+ *                            nearer to dominant (and may change the result), at the cost of one
+ *                            pass over B per round that moves a pivot
  *  TTFP_TUNE_TSQR_LDS_KB     LDS budget of a TSQR workgroup in KiB, 16..152 (default 152):
  *                            smaller budgets give shorter leaf blocks and merges of fewer
  *                            factors (a leaf keeps at least two groups of nc rows and a merge
@@ -229,7 +232,7 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
  *                            1e-10), 3 always three (down to about 1e-16; ttfp_qr_r uses three
  *                            unless 2 is set); 1 Householder TSQR over LDS-resident row blocks
  * Returns TTFP_EINVAL for an unknown parameter or value. */
-enum { TTFP_TUNE_MAXVOL_THREADS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2, TTFP_TUNE_QR = 3 };
+enum { TTFP_TUNE_MAXVOL_ROUNDS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2, TTFP_TUNE_QR = 3 };
 int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value);
 int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
 

@@ -60,7 +60,7 @@ EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price
            "ttfp_mlp_last_error"]
 KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract", "interp", "err_est",
            "gram", "chol", "xform"]
-TUNING = {"maxvol_threads": 0, "tsqr_lds_kb": 1, "graph": 2, "qr": 3}
+TUNING = {"maxvol_rounds": 0, "tsqr_lds_kb": 1, "graph": 2, "qr": 3}
 
 _lib = None
 
@@ -245,7 +245,7 @@ class Pricer:
         return prices, np.split(delta, split), np.split(vega, split), status
 
     def set_tuning(self, **kw):
-        """set_tuning(maxvol_threads=..., tsqr_lds_kb=..., graph=...)"""
+        """set_tuning(maxvol_rounds=..., tsqr_lds_kb=..., graph=..., qr=...)"""
         for k, v in kw.items():
             self._check(self.lib.ttfp_set_tuning(self.ctx, TUNING[k], int(v)))
 

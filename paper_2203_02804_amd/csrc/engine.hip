@@ -58,7 +58,7 @@ struct ttfp_ctx {
     std::vector<ttfp_diag> last_batch_diag;
     int last_n_items = 0;
     // tuning (set by ttfp_set_tuning, chosen by the autotuner)
-    int tune_maxvol_threads = 0;          // 0: chosen per launch from the number of items
+    int tune_maxvol_rounds = 3;           // refinement rounds of maxvol after the block start
     int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 1;                   // graph replay whenever the stream is not the null stream
@@ -157,7 +157,7 @@ ItemSizes item_sizes(int d, int N, int R, int p, int BR)
     s.off_M1 = take(sizeof(cplx) * (size_t)d * R * R);
     s.off_M2 = take(sizeof(cplx) * (size_t)d * R * R);
     s.off_piv = take(sizeof(int) * R);
-    s.off_keys = take(sizeof(float) * (size_t)s.rows_max * 17);   // keys, then viol
+    s.off_keys = take(sizeof(float) * (size_t)s.rows_max * 2);    // keys, then viol
     s.off_Ai = take(sizeof(cplx) * (size_t)R * R);
     const size_t gblk = (size_t)(s.rows_max + GRAM_ROWS_HOST - 1) / GRAM_ROWS_HOST;
     s.off_Qb = take(sizeof(cplx) * (size_t)s.rows_max * nc);
@@ -344,7 +344,7 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             it.M2 = (cplx *)(dev + s.off_M2);
             it.piv = (int *)(dev + s.off_piv);
             it.keys = (float *)(dev + s.off_keys);
-            it.viol = it.keys + (size_t)s.rows_max * 16;
+            it.viol = it.keys + (size_t)s.rows_max;
             it.Ai = (cplx *)(dev + s.off_Ai);
             it.Qb = (cplx *)(dev + s.off_Qb);
             it.Gp = (cplx *)(dev + s.off_Gp);
@@ -429,7 +429,6 @@ void prof_collect(ttfp_ctx *ctx)
 // it static) divided by threads^0.7 (a workgroup's speed grows sublinearly with its size).
 int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
 {
-    if (ctx->tune_maxvol_threads) return ctx->tune_maxvol_threads;
     const long long by_lds = std::max(1LL, (long long)(160 * 1024) / (long long)(dyn_lds + 15 * 1024));
     int best = 1024;
     double best_cost = 1e300;
@@ -443,14 +442,14 @@ int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
     return best;
 }
 
-// Refinement rounds of maxvol after the block start: each marks the rows of B beyond 1 + delta
-// and swaps them in. More rounds give interpolation nearer to dominant, hence crosses that need
-// fewer sweeps and land nearer the exact price: on the d = 5 headline batch of 192 options
-// (within 1e-6 / options/s), with blocks of the pivots and 192 violators: 2 rounds 339/576 at
-// 71.3, 3: 380 at 72.2, 4: 412 at 71.9, 6: 400 at 67.3, 10: 406 at 67.4; with blocks of up to
-// 448 violators: 3 rounds 413 at 75.5, 4: 404 at 73.1 (one box). A round with no violating row
-// costs one early-exit launch.
-constexpr int MAXVOL_REFINE_ROUNDS = 3;
+// Refinement rounds of maxvol after the block start (TTFP_TUNE_MAXVOL_ROUNDS, default 3): each
+// marks the rows of B beyond 1 + delta and swaps them in. More rounds give interpolation nearer to
+// dominant, hence crosses that need fewer sweeps and land nearer the exact price: on the d = 5
+// headline batch of 192 options (within 1e-6 / options/s), with blocks of the pivots and 192
+// violators: 2 rounds 339/576 at 71.3, 3: 380 at 72.2, 4: 412 at 71.9, 6: 400 at 67.3, 10: 406 at
+// 67.4; with blocks of up to 448 violators: 3 rounds 413 at 75.5, 4: 404 at 73.1 (one box). A round
+// with no violating row costs one early-exit launch.
+constexpr int MAXVOL_ROUNDS_MAX = 8;
 
 // Passes of shifted Cholesky QR for a relative rank threshold eps. Each pass resolves the
 // singular values above about the square root of its shift (~1e-6 of the largest), relative to
@@ -521,7 +520,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     // interpolation matrix of every row, then refinement rounds (each returns at once for an
     // item whose rows all satisfy the dominance bound)
     const unsigned gi = cdivu((long long)g.maxrows, MM_ROWS_PER_WG);   // row blocks of k_interp
-    for (int round = 0; round <= MAXVOL_REFINE_ROUNDS; ++round) {
+    for (int round = 0; round <= ctx->tune_maxvol_rounds; ++round) {
         if (round > 0) {
             ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
             const int rm = std::max(g.maxR, 2);
@@ -869,9 +868,9 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
 {
     if (!ctx) return TTFP_EINVAL;
     switch (param) {
-    case TTFP_TUNE_MAXVOL_THREADS:
-        if (value != 0 && value != 256 && value != 512 && value != 1024) break;
-        ctx->tune_maxvol_threads = value;
+    case TTFP_TUNE_MAXVOL_ROUNDS:
+        if (value < 0 || value > MAXVOL_ROUNDS_MAX) break;
+        ctx->tune_maxvol_rounds = value;
         return TTFP_OK;
     case TTFP_TUNE_TSQR_LDS_KB:
         if (value < 16 || value > LDS_BYTES / 1024) break;
@@ -896,7 +895,7 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value)
 {
     if (!ctx || !value) return TTFP_EINVAL;
     switch (param) {
-    case TTFP_TUNE_MAXVOL_THREADS: *value = ctx->tune_maxvol_threads; return TTFP_OK;
+    case TTFP_TUNE_MAXVOL_ROUNDS: *value = ctx->tune_maxvol_rounds; return TTFP_OK;
     case TTFP_TUNE_TSQR_LDS_KB: *value = ctx->tune_tsqr_lds_kb; return TTFP_OK;
     case TTFP_TUNE_GRAPH: *value = ctx->tune_graph; return TTFP_OK;
     case TTFP_TUNE_QR: *value = ctx->tune_qr; return TTFP_OK;
@@ -1288,7 +1287,7 @@ static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, in
     const int nblk = (m + BR - 1) / BR;
     size_t oF = 0, oRl = align_up(oF + 16 * (size_t)m * n), oY = align_up(oRl + 16 * 2 * (size_t)nblk * n * n),
            oW = align_up(oY + 16 * (size_t)m * r), oBt = align_up(oW + 16 * (size_t)m * r), oP = align_up(oBt + 16 * (size_t)m * r),
-           oK = align_up(oP + 4 * (size_t)std::max(r, 1)), oA = align_up(oK + 4 * 17 * (size_t)m),
+           oK = align_up(oP + 4 * (size_t)std::max(r, 1)), oA = align_up(oK + 4 * 2 * (size_t)m),
            gblk = (size_t)(m + GRAM_ROWS_HOST - 1) / GRAM_ROWS_HOST, oQ = align_up(oA + 16 * (size_t)r * r),
            oGp = align_up(oQ + 16 * (size_t)m * n), oGe = align_up(oGp + 16 * gblk * n * n), oXf = align_up(oGe + 4 * gblk),
            oRf = align_up(oXf + 16 * (size_t)n * n), total = align_up(oRf + 16 * (size_t)n * n);
@@ -1304,7 +1303,7 @@ static int raw_item(ttfp_ctx *ctx, int m, int n, int r, Item &it, char *&buf, in
     it.Bt = (cplx *)(buf + oBt);
     it.piv = (int *)(buf + oP);
     it.keys = (float *)(buf + oK);
-    it.viol = it.keys + 16 * (size_t)m;
+    it.viol = it.keys + (size_t)m;
     it.Ai = (cplx *)(buf + oA);
     it.Qb = (cplx *)(buf + oQ);
     it.Gp = (cplx *)(buf + oGp);

@@ -53,7 +53,7 @@ struct Item {
     cplx *M1, *M2;             // d slots of R x R: first / second node moments (Greeks)
     int *piv;                  // R pivot rows
     cplx *Ai;                  // R x R inverse of the pivot rows of Y (maxvol -> k_interp)
-    float *keys;               // rows_max x 16 partial squared row norms of Y (maxvol start)
+    float *keys;               // rows_max squared row norms of Y (maxvol start)
     float *viol;               // rows_max marks of k_interp: a row's largest |B| above the bound, else 0
     cplx *Qb;                  // rows_max x nc_max: the Cholesky QR's transformed fiber
     cplx *Gp;                  // gram_blocks(rows_max) x nc x nc partial Gram matrices

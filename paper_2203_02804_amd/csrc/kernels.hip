@@ -1396,8 +1396,8 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
 // ------------------------------------------------------------------ basis of the kept columns
 // Y = F[:, perm[:r]] R2^{-1} on the FP64 matrix cores, laid out as in k_interp (a wave forms a
 // 16-row panel as up to four 16 x 16 complex tiles, three real MFMA products each); the
-// triangular inverse is held in LDS with its zero lower part. Each row's squared norm is left
-// in four-column partial sums in its key slots (the start of maxvol reads them).
+// triangular inverse is held in LDS with its zero lower part. Each row's squared norm goes to
+// its key (the start of maxvol reads them).
 constexpr int PANEL_WAVES = MM_WAVES;            // 16-row panels per workgroup
 __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const int *active, int t, int dir)
 {
@@ -1446,18 +1446,21 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const i
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = row0 + lk + 4 * v;
+        double nrm = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= ntile) break;
             const int col = 16 * q + li;
             const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
-            double nrm = (row < m && col < r) ? cabs2(val) : 0.0;
+            nrm += (row < m && col < r) ? cabs2(val) : 0.0;
             if (row < m && col < r) it.Y[(size_t)row * r + col] = val;
-            // partial squared norm over the four columns 4 (col / 4) .. 4 (col / 4) + 3
-            nrm += __shfl_xor(nrm, 1, 64);
-            nrm += __shfl_xor(nrm, 2, 64);
-            if (row < m && (li & 3) == 0 && col < r) it.keys[(size_t)row * 16 + col / 4] = (float)nrm;
         }
+        // the row's squared norm: the lane's columns li + 16 q, then the 16 lanes of the row
+        nrm += __shfl_xor(nrm, 1, 64);
+        nrm += __shfl_xor(nrm, 2, 64);
+        nrm += __shfl_xor(nrm, 4, 64);
+        nrm += __shfl_xor(nrm, 8, 64);
+        if (row < m && li == 0) it.keys[row] = (float)nrm;
     }
 }
 
@@ -1499,48 +1502,46 @@ constexpr int MV_KMAX = 512;
 
 // Up to K indices g < n of largest value v[g * stride] (nonnegative floats, largest vmax), among
 // those of value >= lo0: the first ones in index order among those at or above a threshold
-// found by bisection, so that the choice does not depend on scheduling. Writes out[0..Kc) and
-// returns Kc (same in every thread). Every thread of the workgroup must call it.
+// found by bisection (stopped once between K and K + K / 8 values reach it), so that the choice
+// does not depend on scheduling. Writes out[0..Kc) and returns Kc (same in every thread). Every
+// thread of the workgroup must call it.
 __device__ int select_largest(const float *v, int stride, int n, int K, float lo0, float vmax, int *out, ArgMax *red,
                               int *shi, float *shf)
 {
-    const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ int cntb[2][16];
+    const int nthr = blockDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = nthr >> 6;
     __syncthreads();
-    if (threadIdx.x == 0) { shf[0] = lo0; shf[1] = fmaxf(vmax, lo0); }
-    {
-        // when at most K values reach lo0, all of them are taken and no bisection is needed
-        int cnt = 0;
-        for (int g = threadIdx.x; g < n; g += nthr) cnt += v[(size_t)g * stride] >= lo0;
-        double a = (double)cnt;
-        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    int par = 0;
+    // number of values >= thr, in every thread (one barrier; the two count buffers alternate)
+    auto count_ge = [&](float thr) -> int {
+        int c = 0;
+        for (int g = threadIdx.x; g < n; g += nthr) c += v[(size_t)g * stride] >= thr;
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0) cntb[par][wave] = c;
         __syncthreads();
-        if (lane == 0) red[wave].v = a;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double tot = 0.0;
-            for (int w = 0; w < (nthr >> 6); ++w) tot += red[w].v;
-            if (tot <= K) shf[1] = lo0;        // collapses the bisection interval
+        int tot = 0;
+        for (int w = 0; w < nw; ++w) tot += cntb[par][w];
+        par ^= 1;
+        return tot;
+    };
+    float lo = lo0, hi = fmaxf(vmax, lo0);
+    // when at most K values reach lo0, all of them are taken and no bisection is needed
+    if (count_ge(lo0) > K) {
+        const int slack = K >> 3;
+        for (int it2 = 0; it2 < 40; ++it2) {
+            const float mid = 0.5f * (lo + hi);
+            if (!(mid > lo && mid < hi)) break;
+            const int c = count_ge(mid);
+            if (c >= K) {
+                lo = mid;
+                if (c <= K + slack) break;
+            } else {
+                hi = mid;
+            }
         }
     }
-    __syncthreads();
-    for (int it2 = 0; it2 < 40; ++it2) {
-        const float lo = shf[0], hi = shf[1], mid = 0.5f * (lo + hi);
-        if (!(mid > lo && mid < hi)) break;
-        int cnt = 0;
-        for (int g = threadIdx.x; g < n; g += nthr) cnt += v[(size_t)g * stride] >= mid;
-        double a = (double)cnt;
-        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-        __syncthreads();
-        if (lane == 0) red[wave].v = a;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double tot = 0.0;
-            for (int w = 0; w < (nthr >> 6); ++w) tot += red[w].v;
-            if (tot >= K) shf[0] = mid; else shf[1] = mid;
-        }
-        __syncthreads();
-    }
-    const float thr = shf[0];
+    (void)shf;
+    const float thr = lo;
     const int chunk = (n + nthr - 1) / nthr;
     const int g0 = threadIdx.x * chunk, g1 = min(n, g0 + chunk);
     int cnt = 0;
@@ -1749,10 +1750,8 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         float best = -1.0f;
         for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
             float q;
-            float *kp = it.keys + (size_t)i * 16;
             if (dir != 2) {
-                q = 0.0f;                                // partials written by k_basis
-                for (int u = 0; u < (r + 3) / 4; ++u) q += kp[u];
+                q = it.keys[i];                          // the row norm written by k_basis
             } else {
                 const cplx *y = Y + (size_t)i * r;
                 double qq = 0.0;

@@ -1,8 +1,9 @@
 """Autotuner for the pricer's launch parameters.
 
-For a workload shape (d, N, max rank) it times every candidate setting of the tunable
-launch parameters (threads per maxvol workgroup, LDS budget of a TSQR workgroup) on a
-sample batch of options of that shape, and keeps the fastest. Results are stored in a JSON
+For a workload shape (d, N, max rank) it times every candidate setting of the launch
+parameters that leave the result unchanged (graph replay or eager launches; the LDS budget of a
+TSQR workgroup, which sets its leaf and merge shapes) on a sample batch of options of that shape,
+and keeps the fastest. Results are stored in a JSON
 table keyed by "d{d}-N{N}-R{R}" next to this module and applied with `apply`.
 """
 from __future__ import annotations
@@ -16,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning_table.json")
 
 CANDIDATES = {
-    "maxvol_threads": (256, 512, 1024),
+    "graph": (0, 1),
     "tsqr_lds_kb": (48, 76, 152),
 }
 

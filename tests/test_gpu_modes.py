@@ -54,12 +54,12 @@ def test_graph_replay_matches_eager(pricer):
     pricer.set_tuning(graph=0)
 
 
-@pytest.mark.parametrize("threads,lds", [(256, 48), (512, 76), (1024, 152), (0, 100)])
-def test_tunings_agree_with_the_oracle(pricer, threads, lds):
+@pytest.mark.parametrize("rounds,lds", [(0, 48), (2, 76), (3, 152), (5, 100)])
+def test_tunings_agree_with_the_oracle(pricer, rounds, lds):
     opts, g = _batch()
-    pricer.set_tuning(maxvol_threads=threads, tsqr_lds_kb=lds)
+    pricer.set_tuning(maxvol_rounds=rounds, tsqr_lds_kb=lds)
     p, status = pricer.price_batch(opts, g)
-    pricer.set_tuning(maxvol_threads=0, tsqr_lds_kb=152)
+    pricer.set_tuning(maxvol_rounds=3, tsqr_lds_kb=152)
     for o, v in zip(opts, p):
         ref = F.dense_price(o, 48, 14.0, 1.25)
         assert abs(v / ref - 1) < 1e-8
@@ -70,7 +70,7 @@ def test_autotuner_picks_a_valid_setting(pricer, tmp_path):
     opts, g = _batch()
     best, timings = tuning.tune(pricer, opts, g, reps=1, path=str(tmp_path / "t.json"))
     assert set(best) == set(tuning.CANDIDATES)
-    assert len(timings) == 9
+    assert len(timings) == 6
     entry = tuning.apply(pricer, opts[0]["d"], g["N"], g["max_rank"], path=str(tmp_path / "t.json"))
-    assert entry is not None and pricer.get_tuning()["maxvol_threads"] == best["maxvol_threads"]
-    pricer.set_tuning(maxvol_threads=0, tsqr_lds_kb=152)
+    assert entry is not None and pricer.get_tuning()["tsqr_lds_kb"] == best["tsqr_lds_kb"]
+    pricer.set_tuning(graph=1, tsqr_lds_kb=152)
