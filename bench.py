@@ -136,6 +136,52 @@ def book_leg(pricer, n, seed_refs):
                                                                          default=None)}}
 
 
+PAPER_GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_table.json")
+
+
+def paper_table_leg(pricer):
+    """The paper's multi-asset experiment (Sec. V.B, Table I): the call on the minimum in asset
+    coordinates with the single-strip transform, Sigma(0.5), N = 50 nodes with the table's spacing,
+    shift 5 / d, tol 1e-10, rank cap 64; one option per d, priced alone (ttfp_price), against the
+    stored exact one-factor price and, for d <= 4, the stored dense grid sum. Then the bond-dimension
+    study (d = 3, beta = 0.2, 0.5, 1): the mean error against the grid sum over 4 seeds per rank cap."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+
+    with open(PAPER_GOLDEN) as f:
+        gold = json.load(f)
+    rows = []
+    for c in gold["table"]:
+        d = c["d"]
+        opt, g = W.paper_experiment(d)
+        pricer.price(opt, g)                              # first call: allocation
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p, ranks, info, rc = pricer.price(opt, g)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rows.append({"d": d, "eta": 2 * g["L"] / g["N"], "seconds": dt, "status": int(rc), "max_rank": int(ranks.max()),
+                     "sweeps": info["sweeps"], "n_evals": info["n_evals"], "r_comp": info["n_evals"] / float(g["N"]) ** d,
+                     "rel_err_vs_exact": p / c["one_factor"] - 1,
+                     "eps_trunc_vs_grid_sum": (p / c["dense"] - 1) if "dense" in c else None})
+    bond = {}
+    for c in gold["bond"]:
+        errs = {}
+        for R in (3, 6, 12, 24, 48):
+            e = []
+            for seed in range(4):
+                opt, g = W.paper_experiment(3, c["beta"], max_rank=R, seed=seed)
+                p, _, _, _ = pricer.price(opt, g)
+                e.append(abs(p / c["dense"] - 1))
+            errs[str(R)] = float(np.mean(e))
+        bond[str(c["beta"])] = errs
+    return {"workload": "call on the min, Sigma(0.5), r=0.3, sigma=0.5, T=1, S0=K=100, N=50, alpha=5/d, tol 1e-10, "
+                        "rank cap 64, single strip", "table": rows,
+            "bond_dimension_d3": {"mean_rel_err_vs_grid_sum_by_rank_cap": bond, "seeds": 4}}
+
+
 def surrogate_leg(pricer, n_train, tt_rate):
     """Trains the BF16 surrogate ensemble on TT prices (outside any timed region), then times
     its inference on a batch of 65 536 options and reports its gate statistics. Labels: the
@@ -277,6 +323,7 @@ def main():
     ap.add_argument("--no-book", action="store_true", help="skip the batched-book leg")
     ap.add_argument("--book", type=int, default=8192, help="options of the batched book in its leg")
     ap.add_argument("--no-cpu-ttcross", action="store_true", help="skip the CPU TT-cross timing")
+    ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's call-on-min experiment")
     ap.add_argument("--qr", choices=["cholqr", "tsqr", "cholqr2", "cholqr3"], default="cholqr",
                     help="triangular factor of the fibers: shifted Cholesky QR on the matrix cores with passes "
                          "chosen by the rank threshold, Householder TSQR, or two / three Cholesky QR passes")
@@ -393,6 +440,12 @@ def main():
         book = book_leg(pricer, args.book, os.path.join(ROOT, "tests", "golden", "book_slice.json"))
         log(f"bench: book slice {book['options_per_s']:.1f} options/s with Greeks, status {book['status_counts']}")
 
+    paper = None
+    if not args.no_paper_table:
+        paper = paper_table_leg(pricer)
+        log("bench: paper table " + " ".join(f"d={r['d']}:{r['seconds'] * 1e3:.0f}ms/{r['rel_err_vs_exact']:+.1e}"
+                                             for r in paper["table"]))
+
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(batches[args.warmup][0], grid)
@@ -431,6 +484,7 @@ def main():
         "plain": plain,
         "literal_config2": literal,
         "book": book,
+        "paper_table": paper,
         "surrogate": surrogate,
         "kernel_ms": breakdown,
     }

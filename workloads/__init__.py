@@ -180,3 +180,19 @@ def random_small_options(n, seed, d_choices=(1, 2, 3), payoffs=PAYOFFS):
         pay = str(rng.choice(list(payoffs))) if d > 1 else str(rng.choice(["call_max", "put_max"]))
         out.append(option(d, S0, 100.0, T, r, sigma, corr, pay))
     return out
+
+
+# --- the paper's multi-asset experiment (Sec. V.B, Table I and the bond-dimension study) --------
+# grid spacing eta of Table I by dimension (0.2 for the dimensions the table does not list)
+PAPER_TABLE_ETA = {2: 0.5, 3: 0.4, 4: 0.3, 5: 0.3, 6: 0.2, 7: 0.2, 8: 0.2, 9: 0.2, 10: 0.2, 15: 0.2}
+PAPER_TABLE_DIMS = (2, 3, 4, 5, 6, 7, 8, 9, 10, 15)
+
+
+def paper_experiment(d, beta=0.5, tol=1e-10, max_rank=64, max_sweeps=8, seed=0, N=50, eta=None):
+    """The call on the minimum of d assets of the paper's experiment: r = 0.3, sigma = 0.5, T = 1,
+    S0 = K = 100 on every asset, correlation Sigma(beta), priced in asset coordinates with the
+    single-strip transform on N nodes (the paper's 50) of spacing eta (Table I's by default;
+    L = N eta / 2) and the shift alpha = 5 / d on every coordinate. Returns (option, grid)."""
+    opt = option(d, [100.0] * d, 100.0, 1.0, 0.3, [0.5] * d, sigma_beta(d, beta), "call_min_strip")
+    eta = PAPER_TABLE_ETA.get(d, 0.2) if eta is None else eta
+    return opt, grid(N, L=N * eta / 2, alpha=5.0 / d, tol=tol, max_rank=max_rank, max_sweeps=max_sweeps, seed=seed)
