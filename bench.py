@@ -182,6 +182,45 @@ def paper_table_leg(pricer):
             "bond_dimension_d3": {"mean_rel_err_vs_grid_sum_by_rank_cap": bond, "seeds": 4}}
 
 
+LADDER_GOLDEN = os.path.join(ROOT, "tests", "golden", "ladder.json")
+
+
+def ladder_leg(pricer, grid):
+    """A market ladder from one cross (ttfp_price_ladder): the first option of the d = 5 Sigma(0.5)
+    batch at 1024 (S0, K, r) points, against their stored exact one-factor prices. Wall time covers
+    the base cross and the contractions; the contraction's dense FP64 products are timed with HIP
+    events."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+
+    with open(LADDER_GOLDEN) as f:
+        gold = json.load(f)
+    ref = np.asarray(gold["prices"])
+    base = W.config2_batch(1, seed=gold["batch_seed"], corr_kind="beta")[0]
+    S0, K, r = W.ladder_points(base, len(ref), seed=gold["ladder_seed"])
+    pricer.price_ladder(base, grid, S0[:16], K[:16], r[:16])         # first call: allocation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prices, info, rc = pricer.price_ladder(base, grid, S0, K, r)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pricer.profile(True)
+    pricer.price_ladder(base, grid, S0, K, r)
+    n_l, ms, work = pricer.profile_read()["ladder"]
+    pricer.profile(False)
+    rel = np.abs(prices / ref - 1)
+    return {"workload": "1024-point ladder (spots x U[0.85,1.15] per asset, K U[85,115], r U[0,0.06]) around the "
+                        "first d5 Sigma(0.5) option, N=256, tol 1e-8, max rank 64, one cross",
+            "points": len(ref), "seconds": dt, "points_per_s": len(ref) / dt, "status": int(rc),
+            "within_1e-6": int(np.sum(rel <= 1e-6)), "median_rel_err": float(np.median(rel)),
+            "max_rel_err": float(rel.max()),
+            "contraction_gemm": {"kernel": "k_ladder_core", "launches": n_l, "ms": ms,
+                                 "tflops": work / (ms * 1e-3) / 1e12 if ms > 0 else None,
+                                 "frac_fp64_peak": work / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS if ms > 0 else None}}
+
+
 def surrogate_leg(pricer, n_train, tt_rate):
     """Trains the BF16 surrogate ensemble on TT prices (outside any timed region), then times
     its inference on a batch of 65 536 options and reports its gate statistics. Labels: the
@@ -324,6 +363,7 @@ def main():
     ap.add_argument("--book", type=int, default=8192, help="options of the batched book in its leg")
     ap.add_argument("--no-cpu-ttcross", action="store_true", help="skip the CPU TT-cross timing")
     ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's call-on-min experiment")
+    ap.add_argument("--no-ladder", action="store_true", help="skip the market-ladder leg")
     ap.add_argument("--qr", choices=["cholqr", "tsqr", "cholqr2", "cholqr3"], default="cholqr",
                     help="triangular factor of the fibers: shifted Cholesky QR on the matrix cores with passes "
                          "chosen by the rank threshold, Householder TSQR, or two / three Cholesky QR passes")
@@ -440,6 +480,12 @@ def main():
         book = book_leg(pricer, args.book, os.path.join(ROOT, "tests", "golden", "book_slice.json"))
         log(f"bench: book slice {book['options_per_s']:.1f} options/s with Greeks, status {book['status_counts']}")
 
+    ladder = None
+    if not args.no_ladder:
+        ladder = ladder_leg(pricer, grid)
+        log(f"bench: ladder {ladder['points_per_s']:.0f} points/s, {ladder['within_1e-6']}/{ladder['points']} within "
+            f"1e-6, contraction {ladder['contraction_gemm']['tflops']:.1f} TFLOP/s")
+
     paper = None
     if not args.no_paper_table:
         paper = paper_table_leg(pricer)
@@ -484,6 +530,7 @@ def main():
         "plain": plain,
         "literal_config2": literal,
         "book": book,
+        "ladder": ladder,
         "paper_table": paper,
         "surrogate": surrogate,
         "kernel_ms": breakdown,

@@ -177,6 +177,25 @@ int ttfp_batch_diag(ttfp_ctx *ctx, int32_t i, ttfp_diag *diag);
 int ttfp_price_batch_noalloc(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids,
                              double *prices, double *delta, double *vega, int32_t *status);
 
+/* Prices of one option at a ladder of market points that share its volatilities, correlation,
+ * maturity and payoff: point p has spots S0_points[p*d .. p*d+d), strike K_points[p] and rate
+ * r_points[p] (host arrays, n_points >= 1, at most TTFP_MAX_LADDER). One TT-cross builds the
+ * integrand of the base option opt on its grid (the automatic rule of opt, or the given L/alpha),
+ * which every point uses. A point's integrand differs from the base one only through the mean
+ * of w: by exp(-i zeta . dm) with dm = m_w(point) - m_w(base), a product over the coordinates, so
+ * its price is the contraction of the base tensor trains with one weight vector per coordinate
+ * (Sec. IV.A contraction, the quadrature weights times exp(-i zeta_k dm_k)) times
+ * K_p e^{-r_p T} / (K e^{-r T}). For each core the per-point contractions over the nodes form
+ * one dense complex product (points x nodes by nodes x r_{k-1} r_k) on the FP64 matrix cores.
+ * prices[n_points] (host) receives the prices; diag (nullable) the base cross's diagnostics.
+ * Returns the base cross's status (TTFP_OK, TTFP_ENOTCONV, TTFP_EPRECISION: the same warning holds
+ * for every point, whose accuracy is that of the base tensor trains scaled by |exp(alpha . dm)|);
+ * TTFP_EINVAL for an invalid option, point or grid (no prices written). */
+#define TTFP_MAX_LADDER 65536
+int ttfp_price_ladder(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, int32_t n_points,
+                      const double *S0_points, const double *K_points, const double *r_points, double *prices,
+                      ttfp_diag *diag);
+
 /* The integrand of term `term` of an option at npts grid multi-indices idx[npts*d]
  * (host, 0-based), evaluated by the GPU fiber kernel's device function. out[2*npts]
  * receives interleaved real/imaginary parts. */
@@ -244,12 +263,13 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
  * n columns) and triangular transforms (4 m n^2 per pass: X R^{-1} with R^{-1} triangular),
  * basis (4 m r^2), maxvol on its candidate block of K rows (8 K r^2 for the block, 8 (K + r) r
  * per swap for the rank-one updates of the block and of A^{-1}, 8 r^3 per Gauss-Jordan inverse)
- * and the interpolation matrix (8 m r^2); 0 where not counted). */
+ * and the interpolation matrix (8 m r^2), the ladder's per-point node contractions (8 S N r_{k-1} r_k
+ * per core for S points); 0 where not counted). */
 enum {
     TTFP_KERNEL_FIBER = 0, TTFP_KERNEL_TSQR = 1, TTFP_KERNEL_QRCP = 2, TTFP_KERNEL_BASIS = 3,
     TTFP_KERNEL_MAXVOL = 4, TTFP_KERNEL_FINISH = 5, TTFP_KERNEL_CORESUM = 6, TTFP_KERNEL_CONTRACT = 7,
     TTFP_KERNEL_INTERP = 8, TTFP_KERNEL_ERREST = 9, TTFP_KERNEL_GRAM = 10, TTFP_KERNEL_CHOL = 11,
-    TTFP_KERNEL_XFORM = 12, TTFP_KERNEL_COUNT = 13
+    TTFP_KERNEL_XFORM = 12, TTFP_KERNEL_LADDER = 13, TTFP_KERNEL_COUNT = 14
 };
 int ttfp_profile_enable(ttfp_ctx *ctx, int enable);
 int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms, double *work);

@@ -53,13 +53,13 @@ class _Diag(ctypes.Structure):
                 ("maxvol_full_starts", ctypes.c_int64), ("err_est", ctypes.c_double), ("err_samples", ctypes.c_int64)]
 
 
-EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_batch_diag", "ttfp_price_batch_noalloc", "ttfp_eval_integrand",
+EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_batch_diag", "ttfp_price_batch_noalloc", "ttfp_price_ladder", "ttfp_eval_integrand",
            "ttfp_tt_values", "ttfp_tt_export", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
            "ttfp_profile_enable", "ttfp_profile_read", "ttfp_set_tuning", "ttfp_get_tuning", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
            "ttfp_mlp_last_error"]
 KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract", "interp", "err_est",
-           "gram", "chol", "xform"]
+           "gram", "chol", "xform", "ladder"]
 TUNING = {"maxvol_rounds": 0, "tsqr_lds_kb": 1, "graph": 2, "qr": 3}
 
 _lib = None
@@ -82,6 +82,8 @@ def load():
     lib.ttfp_price_batch.argtypes = [vp, ctypes.c_int32, P(_Option), P(_Grid), P(ctypes.c_double),
                                      P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
     lib.ttfp_price_batch_noalloc.argtypes = lib.ttfp_price_batch.argtypes
+    lib.ttfp_price_ladder.argtypes = [vp, P(_Option), P(_Grid), ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double),
+                                      P(ctypes.c_double), P(ctypes.c_double), P(_Diag)]
     lib.ttfp_batch_diag.argtypes = [vp, ctypes.c_int32, P(_Diag)]
     lib.ttfp_eval_integrand.argtypes = [vp, P(_Option), P(_Grid), ctypes.c_int32, ctypes.c_int64,
                                         P(ctypes.c_int32), P(ctypes.c_double)]
@@ -212,6 +214,22 @@ class Pricer:
                                              _ip(ranks), ctypes.byref(diag)))
         n_terms = 1 if (d == 1 or opt.get("payoff") == "call_min_strip") else d
         return out.value, ranks[: n_terms * (d + 1)].reshape(n_terms, d + 1), _diag_dict(diag), rc
+
+    def price_ladder(self, opt, grid, S0_points, K_points, r_points):
+        """Prices of opt at a ladder of market points (spots S0_points [n, d], strikes K_points [n],
+        rates r_points [n]) from one cross of opt (see ttfp_price_ladder). Returns (prices [n],
+        diag dict of the base cross, return code)."""
+        m = _Marshal(opt, grid)
+        d = int(opt["d"])
+        S0p = np.ascontiguousarray(S0_points, np.float64).reshape(-1, d)
+        n = S0p.shape[0]
+        Kp = np.ascontiguousarray(K_points, np.float64).reshape(n)
+        rp = np.ascontiguousarray(r_points, np.float64).reshape(n)
+        out = np.zeros(n)
+        diag = _Diag()
+        rc = self._check(self.lib.ttfp_price_ladder(self.ctx, ctypes.byref(m.opt), ctypes.byref(m.grid), n, _dp(S0p),
+                                                    _dp(Kp), _dp(rp), _dp(out), ctypes.byref(diag)))
+        return out, _diag_dict(diag), rc
 
     def batch_diag(self, i):
         """Diagnostics dict of option i of the last price_batch call."""

@@ -35,6 +35,9 @@ __global__ void k_core_moments(Item *items, const int *active);
 __global__ void k_moments(Item *items, const int *active, cplx *out, int stride);
 __global__ void k_tt_values(const Item *items, int item, long long npts, const int *idx, cplx *out);
 __global__ void k_err_est(Item *items, const int *active);
+__global__ void k_ladder_weights(const Item *items, int item, int k, int S, const double *dm, cplx *W);
+__global__ void k_ladder_core(const Item *items, int item, int k, int S, const cplx *W, cplx *T);
+__global__ void k_ladder_chain(const Item *items, int item, int k, int S, const cplx *T, cplx *V);
 __global__ void k_converge(const Item *items, int *active, OptState *os, int n_opts, const double *item_scale, int *flags);
 }  // namespace ttfp
 
@@ -83,6 +86,7 @@ namespace {
 const size_t ALIGN = 256;
 constexpr int GRAM_ROWS_HOST = 1024;         // fiber rows per Gram workgroup (k_gram)
 constexpr int XF_WAVES_HOST = 12;            // 16-row panels per triangular-transform workgroup (k_xform)
+constexpr int LAD_WAVES_HOST = 4;            // 16-point panels per ladder workgroup (k_ladder_core)
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 #define HIPCHK(expr)                                                                     \
@@ -1102,6 +1106,102 @@ int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
 {
     if (!ctx) return TTFP_EINVAL;
     return price_batch_impl(ctx, n, opts, grids, prices, delta, vega, status);
+}
+
+int ttfp_price_ladder(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, int32_t n_points,
+                      const double *S0_points, const double *K_points, const double *r_points, double *prices,
+                      ttfp_diag *diag)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (!opt || !grid || !prices || !S0_points || !K_points || !r_points || n_points < 1 || n_points > TTFP_MAX_LADDER) {
+        ctx->last_error = "ttfp_price_ladder: null pointer or n_points outside [1, TTFP_MAX_LADDER]";
+        return TTFP_EINVAL;
+    }
+    cplx *dW = nullptr, *dT = nullptr, *dV = nullptr;
+    double *ddm = nullptr;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        OptionPlan P;
+        std::string err;
+        int rc = check_cross_settings(grid, err);
+        if (!rc) rc = build_plan(opt, grid, P, err);
+        if (rc) { ctx->last_error = err; return rc; }
+        const int d = P.d, S = n_points, nt = (int)P.terms.size();
+        // every point: a valid option with the base's volatilities, correlation, maturity, payoff;
+        // its shift of the mean of w per term, and its scale relative to the base's
+        std::vector<double> dm((size_t)nt * S * d), ratio(S);
+        for (int p = 0; p < S; ++p) {
+            ttfp_option o = *opt;
+            o.S0 = S0_points + (size_t)p * d;
+            o.K = K_points[p];
+            o.r = r_points[p];
+            OptionPlan Pp;
+            rc = build_plan(&o, grid, Pp, err);
+            if (rc) { ctx->last_error = "ladder point " + std::to_string(p) + ": " + err; return rc; }
+            for (int t = 0; t < nt; ++t)
+                for (int k = 0; k < d; ++k) dm[((size_t)t * S + p) * d + k] = Pp.terms[t].m[k] - P.terms[t].m[k];
+            ratio[p] = o.K * std::exp(-o.r * o.T) / (opt->K * std::exp(-opt->r * opt->T));
+        }
+        // the base cross
+        std::vector<const OptionPlan *> cp{&P};
+        std::vector<const ttfp_grid *> cg{grid};
+        Batch b;
+        rc = build_items(ctx, cp, cg, b);
+        if (rc) return rc;
+        std::vector<OptResult> res;
+        int mstride = 0;
+        rc = run_batch(ctx, b, cg, res, false, nullptr, mstride);
+        if (rc) return rc;
+        const OptResult &r = res[0];
+        // the per-point contractions, term by term and core by core
+        int Rmax = 1;
+        for (const Item &it : b.items) Rmax = std::max(Rmax, it.R);
+        HIPCHK(hipMalloc(&ddm, sizeof(double) * dm.size()));
+        HIPCHK(hipMalloc(&dW, sizeof(cplx) * (size_t)S * grid->N));
+        HIPCHK(hipMalloc(&dT, sizeof(cplx) * (size_t)S * Rmax * Rmax));
+        HIPCHK(hipMalloc(&dV, sizeof(cplx) * (size_t)S * Rmax));
+        HIPCHK(hipMemcpyAsync(ddm, dm.data(), sizeof(double) * dm.size(), hipMemcpyHostToDevice, ctx->stream));
+        std::vector<double> acc(S, 0.0);
+        std::vector<cplx> Pt(S);
+        for (int t = 0; t < nt; ++t) {
+            const Item &it = b.items[t];
+            for (int k = 0; k < d; ++k) {
+                hipLaunchKernelGGL(k_ladder_weights, dim3(cdivu((long long)S * it.N, 256)), dim3(256), 0, ctx->stream,
+                                   ctx->d_items, t, k, S, ddm + (size_t)t * S * d, dW);
+                {
+                    ProfScope ps(ctx, TTFP_KERNEL_LADDER);
+                    hipLaunchKernelGGL(k_ladder_core, dim3(cdivu(S, 16 * LAD_WAVES_HOST), std::max(it.crow[k], 1)),
+                                       dim3(64 * LAD_WAVES_HOST), 0, ctx->stream, ctx->d_items, t, k, S, dW, dT);
+                    if (ctx->prof) ctx->prof_work[TTFP_KERNEL_LADDER] += 8.0 * S * (double)it.N * it.crow[k] * it.ccol[k];
+                }
+                hipLaunchKernelGGL(k_ladder_chain, dim3(S), dim3(64), 0, ctx->stream, ctx->d_items, t, k, S, dT, dV);
+            }
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpy2DAsync(Pt.data(), sizeof(cplx), dV, sizeof(cplx) * it.R, sizeof(cplx), S,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            for (int p = 0; p < S; ++p) acc[p] += b.item_scale[t] * ratio[p] * Pt[p].x;
+        }
+        (void)hipFree(ddm);
+        (void)hipFree(dW);
+        (void)hipFree(dT);
+        (void)hipFree(dV);
+        ddm = nullptr;
+        dW = dT = dV = nullptr;
+        for (int p = 0; p < S; ++p) prices[p] = acc[p];
+        if (diag) fill_diag(r, diag);
+        ctx->last_items = b.items;
+        ctx->last_n_items = (int)b.items.size();
+        if (ctx->prof) prof_collect(ctx);
+        return r.code;
+    } catch (const std::exception &e) {
+        if (ddm) (void)hipFree(ddm);
+        if (dW) (void)hipFree(dW);
+        if (dT) (void)hipFree(dT);
+        if (dV) (void)hipFree(dV);
+        ctx->last_error = e.what();
+        return TTFP_EDEVICE;
+    }
 }
 
 int ttfp_batch_diag(ttfp_ctx *ctx, int32_t i, ttfp_diag *diag)

@@ -2141,6 +2141,93 @@ __global__ __launch_bounds__(64) void k_contract(Item *items, const int *active)
     }
 }
 
+// ------------------------------------------------------------------ ladders: one cross, many market points
+// W[s][i] = exp(-i z_k(i) dm[s][k]) for core k of the item, z_k(i) = u_k(i) + i alpha_k: the factor
+// by which point s's integrand differs from the base option's along coordinate k (the mean of w
+// shifted by dm[s]).
+__global__ __launch_bounds__(256) void k_ladder_weights(const Item *items, int item, int k, int S, const double *dm,
+                                                        cplx *W)
+{
+    const Item &it = items[item];
+    const int N = it.N;
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)S * N) return;
+    const int s = (int)(e / N), i = (int)(e % N);
+    const double L = it.L[k];
+    const double x = -L + (i + 0.5) * 2.0 * L / N, y = it.alpha[k];
+    const double dmv = dm[(size_t)s * it.d + k];
+    W[e] = cexp_({y * dmv, -x * dmv});           // -i (x + i y) dm
+}
+
+// T[s][a][b] = sum_i W[s][i] G_k[a][i][b]: for each left index a, a points x nodes by nodes x r_k
+// product on the FP64 matrix cores (v_mfma_f64_16x16x4f64, lane layout as in k_interp: A-operand
+// lane (row l % 16, k l / 16), B-operand lane (k l / 16, column l % 16), accumulator rows
+// l / 16 + 4 v). A wave forms 16 points x all r_k columns (up to four 16 x 16 tiles), the complex
+// product by three real ones (Gauss). T rows have stride R (T[(s R + a) R + b]).
+constexpr int LAD_WAVES = 4;
+__global__ __launch_bounds__(64 * LAD_WAVES) void k_ladder_core(const Item *items, int item, int k, int S,
+                                                               const cplx *W, cplx *T)
+{
+    const Item &it = items[item];
+    const int N = it.N, R = it.R, a_n = it.crow[k], b_n = it.ccol[k];
+    const int a = blockIdx.y;
+    if (a >= a_n) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int s0 = (blockIdx.x * LAD_WAVES + wave) * 16;
+    if (s0 >= S) return;
+    const cplx *G = it.cores + (size_t)k * R * N * R + (size_t)a * N * b_n;   // G[i][b] at i b_n + b
+    const int ntile = (b_n + 15) / 16;
+    double4_t prr[4], pii[4], pss[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        pii[q] = prr[q];
+        pss[q] = prr[q];
+    }
+    const int srow = s0 + li;
+    for (int i0 = 0; i0 < N; i0 += 4) {
+        const int i = i0 + lk;
+        const cplx w = (srow < S && i < N) ? W[(size_t)srow * N + i] : cplx{0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= ntile) break;
+            const int col = 16 * q + li;
+            const cplx g = (i < N && col < b_n) ? G[(size_t)i * b_n + col] : cplx{0.0, 0.0};
+            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(w.x, g.x, prr[q], 0, 0, 0);
+            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(w.y, g.y, pii[q], 0, 0, 0);
+            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(w.x + w.y, g.x + g.y, pss[q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = s0 + lk + 4 * v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= ntile) break;
+            const int col = 16 * q + li;
+            if (row < S && col < b_n)
+                T[((size_t)row * R + a) * R + col] = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
+        }
+    }
+}
+
+// V[s] <- V[s] T[s] (row vector times r_{k-1} x r_k), one workgroup per point; the chain starts
+// from the row vector (1) at the first core.
+__global__ __launch_bounds__(64) void k_ladder_chain(const Item *items, int item, int k, int S, const cplx *T, cplx *V)
+{
+    __shared__ cplx v[TTFP_MAX_RANK];
+    const Item &it = items[item];
+    const int R = it.R, a_n = it.crow[k], b_n = it.ccol[k], s = blockIdx.x;
+    if (s >= S) return;
+    for (int a = threadIdx.x; a < a_n; a += blockDim.x) v[a] = k == 0 ? cplx{a == 0 ? 1.0 : 0.0, 0.0} : V[(size_t)s * R + a];
+    __syncthreads();
+    for (int b = threadIdx.x; b < b_n; b += blockDim.x) {
+        cplx acc = {0.0, 0.0};
+        for (int a = 0; a < a_n; ++a) acc = cadd(acc, cmul(v[a], T[((size_t)s * R + a) * R + b]));
+        V[(size_t)s * R + b] = acc;
+    }
+}
+
 // ------------------------------------------------------------------ convergence test on the device
 // After a half sweep: each option's price is the scaled sum of its items' contractions; its
 // relative change against the previous half sweep decides whether it stays active (the rule

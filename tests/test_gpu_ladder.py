@@ -1,0 +1,77 @@
+"""Ladders of market points from one cross (ttfp_price_ladder): each point's price against the
+oracle's dense grid sum for that point's option on the base option's grid (the same grid is
+handed to both sides), plus the base point and the error path."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fourier as F
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pricer():
+    import paper_2203_02804_amd as ttfp
+    p = ttfp.Pricer(0)
+    yield p
+    p.close()
+
+
+def _points(opt, n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = opt["d"]
+    S0 = np.asarray(opt["S0"])[None, :] * rng.uniform(0.85, 1.15, (n, d))
+    K = rng.uniform(85.0, 115.0, n)
+    r = rng.uniform(0.0, 0.06, n)
+    return S0, K, r
+
+
+def _check(pricer, opt, N, tol, R, n, seed, bound):
+    grids = np.array(F.term_grids(opt, N, tol=tol)[1])     # the oracle's grid for the base option
+    g = dict(W.grid(N, tol=tol, max_rank=R, max_sweeps=8), L=grids[:, 0], alpha=grids[:, 1])
+    S0, K, r = _points(opt, n, seed)
+    prices, info, rc = pricer.price_ladder(opt, g, S0, K, r)
+    assert rc == 0, info
+    worst = 0.0
+    for p in range(n):
+        o = dict(opt, S0=S0[p].tolist(), K=float(K[p]), r=float(r[p]))
+        ref = F.dense_price(o, N, grids[:, 0], grids[:, 1])
+        worst = max(worst, abs(prices[p] / ref - 1))
+    print(f"ladder d={opt['d']} {opt['payoff']} N={N}: {n} points, worst rel {worst:.2e}", flush=True)
+    assert worst <= bound
+
+
+def test_two_assets_call_on_max(pricer):
+    opt, _ = W.config1()
+    _check(pricer, opt, 96, 1e-11, 40, 40, 1, 1e-8)
+
+
+def test_three_assets_put_on_max(pricer):
+    opt = W.random_small_options(1, seed=41, d_choices=(3,), payoffs=("put_max",))[0]
+    _check(pricer, opt, 48, 1e-11, 40, 24, 2, 1e-8)
+
+
+def test_paper_experiment_strike_ladder(pricer):
+    # the single-strip call on the minimum in asset coordinates (one term): a strike ladder
+    opt, g = W.paper_experiment(3)
+    K = np.linspace(90.0, 110.0, 21)
+    S0 = np.tile(np.asarray(opt["S0"]), (len(K), 1))
+    r = np.full(len(K), opt["r"])
+    prices, info, rc = pricer.price_ladder(opt, g, S0, K, r)
+    assert rc == 0
+    worst = max(abs(prices[p] / F.dense_price(dict(opt, K=float(K[p])), g["N"], g["L"], g["alpha"]) - 1)
+                for p in range(len(K)))
+    print(f"paper strike ladder d=3: worst rel {worst:.2e}", flush=True)
+    assert worst <= 1e-8
+
+
+def test_base_point_and_errors(pricer):
+    import paper_2203_02804_amd as ttfp
+    opt, _ = W.config1()
+    g = W.grid(64, tol=1e-10, max_rank=24)
+    p0, _, _, rc0 = pricer.price(opt, g)
+    prices, _, rc = pricer.price_ladder(opt, g, [opt["S0"]], [opt["K"]], [opt["r"]])
+    assert rc == rc0 and abs(prices[0] / p0 - 1) < 1e-12
+    with pytest.raises(ttfp.TTFPError):
+        pricer.price_ladder(opt, g, [opt["S0"]], [-1.0], [opt["r"]])

@@ -196,3 +196,13 @@ def paper_experiment(d, beta=0.5, tol=1e-10, max_rank=64, max_sweeps=8, seed=0, 
     opt = option(d, [100.0] * d, 100.0, 1.0, 0.3, [0.5] * d, sigma_beta(d, beta), "call_min_strip")
     eta = PAPER_TABLE_ETA.get(d, 0.2) if eta is None else eta
     return opt, grid(N, L=N * eta / 2, alpha=5.0 / d, tol=tol, max_rank=max_rank, max_sweeps=max_sweeps, seed=seed)
+
+
+# --- market ladders: one option's volatilities, correlation and maturity at many (S0, K, r) -----
+def ladder_points(opt, n, seed=7, spot=(0.85, 1.15), strike=(85.0, 115.0), rate=(0.0, 0.06)):
+    """n market points around opt: spots scaled per asset by U[spot], strikes U[strike], rates
+    U[rate]. Returns (S0 [n, d], K [n], r [n]) as numpy arrays."""
+    rng = _rng(seed)
+    d = opt["d"]
+    S0 = np.asarray(opt["S0"])[None, :] * rng.uniform(spot[0], spot[1], (n, d))
+    return S0, rng.uniform(strike[0], strike[1], n), rng.uniform(rate[0], rate[1], n)
