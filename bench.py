@@ -162,10 +162,22 @@ def paper_table_leg(pricer):
         p, ranks, info, rc = pricer.price(opt, g)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        rows.append({"d": d, "eta": 2 * g["L"] / g["N"], "seconds": dt, "status": int(rc), "max_rank": int(ranks.max()),
-                     "sweeps": info["sweeps"], "n_evals": info["n_evals"], "r_comp": info["n_evals"] / float(g["N"]) ** d,
-                     "rel_err_vs_exact": p / c["one_factor"] - 1,
-                     "eps_trunc_vs_grid_sum": (p / c["dense"] - 1) if "dense" in c else None})
+        row = {"d": d, "eta": 2 * g["L"] / g["N"], "seconds": dt, "status": int(rc), "max_rank": int(ranks.max()),
+               "sweeps": info["sweeps"], "n_evals": info["n_evals"], "r_comp": info["n_evals"] / float(g["N"]) ** d,
+               "rel_err_vs_exact": p / c["one_factor"] - 1,
+               "eps_trunc_vs_grid_sum": (p / c["dense"] - 1) if "dense" in c else None}
+        # the paper's own two-train form: caps D_phi = D_v = 40
+        opt2, g2 = W.paper_experiment(d, max_rank=40)
+        pricer.price_two_trains(opt2, g2, payoff_rank=40)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p2, rcf, rpay, info2, rc2 = pricer.price_two_trains(opt2, g2, payoff_rank=40)
+        torch.cuda.synchronize()
+        row["two_trains"] = {"seconds": time.perf_counter() - t0, "status": int(rc2), "D_phi": int(rcf.max()),
+                             "D_v": int(rpay.max()), "n_evals": info2["n_evals"],
+                             "r_comp": info2["n_evals"] / float(g2["N"]) ** d, "rel_err_vs_exact": p2 / c["one_factor"] - 1,
+                             "eps_trunc_vs_grid_sum": (p2 / c["dense"] - 1) if "dense" in c else None}
+        rows.append(row)
     bond = {}
     for c in gold["bond"]:
         errs = {}
@@ -177,9 +189,22 @@ def paper_table_leg(pricer):
                 e.append(abs(p / c["dense"] - 1))
             errs[str(R)] = float(np.mean(e))
         bond[str(c["beta"])] = errs
+    # the bond-dimension study in the two-train form (D_v = 30, cap D_phi swept)
+    bond2 = {}
+    for c in gold["bond"]:
+        errs = {}
+        for D in (2, 4, 8, 12, 16):
+            e = []
+            for seed in range(4):
+                opt, g = W.paper_experiment(3, c["beta"], max_rank=D, seed=seed)
+                p, _, _, _, _ = pricer.price_two_trains(opt, g, payoff_rank=30)
+                e.append(abs(p / c["dense"] - 1))
+            errs[str(D)] = float(np.mean(e))
+        bond2[str(c["beta"])] = errs
     return {"workload": "call on the min, Sigma(0.5), r=0.3, sigma=0.5, T=1, S0=K=100, N=50, alpha=5/d, tol 1e-10, "
                         "rank cap 64, single strip", "table": rows,
-            "bond_dimension_d3": {"mean_rel_err_vs_grid_sum_by_rank_cap": bond, "seeds": 4}}
+            "bond_dimension_d3": {"mean_rel_err_vs_grid_sum_by_rank_cap": bond, "seeds": 4,
+                                  "two_trains_mean_rel_err_by_D_phi_with_D_v_30": bond2}}
 
 
 LADDER_GOLDEN = os.path.join(ROOT, "tests", "golden", "ladder.json")

@@ -177,6 +177,20 @@ int ttfp_batch_diag(ttfp_ctx *ctx, int32_t i, ttfp_diag *diag);
 int ttfp_price_batch_noalloc(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const ttfp_grid *grids,
                              double *prices, double *delta, double *vega, int32_t *status);
 
+/* The two-train variant of Sec. IV (Eq. braket): each term's integrand is the product of the
+ * characteristic function of w and the payoff transform; instead of one cross of the product, one
+ * cross approximates the characteristic function (rank cap grid->max_rank, the paper's D_phi) and
+ * another the payoff transform (rank cap payoff_rank, the paper's D_v; 0 = grid->max_rank), on the
+ * same grid, and the price is their exact inner product (no conjugation) computed in tensor-train
+ * form, scaled and summed over the terms. In exact arithmetic this is the grid sum of Eq. discr.
+ * ranks_cf / ranks_payoff (nullable) receive n_terms*(d+1) bond ranks of each kind of train.
+ * Status: TTFP_OK when both crosses met the tolerance without a rank cap (each by the relative
+ * change of its own grid sum), else TTFP_ENOTCONV; TTFP_EPRECISION when the product's
+ * cancellation factor kappa times the FP64 unit roundoff exceeds tol. diag (nullable): kappa of
+ * the product, err_est the larger of the two trains' sampled errors, evaluations of both. */
+int ttfp_price_two_trains(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, int32_t payoff_rank,
+                          double *price, int32_t *ranks_cf, int32_t *ranks_payoff, ttfp_diag *diag);
+
 /* Prices of one option at a ladder of market points that share its volatilities, correlation,
  * maturity and payoff: point p has spots S0_points[p*d .. p*d+d), strike K_points[p] and rate
  * r_points[p] (host arrays, n_points >= 1, at most TTFP_MAX_LADDER). One TT-cross builds the

@@ -53,7 +53,7 @@ class _Diag(ctypes.Structure):
                 ("maxvol_full_starts", ctypes.c_int64), ("err_est", ctypes.c_double), ("err_samples", ctypes.c_int64)]
 
 
-EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_batch_diag", "ttfp_price_batch_noalloc", "ttfp_price_ladder", "ttfp_eval_integrand",
+EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price_batch", "ttfp_batch_diag", "ttfp_price_batch_noalloc", "ttfp_price_ladder", "ttfp_price_two_trains", "ttfp_eval_integrand",
            "ttfp_tt_values", "ttfp_tt_export", "ttfp_qr_r", "ttfp_maxvol", "ttfp_strerror", "ttfp_last_error",
            "ttfp_profile_enable", "ttfp_profile_read", "ttfp_set_tuning", "ttfp_get_tuning", "ttfp_mlp_create", "ttfp_mlp_destroy", "ttfp_mlp_n_params",
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
@@ -82,6 +82,8 @@ def load():
     lib.ttfp_price_batch.argtypes = [vp, ctypes.c_int32, P(_Option), P(_Grid), P(ctypes.c_double),
                                      P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
     lib.ttfp_price_batch_noalloc.argtypes = lib.ttfp_price_batch.argtypes
+    lib.ttfp_price_two_trains.argtypes = [vp, P(_Option), P(_Grid), ctypes.c_int32, P(ctypes.c_double),
+                                          P(ctypes.c_int32), P(ctypes.c_int32), P(_Diag)]
     lib.ttfp_price_ladder.argtypes = [vp, P(_Option), P(_Grid), ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double),
                                       P(ctypes.c_double), P(ctypes.c_double), P(_Diag)]
     lib.ttfp_batch_diag.argtypes = [vp, ctypes.c_int32, P(_Diag)]
@@ -214,6 +216,23 @@ class Pricer:
                                              _ip(ranks), ctypes.byref(diag)))
         n_terms = 1 if (d == 1 or opt.get("payoff") == "call_min_strip") else d
         return out.value, ranks[: n_terms * (d + 1)].reshape(n_terms, d + 1), _diag_dict(diag), rc
+
+    def price_two_trains(self, opt, grid, payoff_rank=0):
+        """The two-train variant (ttfp_price_two_trains): returns (price, ranks of the
+        characteristic-function trains [n_terms, d+1], ranks of the payoff trains, diag, code)."""
+        m = _Marshal(opt, grid)
+        d = int(opt["d"])
+        out = ctypes.c_double(0.0)
+        rcf = np.zeros(d * (d + 1), np.int32)
+        rpy = np.zeros(d * (d + 1), np.int32)
+        diag = _Diag()
+        rc = self._check(self.lib.ttfp_price_two_trains(self.ctx, ctypes.byref(m.opt), ctypes.byref(m.grid),
+                                                        int(payoff_rank), ctypes.byref(out), _ip(rcf), _ip(rpy),
+                                                        ctypes.byref(diag)))
+        n_terms = 1 if (d == 1 or opt.get("payoff") == "call_min_strip") else d
+        shape = (n_terms, d + 1)
+        return out.value, rcf[: n_terms * (d + 1)].reshape(shape), rpy[: n_terms * (d + 1)].reshape(shape), \
+            _diag_dict(diag), rc
 
     def price_ladder(self, opt, grid, S0_points, K_points, r_points):
         """Prices of opt at a ladder of market points (spots S0_points [n, d], strikes K_points [n],

@@ -36,6 +36,8 @@ __global__ void k_moments(Item *items, const int *active, cplx *out, int stride)
 __global__ void k_tt_values(const Item *items, int item, long long npts, const int *idx, cplx *out);
 __global__ void k_err_est(Item *items, const int *active);
 __global__ void k_ladder_weights(const Item *items, int item, int k, int S, const double *dm, cplx *W);
+__global__ void k_inner_x(const Item *items, int ia, int ib, int k, const cplx *E, cplx *X);
+__global__ void k_inner_e(const Item *items, int ia, int ib, int k, const cplx *X, cplx *E);
 __global__ void k_ladder_core(const Item *items, int item, int k, int S, const cplx *W, cplx *T);
 __global__ void k_ladder_chain(const Item *items, int item, int k, int S, const cplx *T, cplx *V);
 __global__ void k_converge(const Item *items, int *active, OptState *os, int n_opts, const double *item_scale, int *flags);
@@ -87,6 +89,7 @@ const size_t ALIGN = 256;
 constexpr int GRAM_ROWS_HOST = 1024;         // fiber rows per Gram workgroup (k_gram)
 constexpr int XF_WAVES_HOST = 12;            // 16-row panels per triangular-transform workgroup (k_xform)
 constexpr int LAD_WAVES_HOST = 4;            // 16-point panels per ladder workgroup (k_ladder_core)
+constexpr int INNER_RE_HOST = TTFP_MAX_RANK; // row stride of the inner-product environment (k_inner_*)
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 #define HIPCHK(expr)                                                                     \
@@ -1106,6 +1109,108 @@ int ttfp_price_batch(ttfp_ctx *ctx, int32_t n, const ttfp_option *opts, const tt
 {
     if (!ctx) return TTFP_EINVAL;
     return price_batch_impl(ctx, n, opts, grids, prices, delta, vega, status);
+}
+
+int ttfp_price_two_trains(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, int32_t payoff_rank, double *price,
+                          int32_t *ranks_cf, int32_t *ranks_payoff, ttfp_diag *diag)
+{
+    if (!ctx) return TTFP_EINVAL;
+    if (!opt || !grid || !price || payoff_rank < 0 || payoff_rank > TTFP_MAX_RANK) {
+        ctx->last_error = "ttfp_price_two_trains: null pointer or payoff_rank outside [0, TTFP_MAX_RANK]";
+        return TTFP_EINVAL;
+    }
+    cplx *dE = nullptr, *dX = nullptr;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        OptionPlan P;
+        std::string err;
+        int rc = check_cross_settings(grid, err);
+        if (!rc) rc = build_plan(opt, grid, P, err);
+        if (rc) { ctx->last_error = err; return rc; }
+        ttfp_grid gpay = *grid;
+        if (payoff_rank > 0) gpay.max_rank = payoff_rank;
+        rc = check_cross_settings(&gpay, err);
+        if (rc) { ctx->last_error = err; return rc; }
+        // the characteristic-function trains (no payoff factors) and the payoff trains (the
+        // Gaussian exponent set to zero), on the same per-term grids
+        OptionPlan Pcf = P, Ppay = P;
+        for (TermPlan &tp : Pcf.terms) tp.kind.assign(P.d, KIND_ONE);
+        for (TermPlan &tp : Ppay.terms) {
+            std::fill(tp.m.begin(), tp.m.end(), 0.0);
+            std::fill(tp.C.begin(), tp.C.end(), 0.0);
+        }
+        std::vector<const OptionPlan *> cp{&Pcf, &Ppay};
+        std::vector<const ttfp_grid *> cg{grid, &gpay};
+        Batch b;
+        rc = build_items(ctx, cp, cg, b);
+        if (rc) return rc;
+        std::vector<OptResult> res;
+        int mstride = 0;
+        rc = run_batch(ctx, b, cg, res, false, nullptr, mstride);
+        if (rc) return rc;
+        const int nt = (int)P.terms.size(), d = P.d;
+        HIPCHK(hipMalloc(&dE, sizeof(cplx) * INNER_RE_HOST * INNER_RE_HOST));
+        HIPCHK(hipMalloc(&dX, sizeof(cplx) * (size_t)grid->max_rank * grid->N * gpay.max_rank));
+        double total = 0.0, imag = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            const Item &A = b.items[t], &B = b.items[nt + t];
+            for (int k = 0; k < d; ++k) {
+                const long long nx = (long long)A.crow[k] * A.N * B.ccol[k];
+                hipLaunchKernelGGL(k_inner_x, dim3(cdivu(nx, 256)), dim3(256), 0, ctx->stream, ctx->d_items, t, nt + t, k, dE, dX);
+                hipLaunchKernelGGL(k_inner_e, dim3(cdivu((long long)B.ccol[k] * A.ccol[k], 256)), dim3(256), 0, ctx->stream,
+                                   ctx->d_items, t, nt + t, k, dX, dE);
+            }
+            HIPCHK(hipGetLastError());
+            cplx v;
+            HIPCHK(hipMemcpyAsync(&v, dE, sizeof(cplx), hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            total += P.terms[t].scale * v.x;
+            imag += P.terms[t].scale * v.y;
+        }
+        (void)hipFree(dE);
+        (void)hipFree(dX);
+        dE = dX = nullptr;
+        *price = total;
+        // status: both crosses converged without a rank cap, and the product's cancellation allows
+        // the tolerance
+        OptResult r = res[0];
+        const OptResult &q = res[1];
+        r.price = total;
+        r.imag = imag;
+        r.converged = r.converged && q.converged;
+        r.capped = r.capped || q.capped;
+        r.sweeps = std::max(r.sweeps, q.sweeps);
+        r.evals += q.evals;
+        r.swaps += q.swaps;
+        r.full_starts += q.full_starts;
+        r.singular = r.singular || q.singular;
+        r.err_est = std::isnan(r.err_est) ? q.err_est : (std::isnan(q.err_est) ? r.err_est : std::max(r.err_est, q.err_est));
+        r.err_samples += q.err_samples;
+        double mass = 0.0;
+        for (const TermPlan &tp : P.terms) mass += tp.absmass;
+        r.kappa = mass / std::max(std::fabs(total), 1e-300);
+        r.code = (r.converged && !r.capped) ? TTFP_OK : TTFP_ENOTCONV;
+        if (r.kappa * 2.220446049250313e-16 > grid->tol || r.singular || !std::isfinite(total)) r.code = TTFP_EPRECISION;
+        for (int t = 0; t < nt; ++t) {
+            for (int w = 0; w < 2; ++w) {
+                int32_t *rk = w == 0 ? ranks_cf : ranks_payoff;
+                if (!rk) continue;
+                const Item &it = b.items[w * nt + t];
+                rk += (size_t)t * (d + 1);
+                rk[0] = 1;
+                for (int k = 0; k < d; ++k) rk[k + 1] = it.ccol[k];
+            }
+        }
+        if (diag) fill_diag(r, diag);
+        ctx->last_items = b.items;
+        ctx->last_n_items = (int)b.items.size();
+        return r.code;
+    } catch (const std::exception &e) {
+        if (dE) (void)hipFree(dE);
+        if (dX) (void)hipFree(dX);
+        ctx->last_error = e.what();
+        return TTFP_EDEVICE;
+    }
 }
 
 int ttfp_price_ladder(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *grid, int32_t n_points,

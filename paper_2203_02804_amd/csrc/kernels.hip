@@ -293,6 +293,7 @@ __device__ __forceinline__ int rand_index(uint64_t seed, uint64_t a, uint64_t b,
 // joint factor (-1)^(d+1) / (1 + i sum_k z_k) (strip_joint).
 __device__ __forceinline__ cplx factor(int kind, cplx z)
 {
+    if (kind == 4) return {1.0, 0.0};             // no payoff factor
     cplx iz = {-z.y, z.x};
     if (kind == 0) return cdiv({1.0, 0.0}, cmul(iz, {1.0 + iz.x, iz.y}));
     cplx v = cdiv({1.0, 0.0}, iz);
@@ -2226,6 +2227,44 @@ __global__ __launch_bounds__(64) void k_ladder_chain(const Item *items, int item
         for (int a = 0; a < a_n; ++a) acc = cadd(acc, cmul(v[a], T[((size_t)s * R + a) * R + b]));
         V[(size_t)s * R + b] = acc;
     }
+}
+
+// ------------------------------------------------------------------ inner product of two tensor trains
+// <B|A> = sum_i B(i) A(i) (no conjugation: the integrand is the product of the two functions),
+// core by core with the environment E[a1][a2] (a1: B's left index, a2: A's):
+//   X[a2][i][b1] = sum_a1 E[a1][a2] B_k[a1][i][b1]          (k_inner_x, one thread per entry)
+//   E'[b1][b2]   = sum_{a2, i} X[a2][i][b1] A_k[a2][i][b2]   (k_inner_e, one thread per entry)
+// E starts as the 1 x 1 matrix (1); after the last core E[0][0] is the inner product. Cores are laid
+// out a x N x b (entry (a N + i) b_n + b of the item's slot k); E has row stride RE.
+constexpr int INNER_RE = TTFP_MAX_RANK;
+__global__ __launch_bounds__(256) void k_inner_x(const Item *items, int ia, int ib, int k, const cplx *E, cplx *X)
+{
+    const Item &A = items[ia], &B = items[ib];
+    const int N = A.N, a1n = B.crow[k], b1n = B.ccol[k], a2n = A.crow[k];
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)a2n * N * b1n) return;
+    const int a2 = (int)(e / ((long long)N * b1n)), rem = (int)(e % ((long long)N * b1n)), i = rem / b1n, b1 = rem % b1n;
+    const cplx *Bk = B.cores + (size_t)k * B.R * N * B.R;
+    cplx acc = {0.0, 0.0};
+    for (int a1 = 0; a1 < a1n; ++a1) {
+        const cplx ev = k == 0 ? cplx{1.0, 0.0} : E[a1 * INNER_RE + a2];
+        acc = cadd(acc, cmul(ev, Bk[((size_t)a1 * N + i) * b1n + b1]));
+    }
+    X[e] = acc;
+}
+__global__ __launch_bounds__(256) void k_inner_e(const Item *items, int ia, int ib, int k, const cplx *X, cplx *E)
+{
+    const Item &A = items[ia], &B = items[ib];
+    const int N = A.N, b1n = B.ccol[k], a2n = A.crow[k], b2n = A.ccol[k];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= b1n * b2n) return;
+    const int b1 = e / b2n, b2 = e % b2n;
+    const cplx *Ak = A.cores + (size_t)k * A.R * N * A.R;
+    cplx acc = {0.0, 0.0};
+    for (int a2 = 0; a2 < a2n; ++a2)
+        for (int i = 0; i < N; ++i)
+            acc = cadd(acc, cmul(X[((size_t)a2 * N + i) * b1n + b1], Ak[((size_t)a2 * N + i) * b2n + b2]));
+    E[b1 * INNER_RE + b2] = acc;
 }
 
 // ------------------------------------------------------------------ convergence test on the device

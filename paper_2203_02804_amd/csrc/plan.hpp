@@ -8,8 +8,9 @@
 namespace ttfp {
 
 // KIND_STRIP: coordinate of the single-strip call on the minimum (factor 1/(i z_k), times the
-// joint factor (-1)^(d+1) / (1 + i sum_k z_k) that every coordinate of that term shares)
-enum FactorKind { KIND_CALL = 0, KIND_LT = 1, KIND_GT = 2, KIND_STRIP = 3 };
+// joint factor (-1)^(d+1) / (1 + i sum_k z_k) that every coordinate of that term shares);
+// KIND_ONE: no payoff factor (the characteristic function's own train in the two-train variant)
+enum FactorKind { KIND_CALL = 0, KIND_LT = 1, KIND_GT = 2, KIND_STRIP = 3, KIND_ONE = 4 };
 
 // One separable term of an option: the Gaussian of w = P x and one payoff factor per
 // coordinate, on the grid u_k(i) = -L_k + (i + 1/2) 2 L_k / N shifted by i alpha_k.
