@@ -125,6 +125,49 @@ def discounted_expected_max2(S1, S2, T, s1, s2, rho):
     return S2 + margrabe_exchange(S1, S2, T, s1, s2, rho)
 
 
+# ------------------------------------------------------------------ Merton jumps: series over the jump count
+
+def merton_series(S0, K, T, r, sigma, corr, lam, muJ, CJ, payoff="call_max", n_max=None):
+    """Price under Merton's jump diffusion (the extension of Sec. VI) with log-jump sizes
+    N(muJ, CJ) arriving at rate lam (one Poisson clock for all assets), d = 1 or 2, by
+    conditioning on the number n of jumps: given n, ln(S_T) is Gaussian with mean
+    ln S0 + (r - sigma^2/2 - lam kappa) T + n muJ and covariance T diag(sigma) corr diag(sigma)
+    + n CJ (kappa_j = exp(muJ_j + CJ_jj / 2) - 1), which is a GBM with adjusted spots, volatilities
+    and correlation: priced by Black-Scholes (d = 1) or Stulz (d = 2), weighted by the Poisson
+    probabilities."""
+    S0 = np.atleast_1d(np.asarray(S0, float))
+    sigma = np.atleast_1d(np.asarray(sigma, float))
+    d = len(S0)
+    corr = np.asarray(corr, float).reshape(d, d)
+    muJ = np.atleast_1d(np.asarray(muJ, float))
+    CJ = np.asarray(CJ, float).reshape(d, d)
+    kappa = np.exp(muJ + 0.5 * np.diag(CJ)) - 1.0
+    C0 = T * np.outer(sigma, sigma) * corr
+    lt = lam * T
+    if n_max is None:
+        n_max = int(lt + 12.0 * math.sqrt(lt + 1.0) + 20)
+    total = 0.0
+    for n in range(n_max + 1):
+        w = math.exp(-lt + n * math.log(lt) - math.lgamma(n + 1)) if lt > 0 else (1.0 if n == 0 else 0.0)
+        if w == 0.0:
+            continue
+        C = C0 + n * CJ
+        s = np.sqrt(np.diag(C) / T)
+        # forward of asset j given n jumps: S0 e^{(r - lam kappa) T + n (muJ + CJ_jj / 2)}
+        fwd = S0 * np.exp((r - lam * kappa) * T + n * (muJ + 0.5 * np.diag(CJ)))
+        S_eff = fwd * math.exp(-r * T)
+        if d == 1:
+            v = bs_call(S_eff[0], K, T, r, s[0])
+        elif payoff == "call_max":
+            v = stulz_call_max(S_eff[0], S_eff[1], K, T, r, s[0], s[1], C[0, 1] / (T * s[0] * s[1]))
+        elif payoff == "call_min":
+            v = stulz_call_min(S_eff[0], S_eff[1], K, T, r, s[0], s[1], C[0, 1] / (T * s[0] * s[1]))
+        else:
+            raise ValueError(payoff)
+        total += w * v
+    return total
+
+
 # ------------------------------------------------------------------ one-factor quadrature, any d
 
 def one_factor_price(S0, K, T, r, sigma, rho, payoff="call_max", n_hermite=160):

@@ -23,6 +23,13 @@
  * the product of factors is replaced by the joint transform
  *   (-1)^(d+1) / ((1 + i sum_k z_k) prod_k (i z_k)),   Im z_k > 0, sum_k Im z_k > 1.
  *
+ * Jumps (Merton's model, the extension named in Sec. VI): with lamT = lambda T > 0 the
+ * characteristic function carries the compound-Poisson factor of normally distributed log-jump
+ * sizes with mean mJ[d] and covariance CJ[d*d] (in the term's coordinates), evaluated at -z like
+ * the Gaussian part:
+ *   exp(lamT (exp(-i z.mJ - 1/2 z^T CJ z) - 1)),
+ * and m carries the martingale compensator (see fourier.log_moments).
+ *
  * Every point evaluates the full quadratic form from scratch: O(d^2) per point,
  * deliberately without any reuse between points. The sum over the last index is
  * accumulated into a row sum, and row sums are accumulated with Kahan
@@ -48,15 +55,21 @@ static double complex node(int k, int i, int N, const double *L, const double *a
     return (-L[k] + ((double)i + 0.5) * eta) + I * alpha[k];
 }
 
-static double complex integrand(int d, const double complex *z, const double *m, const double *C,
-                                const int *kind)
+static double complex quad_exponent(int d, const double complex *z, const double *m, const double *C)
 {
     double complex e = 0.0;
     for (int k = 0; k < d; ++k) e += -I * z[k] * m[k];
     double complex q = 0.0;
     for (int k = 0; k < d; ++k)
         for (int l = 0; l < d; ++l) q += z[k] * C[k * d + l] * z[l];
-    e -= 0.5 * q;
+    return e - 0.5 * q;
+}
+
+static double complex integrand(int d, const double complex *z, const double *m, const double *C,
+                                const int *kind, double lamT, const double *mJ, const double *CJ)
+{
+    double complex e = quad_exponent(d, z, m, C);
+    if (lamT > 0.0) e += lamT * (cexp(quad_exponent(d, z, mJ, CJ)) - 1.0);
     double complex h = 1.0;
     if (kind[0] == 3) {
         double complex sz = 0.0;
@@ -74,8 +87,9 @@ static double complex integrand(int d, const double complex *z, const double *m,
 /* Partial sum over the rows [row_begin, row_end) of the grid (a row fixes every index but
  * the last). out[0] + i out[1] = S ; out[2] = sum |F| (for the cancellation diagnostic). */
 void dense_term_sum_rows(int d, int N, const double *m, const double *C, const double *L,
-                         const double *alpha, const int *kind, int nthreads, int64_t row_begin,
-                         int64_t row_end, double *out)
+                         const double *alpha, const int *kind, double lamT, const double *mJ,
+                         const double *CJ, int nthreads, int64_t row_begin, int64_t row_end,
+                         double *out)
 {
     double sre = 0.0, sim = 0.0, sabs = 0.0;
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -94,7 +108,7 @@ void dense_term_sum_rows(int d, int N, const double *m, const double *C, const d
             double ra = 0.0;
             for (int i = 0; i < N; ++i) {
                 z[d - 1] = node(d - 1, i, N, L, alpha);
-                double complex f = integrand(d, z, m, C, kind);
+                double complex f = integrand(d, z, m, C, kind, lamT, mJ, CJ);
                 rs += f;
                 ra += cabs(f);
             }
@@ -123,23 +137,24 @@ void dense_term_sum_rows(int d, int N, const double *m, const double *C, const d
 
 /* The full sum over all N^d points. */
 void dense_term_sum(int d, int N, const double *m, const double *C, const double *L,
-                    const double *alpha, const int *kind, int nthreads, double *out)
+                    const double *alpha, const int *kind, double lamT, const double *mJ,
+                    const double *CJ, int nthreads, double *out)
 {
     int64_t rows = 1;
     for (int k = 0; k < d - 1; ++k) rows *= N;
-    dense_term_sum_rows(d, N, m, C, L, alpha, kind, nthreads, 0, rows, out);
+    dense_term_sum_rows(d, N, m, C, L, alpha, kind, lamT, mJ, CJ, nthreads, 0, rows, out);
 }
 
 /* Integrand values at npts multi-indices idx[p*d + k] (0-based grid indices). */
 void integrand_points(int d, int N, const double *m, const double *C, const double *L,
-                      const double *alpha, const int *kind, int64_t npts, const int32_t *idx,
-                      double *out)
+                      const double *alpha, const int *kind, double lamT, const double *mJ,
+                      const double *CJ, int64_t npts, const int32_t *idx, double *out)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < npts; ++p) {
         double complex z[64];
         for (int k = 0; k < d; ++k) z[k] = node(k, idx[p * d + k], N, L, alpha);
-        double complex f = integrand(d, z, m, C, kind);
+        double complex f = integrand(d, z, m, C, kind, lamT, mJ, CJ);
         out[2 * p] = creal(f);
         out[2 * p + 1] = cimag(f);
     }

@@ -48,8 +48,9 @@ exp(-a_k X_k) = exp(-tau), with a_k the distance to the factor's pole
 for max / min indicators). tau = ln(100 / tol) clamped to [18, 34.5]: a tighter target
 costs a larger shift, and the shift's damping e^{alpha.w} multiplies the absolute
 size of the summand (the cancellation factor) faster than it removes aliasing. When the
-damping exponent Phi = alpha.m + alpha^T C_w alpha / 2 of that choice exceeds 12 (coarse
-grids), tau is lowered by bisection on [2, tau] (60 halvings) until Phi <= 12.
+damping exponent Phi = ln E[e^{alpha.w}] = alpha.m + alpha^T C_w alpha / 2 (plus, with Merton
+jumps, lambda T (E[e^{alpha.J_w}] - 1)) of that choice exceeds 12 (coarse grids), tau is lowered by
+bisection on [2, tau] (60 halvings) until Phi <= 12.
 
 Parity: pinned in tests/test_oracle_fourier.py against Black-Scholes (d=1), the
 two-asset closed forms (d=2), the one-factor quadrature (d=3, 5), put-call parity,
@@ -85,12 +86,13 @@ def _load():
         lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
-        lib.dense_term_sum.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip, ctypes.c_int, dp]
+        cd = ctypes.c_double
+        lib.dense_term_sum.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip, cd, dp, dp, ctypes.c_int, dp]
         lib.dense_term_sum.restype = None
-        lib.dense_term_sum_rows.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip, ctypes.c_int,
+        lib.dense_term_sum_rows.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip, cd, dp, dp, ctypes.c_int,
                                             ctypes.c_int64, ctypes.c_int64, dp]
         lib.dense_term_sum_rows.restype = None
-        lib.integrand_points.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip,
+        lib.integrand_points.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip, cd, dp, dp,
                                          ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), dp]
         lib.integrand_points.restype = None
         _lib = lib
@@ -103,13 +105,28 @@ def _dp(a):
 
 # ------------------------------------------------------------------------------- model
 
+def jumps(opt):
+    """(lambda, mean[d], cov[d, d]) of the log-jump sizes of Merton's model (the extension named
+    in Sec. VI); lambda = 0 when the option has no jumps."""
+    d = opt["d"]
+    lam = float(opt.get("jump_rate", 0.0) or 0.0)
+    if lam <= 0.0:
+        return 0.0, np.zeros(d), np.zeros((d, d))
+    return lam, np.asarray(opt["jump_mean"], float), np.asarray(opt["jump_cov"], float)
+
+
 def log_moments(opt):
-    """Mean and covariance of x = ln(S_T / K) under the risk-neutral GBM."""
+    """Mean and covariance of the diffusion part of x = ln(S_T / K) under the risk-neutral
+    measure: GBM, plus (with jumps) the compensator -lambda kappa_j T in the mean that keeps
+    e^{-rT} S_T^j a martingale, kappa_j = E[e^{J_j}] - 1 = exp(muJ_j + CJ_jj / 2) - 1."""
     S0 = np.asarray(opt["S0"], float)
     sig = np.asarray(opt["sigma"], float)
     R = np.asarray(opt["corr"], float)
     T, r, K = opt["T"], opt["r"], opt["K"]
     m = np.log(S0 / K) + (r - 0.5 * sig ** 2) * T
+    lam, muJ, CJ = jumps(opt)
+    if lam > 0.0:
+        m = m - lam * T * (np.exp(muJ + 0.5 * np.diag(CJ)) - 1.0)
     C = T * np.outer(sig, sig) * R
     return m, C
 
@@ -119,9 +136,12 @@ def terms(opt):
     sign[d] (+1: contour above the real axis, -1: below)."""
     d = opt["d"]
     m, C = log_moments(opt)
+    lam, muJ, CJ = jumps(opt)
+    lamT = lam * opt["T"]
     pay = opt["payoff"]
     if pay == "call_min_strip":
-        return [dict(P=np.eye(d), m=m, C=C, kind=np.full(d, KIND_STRIP, dtype=np.int32), sign=np.ones(d))]
+        return [dict(P=np.eye(d), m=m, C=C, kind=np.full(d, KIND_STRIP, dtype=np.int32), sign=np.ones(d),
+                     lamT=lamT, mJ=muJ, CJ=CJ)]
     out = []
     for j in range(d):
         P = np.zeros((d, d))
@@ -145,7 +165,7 @@ def terms(opt):
             sign[1:] = 1.0
         else:
             raise ValueError(pay)
-        out.append(dict(P=P, m=P @ m, C=P @ C @ P.T, kind=kind, sign=sign))
+        out.append(dict(P=P, m=P @ m, C=P @ C @ P.T, kind=kind, sign=sign, lamT=lamT, mJ=P @ muJ, CJ=P @ CJ @ P.T))
         if d == 1:
             break
     return out
@@ -167,6 +187,10 @@ def _rule_at(term, N, tau, prec):
         else:
             alpha[k] = term["sign"][k] * a[k]
     phi = float(alpha @ term["m"] + 0.5 * alpha @ term["C"] @ alpha)
+    lamT = float(term.get("lamT", 0.0))
+    if lamT > 0.0:
+        # the jump part of the cumulant generating function: lambda T (E[e^{alpha.J}] - 1)
+        phi += lamT * math.expm1(float(alpha @ term["mJ"] + 0.5 * alpha @ term["CJ"] @ alpha))
     return L, alpha, phi
 
 
@@ -218,6 +242,13 @@ def term_grids(opt, N, L=None, alpha=None, tol=DEFAULT_TOL):
     return ts, out
 
 
+def _jump_args(term, d):
+    lamT = float(term.get("lamT", 0.0))
+    mJ = np.ascontiguousarray(term.get("mJ", np.zeros(d)), float)
+    CJ = np.ascontiguousarray(term.get("CJ", np.zeros((d, d))), float)
+    return lamT, mJ, CJ
+
+
 def dense_term(term, N, L, alpha, nthreads=0):
     """(complex S, sum |F|) for one term."""
     lib = _load()
@@ -227,9 +258,11 @@ def dense_term(term, N, L, alpha, nthreads=0):
     kind = np.ascontiguousarray(term["kind"], np.int32)
     L = np.ascontiguousarray(L, float)
     alpha = np.ascontiguousarray(alpha, float)
+    lamT, mJ, CJ = _jump_args(term, d)
     out = np.zeros(3)
     lib.dense_term_sum(d, N, _dp(m), _dp(C), _dp(L), _dp(alpha),
-                       kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(nthreads), _dp(out))
+                       kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), lamT, _dp(mJ), _dp(CJ), int(nthreads),
+                       _dp(out))
     return complex(out[0], out[1]), float(out[2])
 
 
@@ -242,9 +275,10 @@ def dense_term_rows(term, N, L, alpha, row_begin, row_end, nthreads=0):
     kind = np.ascontiguousarray(term["kind"], np.int32)
     L = np.ascontiguousarray(L, float)
     alpha = np.ascontiguousarray(alpha, float)
+    lamT, mJ, CJ = _jump_args(term, d)
     out = np.zeros(3)
     lib.dense_term_sum_rows(d, N, _dp(m), _dp(C), _dp(L), _dp(alpha),
-                            kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(nthreads),
+                            kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), lamT, _dp(mJ), _dp(CJ), int(nthreads),
                             int(row_begin), int(row_end), _dp(out))
     return complex(out[0], out[1]), float(out[2])
 
@@ -286,8 +320,9 @@ def integrand_at(term, N, L, alpha, idx):
     kind = np.ascontiguousarray(term["kind"], np.int32)
     L = np.ascontiguousarray(L, float)
     alpha = np.ascontiguousarray(alpha, float)
+    lamT, mJ, CJ = _jump_args(term, d)
     lib.integrand_points(d, N, _dp(m), _dp(C), _dp(L), _dp(alpha),
-                         kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), n,
+                         kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), lamT, _dp(mJ), _dp(CJ), n,
                          idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(out))
     return out[0::2] + 1j * out[1::2]
 

@@ -36,6 +36,14 @@ def mc_price(opt, n_paths, seed=0, chunk=1 << 20, antithetic=True):
     drift = (r - 0.5 * sig ** 2) * T
     vol = sig * math.sqrt(T)
     rng = np.random.Generator(np.random.PCG64(seed))
+    lam = float(opt.get("jump_rate", 0.0) or 0.0)
+    if lam > 0.0:
+        # Merton jumps: a Poisson number of N(muJ, CJ) log-jumps, compensated in the drift
+        muJ = np.asarray(opt["jump_mean"], float)
+        CJ = np.asarray(opt["jump_cov"], float)
+        LJ = np.linalg.cholesky(CJ + 1e-300 * np.eye(d)) if np.any(CJ) else np.zeros((d, d))
+        drift = drift - lam * T * (np.exp(muJ + 0.5 * np.diag(CJ)) - 1.0)
+        return _mc_jumps(opt["payoff"], S0, K, T, r, drift, vol, Lc, lam, muJ, LJ, n_paths, rng, chunk)
     s1 = 0.0
     s2 = 0.0
     n_done = 0
@@ -61,3 +69,24 @@ def mc_price(opt, n_paths, seed=0, chunk=1 << 20, antithetic=True):
     var = max(s2 / m - mean * mean, 0.0)
     disc = math.exp(-r * T)
     return disc * mean, disc * math.sqrt(var / m)
+
+
+def _mc_jumps(kind, S0, K, T, r, drift, vol, Lc, lam, muJ, LJ, n_paths, rng, chunk):
+    """Plain (non-antithetic) sampling of the jump-diffusion terminal law: given the Poisson count
+    n, the jump part is n muJ + sqrt(n) LJ Z'."""
+    d = len(S0)
+    s1 = s2 = 0.0
+    done = 0
+    while done < n_paths:
+        n = min(chunk, n_paths - done)
+        W = rng.standard_normal((n, d)) @ Lc.T
+        cnt = rng.poisson(lam * T, n).astype(float)
+        J = cnt[:, None] * muJ[None, :] + np.sqrt(cnt)[:, None] * (rng.standard_normal((n, d)) @ LJ.T)
+        v = payoff(kind, S0 * np.exp(drift + vol * W + J), K)
+        s1 += float(v.sum())
+        s2 += float((v * v).sum())
+        done += n
+    mean = s1 / done
+    var = max(s2 / done - mean * mean, 0.0)
+    disc = math.exp(-r * T)
+    return disc * mean, disc * math.sqrt(var / done)

@@ -65,12 +65,32 @@ def wishart_correlation(rng: np.random.Generator, d: int, dof: int, lam_floor: f
             return r.tolist()
 
 
-def option(d, S0, K, T, r, sigma, corr, payoff="call_max") -> dict:
+def option(d, S0, K, T, r, sigma, corr, payoff="call_max", jumps=None) -> dict:
+    """jumps: None, or (rate, mean[d], cov[d][d]) of Merton's log-jump sizes (Sec. VI)."""
     if payoff not in ALL_PAYOFFS:
         raise ValueError(payoff)
-    return dict(d=int(d), S0=[float(x) for x in S0], K=float(K), T=float(T), r=float(r),
-                sigma=[float(x) for x in sigma], corr=[[float(x) for x in row] for row in corr],
-                payoff=payoff)
+    o = dict(d=int(d), S0=[float(x) for x in S0], K=float(K), T=float(T), r=float(r),
+             sigma=[float(x) for x in sigma], corr=[[float(x) for x in row] for row in corr],
+             payoff=payoff)
+    if jumps is not None:
+        lam, mu, cov = jumps
+        o.update(jump_rate=float(lam), jump_mean=[float(x) for x in mu], jump_cov=[[float(x) for x in row] for row in cov])
+    return o
+
+
+def merton_options(n, seed=11, d_choices=(1, 2, 3), payoffs=("call_max", "call_min", "put_max")):
+    """Random options with Merton jumps: the market draws of random_small_options, a jump rate
+    U[0.2, 2] per year, log-jump means U[-0.2, 0.1] and a log-jump covariance 0.1^2 x (a
+    Sigma(beta) matrix, beta U[0, 1]) scaled by U[0.5, 2] per asset."""
+    rng = _rng(seed)
+    out = []
+    for o in random_small_options(n, seed=seed + 1000, d_choices=d_choices, payoffs=payoffs):
+        d = o["d"]
+        s = 0.1 * rng.uniform(0.5, 2.0, d)
+        cov = np.asarray(sigma_beta(d, rng.uniform(0.0, 1.0))) * np.outer(s, s)
+        out.append(dict(o, jump_rate=float(rng.uniform(0.2, 2.0)), jump_mean=rng.uniform(-0.2, 0.1, d).tolist(),
+                        jump_cov=cov.tolist()))
+    return out
 
 
 def grid(N, L=None, alpha=None, tol=1e-8, max_rank=32, max_sweeps=6, seed=0) -> dict:
