@@ -58,7 +58,14 @@ typedef enum { TTFP_CALL_MAX = 0, TTFP_PUT_MAX = 1, TTFP_CALL_MIN = 2, TTFP_CALL
 #define TTFP_MAX_D 32      /* largest number of assets */
 #define TTFP_MAX_RANK 64   /* largest TT rank (plus enrichment columns <= 68) */
 
-/* One option. S0[d], sigma[d] and corr[d*d] (row-major) are host arrays. */
+/* One option. S0[d], sigma[d] and corr[d*d] (row-major) are host arrays.
+ * Jumps (Merton's model, the characteristic-function extension of Sec. VI): jump_rate > 0 adds a
+ * compound-Poisson part with one clock at that rate per year and normally distributed log-jump
+ * sizes of mean jump_mean[d] and covariance jump_cov[d*d] (symmetric, positive semidefinite); the
+ * mean of ln S_T carries the compensator -jump_rate (e^{jump_mean_j + jump_cov_jj/2} - 1) T that
+ * keeps the discounted prices martingales, and the characteristic function gains the factor
+ * exp(jump_rate T (E[e^{i z.J}] - 1)). jump_rate = 0 (the pointers may be NULL): plain GBM.
+ * Delta and vega keep their forms (the jump part does not depend on S0 or sigma). */
 typedef struct {
     int32_t d;
     int32_t payoff;            /* ttfp_payoff */
@@ -66,6 +73,9 @@ typedef struct {
     const double *sigma;
     const double *corr;
     double K, T, r;
+    double jump_rate;
+    const double *jump_mean;
+    const double *jump_cov;
 } ttfp_option;
 
 /* Grid and TT-cross settings.

@@ -34,7 +34,9 @@ class _Option(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("payoff", ctypes.c_int32),
                 ("S0", ctypes.POINTER(ctypes.c_double)), ("sigma", ctypes.POINTER(ctypes.c_double)),
                 ("corr", ctypes.POINTER(ctypes.c_double)),
-                ("K", ctypes.c_double), ("T", ctypes.c_double), ("r", ctypes.c_double)]
+                ("K", ctypes.c_double), ("T", ctypes.c_double), ("r", ctypes.c_double),
+                ("jump_rate", ctypes.c_double), ("jump_mean", ctypes.POINTER(ctypes.c_double)),
+                ("jump_cov", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Grid(ctypes.Structure):
@@ -125,8 +127,17 @@ class _Marshal:
         self.corr = np.ascontiguousarray(opt["corr"], np.float64).reshape(-1)
         if self.S0.shape != (d,) or self.sigma.shape != (d,) or self.corr.shape != (d * d,):
             raise ValueError("option arrays do not match d")
+        lam = float(opt.get("jump_rate", 0.0) or 0.0)
+        null = ctypes.POINTER(ctypes.c_double)()
+        self.jm = self.jc = None
+        if lam > 0.0:
+            self.jm = np.ascontiguousarray(opt["jump_mean"], np.float64).reshape(-1)
+            self.jc = np.ascontiguousarray(opt["jump_cov"], np.float64).reshape(-1)
+            if self.jm.shape != (d,) or self.jc.shape != (d * d,):
+                raise ValueError("jump arrays do not match d")
         self.opt = _Option(d, PAYOFF_CODES[opt.get("payoff", "call_max")], _dp(self.S0), _dp(self.sigma),
-                           _dp(self.corr), float(opt["K"]), float(opt["T"]), float(opt["r"]))
+                           _dp(self.corr), float(opt["K"]), float(opt["T"]), float(opt["r"]), lam,
+                           _dp(self.jm) if self.jm is not None else null, _dp(self.jc) if self.jc is not None else null)
         L, A = grid.get("L"), grid.get("alpha")
         self.Lk = self.Ak = None
         Ls = As = 0.0

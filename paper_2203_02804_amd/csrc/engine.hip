@@ -132,7 +132,7 @@ int tsqr_levels(int rows, int BR, int G)
 
 struct ItemSizes {
     size_t bytes;
-    size_t off_m, off_C, off_L, off_a, off_kind, off_I, off_J, off_F, off_Rl, off_Ri, off_perm, off_Y, off_W,
+    size_t off_m, off_C, off_mJ, off_CJ, off_L, off_a, off_kind, off_I, off_J, off_F, off_Rl, off_Ri, off_perm, off_Y, off_W,
         off_Bt, off_cores, off_M, off_M1, off_M2, off_piv, off_keys, off_Ai, off_Qb, off_Gp, off_Ge, off_Xf, off_Rf;
     int rows_max, nblk_max;
 };
@@ -147,6 +147,8 @@ ItemSizes item_sizes(int d, int N, int R, int p, int BR)
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     s.off_m = take(sizeof(double) * d);
     s.off_C = take(sizeof(double) * d * d);
+    s.off_mJ = take(sizeof(double) * d);
+    s.off_CJ = take(sizeof(double) * d * d);
     s.off_L = take(sizeof(double) * d);
     s.off_a = take(sizeof(double) * d);
     s.off_kind = take(sizeof(int) * d);
@@ -333,6 +335,9 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             it.seed = g->seed * 0x100000001B3ull + (uint64_t)t * 0x9E3779B97F4A7C15ull + 1;
             it.m = (const double *)(dev + s.off_m);
             it.C = (const double *)(dev + s.off_C);
+            it.mJ = (const double *)(dev + s.off_mJ);
+            it.CJ = (const double *)(dev + s.off_CJ);
+            it.lamT = tp.lamT;
             it.L = (const double *)(dev + s.off_L);
             it.alpha = (const double *)(dev + s.off_a);
             it.kind = (const int *)(dev + s.off_kind);
@@ -366,6 +371,8 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
             std::memset(host.data(), 0, head);
             std::memcpy(host.data() + s.off_m, tp.m.data(), sizeof(double) * P.d);
             std::memcpy(host.data() + s.off_C, tp.C.data(), sizeof(double) * P.d * P.d);
+            std::memcpy(host.data() + s.off_mJ, tp.mJ.data(), sizeof(double) * P.d);
+            std::memcpy(host.data() + s.off_CJ, tp.CJ.data(), sizeof(double) * P.d * P.d);
             std::memcpy(host.data() + s.off_L, tp.L.data(), sizeof(double) * P.d);
             std::memcpy(host.data() + s.off_a, tp.alpha.data(), sizeof(double) * P.d);
             std::memcpy(host.data() + s.off_kind, tp.kind.data(), sizeof(int) * P.d);
@@ -1132,12 +1139,13 @@ int ttfp_price_two_trains(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid
         rc = check_cross_settings(&gpay, err);
         if (rc) { ctx->last_error = err; return rc; }
         // the characteristic-function trains (no payoff factors) and the payoff trains (the
-        // Gaussian exponent set to zero), on the same per-term grids
+        // whole exponent, Gaussian and jump parts, set to zero), on the same per-term grids
         OptionPlan Pcf = P, Ppay = P;
         for (TermPlan &tp : Pcf.terms) tp.kind.assign(P.d, KIND_ONE);
         for (TermPlan &tp : Ppay.terms) {
             std::fill(tp.m.begin(), tp.m.end(), 0.0);
             std::fill(tp.C.begin(), tp.C.end(), 0.0);
+            tp.lamT = 0.0;
         }
         std::vector<const OptionPlan *> cp{&Pcf, &Ppay};
         std::vector<const ttfp_grid *> cg{grid, &gpay};
@@ -1390,9 +1398,9 @@ int ttfp_eval_integrand(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *
     const TermPlan &tp = P.terms[term];
     const int d = P.d;
     // one small allocation holding the term data, indices and output
-    size_t o_m = 0, o_C = align_up(o_m + 8 * d), o_L = align_up(o_C + 8 * d * d), o_a = align_up(o_L + 8 * d),
-           o_k = align_up(o_a + 8 * d), o_i = align_up(o_k + 4 * d), o_o = align_up(o_i + 4 * (size_t)npts * d),
-           total = align_up(o_o + 16 * (size_t)npts);
+    size_t o_m = 0, o_C = align_up(o_m + 8 * d), o_mJ = align_up(o_C + 8 * d * d), o_CJ = align_up(o_mJ + 8 * d),
+           o_L = align_up(o_CJ + 8 * d * d), o_a = align_up(o_L + 8 * d), o_k = align_up(o_a + 8 * d),
+           o_i = align_up(o_k + 4 * d), o_o = align_up(o_i + 4 * (size_t)npts * d), total = align_up(o_o + 16 * (size_t)npts);
     char *buf = nullptr;
     Item *dit = nullptr;
     HIPCHK(hipMalloc(&buf, total));
@@ -1403,12 +1411,17 @@ int ttfp_eval_integrand(ttfp_ctx *ctx, const ttfp_option *opt, const ttfp_grid *
     it.N = grid->N;
     it.m = (const double *)(buf + o_m);
     it.C = (const double *)(buf + o_C);
+    it.mJ = (const double *)(buf + o_mJ);
+    it.CJ = (const double *)(buf + o_CJ);
+    it.lamT = tp.lamT;
     it.L = (const double *)(buf + o_L);
     it.alpha = (const double *)(buf + o_a);
     it.kind = (const int *)(buf + o_k);
     hipError_t e = hipSuccess;
     e = e ? e : hipMemcpy(buf + o_m, tp.m.data(), 8 * d, hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(buf + o_C, tp.C.data(), 8 * d * d, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(buf + o_mJ, tp.mJ.data(), 8 * d, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(buf + o_CJ, tp.CJ.data(), 8 * d * d, hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(buf + o_L, tp.L.data(), 8 * d, hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(buf + o_a, tp.alpha.data(), 8 * d, hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(buf + o_k, tp.kind.data(), 4 * d, hipMemcpyHostToDevice);

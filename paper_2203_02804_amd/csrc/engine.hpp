@@ -35,6 +35,9 @@ struct Item {
     int n_samp;                // random grid points of the sampled error estimate
     const double *m;           // [d]    mean of w
     const double *C;           // [d*d]  covariance of w
+    const double *mJ;          // [d]    Merton jumps: mean of the log-jump sizes in w
+    const double *CJ;          // [d*d]  their covariance in w
+    double lamT;               // jump rate times maturity (0: no jumps)
     const double *L;           // [d]    half-widths
     const double *alpha;       // [d]    contour shifts
     const int *kind;           // [d]    payoff factor kinds

@@ -314,7 +314,7 @@ __device__ cplx integrand(const Item &it, const int *idx)
         double L = it.L[k];
         z[k] = {-L + (idx[k] + 0.5) * 2.0 * L * invN, it.alpha[k]};
     }
-    cplx e = {0.0, 0.0}, h = {1.0, 0.0}, zs = {0.0, 0.0};
+    cplx e = {0.0, 0.0}, h = {1.0, 0.0}, zs = {0.0, 0.0}, ej = {0.0, 0.0};
     for (int k = 0; k < d; ++k) {
         const double *Ck = it.C + k * d;
         cplx q = {0.0, 0.0};
@@ -322,8 +322,19 @@ __device__ cplx integrand(const Item &it, const int *idx)
         // z_k * (-i m_k - q/2)
         cplx w = {-0.5 * q.x, -it.m[k] - 0.5 * q.y};
         e = cadd(e, cmul(z[k], w));
+        if (it.lamT > 0.0) {
+            const double *CJk = it.CJ + k * d;
+            cplx qj = {0.0, 0.0};
+            for (int l = 0; l < d; ++l) qj = {qj.x + CJk[l] * z[l].x, qj.y + CJk[l] * z[l].y};
+            ej = cadd(ej, cmul(z[k], {-0.5 * qj.x, -it.mJ[k] - 0.5 * qj.y}));
+        }
         h = cmul(h, factor(it.kind[k], z[k]));
         zs = cadd(zs, z[k]);
+    }
+    if (it.lamT > 0.0) {
+        // Merton jumps: exp(lamT (exp(-i z.mJ - z^T CJ z / 2) - 1))
+        const cplx g = cexp_(ej);
+        e = cadd(e, {it.lamT * (g.x - 1.0), it.lamT * g.y});
     }
     if (it.kind[0] == 3) h = cmul(h, strip_joint(d, zs));
     return cmul(cexp_(e), h);
@@ -412,11 +423,14 @@ __global__ void k_init(Item *items, int n_items)
 //   tau = -sum_{l != k} C_kl z_l,   H = prod_{l != k} h_l(z_l),
 // so that each entry costs one complex multiply-add, one exp and one sincos:
 //   F = exp(E_0 + z_k tau + c_k(i)) H h_k(z_k),  c_k(i) = z_k (-i m_k) - C_kk z_k^2 / 2,
-// with c_k and h_k tabulated per node in LDS.
+// with c_k and h_k tabulated per node in LDS. With Merton jumps the exponent gains
+// lamT (exp(J_0 + z_k tau_J + j_k(i)) - 1), J_0, tau_J and j_k formed from mJ and CJ the same way:
+// one more exp and sincos per entry.
 __global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, int t, int dir, int mode)
 {
     __shared__ cplx ctab[MAXN];
     __shared__ cplx htab[MAXN];
+    __shared__ cplx jtab[MAXN];
     const int item = blockIdx.y;
     if (!active[item]) return;
     Item &it = items[item];
@@ -438,11 +452,16 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, i
     // node tables of coordinate k
     const double Lk = it.L[k], etak = 2.0 * Lk / N, ak = it.alpha[k], mk = it.m[k], Ckk = it.C[k * d + k];
     const int kindk = it.kind[k];
+    const bool jumps = it.lamT > 0.0;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const cplx z = {-Lk + (i + 0.5) * etak, ak};
         const cplx w = {-0.5 * Ckk * z.x, -mk - 0.5 * Ckk * z.y};     // -i m_k - C_kk z / 2
         ctab[i] = cmul(z, w);
         htab[i] = factor(kindk, z);
+        if (jumps) {
+            const double CJkk = it.CJ[k * d + k];
+            jtab[i] = cmul(z, {-0.5 * CJkk * z.x, -it.mJ[k] - 0.5 * CJkk * z.y});
+        }
     }
     __syncthreads();
     const long long pidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -468,6 +487,7 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, i
         z[l] = {-L + (ix + 0.5) * 2.0 * L * invN, it.alpha[l]};
     }
     cplx e0 = {0.0, 0.0}, tau = {0.0, 0.0}, H = {1.0, 0.0}, zrest = {0.0, 0.0};
+    cplx j0 = {0.0, 0.0}, tauj = {0.0, 0.0};       // the jump exponent's counterparts
     const bool strip = it.kind[0] == 3;
     for (int l = 0; l < d; ++l) {
         if (l == k) continue;
@@ -482,12 +502,26 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, i
         e0 = cadd(e0, cmul(z[l], w));
         tau = {tau.x - it.C[k * d + l] * z[l].x, tau.y - it.C[k * d + l] * z[l].y};
         H = cmul(H, factor(it.kind[l], z[l]));
+        if (jumps) {
+            const double *CJl = it.CJ + l * d;
+            cplx qj = {0.0, 0.0};
+            for (int l2 = 0; l2 < d; ++l2) {
+                if (l2 == k) continue;
+                qj = {qj.x + CJl[l2] * z[l2].x, qj.y + CJl[l2] * z[l2].y};
+            }
+            j0 = cadd(j0, cmul(z[l], {-0.5 * qj.x, -it.mJ[l] - 0.5 * qj.y}));
+            tauj = {tauj.x - it.CJ[k * d + l] * z[l].x, tauj.y - it.CJ[k * d + l] * z[l].y};
+        }
     }
     cplx *out = mode == 0 ? it.F : it.cores + (size_t)k * R * N * R;
     const int nc = s.nc;
     for (int i = 0; i < N; ++i) {
         const cplx zk = {-Lk + (i + 0.5) * etak, ak};
-        const cplx ex = cadd(cadd(e0, cmul(zk, tau)), ctab[i]);
+        cplx ex = cadd(cadd(e0, cmul(zk, tau)), ctab[i]);
+        if (jumps) {
+            const cplx g = cexp_(cadd(cadd(j0, cmul(zk, tauj)), jtab[i]));
+            ex = cadd(ex, {it.lamT * (g.x - 1.0), it.lamT * g.y});
+        }
         cplx v = cmul(cexp_(ex), cmul(H, htab[i]));
         if (strip) v = cmul(v, strip_joint(d, cadd(zrest, zk)));
         const size_t row = (dir == 0) ? (size_t)g * N + i : (size_t)i * ng + g;

@@ -5,6 +5,11 @@
 // the characteristic function of Sec. III.C is written with the maturity in its
 // quadratic term.
 //
+// Merton jumps (the extension named in Sec. VI): with a Poisson clock of rate lambda and normal
+// log-jumps J ~ N(muJ, CJ), the mean carries the compensator -lambda T (e^{muJ_j + CJ_jj/2} - 1)
+// and the characteristic function the factor exp(lambda T (E[e^{i z.J}] - 1)); in the coordinates
+// w = P x of a term the jumps have mean P muJ and covariance P CJ P^T.
+//
 // Term decomposition: (max_j e^{x_j} - 1)^+ = sum_j (e^{x_j} - 1)^+ prod_{l != j} 1{x_l < x_j}.
 // Term j uses w_0 = x_j, w_l = x_l - x_j (l != j in increasing order), so that its payoff
 // is a product of one-dimensional factors whose transforms are
@@ -21,8 +26,9 @@
 // exp(-a_k 2 pi / eta_k) = exp(-tau), eta_k = 2 L_k / N (the aliasing period in x is
 // 2 pi / eta_k). tau = ln(100 / tol) clamped to [18, 34.5]: the damping e^{alpha.w} of a
 // larger shift inflates the absolute size of the summand faster than it cuts aliasing. When
-// the damping exponent Phi = alpha.m + alpha^T C_w alpha / 2 exceeds 12 (coarse grids), tau
-// is lowered by bisection on [2, tau] (60 halvings) until Phi <= 12.
+// the damping exponent Phi = ln E[e^{alpha.w}] = alpha.m + alpha^T C_w alpha / 2 (plus the jump
+// part lambda T (E[e^{alpha.J_w}] - 1)) exceeds 12 (coarse grids), tau is lowered by bisection on
+// [2, tau] (60 halvings) until Phi <= 12.
 #include "plan.hpp"
 
 #include <algorithm>
@@ -39,6 +45,23 @@ static double grid_tau(double tol) { return std::min(34.5, std::max(18.0, std::l
 
 static const double PHI_MAX = 12.0;
 
+// ln E[e^{alpha.w}] of a term: the Gaussian part and, with jumps, lambda T (E[e^{alpha.J_w}] - 1)
+static double damping_exponent(const TermPlan &tp, const std::vector<double> &alpha)
+{
+    const int d = tp.d;
+    double phi = 0.0, pj = 0.0;
+    for (int a = 0; a < d; ++a) {
+        phi += alpha[a] * tp.m[a];
+        for (int b = 0; b < d; ++b) phi += 0.5 * alpha[a] * tp.C[(size_t)a * d + b] * alpha[b];
+        if (tp.lamT > 0.0) {
+            pj += alpha[a] * tp.mJ[a];
+            for (int b = 0; b < d; ++b) pj += 0.5 * alpha[a] * tp.CJ[(size_t)a * d + b] * alpha[b];
+        }
+    }
+    if (tp.lamT > 0.0) phi += tp.lamT * std::expm1(pj);
+    return phi;
+}
+
 // Automatic (L, alpha) of one term for exponent tau; returns the damping exponent Phi.
 static double rule_at(const TermPlan &tp, int N, double tau, const std::vector<double> &prec,
                       std::vector<double> &L, std::vector<double> &alpha)
@@ -52,12 +75,7 @@ static double rule_at(const TermPlan &tp, int N, double tau, const std::vector<d
         if (tp.kind[k] == KIND_STRIP) alpha[k] = dist + 1.0 / d;   // sum_k dist from the joint pole too
         else alpha[k] = (tp.kind[k] == KIND_CALL && tp.sign[k] > 0) ? 1.0 + dist : tp.sign[k] * dist;
     }
-    double phi = 0.0;
-    for (int a = 0; a < d; ++a) {
-        phi += alpha[a] * tp.m[a];
-        for (int b = 0; b < d; ++b) phi += 0.5 * alpha[a] * tp.C[(size_t)a * d + b] * alpha[b];
-    }
-    return phi;
+    return damping_exponent(tp, alpha);
 }
 
 // Cholesky of a symmetric positive definite n x n matrix (row-major). False if not SPD.
@@ -156,11 +174,36 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
     }
     std::vector<double> Lc;
     if (!cholesky(out.corr, d, Lc)) { err = "corr is not positive definite"; return TTFP_EINVAL; }
+    // jumps
+    const double lam = o->jump_rate;
+    if (!finite(lam) || lam < 0.0) { err = "jump_rate must be finite and >= 0"; return TTFP_EINVAL; }
+    std::vector<double> muJ(d, 0.0), CJx((size_t)d * d, 0.0);
+    if (lam > 0.0) {
+        if (!o->jump_mean || !o->jump_cov) { err = "jump_mean and jump_cov must be non-NULL when jump_rate > 0"; return TTFP_EINVAL; }
+        double dmax = 0.0;
+        for (int i = 0; i < d; ++i) {
+            muJ[i] = o->jump_mean[i];
+            if (!finite(muJ[i])) { err = "jump_mean must be finite"; return TTFP_EINVAL; }
+            for (int j = 0; j < d; ++j) {
+                const double a = o->jump_cov[(size_t)i * d + j], b = o->jump_cov[(size_t)j * d + i];
+                if (!finite(a) || std::fabs(a - b) > 1e-12 * (1.0 + std::fabs(a))) { err = "jump_cov must be symmetric and finite"; return TTFP_EINVAL; }
+                CJx[(size_t)i * d + j] = a;
+            }
+            if (CJx[(size_t)i * d + i] < 0.0) { err = "jump_cov must have a nonnegative diagonal"; return TTFP_EINVAL; }
+            dmax = std::max(dmax, CJx[(size_t)i * d + i]);
+        }
+        // positive semidefinite: Cholesky of CJ + 1e-12 (1 + max diag) I
+        std::vector<double> Cs = CJx, Ls;
+        for (int i = 0; i < d; ++i) Cs[(size_t)i * d + i] += 1e-12 * (1.0 + dmax);
+        if (!cholesky(Cs, d, Ls)) { err = "jump_cov is not positive semidefinite"; return TTFP_EINVAL; }
+    }
 
     // log-moneyness moments
     std::vector<double> mx(d), Cx((size_t)d * d);
-    for (int j = 0; j < d; ++j)
+    for (int j = 0; j < d; ++j) {
         mx[j] = std::log(out.S0[j] / out.K) + (out.r - 0.5 * out.sigma[j] * out.sigma[j]) * out.T;
+        if (lam > 0.0) mx[j] -= lam * out.T * std::expm1(muJ[j] + 0.5 * CJx[(size_t)j * d + j]);   // compensator
+    }
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j)
             Cx[(size_t)i * d + j] = out.T * out.sigma[i] * out.sigma[j] * out.corr[(size_t)i * d + j];
@@ -203,6 +246,26 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
                 for (int k = 0; k < d; ++k) s += PC[(size_t)a * d + k] * tp.P[(size_t)b * d + k];
                 tp.C[(size_t)a * d + b] = s;
             }
+        // jumps in the term's coordinates
+        tp.lamT = lam * out.T;
+        tp.mJ.assign(d, 0.0);
+        tp.CJ.assign((size_t)d * d, 0.0);
+        if (lam > 0.0) {
+            std::vector<double> PJ((size_t)d * d, 0.0);
+            for (int a = 0; a < d; ++a)
+                for (int k = 0; k < d; ++k) {
+                    tp.mJ[a] += tp.P[(size_t)a * d + k] * muJ[k];
+                    double s = 0.0;
+                    for (int l = 0; l < d; ++l) s += tp.P[(size_t)a * d + l] * CJx[(size_t)l * d + k];
+                    PJ[(size_t)a * d + k] = s;
+                }
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) {
+                    double s = 0.0;
+                    for (int k = 0; k < d; ++k) s += PJ[(size_t)a * d + k] * tp.P[(size_t)b * d + k];
+                    tp.CJ[(size_t)a * d + b] = s;
+                }
+        }
         tp.kind.assign(d, KIND_CALL);
         tp.sign.assign(d, 1);
         if (strip) {
@@ -280,14 +343,10 @@ int build_plan(const ttfp_option *o, const ttfp_grid *g, OptionPlan &out, std::s
         for (int k = 0; k < d; ++k) sc *= (2.0 * tp.L[k] / N) / TWO_PI;
         tp.scale = sc;
         // Absolute size of the sum, by the Gaussian peak approximation:
-        // sum |integrand| ~ e^{alpha.m + alpha^T C alpha / 2} prod_k |h_k(i alpha_k)|
+        // sum |integrand| ~ E[e^{alpha.w}] prod_k |h_k(i alpha_k)|
         //                  x (2 pi)^{d/2} det(C)^{-1/2} / prod_k eta_k;
         // divided by the price it estimates the cancellation factor of the quadrature.
-        double expo = 0.0;
-        for (int a = 0; a < d; ++a) {
-            expo += tp.alpha[a] * tp.m[a];
-            for (int b = 0; b < d; ++b) expo += 0.5 * tp.alpha[a] * tp.C[(size_t)a * d + b] * tp.alpha[b];
-        }
+        const double expo = damping_exponent(tp, tp.alpha);
         std::vector<double> Lw;
         cholesky(tp.C, d, Lw);
         double logdet = 0.0;

@@ -23,6 +23,9 @@ struct TermPlan {
     std::vector<double> alpha;  // signed contour shifts
     std::vector<int> kind;      // payoff factor per coordinate
     std::vector<int> sign;      // +1 strip above the real axis, -1 below
+    std::vector<double> mJ;     // Merton jumps: mean of the log-jump sizes in w coordinates
+    std::vector<double> CJ;     // their covariance in w coordinates, d x d row-major
+    double lamT = 0.0;          // jump rate times maturity (0: no jumps)
     double scale = 0.0;         // K e^{-rT} prod_k eta_k / (2 pi)
     double absmass = 0.0;       // estimate of scale * sum |integrand| over the grid
 };

@@ -47,6 +47,28 @@ def test_plan_matches_oracle_grid_rule(seed):
                     assert np.allclose(A[t], At, rtol=1e-12)
 
 
+def test_plan_with_jumps_matches_oracle_grid_rule():
+    # Merton jumps enter the damping exponent of the rule (the jump cumulant at the shift)
+    for opt in W.merton_options(6, seed=21, d_choices=(1, 2, 3)):
+        for N in (64, 128):
+            L, A = ttfp.plan(opt, W.grid(N, tol=1e-10))
+            _, grids = F.term_grids(opt, N, tol=1e-10)
+            for t, (Lt, At) in enumerate(grids):
+                assert np.allclose(L[t], Lt, rtol=1e-12) and np.allclose(A[t], At, rtol=1e-12)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(jump_rate=-1.0, jump_mean=[0.0, 0.0], jump_cov=[[0.01, 0.0], [0.0, 0.01]]),
+    dict(jump_rate=1.0, jump_mean=[0.0, 0.0], jump_cov=[[0.01, 0.02], [0.0, 0.01]]),    # not symmetric
+    dict(jump_rate=1.0, jump_mean=[0.0, 0.0], jump_cov=[[0.01, 0.05], [0.05, 0.01]]),   # not semidefinite
+    dict(jump_rate=1.0, jump_mean=[float("nan"), 0.0], jump_cov=[[0.01, 0.0], [0.0, 0.01]]),
+])
+def test_plan_rejects_invalid_jumps(bad):
+    opt, g = W.config1()
+    with pytest.raises(ttfp.TTFPError):
+        ttfp.plan(dict(opt, **bad), g)
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 5])
 def test_plan_single_strip_min_matches_oracle(d):
     rng = np.random.Generator(np.random.PCG64(40 + d))

@@ -70,3 +70,21 @@ def test_bond_dimension_of_the_characteristic_function(pricer, gold):
         print(f"two trains beta={beta}: " + " ".join(f"D_phi={k}: {v:.1e}" for k, v in errs.items()), flush=True)
         assert errs[16] < 1e-6
         assert errs[2] > 100 * errs[16]
+
+
+def test_two_trains_with_jumps(pricer):
+    # with Merton jumps the jump factor belongs to the characteristic-function train only: the
+    # payoff train of a rotated call-on-max term stays rank one and the price matches the grid sum.
+    # Without the payoff's decay the characteristic function alone needs rank up to N here, so N
+    # stays below the rank cap.
+    opt = W.merton_options(1, seed=34, d_choices=(2,), payoffs=("call_max",))[0]
+    N = 48
+    grids = np.array(F.term_grids(opt, N, tol=1e-11)[1])
+    g = dict(W.grid(N, tol=1e-11, max_rank=64, max_sweeps=16), L=grids[:, 0], alpha=grids[:, 1])
+    p, rcf, rpay, info, rc = pricer.price_two_trains(opt, g, payoff_rank=8)
+    ref = F.dense_price(opt, N, grids[:, 0], grids[:, 1])
+    print(f"two trains merton: rel {p / ref - 1:+.2e} status {rc} D_phi {rcf.max()} payoff ranks {rpay.tolist()}",
+          flush=True)
+    assert rc == 0
+    assert abs(p / ref - 1) <= 1e-8
+    assert rpay.max() == 1
