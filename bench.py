@@ -393,6 +393,8 @@ def main():
                     help="triangular factor of the fibers: shifted Cholesky QR on the matrix cores with passes "
                          "chosen by the rank threshold, Householder TSQR, or two / three Cholesky QR passes")
     ap.add_argument("--mv-rounds", type=int, default=3, help="maxvol refinement rounds after the block start")
+    ap.add_argument("--mv-warm", type=int, default=1, choices=(0, 1),
+                    help="maxvol starts from the previous same-direction pivots (1) or always by elimination (0)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of a known size (scales the HBM byte counters of a profiler)")
     args = ap.parse_args()
@@ -425,7 +427,8 @@ def main():
     batches = [W.config2_batch(B, seed=sd, corr_kind="beta") for sd in seeds]
     refs = np.concatenate([load_refs(sd, B) for sd in seeds[args.warmup:]])
     pricer = ttfp.Pricer(0)
-    pricer.set_tuning(qr={"cholqr": 0, "tsqr": 1, "cholqr2": 2, "cholqr3": 3}[args.qr], maxvol_rounds=args.mv_rounds)
+    pricer.set_tuning(qr={"cholqr": 0, "tsqr": 1, "cholqr2": 2, "cholqr3": 3}[args.qr], maxvol_rounds=args.mv_rounds,
+                      maxvol_warm=args.mv_warm)
     log(f"bench: d=5 Sigma(0.5) N={args.N} R={args.max_rank} batch={B} warmup={args.warmup} steps={args.steps}")
     prices, status, elapsed, prof = time_batches(pricer, batches, grid, args.warmup, not args.no_profile)
     n_opt = B * args.steps

@@ -274,8 +274,17 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
  *                            resolved down to about 1e-12 of the largest, to 1e-5 relative above
  *                            1e-10), 3 always three (down to about 1e-16; ttfp_qr_r uses three
  *                            unless 2 is set); 1 Householder TSQR over LDS-resident row blocks
+ *  TTFP_TUNE_MAXVOL_WARM     1 (default): from the second half sweep in a direction on, maxvol
+ *                            starts from the pivots that the previous half sweep in that
+ *                            direction chose at the same core (their multi-indices mapped onto
+ *                            the current fiber's rows), when all r of them map and their block
+ *                            is not near-singular, instead of eliminating on its candidate
+ *                            block; 0: always the elimination start. Either start is followed
+ *                            by the same swaps and refinement to dominance; the pivots found
+ *                            (and so the result) may differ
  * Returns TTFP_EINVAL for an unknown parameter or value. */
-enum { TTFP_TUNE_MAXVOL_ROUNDS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2, TTFP_TUNE_QR = 3 };
+enum { TTFP_TUNE_MAXVOL_ROUNDS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2, TTFP_TUNE_QR = 3,
+       TTFP_TUNE_MAXVOL_WARM = 4 };
 int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value);
 int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
 

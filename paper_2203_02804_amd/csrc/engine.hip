@@ -25,7 +25,7 @@ __global__ void k_gram(Item *items, const int *active, int t, int dir, int pass)
 __global__ void k_chol(Item *items, const int *active, int t, int dir, int pass, int last);
 __global__ void k_xform(Item *items, const int *active, int t, int dir, int pass);
 __global__ void k_basis(Item *items, const int *active, int t, int dir);
-__global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax);
+__global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm);
 __global__ void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax);
 __global__ void k_interp(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_finish(Item *items, const int *active, int t, int dir);
@@ -64,6 +64,7 @@ struct ttfp_ctx {
     int last_n_items = 0;
     // tuning (set by ttfp_set_tuning, chosen by the autotuner)
     int tune_maxvol_rounds = 3;           // refinement rounds of maxvol after the block start
+    int tune_maxvol_warm = 1;             // maxvol starts from the previous same-direction pivots
     int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 1;                   // graph replay whenever the stream is not the null stream
@@ -529,7 +530,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
         const int rm = std::max(g.maxR, 2);
         const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
         const unsigned th = (unsigned)maxvol_threads(ctx, n_items, lds);
-        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(th), lds, st, it, act, t, dir, rm);
+        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(th), lds, st, it, act, t, dir, rm, ctx->tune_maxvol_warm);
     }
     // interpolation matrix of every row, then refinement rounds (each returns at once for an
     // item whose rows all satisfy the dominance bound)
@@ -898,6 +899,10 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
         if (value < 0 || value > 3) break;
         ctx->tune_qr = value;
         return TTFP_OK;
+    case TTFP_TUNE_MAXVOL_WARM:
+        if (value != 0 && value != 1) break;
+        ctx->tune_maxvol_warm = value;
+        return TTFP_OK;
     default:
         break;
     }
@@ -913,6 +918,7 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value)
     case TTFP_TUNE_TSQR_LDS_KB: *value = ctx->tune_tsqr_lds_kb; return TTFP_OK;
     case TTFP_TUNE_GRAPH: *value = ctx->tune_graph; return TTFP_OK;
     case TTFP_TUNE_QR: *value = ctx->tune_qr; return TTFP_OK;
+    case TTFP_TUNE_MAXVOL_WARM: *value = ctx->tune_maxvol_warm; return TTFP_OK;
     default: return TTFP_EINVAL;
     }
 }
@@ -1609,7 +1615,7 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
         const int rm = std::max(r, 2);
         const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
         const unsigned th = (unsigned)maxvol_threads(ctx, 1, lds);
-        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
+        hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm, 0);
         // refinement rounds until every row satisfies the dominance bound (each round returns at
         // once when none violates)
         const unsigned gi = cdivu((long long)m, MM_ROWS_PER_WG);

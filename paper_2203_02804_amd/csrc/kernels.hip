@@ -1606,12 +1606,15 @@ __device__ int select_largest(const float *v, int stride, int n, int K, float lo
 }
 
 // A^{-1} = Y[piv]^{-1} (r x r, row stride r) by Gauss-Jordan with partial pivoting, in LDS.
-// An exactly singular pivot leaves its column at zero and sets it.mv_singular.
-__device__ void gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag, cplx *Ai, cplx *fcol, int *shi, Item &it)
+// An exactly singular pivot leaves its column at zero and sets it.mv_singular. Returns the
+// smallest squared modulus of the pivots (the same in every thread).
+__device__ double gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag, cplx *Ai, cplx *fcol, int *shi, Item &it,
+                             bool flag_singular = true)
 {
     // pivot row of Ag and Ai (scaled) and the old row j of both, for the in-place update
     __shared__ cplx pa[TTFP_MAX_RANK], pi[TTFP_MAX_RANK], ja[TTFP_MAX_RANK], ji[TTFP_MAX_RANK];
     const int nthr = blockDim.x, lane = threadIdx.x & 63;
+    double minp = INFINITY;
     __syncthreads();
     for (int e = threadIdx.x; e < r * r; e += nthr) {
         const int a = e / r, c = e % r;
@@ -1635,8 +1638,9 @@ __device__ void gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag
         const int p = shi[0];
         const cplx gjj = Ag[p * r + j];
         const bool sing = !(fmax(fabs(gjj.x), fabs(gjj.y)) > 0.0) || !(cabs2(gjj) <= 1e300);
+        minp = sing ? 0.0 : fmin(minp, cabs2(gjj));
         const cplx inv = sing ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, gjj);
-        if (sing && threadIdx.x == 0) it.mv_singular = 1;
+        if (sing && flag_singular && threadIdx.x == 0) it.mv_singular = 1;
         // rows j and p trade places; the pivot row is scaled; fcol holds column j of the
         // swapped matrix (the elimination factors)
         for (int c = threadIdx.x; c < r; c += nthr) {
@@ -1661,6 +1665,52 @@ __device__ void gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag
         }
         __syncthreads();
     }
+    return minp;
+}
+
+// Bc = Y[cand] A^{-1} (Kc x r, row-major) on the FP64 matrix cores: each wave forms 16-row panels
+// of the candidate block (all r columns as up to four 16 x 16 tiles, three real products per complex
+// one, Gauss); A^{-1} is in LDS with row stride r. Operand and accumulator lane layouts as in
+// k_interp. Every thread of the workgroup calls it; control flow is uniform within a wave.
+__device__ void block_times_inverse(const cplx *Y, const int *cand, int Kc, int r, const cplx *Ai, cplx *Bc)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4, ntile = (r + 15) / 16;
+    for (int g0 = 16 * wave; g0 < Kc; g0 += 16 * nw) {
+        double4_t prr[4], pii[4], pss[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+            pii[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+            pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        }
+        const int arow = g0 + li;
+        const cplx *y = Y + (size_t)cand[min(arow, Kc - 1)] * r;
+        for (int k0 = 0; k0 < r; k0 += 4) {
+            const int kk = k0 + lk;
+            const cplx a = (arow < Kc && kk < r) ? y[kk] : cplx{0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= ntile) break;
+                const int jj = 16 * q + li;
+                const cplx b = (kk < r && jj < r) ? Ai[kk * r + jj] : cplx{0.0, 0.0};
+                prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
+                pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
+                pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = g0 + lk + 4 * v;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= ntile) break;
+                const int col = 16 * q + li;
+                if (row < Kc && col < r)
+                    Bc[(size_t)row * r + col] = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
+            }
+        }
+    }
 }
 
 // maxvol swaps on the candidate block Bc (Kc x r, global memory, rows cand[0..Kc)); returns the
@@ -1674,13 +1724,14 @@ __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, do
     const int nthr = blockDim.x;
     int swaps = 0;
     const long long tot = (long long)Kc * r;
+    // the entry of largest modulus; after each swap it is found in the update pass itself
+    ArgMax a = {-1.0, 0x7fffffff};
+    for (long long e = threadIdx.x; e < tot; e += nthr) {
+        const double v = cabs2(Bc[e]);
+        a = better(a, ArgMax{v <= 1e300 ? v : -1.0, (int)e});
+    }
+    a = block_argmax(a, red);
     while (swaps < maxit) {
-        ArgMax a = {-1.0, 0x7fffffff};
-        for (long long e = threadIdx.x; e < tot; e += nthr) {
-            const double v = cabs2(Bc[e]);
-            a = better(a, ArgMax{v <= 1e300 ? v : -1.0, (int)e});
-        }
-        a = block_argmax(a, red);
         if (!(a.v > lim) || a.i < 0 || a.i >= tot) break;
         const int qs = a.i / r, js = a.i % r;
         const cplx b = Bc[(size_t)qs * r + js];
@@ -1694,15 +1745,20 @@ __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, do
             for (int i = threadIdx.x; i < r; i += nthr) acol[i] = cdiv(Ai[i * r + js], b);
         if (threadIdx.x == 0) piv[js] = cand[qs];
         __syncthreads();
+        ArgMax an = {-1.0, 0x7fffffff};
         for (long long e = threadIdx.x; e < tot; e += nthr) {
             const int q = (int)(e / r), c = (int)(e % r);
-            Bc[e] = csub(Bc[e], cmul(colv[q], prow[c]));
+            const cplx v = csub(Bc[e], cmul(colv[q], prow[c]));
+            Bc[e] = v;
+            const double v2 = cabs2(v);
+            an = better(an, ArgMax{v2 <= 1e300 ? v2 : -1.0, (int)e});
         }
         if (Ai)
             for (int e = threadIdx.x; e < r * r; e += nthr) Ai[e] = csub(Ai[e], cmul(acol[e / r], prow[e % r]));
-        __syncthreads();
+        a = block_argmax(an, red);             // its barriers also publish the updated block
         ++swaps;
     }
+    __syncthreads();
     return swaps;
 }
 
@@ -1710,7 +1766,7 @@ __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, do
 // memory, row g of S is row rowmap[g] of Y, or row g when rowmap is null). chosen[n] flags the
 // rows taken (cleared by the caller). Stops at the first column whose largest remaining entry
 // has squared modulus <= ptol2 and returns its index; returns r when all r pivots were found.
-__device__ int lu_start(cplx *S, int n, int r, const int *rowmap, int *chosen, int *piv, double ptol2, cplx *prow,
+__device__ __forceinline__ int lu_start(cplx *S, int n, int r, const int *rowmap, int *chosen, int *piv, double ptol2, cplx *prow,
                         ArgMax *red, int *shi)
 {
     const int nthr = blockDim.x;
@@ -1743,9 +1799,56 @@ __device__ int lu_start(cplx *S, int n, int r, const int *rowmap, int *chosen, i
     return r;
 }
 
+// Warm start of a step from the pivots that the previous half sweep in the same direction chose at
+// this core: each of its multi-indices (the old index set I_{k+1} of a left-to-right step, J_k of a
+// right-to-left one) whose prefix (suffix) is still in the current neighbouring set I_k (J_{k+1})
+// names one fiber row, a N + i (i nb + b). Writes those rows to piv and returns their number (the
+// same in every thread); returns 0 when two would coincide. Every thread must call it.
+__device__ int map_previous_pivots(const Item &it, const StepShape &s, int dir, int *piv, int *shi)
+{
+    __shared__ int found[TTFP_MAX_RANK];
+    const int d = it.d, R = it.R, N = it.N, k = s.k, nthr = blockDim.x;
+    const int n_old = min(dir == 0 ? it.nI[k + 1] : it.nJ[k], TTFP_MAX_RANK);
+    const int n_cur = dir == 0 ? it.nI[k] : it.nJ[k + 1];
+    const int *oldset = it.Iset + (size_t)(k + 1) * R * d, *curset = it.Iset + (size_t)k * R * d;
+    if (dir != 0) {
+        oldset = it.Jset + (size_t)k * R * d;
+        curset = it.Jset + (size_t)(k + 1) * R * d;
+    }
+    const int c0 = dir == 0 ? 0 : k + 1, c1 = dir == 0 ? k : d;     // the shared coordinates
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_old; q += nthr) found[q] = -1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n_old * n_cur; e += nthr) {
+        const int q = e / n_cur, a = e % n_cur;
+        bool match = true;
+        for (int c = c0; c < c1 && match; ++c) match = oldset[q * d + c] == curset[a * d + c];
+        if (match) found[q] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int n0 = 0;
+        for (int q = 0; q < n_old; ++q) {
+            const int a = found[q];
+            if (a < 0) continue;
+            const int i = oldset[q * d + k];
+            if (i < 0 || i >= N) continue;
+            const int row = dir == 0 ? a * N + i : i * n_cur + a;
+            if (row < 0 || row >= s.rows) continue;
+            bool dup = false;
+            for (int u = 0; u < n0 && !dup; ++u) dup = piv[u] == row;
+            if (dup) { n0 = 0; break; }
+            piv[n0++] = row;
+        }
+        shi[3] = n0;
+    }
+    __syncthreads();
+    return shi[3];
+}
+
 // Abuf is dynamic LDS of 2 rmax^2 complex entries (rmax: the largest rank of the launch): the
 // key buffer of the start and the two r x r blocks of the Gauss-Jordan inverse.
-__global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax)
+__global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm)
 {
     extern __shared__ cplx Abuf[];
     const int cap = 2 * rmax * rmax;                 // entries of Abuf
@@ -1780,31 +1883,34 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     int K = MV_KMAX;
     K = min(K, nk);
     float *key = (float *)Abuf;
-    float kmax = 0.0f;
-    for (int g = threadIdx.x; g < nk; g += nthr) {
-        float best = -1.0f;
-        for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
-            float q;
-            if (dir != 2) {
-                q = it.keys[i];                          // the row norm written by k_basis
-            } else {
-                const cplx *y = Y + (size_t)i * r;
-                double qq = 0.0;
-                for (int c = 0; c < r; ++c) qq += cabs2(y[c]);
-                q = (float)qq;
+    // the group keys in Abuf (formed again by the fallback below when a warm start's inverse has
+    // overwritten them); returns their largest value, in every thread
+    auto group_keys = [&](bool clear_marks) -> float {
+        float kx = 0.0f;
+        for (int g = threadIdx.x; g < nk; g += nthr) {
+            float best = -1.0f;
+            for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
+                float q;
+                if (dir != 2) {
+                    q = it.keys[i];                          // the row norm written by k_basis
+                } else {
+                    const cplx *y = Y + (size_t)i * r;
+                    double qq = 0.0;
+                    for (int c = 0; c < r; ++c) qq += cabs2(y[c]);
+                    q = (float)qq;
+                }
+                if (clear_marks) it.viol[i] = 0.0f;
+                if (!(q >= 0.0f && q <= 3.0e38f)) q = 0.0f;     // a non-finite row is never a pivot
+                best = fmaxf(best, q);
             }
-            it.viol[i] = 0.0f;
-            if (!(q >= 0.0f && q <= 3.0e38f)) q = 0.0f;     // a non-finite row is never a pivot
-            best = fmaxf(best, q);
+            key[g] = fmaxf(best, 0.0f);
+            kx = fmaxf(kx, key[g]);
         }
-        key[g] = fmaxf(best, 0.0f);
-        kmax = fmaxf(kmax, key[g]);
-    }
-    {
-        ArgMax a = {(double)kmax, 0};
+        ArgMax a = {(double)kx, 0};
         a = block_argmax(a, red);
-        kmax = (float)a.v;
-    }
+        return (float)a.v;
+    };
+    float kmax = group_keys(true);
     // ---- 1b. the K largest groups, resolved to their largest-norm row
     const int Kc = select_largest(key, 1, nk, K, 0.0f, kmax, cand, red, shi, shf);
     for (int q = threadIdx.x; q < Kc; q += nthr) {
@@ -1828,89 +1934,85 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     // all m rows (row flags and the larger block's row list live in the output B, which only
     // k_interp writes).
     const double ptol2 = 1e-12 * (double)kmax;
-    cplx *S = W;
-    for (long long e = threadIdx.x; e < (long long)Kc * r; e += nthr)
-        S[e] = Y[(size_t)cand[e / r] * r + e % r];
-    __syncthreads();
-    int nf = lu_start(S, Kc, r, cand, chosen, piv, ptol2, prow, red, shi);
-    if (nf < r) {
-        int *flag = reinterpret_cast<int *>(B);
-        int *rows2 = flag + m;
-        const int K2 = min(min(2048, m), nk);
-        int n2 = m;
-        const int *map = nullptr;
-        if (K2 < m) {
-            // group keys are still in Abuf: the K2 largest groups, resolved to rows
-            int *grp = rows2;
-            n2 = select_largest(key, 1, nk, K2, 0.0f, kmax, grp, red, shi, shf);
-            for (int q = threadIdx.x; q < n2; q += nthr) {
-                const int g = grp[q];
-                int bi = g * gsz;
-                double best = -1.0;
-                for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
-                    const cplx *y = Y + (size_t)i * r;
-                    double v = 0.0;
-                    for (int c = 0; c < r; ++c) v += cabs2(y[c]);
-                    if (v > best) { best = v; bi = i; }
-                }
-                grp[q] = bi;
-            }
-            __syncthreads();
-            map = rows2;
-        }
-        for (int pass = 0; pass < 2 && nf < r; ++pass) {
-            if (pass == 0 && n2 == m) continue;        // the larger block is all rows already
-            const int nn = pass == 0 ? n2 : m;
-            const int *mp = pass == 0 ? map : nullptr;
-            for (long long e = threadIdx.x; e < (long long)nn * r; e += nthr) {
-                const int g = (int)(e / r);
-                S[e] = Y[(size_t)(mp ? mp[g] : g) * r + e % r];
-            }
-            for (int g = threadIdx.x; g < nn; g += nthr) flag[g] = 0;
-            __syncthreads();
-            nf = lu_start(S, nn, r, mp, flag, piv, pass == 0 ? ptol2 : 0.0, prow, red, shi);
-        }
+    // Warm start (warm = 1, from the second half sweep in a direction on): the pivots of the
+    // previous half sweep in this direction, when all r of them name rows of this fiber and their
+    // block is not near-singular (smallest Gauss-Jordan pivot above the elimination's threshold);
+    // the elimination start is then skipped and A^{-1} is already formed.
+    bool warm_ok = false;
+    if (warm && dir != 2 && it.half >= 2 + dir && map_previous_pivots(it, s, dir, piv, shi) == r)
+        warm_ok = gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it, false) > ptol2;
+    if (!warm_ok) {
+        cplx *S = W;
+        for (long long e = threadIdx.x; e < (long long)Kc * r; e += nthr)
+            S[e] = Y[(size_t)cand[e / r] * r + e % r];
+        __syncthreads();
+        int nf = lu_start(S, Kc, r, cand, chosen, piv, ptol2, prow, red, shi);
         if (nf < r) {
-            // Y itself is rank deficient: the remaining pivots are the lowest untaken rows
-            if (threadIdx.x == 0) {
-                int next = 0;
-                for (int j = nf; j < r; ++j) {
-                    bool used = true;
-                    while (used && next < m) {
-                        used = false;
-                        for (int q = 0; q < j; ++q) used |= piv[q] == next;
-                        if (used) ++next;
+            int *flag = reinterpret_cast<int *>(B);
+            int *rows2 = flag + m;
+            const int K2 = min(min(2048, m), nk);
+            int n2 = m;
+            const int *map = nullptr;
+            if (K2 < m) {
+                // the K2 largest groups (their keys formed again: a warm start's inverse may
+                // have used Abuf), resolved to rows
+                (void)group_keys(false);
+                int *grp = rows2;
+                n2 = select_largest(key, 1, nk, K2, 0.0f, kmax, grp, red, shi, shf);
+                for (int q = threadIdx.x; q < n2; q += nthr) {
+                    const int g = grp[q];
+                    int bi = g * gsz;
+                    double best = -1.0;
+                    for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
+                        const cplx *y = Y + (size_t)i * r;
+                        double v = 0.0;
+                        for (int c = 0; c < r; ++c) v += cabs2(y[c]);
+                        if (v > best) { best = v; bi = i; }
                     }
-                    piv[j] = min(next, m - 1);
-                    ++next;
+                    grp[q] = bi;
                 }
-                it.mv_singular = 1;
+                __syncthreads();
+                map = rows2;
             }
-            __syncthreads();
+            for (int pass = 0; pass < 2 && nf < r; ++pass) {
+                if (pass == 0 && n2 == m) continue;        // the larger block is all rows already
+                const int nn = pass == 0 ? n2 : m;
+                const int *mp = pass == 0 ? map : nullptr;
+                for (long long e = threadIdx.x; e < (long long)nn * r; e += nthr) {
+                    const int g = (int)(e / r);
+                    S[e] = Y[(size_t)(mp ? mp[g] : g) * r + e % r];
+                }
+                for (int g = threadIdx.x; g < nn; g += nthr) flag[g] = 0;
+                __syncthreads();
+                nf = lu_start(S, nn, r, mp, flag, piv, pass == 0 ? ptol2 : 0.0, prow, red, shi);
+            }
+            if (nf < r) {
+                // Y itself is rank deficient: the remaining pivots are the lowest untaken rows
+                if (threadIdx.x == 0) {
+                    int next = 0;
+                    for (int j = nf; j < r; ++j) {
+                        bool used = true;
+                        while (used && next < m) {
+                            used = false;
+                            for (int q = 0; q < j; ++q) used |= piv[q] == next;
+                            if (used) ++next;
+                        }
+                        piv[j] = min(next, m - 1);
+                        ++next;
+                    }
+                    it.mv_singular = 1;
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) it.mv_full += 1;
         }
-        if (threadIdx.x == 0) it.mv_full += 1;
+        __syncthreads();
+        // ---- 2. A^{-1} (unless the warm start formed it)
+        gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
     }
-    __syncthreads();
-    // ---- 2. A^{-1} and the block's rows of B (in W, over the start's copy)
-    gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
+    // the block's rows of B (in W, over the start's copy)
     cplx *Bc = W;
-    {
-        const int ncg = (r + 3) / 4;
-        for (int q = threadIdx.x; q < Kc * ncg; q += nthr) {
-            const int g = q / ncg, c0 = 4 * (q % ncg);
-            const cplx *y = Y + (size_t)cand[g] * r;
-            cplx acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-            for (int l = 0; l < r; ++l) {
-                const cplx yl = y[l];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (c0 + u < r) acc[u] = cadd(acc[u], cmul(yl, Ai[l * r + c0 + u]));
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (c0 + u < r) Bc[(size_t)g * r + c0 + u] = acc[u];
-        }
-    }
+    block_times_inverse(Y, cand, Kc, r, Ai, Bc);
     __syncthreads();
     // ---- 3. swaps within the block, 4. A^{-1} of the final pivots
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);

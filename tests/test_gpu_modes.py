@@ -54,12 +54,12 @@ def test_graph_replay_matches_eager(pricer):
     pricer.set_tuning(graph=0)
 
 
-@pytest.mark.parametrize("rounds,lds", [(0, 48), (2, 76), (3, 152), (5, 100)])
-def test_tunings_agree_with_the_oracle(pricer, rounds, lds):
+@pytest.mark.parametrize("rounds,lds,warm", [(0, 48, 1), (2, 76, 0), (3, 152, 1), (3, 152, 0), (5, 100, 1)])
+def test_tunings_agree_with_the_oracle(pricer, rounds, lds, warm):
     opts, g = _batch()
-    pricer.set_tuning(maxvol_rounds=rounds, tsqr_lds_kb=lds)
+    pricer.set_tuning(maxvol_rounds=rounds, tsqr_lds_kb=lds, maxvol_warm=warm)
     p, status = pricer.price_batch(opts, g)
-    pricer.set_tuning(maxvol_rounds=3, tsqr_lds_kb=152)
+    pricer.set_tuning(maxvol_rounds=3, tsqr_lds_kb=152, maxvol_warm=1)
     for o, v in zip(opts, p):
         ref = F.dense_price(o, 48, 14.0, 1.25)
         assert abs(v / ref - 1) < 1e-8
