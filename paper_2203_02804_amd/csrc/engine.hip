@@ -442,20 +442,9 @@ void prof_collect(ttfp_ctx *ctx)
 // Threads per maxvol workgroup (one workgroup per item): the size that minimises the number of
 // rounds of resident workgroups (at most 2048 threads and 160 KiB of LDS per CU, about 15 KiB of
 // it static) divided by threads^0.7 (a workgroup's speed grows sublinearly with its size).
-int maxvol_threads(const ttfp_ctx *ctx, int n_items, size_t dyn_lds)
-{
-    const long long by_lds = std::max(1LL, (long long)(160 * 1024) / (long long)(dyn_lds + 15 * 1024));
-    int best = 1024;
-    double best_cost = 1e300;
-    for (int t : {1024, 512, 256}) {
-        const long long per_cu = std::min<long long>(2048 / t, by_lds);
-        const long long slots = per_cu * std::max(ctx->n_cu, 1);
-        const double rounds = (double)((n_items + slots - 1) / slots);
-        const double cost = rounds / std::pow((double)t, 0.7);
-        if (cost < best_cost * (1.0 - 1e-9)) { best_cost = cost; best = t; }
-    }
-    return best;
-}
+// maxvol and its refinement run 1024 threads per workgroup (the Gauss-Jordan inverse holds A in
+// the registers of exactly that many threads); rmax^2 complex entries of dynamic LDS.
+constexpr unsigned MAXVOL_THREADS = 1024;
 
 // Refinement rounds of maxvol after the block start (TTFP_TUNE_MAXVOL_ROUNDS, default 3): each
 // marks the rows of B beyond 1 + delta and swaps them in. More rounds give interpolation nearer to
@@ -528,23 +517,26 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     {
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
         const int rm = std::max(g.maxR, 2);
-        const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
-        const unsigned th = (unsigned)maxvol_threads(ctx, n_items, lds);
-        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(th), lds, st, it, act, t, dir, rm, ctx->tune_maxvol_warm);
+        const size_t lds = (size_t)rm * rm * sizeof(cplx);
+        hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(MAXVOL_THREADS), lds, st, it, act, t, dir, rm, ctx->tune_maxvol_warm);
     }
-    // interpolation matrix of every row, then refinement rounds (each returns at once for an
-    // item whose rows all satisfy the dominance bound)
+    // checking passes of the interpolation matrix over every row, each followed by a refinement
+    // round (both return at once for an item whose rows all satisfy the dominance bound), then the
+    // pass that stores B
     const unsigned gi = cdivu((long long)g.maxrows, MM_ROWS_PER_WG);   // row blocks of k_interp
-    for (int round = 0; round <= ctx->tune_maxvol_rounds; ++round) {
-        if (round > 0) {
-            ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
-            const int rm = std::max(g.maxR, 2);
-            const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
-            hipLaunchKernelGGL(k_maxvol_refine, dim3(ny), dim3((unsigned)maxvol_threads(ctx, n_items, lds)), lds, st, it, act, t,
-                               dir, rm);
+    for (int round = 0; round < ctx->tune_maxvol_rounds; ++round) {
+        {
+            ProfScope ps(ctx, TTFP_KERNEL_INTERP);
+            hipLaunchKernelGGL(k_interp, dim3(gi, ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir, round > 0 ? 1 : 0);
         }
+        ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
+        const int rm = std::max(g.maxR, 2);
+        const size_t lds = (size_t)rm * rm * sizeof(cplx);
+        hipLaunchKernelGGL(k_maxvol_refine, dim3(ny), dim3(MAXVOL_THREADS), lds, st, it, act, t, dir, rm);
+    }
+    {
         ProfScope ps(ctx, TTFP_KERNEL_INTERP);
-        hipLaunchKernelGGL(k_interp, dim3(gi, ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir, round > 0 ? 1 : 0);
+        hipLaunchKernelGGL(k_interp, dim3(gi, ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir, 2);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_FINISH);
@@ -1613,16 +1605,17 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
     e = e ? e : hipMemcpy(it.Y, A, 16 * (size_t)m * r, hipMemcpyHostToDevice);
     if (!e) {
         const int rm = std::max(r, 2);
-        const size_t lds = (size_t)2 * rm * rm * sizeof(cplx);
-        const unsigned th = (unsigned)maxvol_threads(ctx, 1, lds);
+        const size_t lds = (size_t)rm * rm * sizeof(cplx);
+        const unsigned th = MAXVOL_THREADS;
         hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm, 0);
         // refinement rounds until every row satisfies the dominance bound (each round returns at
         // once when none violates)
         const unsigned gi = cdivu((long long)m, MM_ROWS_PER_WG);
-        for (int round = 0; round <= 8; ++round) {
-            if (round > 0) hipLaunchKernelGGL(k_maxvol_refine, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
+        for (int round = 0; round < 8; ++round) {
             hipLaunchKernelGGL(k_interp, dim3(gi, 1), dim3(64 * MM_WAVES), 0, ctx->stream, dit, act, 0, 2, round > 0 ? 1 : 0);
+            hipLaunchKernelGGL(k_maxvol_refine, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
         }
+        hipLaunchKernelGGL(k_interp, dim3(gi, 1), dim3(64 * MM_WAVES), 0, ctx->stream, dit, act, 0, 2, 2);
         e = hipGetLastError();
     }
     e = e ? e : hipStreamSynchronize(ctx->stream);

@@ -1605,110 +1605,132 @@ __device__ int select_largest(const float *v, int stride, int n, int K, float lo
     return min(K, shi[2]);
 }
 
-// A^{-1} = Y[piv]^{-1} (r x r, row stride r) by Gauss-Jordan with partial pivoting, in LDS.
-// An exactly singular pivot leaves its column at zero and sets it.mv_singular. Returns the
-// smallest squared modulus of the pivots (the same in every thread).
-__device__ double gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ag, cplx *Ai, cplx *fcol, int *shi, Item &it,
+// A^{-1} = Y[piv]^{-1} (r x r, row stride r) by Gauss-Jordan with partial pivoting: A is held in
+// registers (thread t holds row t / 16, columns t % 16 + 16 u, u = 0..3; the maxvol kernels run
+// 1024 threads and r <= 64) and A^{-1} in LDS, so that only one r x r matrix occupies LDS; vec
+// (LDS, 5 r entries) holds the pivot rows of both, the old row j of both and column j of A.
+// An exactly singular pivot leaves its column at zero and sets it.mv_singular (when
+// flag_singular). Returns the smallest squared modulus of the pivots (the same in every thread).
+constexpr int GJ_THREADS = 1024;
+static_assert(GJ_THREADS == 16 * TTFP_MAX_RANK, "one row of A per 16 threads");
+__device__ double gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ai, cplx *vec, int *shi, Item &it,
                              bool flag_singular = true)
 {
-    // pivot row of Ag and Ai (scaled) and the old row j of both, for the in-place update
-    __shared__ cplx pa[TTFP_MAX_RANK], pi[TTFP_MAX_RANK], ja[TTFP_MAX_RANK], ji[TTFP_MAX_RANK];
-    const int nthr = blockDim.x, lane = threadIdx.x & 63;
+    (void)shi;
+    cplx *pa = vec, *pi = vec + r, *ja = vec + 2 * r, *ji = vec + 3 * r, *fcol = vec + 4 * r;
+    const int a = threadIdx.x >> 4, c0 = threadIdx.x & 15;
+    const bool arow = a < r;
     double minp = INFINITY;
+    // the thread's four entries of A, in named registers (an array indexed by a runtime slot
+    // would be placed in scratch memory)
+    cplx ag0 = {0.0, 0.0}, ag1 = {0.0, 0.0}, ag2 = {0.0, 0.0}, ag3 = {0.0, 0.0};
     __syncthreads();
-    for (int e = threadIdx.x; e < r * r; e += nthr) {
-        const int a = e / r, c = e % r;
-        Ag[e] = Y[(size_t)min(max(piv[a], 0), m - 1) * r + c];
-        Ai[e] = (a == c) ? cplx{1.0, 0.0} : cplx{0.0, 0.0};
-    }
-    __syncthreads();
+    const cplx *yrow = Y + (size_t)min(max(arow ? piv[a] : 0, 0), m - 1) * r;
+    auto init = [&](cplx &v, int c) {
+        if (arow && c < r) {
+            v = yrow[c];
+            Ai[a * r + c] = (a == c) ? cplx{1.0, 0.0} : cplx{0.0, 0.0};
+        }
+    };
+    init(ag0, c0);
+    init(ag1, c0 + 16);
+    init(ag2, c0 + 32);
+    init(ag3, c0 + 48);
     for (int j = 0; j < r; ++j) {
-        // partial pivoting: the first row of the largest modulus in column j (rows j..r-1), by wave 0
-        if (threadIdx.x < 64) {
-            ArgMax b = {-2.0, r};
-            for (int a = j + lane; a < r; a += 64) {
-                double v = cabs2(Ag[a * r + j]);
-                if (!(v >= 0.0)) v = -1.0;              // a non-finite entry ranks below every number
-                b = better(b, ArgMax{v, a});
-            }
-            b = wave_argmax(b);
-            if (lane == 0) shi[0] = b.i;
+        // column j of A, published by its owners (the threads whose slot u holds column c0 + 16 u = j)
+        if (arow) {
+            if (c0 == j) fcol[a] = ag0;
+            else if (c0 + 16 == j) fcol[a] = ag1;
+            else if (c0 + 32 == j) fcol[a] = ag2;
+            else if (c0 + 48 == j) fcol[a] = ag3;
         }
         __syncthreads();
-        const int p = shi[0];
-        const cplx gjj = Ag[p * r + j];
+        // partial pivoting: the first row of the largest modulus in column j (rows j..r-1), found
+        // by every thread from the r - j entries (broadcast LDS reads)
+        int p = r;
+        double best = -2.0;
+        for (int q = j; q < r; ++q) {
+            double v = cabs2(fcol[q]);
+            if (!(v >= 0.0)) v = -1.0;                  // a non-finite entry ranks below every number
+            if (v > best) { best = v; p = q; }
+        }
+        p = min(p, r - 1);
+        const cplx gjj = fcol[p];
         const bool sing = !(fmax(fabs(gjj.x), fabs(gjj.y)) > 0.0) || !(cabs2(gjj) <= 1e300);
         minp = sing ? 0.0 : fmin(minp, cabs2(gjj));
         const cplx inv = sing ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, gjj);
         if (sing && flag_singular && threadIdx.x == 0) it.mv_singular = 1;
-        // rows j and p trade places; the pivot row is scaled; fcol holds column j of the
-        // swapped matrix (the elimination factors)
-        for (int c = threadIdx.x; c < r; c += nthr) {
-            pa[c] = cmul(Ag[p * r + c], inv);
-            pi[c] = cmul(Ai[p * r + c], inv);
-            ja[c] = Ag[j * r + c];
-            ji[c] = Ai[j * r + c];
-            fcol[c] = c == p ? Ag[j * r + j] : Ag[c * r + j];
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < r * r; e += nthr) {
-            const int a = e / r, c = e % r;
-            if (a == j) {
-                Ag[e] = pa[c];
-                Ai[e] = pi[c];
-            } else {
-                const cplx f = fcol[a];
-                const cplx ga = a == p ? ja[c] : Ag[e], ia = a == p ? ji[c] : Ai[e];
-                Ag[e] = csub(ga, cmul(f, pa[c]));
-                Ai[e] = csub(ia, cmul(f, pi[c]));
+        // rows j and p trade places and the pivot row is scaled: the pivot rows (scaled) and the old
+        // rows j of A and of A^{-1}
+        auto rows = [&](const cplx &v, int c) {
+            if (c < r) {
+                if (a == p) {
+                    pa[c] = cmul(v, inv);
+                    pi[c] = cmul(Ai[p * r + c], inv);
+                }
+                if (a == j) {
+                    ja[c] = v;
+                    ji[c] = Ai[j * r + c];
+                }
             }
+        };
+        rows(ag0, c0);
+        rows(ag1, c0 + 16);
+        rows(ag2, c0 + 32);
+        rows(ag3, c0 + 48);
+        __syncthreads();
+        // elimination; the factor of row a is A(a, j), that of the swapped row p is A(j, j)
+        if (arow) {
+            const cplx f = a == p ? fcol[j] : fcol[a];
+            auto elim = [&](cplx &v, int c) {
+                if (c < r) {
+                    if (a == j) {
+                        v = pa[c];
+                        Ai[a * r + c] = pi[c];
+                    } else {
+                        const cplx ga = a == p ? ja[c] : v, ia = a == p ? ji[c] : Ai[a * r + c];
+                        v = csub(ga, cmul(f, pa[c]));
+                        Ai[a * r + c] = csub(ia, cmul(f, pi[c]));
+                    }
+                }
+            };
+            elim(ag0, c0);
+            elim(ag1, c0 + 16);
+            elim(ag2, c0 + 32);
+            elim(ag3, c0 + 48);
         }
         __syncthreads();
     }
     return minp;
 }
 
-// Bc = Y[cand] A^{-1} (Kc x r, row-major) on the FP64 matrix cores: each wave forms 16-row panels
-// of the candidate block (all r columns as up to four 16 x 16 tiles, three real products per complex
-// one, Gauss); A^{-1} is in LDS with row stride r. Operand and accumulator lane layouts as in
-// k_interp. Every thread of the workgroup calls it; control flow is uniform within a wave.
+// Bc = Y[cand] A^{-1} (Kc x r, row-major) on the FP64 matrix cores: each wave forms 16 x 16 tiles
+// of the candidate block one at a time (three real products per complex one, Gauss), so that the
+// accumulators take 24 registers and the maxvol kernels keep two workgroups per CU; A^{-1} is in
+// LDS with row stride r. Operand and accumulator lane layouts as in k_interp. Every thread of the
+// workgroup calls it; control flow is uniform within a wave.
 __device__ void block_times_inverse(const cplx *Y, const int *cand, int Kc, int r, const cplx *Ai, cplx *Bc)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4, ntile = (r + 15) / 16;
-    for (int g0 = 16 * wave; g0 < Kc; g0 += 16 * nw) {
-        double4_t prr[4], pii[4], pss[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-            pii[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-            pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-        }
-        const int arow = g0 + li;
+    const int ntot = ((Kc + 15) / 16) * ntile;
+    for (int tt = wave; tt < ntot; tt += nw) {
+        const int g0 = 16 * (tt / ntile), q = tt % ntile;
+        double4_t prr = {0.0, 0.0, 0.0, 0.0}, pii = {0.0, 0.0, 0.0, 0.0}, pss = {0.0, 0.0, 0.0, 0.0};
+        const int arow = g0 + li, jj = 16 * q + li;
         const cplx *y = Y + (size_t)cand[min(arow, Kc - 1)] * r;
         for (int k0 = 0; k0 < r; k0 += 4) {
             const int kk = k0 + lk;
             const cplx a = (arow < Kc && kk < r) ? y[kk] : cplx{0.0, 0.0};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q >= ntile) break;
-                const int jj = 16 * q + li;
-                const cplx b = (kk < r && jj < r) ? Ai[kk * r + jj] : cplx{0.0, 0.0};
-                prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
-                pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
-                pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
-            }
+            const cplx b = (kk < r && jj < r) ? Ai[kk * r + jj] : cplx{0.0, 0.0};
+            prr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr, 0, 0, 0);
+            pii = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii, 0, 0, 0);
+            pss = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss, 0, 0, 0);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = g0 + lk + 4 * v;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q >= ntile) break;
-                const int col = 16 * q + li;
-                if (row < Kc && col < r)
-                    Bc[(size_t)row * r + col] = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
-            }
+            if (row < Kc && jj < r) Bc[(size_t)row * r + jj] = {prr[v] - pii[v], pss[v] - prr[v] - pii[v]};
         }
     }
 }
@@ -1764,10 +1786,12 @@ __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, do
 
 // Start of maxvol by Gaussian elimination with partial pivoting on a block S (n x r, global
 // memory, row g of S is row rowmap[g] of Y, or row g when rowmap is null). chosen[n] flags the
-// rows taken (cleared by the caller). Stops at the first column whose largest remaining entry
-// has squared modulus <= ptol2 and returns its index; returns r when all r pivots were found.
+// rows taken (cleared by the caller); gsel (optional) receives the block row of each pivot. Stops
+// at the first column whose largest remaining entry has squared modulus <= ptol2 and returns its
+// index; returns r when all r pivots were found. A pivot row keeps its values from the step that
+// chose it (its entries from that column on are the elimination's U row).
 __device__ __forceinline__ int lu_start(cplx *S, int n, int r, const int *rowmap, int *chosen, int *piv, double ptol2, cplx *prow,
-                        ArgMax *red, int *shi)
+                        ArgMax *red, int *shi, int *gsel = nullptr)
 {
     const int nthr = blockDim.x;
     for (int j = 0; j < r; ++j) {
@@ -1785,6 +1809,7 @@ __device__ __forceinline__ int lu_start(cplx *S, int n, int r, const int *rowmap
         if (threadIdx.x == 0) {
             chosen[p] = 1;
             piv[j] = rowmap ? rowmap[p] : p;
+            if (gsel) gsel[j] = p;
         }
         __syncthreads();
         const int w = r - j - 1;
@@ -1846,19 +1871,21 @@ __device__ int map_previous_pivots(const Item &it, const StepShape &s, int dir, 
     return shi[3];
 }
 
-// Abuf is dynamic LDS of 2 rmax^2 complex entries (rmax: the largest rank of the launch): the
-// key buffer of the start and the two r x r blocks of the Gauss-Jordan inverse.
-__global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm)
+// Abuf is dynamic LDS of rmax^2 complex entries (rmax: the largest rank of the launch): the key
+// buffer of the start, then A^{-1} (the Gauss-Jordan inverse keeps A itself in registers). With
+// the static arrays a workgroup takes under 80 KiB at rank 64, so two run on a CU. 1024 threads.
+__global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm)
 {
     extern __shared__ cplx Abuf[];
-    const int cap = 2 * rmax * rmax;                 // entries of Abuf
-    cplx *Ag = Abuf, *Ai = Abuf + rmax * rmax;
+    const int cap = rmax * rmax;                     // entries of Abuf
+    cplx *Ai = Abuf;
     __shared__ cplx prow[TTFP_MAX_RANK];
     __shared__ cplx fcol[TTFP_MAX_RANK];
     __shared__ int piv[TTFP_MAX_RANK];
+    __shared__ int gsel[TTFP_MAX_RANK];
     __shared__ int cand[MV_KMAX];
-    __shared__ int chosen[MV_KMAX];
     __shared__ cplx colv[MV_KMAX];
+    int *chosen = reinterpret_cast<int *>(colv);     // the start's row flags (colv is free then)
     __shared__ ArgMax red[17];
     __shared__ int shi[4];
     __shared__ float shf[2];
@@ -1883,8 +1910,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     int K = MV_KMAX;
     K = min(K, nk);
     float *key = (float *)Abuf;
-    // the group keys in Abuf (formed again by the fallback below when a warm start's inverse has
-    // overwritten them); returns their largest value, in every thread
+    // the group keys in Abuf; returns their largest value, in every thread
     auto group_keys = [&](bool clear_marks) -> float {
         float kx = 0.0f;
         for (int g = threadIdx.x; g < nk; g += nthr) {
@@ -1924,7 +1950,6 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
             if (v > best) { best = v; bi = i; }
         }
         cand[q] = bi;
-        chosen[q] = 0;
     }
     __syncthreads();
     // ---- 1c. start: elimination with partial pivoting on the block S = Y[cand] (a copy in W).
@@ -1940,52 +1965,46 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     // the elimination start is then skipped and A^{-1} is already formed.
     bool warm_ok = false;
     if (warm && dir != 2 && it.half >= 2 + dir && map_previous_pivots(it, s, dir, piv, shi) == r)
-        warm_ok = gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it, false) > ptol2;
+        warm_ok = gj_inverse(Y, piv, r, m, Ai, colv, shi, it, false) > ptol2;
     if (!warm_ok) {
         cplx *S = W;
         for (long long e = threadIdx.x; e < (long long)Kc * r; e += nthr)
             S[e] = Y[(size_t)cand[e / r] * r + e % r];
+        for (int g = threadIdx.x; g < Kc; g += nthr) chosen[g] = 0;
         __syncthreads();
-        int nf = lu_start(S, Kc, r, cand, chosen, piv, ptol2, prow, red, shi);
+        int nf = lu_start(S, Kc, r, cand, chosen, piv, ptol2, prow, red, shi, gsel);
         if (nf < r) {
-            int *flag = reinterpret_cast<int *>(B);
-            int *rows2 = flag + m;
-            const int K2 = min(min(2048, m), nk);
-            int n2 = m;
-            const int *map = nullptr;
-            if (K2 < m) {
-                // the K2 largest groups (their keys formed again: a warm start's inverse may
-                // have used Abuf), resolved to rows
-                (void)group_keys(false);
-                int *grp = rows2;
-                n2 = select_largest(key, 1, nk, K2, 0.0f, kmax, grp, red, shi, shf);
-                for (int q = threadIdx.x; q < n2; q += nthr) {
-                    const int g = grp[q];
-                    int bi = g * gsz;
-                    double best = -1.0;
-                    for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
-                        const cplx *y = Y + (size_t)i * r;
-                        double v = 0.0;
-                        for (int c = 0; c < r; ++c) v += cabs2(y[c]);
-                        if (v > best) { best = v; bi = i; }
-                    }
-                    grp[q] = bi;
+            // The block spans only nf dimensions (this happens when many integrand values underflow
+            // to zero and the largest rows share their support): the elimination continues over all
+            // m rows. With U the nf pivot rows as eliminated (U11 their leading triangle, U12 the
+            // rest), every row's residual in the columns nf..r-1 is R_i = Y[i, nf:] - Y[i, :nf] T,
+            // T = U11^{-1} U12 (the values the same elimination would leave in it); elimination
+            // with partial pivoting on R gives the remaining pivots.
+            const int w = r - nf;
+            int *flag = reinterpret_cast<int *>(B);      // m row flags (B is written only by k_interp)
+            cplx *U = Abuf;                              // nf x r (nf r < cap)
+            for (int e = threadIdx.x; e < nf * r; e += nthr) U[e] = S[(size_t)gsel[e / r] * r + e % r];
+            for (int i = threadIdx.x; i < m; i += nthr) flag[i] = 0;
+            __syncthreads();
+            for (int q = threadIdx.x; q < nf; q += nthr) flag[piv[q]] = 1;
+            // T in place of U12 by back substitution, one column per thread
+            for (int c = threadIdx.x; c < w; c += nthr)
+                for (int q = nf - 1; q >= 0; --q) {
+                    cplx acc = U[q * r + nf + c];
+                    for (int q2 = q + 1; q2 < nf; ++q2) acc = csub(acc, cmul(U[q * r + q2], U[q2 * r + nf + c]));
+                    U[q * r + nf + c] = cdiv(acc, U[q * r + q]);
                 }
-                __syncthreads();
-                map = rows2;
+            __syncthreads();
+            cplx *Rm = W;                                // m x w residuals (the block copy is no longer needed)
+            for (long long e = threadIdx.x; e < (long long)m * w; e += nthr) {
+                const int i = (int)(e / w), c = (int)(e % w);
+                const cplx *y = Y + (size_t)i * r;
+                cplx acc = y[nf + c];
+                for (int q = 0; q < nf; ++q) acc = csub(acc, cmul(y[q], U[q * r + nf + c]));
+                Rm[e] = acc;
             }
-            for (int pass = 0; pass < 2 && nf < r; ++pass) {
-                if (pass == 0 && n2 == m) continue;        // the larger block is all rows already
-                const int nn = pass == 0 ? n2 : m;
-                const int *mp = pass == 0 ? map : nullptr;
-                for (long long e = threadIdx.x; e < (long long)nn * r; e += nthr) {
-                    const int g = (int)(e / r);
-                    S[e] = Y[(size_t)(mp ? mp[g] : g) * r + e % r];
-                }
-                for (int g = threadIdx.x; g < nn; g += nthr) flag[g] = 0;
-                __syncthreads();
-                nf = lu_start(S, nn, r, mp, flag, piv, pass == 0 ? ptol2 : 0.0, prow, red, shi);
-            }
+            __syncthreads();
+            nf += lu_start(Rm, m, w, nullptr, flag, piv + nf, 0.0, prow, red, shi);
             if (nf < r) {
                 // Y itself is rank deficient: the remaining pivots are the lowest untaken rows
                 if (threadIdx.x == 0) {
@@ -2008,7 +2027,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
         }
         __syncthreads();
         // ---- 2. A^{-1} (unless the warm start formed it)
-        gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
+        gj_inverse(Y, piv, r, m, Ai, colv, shi, it);
     }
     // the block's rows of B (in W, over the start's copy)
     cplx *Bc = W;
@@ -2017,7 +2036,7 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
     // ---- 3. swaps within the block, 4. A^{-1} of the final pivots
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red, Ai, fcol);
-    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
+    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ai, colv, shi, it);
     __syncthreads();
     for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
     for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
@@ -2034,10 +2053,10 @@ __global__ __launch_bounds__(1024) void k_maxvol(Item *items, const int *active,
 
 // Refinement round: the pivots and up to MV_KMAX - r rows that k_interp found violating (largest
 // first) form the block; swaps as in k_maxvol. Returns at once when no row violated.
-__global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax)
+__global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax)
 {
     extern __shared__ cplx Abuf[];
-    cplx *Ag = Abuf, *Ai = Abuf + rmax * rmax;
+    cplx *Ai = Abuf;                                 // rmax^2 entries
     __shared__ cplx prow[TTFP_MAX_RANK];
     __shared__ cplx fcol[TTFP_MAX_RANK];
     __shared__ int piv[TTFP_MAX_RANK];
@@ -2058,7 +2077,6 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
     const int m = s.rows, r = it.rsel, nthr = blockDim.x;
     const cplx *Y = it.Y;
     cplx *W = it.W;
-    const cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
     for (int c = threadIdx.x; c < r; c += nthr) {
         piv[c] = it.piv[c];
         cand[c] = piv[c];
@@ -2078,19 +2096,19 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
     const int Kc = r + nv;
     __syncthreads();
     for (int i = threadIdx.x; i < m; i += nthr) it.viol[i] = 0.0f;   // for the next k_interp
-    // block rows: the pivots (rows of the identity) and the violating rows of B
+    // block rows: the pivots (rows of the identity) and the violating rows of B = Y A^{-1},
+    // formed here on the matrix cores (the checking passes of k_interp do not store B)
     cplx *Bc = W;
-    for (int e = threadIdx.x; e < Kc * r; e += nthr) {
-        const int q = e / r, c = e % r;
-        Bc[e] = q < r ? cplx{q == c ? 1.0 : 0.0, 0.0}
-                      : B[dir == 1 ? (size_t)c * m + cand[q] : (size_t)cand[q] * r + c];
+    for (int e = threadIdx.x; e < r * r; e += nthr) {
+        Ai[e] = it.Ai[e];
+        Bc[e] = cplx{e / r == e % r ? 1.0 : 0.0, 0.0};
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < r * r; e += nthr) Ai[e] = it.Ai[e];
+    block_times_inverse(Y, cand + r, Kc - r, r, Ai, Bc + (size_t)r * r);
     __syncthreads();
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red, Ai, fcol);
-    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ag, Ai, fcol, shi, it);
+    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ai, colv, shi, it);
     __syncthreads();
     if (swaps > 0) {
         for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
@@ -2112,7 +2130,10 @@ __global__ __launch_bounds__(1024) void k_maxvol_refine(Item *items, const int *
 // accumulator rows l / 16 + 4 v, column l % 16 (v = 0..3; the layout was checked by a probe
 // against a host product). B goes straight into the core's slot. Rows whose largest |B_ij|
 // exceeds 1 + delta are marked (largest squared modulus in viol) and the item is flagged for a
-// refinement round. mode 1: only after a refinement that moved a pivot.
+// refinement round. mode 0: a checking pass over every item; mode 1: a checking pass, only after a
+// refinement that moved a pivot; mode 2: the final pass over every item, which stores B (into the
+// core slot) and marks nothing. Only the final pass writes B: a checking pass reads Y and writes
+// the marks alone.
 constexpr int INTERP_WAVES = MM_WAVES;           // 16-row panels per workgroup
 __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const int *active, int t, int dir, int mode)
 {
@@ -2123,6 +2144,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
     if (mode == 1 && !it.mv_dirty) return;
+    const bool store = mode == 2;
     const int r = it.rsel, m = s.rows;
     const int rows_per_wg = 16 * INTERP_WAVES;
     if (blockIdx.x * rows_per_wg >= m) return;
@@ -2173,10 +2195,11 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
             const int col = 16 * q + li;
             if (row < m && col < r) {
                 const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
-                B[dir == 1 ? (size_t)col * m + row : (size_t)row * r + col] = val;
+                if (store) B[dir == 1 ? (size_t)col * m + row : (size_t)row * r + col] = val;
                 mx = fmax(mx, cabs2(val));
             }
         }
+        if (store) continue;
         // largest entry of the row over the 16 lanes that hold its columns
         for (int o = 8; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
         if (li == 0 && row < m && mx > lim && mx <= 1e300) {
