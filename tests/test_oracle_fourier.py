@@ -195,7 +195,8 @@ def test_dense_two_asset_sum_rule():
 
 @pytest.mark.slow
 def test_dense_three_assets_random_correlation_against_mc():
+    # brute-force Monte Carlo with 10^8 paths (exact terminal sampling) at d = 3 with a random correlation
     opt = W.random_small_options(1, seed=8, d_choices=(3,), payoffs=("call_max",))[0]
-    v, se = mc.mc_price(opt, 20_000_000, seed=3)
+    v, se = mc.mc_price(opt, 100_000_000, seed=3)
     p = F.dense_price(opt, 96)
     assert abs(p - v) < 4 * se
