@@ -395,6 +395,9 @@ def main():
     ap.add_argument("--mv-rounds", type=int, default=3, help="maxvol refinement rounds after the block start")
     ap.add_argument("--mv-warm", type=int, default=1, choices=(0, 1),
                     help="maxvol starts from the previous same-direction pivots (1) or always by elimination (0)")
+    ap.add_argument("--mm-waves", type=int, default=None, choices=(8, 16),
+                    help="16-row panels per workgroup of the basis and interpolation products (default: the "
+                         "autotuner's stored choice for the workload's shape, else 8)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of a known size (scales the HBM byte counters of a profiler)")
     args = ap.parse_args()
@@ -429,8 +432,12 @@ def main():
     pricer = ttfp.Pricer(0)
     pricer.set_tuning(qr={"cholqr": 0, "tsqr": 1, "cholqr2": 2, "cholqr3": 3}[args.qr], maxvol_rounds=args.mv_rounds,
                       maxvol_warm=args.mv_warm)
+    if args.mm_waves is not None:
+        pricer.autotune = False
+        pricer.set_tuning(mm_waves=args.mm_waves)
     log(f"bench: d=5 Sigma(0.5) N={args.N} R={args.max_rank} batch={B} warmup={args.warmup} steps={args.steps}")
     prices, status, elapsed, prof = time_batches(pricer, batches, grid, args.warmup, not args.no_profile)
+    launch_tuning = pricer.get_tuning()
     n_opt = B * args.steps
     rel = np.abs(prices / refs - 1.0)
     good = int(np.sum(rel <= 1e-6))
@@ -546,7 +553,7 @@ def main():
                                f"other draws, N={args.N}, tol 1e-8, max rank {args.max_rank}, batched TT-cross; "
                                f"value counts options within 1e-6 of the one-factor reference",
                    "global_batch": B, "d": 5, "N": args.N, "max_rank": args.max_rank, "tol": 1e-8,
-                   "parallelism": "none (1 GPU)"},
+                   "parallelism": "none (1 GPU)", "launch_tuning": launch_tuning},
         "roofline": roofline,
         "cpu_baseline": base,
         "throughput_all_options_per_s": n_opt / elapsed,

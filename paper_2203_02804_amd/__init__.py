@@ -62,7 +62,7 @@ EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price
            "ttfp_mlp_last_error"]
 KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract", "interp", "err_est",
            "gram", "chol", "xform", "ladder"]
-TUNING = {"maxvol_rounds": 0, "tsqr_lds_kb": 1, "graph": 2, "qr": 3, "maxvol_warm": 4}
+TUNING = {"maxvol_rounds": 0, "tsqr_lds_kb": 1, "graph": 2, "qr": 3, "maxvol_warm": 4, "mm_waves": 5}
 
 _lib = None
 
@@ -198,6 +198,20 @@ class Pricer:
         rc = self.lib.ttfp_create(ctypes.byref(self.ctx), int(device), ctypes.c_void_p(stream.cuda_stream))
         if rc != 0:
             raise TTFPError(rc, "ttfp_create failed")
+        # price_batch applies the autotuner's stored launch setting for its batch's shape (only
+        # settings that leave results unchanged bit for bit); False keeps the context's own
+        self.autotune = True
+
+    def _apply_tuned(self, opts, grids):
+        if not self.autotune or not opts:
+            return None
+        ds = {int(o["d"]) for o in opts}
+        Ns = {int(g["N"]) for g in grids}
+        Rs = {int(g.get("max_rank", 32)) for g in grids}
+        if len(ds) == 1 and len(Ns) == 1 and len(Rs) == 1:
+            from . import tuning
+            return tuning.apply(self, ds.pop(), Ns.pop(), Rs.pop())
+        return None
 
     def close(self):
         if self.ctx:
@@ -275,6 +289,7 @@ class Pricer:
         n = len(opts)
         if isinstance(grids, dict):
             grids = [grids] * n
+        self._apply_tuned(opts, grids)
         ms = [_Marshal(o, g) for o, g in zip(opts, grids)]
         copts = (_Option * n)(*[m.opt for m in ms])
         cgrids = (_Grid * n)(*[m.grid for m in ms])

@@ -24,10 +24,10 @@ __global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, i
 __global__ void k_gram(Item *items, const int *active, int t, int dir, int pass);
 __global__ void k_chol(Item *items, const int *active, int t, int dir, int pass, int last);
 __global__ void k_xform(Item *items, const int *active, int t, int dir, int pass);
-__global__ void k_basis(Item *items, const int *active, int t, int dir);
+template <int W> __global__ void k_basis(Item *items, const int *active, int t, int dir);
 __global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm);
 __global__ void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax);
-__global__ void k_interp(Item *items, const int *active, int t, int dir, int mode);
+template <int W> __global__ void k_interp(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_finish(Item *items, const int *active, int t, int dir);
 __global__ void k_core_sum(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_contract(Item *items, const int *active);
@@ -65,6 +65,7 @@ struct ttfp_ctx {
     // tuning (set by ttfp_set_tuning, chosen by the autotuner)
     int tune_maxvol_rounds = 3;           // refinement rounds of maxvol after the block start
     int tune_maxvol_warm = 1;             // maxvol starts from the previous same-direction pivots
+    int tune_mm_waves = 8;                // 16-row panels per workgroup of the basis and interpolation products
     int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 1;                   // graph replay whenever the stream is not the null stream
@@ -485,6 +486,24 @@ void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int 
     }
 }
 
+// The basis and interpolation products with TTFP_TUNE_MM_WAVES 16-row panels per workgroup.
+void launch_basis(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir)
+{
+    if (ctx->tune_mm_waves == 16)
+        hipLaunchKernelGGL(k_basis<16>, dim3(cdivu(rows, 16 * 16), ny), dim3(64 * 16), 0, st, it, act, t, dir);
+    else
+        hipLaunchKernelGGL(k_basis<8>, dim3(cdivu(rows, 16 * 8), ny), dim3(64 * 8), 0, st, it, act, t, dir);
+}
+
+void launch_interp(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir,
+                   int mode)
+{
+    if (ctx->tune_mm_waves == 16)
+        hipLaunchKernelGGL(k_interp<16>, dim3(cdivu(rows, 16 * 16), ny), dim3(64 * 16), 0, st, it, act, t, dir, mode);
+    else
+        hipLaunchKernelGGL(k_interp<8>, dim3(cdivu(rows, 16 * 8), ny), dim3(64 * 8), 0, st, it, act, t, dir, mode);
+}
+
 int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
 {
     hipStream_t st = ctx->stream;
@@ -512,7 +531,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_BASIS);
-        hipLaunchKernelGGL(k_basis, dim3(cdivu((long long)g.maxrows, MM_ROWS_PER_WG), ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir);
+        launch_basis(ctx, st, it, act, g.maxrows, ny, t, dir);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
@@ -523,11 +542,10 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     // checking passes of the interpolation matrix over every row, each followed by a refinement
     // round (both return at once for an item whose rows all satisfy the dominance bound), then the
     // pass that stores B
-    const unsigned gi = cdivu((long long)g.maxrows, MM_ROWS_PER_WG);   // row blocks of k_interp
     for (int round = 0; round < ctx->tune_maxvol_rounds; ++round) {
         {
             ProfScope ps(ctx, TTFP_KERNEL_INTERP);
-            hipLaunchKernelGGL(k_interp, dim3(gi, ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir, round > 0 ? 1 : 0);
+            launch_interp(ctx, st, it, act, g.maxrows, ny, t, dir, round > 0 ? 1 : 0);
         }
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
         const int rm = std::max(g.maxR, 2);
@@ -536,7 +554,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_INTERP);
-        hipLaunchKernelGGL(k_interp, dim3(gi, ny), dim3(64 * MM_WAVES), 0, st, it, act, t, dir, 2);
+        launch_interp(ctx, st, it, act, g.maxrows, ny, t, dir, 2);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_FINISH);
@@ -895,6 +913,10 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
         if (value != 0 && value != 1) break;
         ctx->tune_maxvol_warm = value;
         return TTFP_OK;
+    case TTFP_TUNE_MM_WAVES:
+        if (value != 8 && value != 16) break;
+        ctx->tune_mm_waves = value;
+        return TTFP_OK;
     default:
         break;
     }
@@ -911,6 +933,7 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value)
     case TTFP_TUNE_GRAPH: *value = ctx->tune_graph; return TTFP_OK;
     case TTFP_TUNE_QR: *value = ctx->tune_qr; return TTFP_OK;
     case TTFP_TUNE_MAXVOL_WARM: *value = ctx->tune_maxvol_warm; return TTFP_OK;
+    case TTFP_TUNE_MM_WAVES: *value = ctx->tune_mm_waves; return TTFP_OK;
     default: return TTFP_EINVAL;
     }
 }
@@ -1610,12 +1633,11 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
         hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm, 0);
         // refinement rounds until every row satisfies the dominance bound (each round returns at
         // once when none violates)
-        const unsigned gi = cdivu((long long)m, MM_ROWS_PER_WG);
         for (int round = 0; round < 8; ++round) {
-            hipLaunchKernelGGL(k_interp, dim3(gi, 1), dim3(64 * MM_WAVES), 0, ctx->stream, dit, act, 0, 2, round > 0 ? 1 : 0);
+            launch_interp(ctx, ctx->stream, dit, act, m, 1, 0, 2, round > 0 ? 1 : 0);
             hipLaunchKernelGGL(k_maxvol_refine, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
         }
-        hipLaunchKernelGGL(k_interp, dim3(gi, 1), dim3(64 * MM_WAVES), 0, ctx->stream, dit, act, 0, 2, 2);
+        launch_interp(ctx, ctx->stream, dit, act, m, 1, 0, 2, 2);
         e = hipGetLastError();
     }
     e = e ? e : hipStreamSynchronize(ctx->stream);

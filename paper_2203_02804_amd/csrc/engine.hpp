@@ -14,9 +14,6 @@ namespace ttfp {
 
 constexpr int MAXD = TTFP_MAX_D;
 constexpr int MAXNC = TTFP_MAX_RANK + 4;     // fiber columns: rank + enrichment
-// rows of Y (k_basis) or B (k_interp) per workgroup: one 16-row panel per wave, 8 waves
-constexpr int MM_WAVES = 8;
-constexpr int MM_ROWS_PER_WG = 16 * MM_WAVES;
 // threads of the column-pivoted QR (one workgroup per item; its LDS allows one per CU)
 constexpr int QRCP_THREADS = 1024;
 constexpr int MAXN = 1024;                   // nodes per coordinate

@@ -1433,8 +1433,11 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
 // 16-row panel as up to four 16 x 16 complex tiles, three real MFMA products each); the
 // triangular inverse is held in LDS with its zero lower part. Each row's squared norm goes to
 // its key (the start of maxvol reads them).
-constexpr int PANEL_WAVES = MM_WAVES;            // 16-row panels per workgroup
-__global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const int *active, int t, int dir)
+// PANEL_WAVES 16-row panels per workgroup, 8 or 16: a launch tuning that leaves every result bit
+// unchanged (a row's product does not depend on the workgroup it falls in). With 16 the 64 KiB
+// staging of R^-1 serves twice the rows.
+template <int PANEL_WAVES>
+__global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, const int *active, int t, int dir)
 {
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
     __shared__ int pm[TTFP_MAX_RANK];
@@ -1498,6 +1501,8 @@ __global__ __launch_bounds__(64 * PANEL_WAVES) void k_basis(Item *items, const i
         if (row < m && li == 0) it.keys[row] = (float)nrm;
     }
 }
+template __global__ void k_basis<8>(Item *, const int *, int, int);
+template __global__ void k_basis<16>(Item *, const int *, int, int);
 
 // ------------------------------------------------------------------ maxvol
 // block-wide argmax (ties: lowest flat index); every thread receives the result: within each wave
@@ -2134,8 +2139,9 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const in
 // refinement that moved a pivot; mode 2: the final pass over every item, which stores B (into the
 // core slot) and marks nothing. Only the final pass writes B: a checking pass reads Y and writes
 // the marks alone.
-constexpr int INTERP_WAVES = MM_WAVES;           // 16-row panels per workgroup
-__global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const int *active, int t, int dir, int mode)
+// INTERP_WAVES 16-row panels per workgroup: 8 or 16, as for k_basis.
+template <int INTERP_WAVES>
+__global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, const int *active, int t, int dir, int mode)
 {
     __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
     const int item = blockIdx.y;
@@ -2208,6 +2214,8 @@ __global__ __launch_bounds__(64 * INTERP_WAVES) void k_interp(Item *items, const
         }
     }
 }
+template __global__ void k_interp<8>(Item *, const int *, int, int, int);
+template __global__ void k_interp<16>(Item *, const int *, int, int, int);
 
 // ------------------------------------------------------------------ index sets and core placement
 __global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, int t, int dir)
