@@ -74,6 +74,7 @@ struct Item {
     int mv_singular;                  // a maxvol start matrix was exactly singular
     int mv_viol;                      // k_interp found rows with |B_ij| > 1 + delta
     int mv_dirty;                     // the pivots moved since B was last formed
+    double mv_colmax;                 // largest squared column norm of A^{-1} (the checking passes' row bound)
     double work[TTFP_KERNEL_COUNT];   // algorithmic work per kernel family (bytes or flops)
     cplx P;                           // latest contraction of the tensor train
     double err_abs, err_ref;          // sampled error: sum |TT - A| and sum |A| over n_samp points

@@ -393,6 +393,7 @@ __global__ void k_init(Item *items, int n_items)
     it.mv_singular = 0;
     it.mv_viol = 0;
     it.mv_dirty = 0;
+    it.mv_colmax = INFINITY;
     for (int q = 0; q < TTFP_KERNEL_COUNT; ++q) it.work[q] = 0.0;
     it.capped = 0;
     long long cnt = 1;
@@ -1876,6 +1877,20 @@ __device__ int map_previous_pivots(const Item &it, const StepShape &s, int dir, 
     return shi[3];
 }
 
+// The largest squared column norm of A^{-1} (LDS, r x r, row stride r), by wave 0, into
+// it.mv_colmax: with the squared row norms of Y it bounds every |B_ij|^2 = |y_i A^{-1} e_j|^2 by
+// Cauchy-Schwarz, which lets k_interp's checking passes skip rows that cannot violate.
+__device__ void store_colmax(const cplx *Ai, int r, Item &it)
+{
+    if (threadIdx.x < 64) {
+        double v = 0.0;
+        if ((int)threadIdx.x < r)
+            for (int k = 0; k < r; ++k) v += cabs2(Ai[k * r + threadIdx.x]);
+        v = wave_max(v);
+        if (threadIdx.x == 0) it.mv_colmax = v;
+    }
+}
+
 // Abuf is dynamic LDS of rmax^2 complex entries (rmax: the largest rank of the launch): the key
 // buffer of the start, then A^{-1} (the Gauss-Jordan inverse keeps A itself in registers). With
 // the static arrays a workgroup takes under 80 KiB at rank 64, so two run on a CU. 1024 threads.
@@ -2045,6 +2060,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *acti
     __syncthreads();
     for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
     for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
+    store_colmax(Ai, r, it);
     if (threadIdx.x == 0) {
         it.mv_iters += swaps;
         it.mv_viol = 0;
@@ -2118,6 +2134,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const in
     if (swaps > 0) {
         for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
         for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
+        store_colmax(Ai, r, it);
     }
     if (threadIdx.x == 0) {
         it.mv_iters += swaps;
@@ -2154,13 +2171,29 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
     const int r = it.rsel, m = s.rows;
     const int rows_per_wg = 16 * INTERP_WAVES;
     if (blockIdx.x * rows_per_wg >= m) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_INTERP] += 8.0 * (double)m * r * r;
+    const double lim = (1.0 + it.delta) * (1.0 + it.delta);
+    // A checking pass skips the rows that cannot violate: |B_ij|^2 <= |y_i|^2 max_j |A^{-1} e_j|^2
+    // (the row norms from k_basis, held as floats: the margin covers their rounding). A workgroup
+    // whose rows all stay below the bound returns before staging A^{-1}; so does a wave.
+    const bool check = !store && dir != 2;
+    const double cm = 1.001 * it.mv_colmax;
+    if (check) {
+        const int row = blockIdx.x * rows_per_wg + (int)threadIdx.x;
+        const bool need = (int)threadIdx.x < rows_per_wg && row < m && !((double)it.keys[row] * cm <= lim);
+        if (!__syncthreads_or(need)) return;
+    }
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ai[e] = it.Ai[e];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = blockIdx.x * rows_per_wg + wave * 16;
     if (row0 >= m) return;
     const int li = lane & 15, lk = lane >> 4;
+    if (check) {
+        const int row = row0 + li;
+        if (!__any(row < m && !((double)it.keys[row] * cm <= lim))) return;
+    }
+    // the work done: this panel's rows
+    if (lane == 0) atomicAdd(&it.work[TTFP_KERNEL_INTERP], 8.0 * (double)min(16, m - row0) * r * r);
     const int ntile = (r + 15) / 16;
     const cplx *Y = it.Y;
     // complex products by three real ones (Gauss): prr = Ar Br, pii = Ai Bi, pss = (Ar + Ai)(Br + Bi);
@@ -2190,7 +2223,6 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
     // a x N x b layout) and B transposed for a right-to-left one (rows (i, b), columns a);
     // the raw entry point's B is row-major in Bt
     cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
-    const double lim = (1.0 + it.delta) * (1.0 + it.delta);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = row0 + lk + 4 * v;
