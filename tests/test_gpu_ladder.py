@@ -29,7 +29,9 @@ def _points(opt, n, seed):
 
 def _check(pricer, opt, N, tol, R, n, seed, bound):
     grids = np.array(F.term_grids(opt, N, tol=tol)[1])     # the oracle's grid for the base option
-    g = dict(W.grid(N, tol=tol, max_rank=R, max_sweeps=8), L=grids[:, 0], alpha=grids[:, 1])
+    # 12 sweeps: at tol 1e-11 the three-asset cross started from the previous pivots needs 18 half
+    # sweeps to meet the price-change test (15 with the elimination start)
+    g = dict(W.grid(N, tol=tol, max_rank=R, max_sweeps=12), L=grids[:, 0], alpha=grids[:, 1])
     S0, K, r = _points(opt, n, seed)
     prices, info, rc = pricer.price_ladder(opt, g, S0, K, r)
     assert rc == 0, info
