@@ -330,7 +330,13 @@ def measured_traffic(kernel):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    entry = t.get("kernels", {}).get(kernel)
+    kernels = t.get("kernels", {})
+    entry = kernels.get(kernel)
+    if entry is None:
+        # a templated kernel is listed with its instantiation, e.g. k_interp<8>: the one launched
+        # most often
+        inst = [v for k, v in kernels.items() if k.startswith(kernel + "<")]
+        entry = max(inst, key=lambda v: v.get("dispatches", 0)) if inst else None
     if entry is None or t.get("kernels_sha256") != kernels_digest():
         return None
     return entry["bytes_per_launch"]
