@@ -446,6 +446,9 @@ void prof_collect(ttfp_ctx *ctx)
 // maxvol and its refinement run 1024 threads per workgroup (the Gauss-Jordan inverse holds A in
 // the registers of exactly that many threads); rmax^2 complex entries of dynamic LDS.
 constexpr unsigned MAXVOL_THREADS = 1024;
+// k_maxvol's dynamic LDS holds at least the blocked elimination's panel and trailing parts: 512
+// candidate rows x (7 + 1) complex entries (64 KiB)
+constexpr int MAXVOL_LDS_MIN = 512 * 8;
 
 // Refinement rounds of maxvol after the block start (TTFP_TUNE_MAXVOL_ROUNDS, default 3): each
 // marks the rows of B beyond 1 + delta and swaps them in. More rounds give interpolation nearer to
@@ -536,7 +539,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     {
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
         const int rm = std::max(g.maxR, 2);
-        const size_t lds = (size_t)rm * rm * sizeof(cplx);
+        const size_t lds = (size_t)std::max(rm * rm, MAXVOL_LDS_MIN) * sizeof(cplx);
         hipLaunchKernelGGL(k_maxvol, dim3(ny), dim3(MAXVOL_THREADS), lds, st, it, act, t, dir, rm, ctx->tune_maxvol_warm);
     }
     // checking passes of the interpolation matrix over every row, each followed by a refinement
@@ -1628,7 +1631,7 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
     e = e ? e : hipMemcpy(it.Y, A, 16 * (size_t)m * r, hipMemcpyHostToDevice);
     if (!e) {
         const int rm = std::max(r, 2);
-        const size_t lds = (size_t)rm * rm * sizeof(cplx);
+        const size_t lds = (size_t)std::max(rm * rm, MAXVOL_LDS_MIN) * sizeof(cplx);
         const unsigned th = MAXVOL_THREADS;
         hipLaunchKernelGGL(k_maxvol, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm, 0);
         // refinement rounds until every row satisfies the dominance bound (each round returns at

@@ -1830,6 +1830,74 @@ __device__ __forceinline__ int lu_start(cplx *S, int n, int r, const int *rowmap
     return r;
 }
 
+// The same elimination (the same pivots up to rounding) blocked by panels of MV_NB columns: the
+// panel of the block's rows is factored in LDS (P, column-major, n x w), then the trailing
+// columns of the non-chosen rows take the whole panel's update in one pass over S, with the
+// pivot rows' trailing parts V (w x nt, LDS) formed by forward substitution. S is then read and
+// written once per panel instead of once per column. Returns r, or the first column without a
+// pivot above ptol2 (S is then not in the unblocked elimination's state: the caller eliminates
+// again with lu_start). Every thread of the workgroup calls it.
+constexpr int MV_NB = 7;
+__device__ int lu_start_blocked(cplx *S, int n, int r, const int *rowmap, int *chosen, int *piv, int *gsel, double ptol2,
+                                cplx *P, cplx *V, cplx *prow, cplx *pvt, int *pv, ArgMax *red)
+{
+    const int nthr = blockDim.x;
+    for (int j0 = 0; j0 < r; j0 += MV_NB) {
+        const int w = min(MV_NB, r - j0);
+        for (int e = threadIdx.x; e < n * w; e += nthr) {
+            const int g = e / w, t = e % w;
+            P[t * n + g] = S[(size_t)g * r + j0 + t];
+        }
+        __syncthreads();
+        for (int t = 0; t < w; ++t) {
+            ArgMax a = {-1.0, 0x7fffffff};
+            for (int g = threadIdx.x; g < n; g += nthr)
+                if (!chosen[g]) {
+                    const double v = cabs2(P[t * n + g]);
+                    a = better(a, ArgMax{v <= 1e300 ? v : -1.0, g});
+                }
+            a = block_argmax(a, red);
+            if (!(a.v > ptol2) || a.i < 0 || a.i >= n) return j0 + t;     // same decision in every thread
+            const int p = a.i;
+            const cplx pinv = cdiv({1.0, 0.0}, P[t * n + p]);
+            for (int c = t + 1 + threadIdx.x; c < w; c += nthr) prow[c] = cmul(P[c * n + p], pinv);
+            if (threadIdx.x == 0) {
+                chosen[p] = 1;
+                piv[j0 + t] = rowmap ? rowmap[p] : p;
+                gsel[j0 + t] = p;
+                pv[t] = p;
+                pvt[t] = P[t * n + p];
+            }
+            __syncthreads();
+            const int ww = w - t - 1;
+            for (int e = threadIdx.x; e < n * ww; e += nthr) {
+                const int g = e % n, c = t + 1 + e / n;
+                if (!chosen[g]) P[c * n + g] = csub(P[c * n + g], cmul(P[t * n + g], prow[c]));
+            }
+            __syncthreads();
+        }
+        const int nt = r - j0 - w;
+        if (nt <= 0) break;
+        // V[t] = the pivot row p_t's trailing part after the panel's earlier steps, scaled by its pivot
+        for (int c = threadIdx.x; c < nt; c += nthr)
+            for (int t = 0; t < w; ++t) {
+                cplx acc = S[(size_t)pv[t] * r + j0 + w + c];
+                for (int t2 = 0; t2 < t; ++t2) acc = csub(acc, cmul(P[t2 * n + pv[t]], V[t2 * nt + c]));
+                V[t * nt + c] = cdiv(acc, pvt[t]);
+            }
+        __syncthreads();
+        for (long long e = threadIdx.x; e < (long long)n * nt; e += nthr) {
+            const int g = (int)(e / nt), c = (int)(e % nt);
+            if (chosen[g]) continue;
+            cplx acc = S[(size_t)g * r + j0 + w + c];
+            for (int t = 0; t < w; ++t) acc = csub(acc, cmul(P[t * n + g], V[t * nt + c]));
+            S[(size_t)g * r + j0 + w + c] = acc;
+        }
+        __syncthreads();
+    }
+    return r;
+}
+
 // Warm start of a step from the pivots that the previous half sweep in the same direction chose at
 // this core: each of its multi-indices (the old index set I_{k+1} of a left-to-right step, J_k of a
 // right-to-left one) whose prefix (suffix) is still in the current neighbouring set I_k (J_{k+1})
@@ -1891,18 +1959,21 @@ __device__ void store_colmax(const cplx *Ai, int r, Item &it)
     }
 }
 
-// Abuf is dynamic LDS of rmax^2 complex entries (rmax: the largest rank of the launch): the key
-// buffer of the start, then A^{-1} (the Gauss-Jordan inverse keeps A itself in registers). With
-// the static arrays a workgroup takes under 80 KiB at rank 64, so two run on a CU. 1024 threads.
+// Abuf is dynamic LDS of max(rmax^2, 8 MV_KMAX) complex entries (64 KiB; rmax: the largest rank
+// of the launch): the key buffer of the start, the blocked elimination's panel, then A^{-1} (the
+// Gauss-Jordan inverse keeps A itself in registers). With the static arrays a workgroup takes
+// under 80 KiB, so two run on a CU. 1024 threads.
 __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm)
 {
     extern __shared__ cplx Abuf[];
-    const int cap = rmax * rmax;                     // entries of Abuf
+    const int cap = max(rmax * rmax, MV_KMAX * (MV_NB + 1));   // entries of Abuf
     cplx *Ai = Abuf;
     __shared__ cplx prow[TTFP_MAX_RANK];
     __shared__ cplx fcol[TTFP_MAX_RANK];
     __shared__ int piv[TTFP_MAX_RANK];
     __shared__ int gsel[TTFP_MAX_RANK];
+    __shared__ cplx pvt[MV_NB];
+    __shared__ int pv[MV_NB];
     __shared__ int cand[MV_KMAX];
     __shared__ cplx colv[MV_KMAX];
     int *chosen = reinterpret_cast<int *>(colv);     // the start's row flags (colv is free then)
@@ -1992,7 +2063,17 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *acti
             S[e] = Y[(size_t)cand[e / r] * r + e % r];
         for (int g = threadIdx.x; g < Kc; g += nthr) chosen[g] = 0;
         __syncthreads();
-        int nf = lu_start(S, Kc, r, cand, chosen, piv, ptol2, prow, red, shi, gsel);
+        // panel-blocked in LDS (the panel in Abuf, the pivot rows' trailing parts after it)
+        int nf = lu_start_blocked(S, Kc, r, cand, chosen, piv, gsel, ptol2, Abuf, Abuf + MV_KMAX * MV_NB, prow, pvt, pv, red);
+        if (nf < r) {
+            // a rank-deficient block: eliminated again unblocked, which leaves the pivot rows as
+            // the continuation below needs them
+            for (long long e = threadIdx.x; e < (long long)Kc * r; e += nthr)
+                S[e] = Y[(size_t)cand[e / r] * r + e % r];
+            for (int g = threadIdx.x; g < Kc; g += nthr) chosen[g] = 0;
+            __syncthreads();
+            nf = lu_start(S, Kc, r, cand, chosen, piv, ptol2, prow, red, shi, gsel);
+        }
         if (nf < r) {
             // The block spans only nf dimensions (this happens when many integrand values underflow
             // to zero and the largest rows share their support): the elimination continues over all
