@@ -1285,10 +1285,12 @@ __global__ __launch_bounds__(64 * XF_WAVES) void k_xform(Item *items, const int 
         pss[q] = prr[q];
     }
     const int arow = row0 + li;
+    // the left operand of the next k-step is loaded while this one's products run
+    cplx an = (arow < m && lk < nc) ? src[(size_t)arow * nc + lk] : cplx{0.0, 0.0};
     for (int k0 = 0; k0 < nc; k0 += 4) {
         const int kk = k0 + lk;
-        const bool in = arow < m && kk < nc;
-        const cplx a = in ? src[(size_t)arow * nc + kk] : cplx{0.0, 0.0};
+        const cplx a = an;
+        if (k0 + 4 < nc) an = (arow < m && kk + 4 < nc) ? src[(size_t)arow * nc + kk + 4] : cplx{0.0, 0.0};
         const double ar = a.x * sc, ai = a.y * sc, as = ar + ai;
         const int kr = kk < nc ? kk : 0;           // rows of Xf past nc: the operand is zero anyway
 #pragma unroll
@@ -1469,9 +1471,12 @@ __global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, cons
         pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int arow = row0 + li;
+    // the left operand of the next k-step is loaded while this one's products run
+    cplx an = (arow < m && lk < r) ? it.F[(size_t)arow * nc + pm[lk]] : cplx{0.0, 0.0};
     for (int k0 = 0; k0 < r; k0 += 4) {
         const int kk = k0 + lk;
-        const cplx a = (arow < m && kk < r) ? it.F[(size_t)arow * nc + pm[kk]] : cplx{0.0, 0.0};
+        const cplx a = an;
+        if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? it.F[(size_t)arow * nc + pm[kk + 4]] : cplx{0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= ntile) break;
@@ -2287,9 +2292,12 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
         pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int arow = row0 + li;
+    // the left operand of the next k-step is loaded while this one's products run
+    cplx an = (arow < m && lk < r) ? Y[(size_t)arow * r + lk] : cplx{0.0, 0.0};
     for (int k0 = 0; k0 < r; k0 += 4) {
         const int kk = k0 + lk;
-        const cplx a = (arow < m && kk < r) ? Y[(size_t)arow * r + kk] : cplx{0.0, 0.0};
+        const cplx a = an;
+        if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? Y[(size_t)arow * r + kk + 4] : cplx{0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q >= ntile) break;
