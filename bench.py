@@ -404,6 +404,8 @@ def main():
     ap.add_argument("--mm-waves", type=int, default=None, choices=(8, 16),
                     help="16-row panels per workgroup of the basis and interpolation products (default: the "
                          "autotuner's stored choice for the workload's shape, else 8)")
+    ap.add_argument("--gram-threads", type=int, default=None, choices=(512, 1024),
+                    help="threads per Gram workgroup (default: the autotuner's stored choice, else 512)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of a known size (scales the HBM byte counters of a profiler)")
     args = ap.parse_args()
@@ -438,9 +440,12 @@ def main():
     pricer = ttfp.Pricer(0)
     pricer.set_tuning(qr={"cholqr": 0, "tsqr": 1, "cholqr2": 2, "cholqr3": 3}[args.qr], maxvol_rounds=args.mv_rounds,
                       maxvol_warm=args.mv_warm)
-    if args.mm_waves is not None:
+    if args.mm_waves is not None or args.gram_threads is not None:
         pricer.autotune = False
-        pricer.set_tuning(mm_waves=args.mm_waves)
+        if args.mm_waves is not None:
+            pricer.set_tuning(mm_waves=args.mm_waves)
+        if args.gram_threads is not None:
+            pricer.set_tuning(gram_threads=args.gram_threads)
     log(f"bench: d=5 Sigma(0.5) N={args.N} R={args.max_rank} batch={B} warmup={args.warmup} steps={args.steps}")
     prices, status, elapsed, prof = time_batches(pricer, batches, grid, args.warmup, not args.no_profile)
     launch_tuning = pricer.get_tuning()

@@ -21,7 +21,7 @@ __global__ void k_fiber(Item *items, const int *active, int t, int dir, int mode
 __global__ void k_eval_points(const Item *items, long long npts, const int *idx, cplx *out);
 __global__ void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G);
 __global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G);
-__global__ void k_gram(Item *items, const int *active, int t, int dir, int pass);
+template <int W> __global__ void k_gram(Item *items, const int *active, int t, int dir, int pass);
 __global__ void k_chol(Item *items, const int *active, int t, int dir, int pass, int last);
 __global__ void k_xform(Item *items, const int *active, int t, int dir, int pass);
 template <int W> __global__ void k_basis(Item *items, const int *active, int t, int dir);
@@ -66,6 +66,7 @@ struct ttfp_ctx {
     int tune_maxvol_rounds = 3;           // refinement rounds of maxvol after the block start
     int tune_maxvol_warm = 1;             // maxvol starts from the previous same-direction pivots
     int tune_mm_waves = 8;                // 16-row panels per workgroup of the basis and interpolation products
+    int tune_gram_threads = 512;          // threads of a Gram workgroup (two tiles or one tile per wave)
     int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 1;                   // graph replay whenever the stream is not the null stream
@@ -482,7 +483,10 @@ void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int 
         }
         {
             ProfScope ps(ctx, TTFP_KERNEL_GRAM);
-            hipLaunchKernelGGL(k_gram, dim3(gb, ny), dim3(512), 0, st, it, act, t, dir, pass);
+            if (ctx->tune_gram_threads == 1024)
+                hipLaunchKernelGGL(k_gram<1024>, dim3(gb, ny), dim3(1024), 0, st, it, act, t, dir, pass);
+            else
+                hipLaunchKernelGGL(k_gram<512>, dim3(gb, ny), dim3(512), 0, st, it, act, t, dir, pass);
         }
         ProfScope ps(ctx, TTFP_KERNEL_CHOL);
         hipLaunchKernelGGL(k_chol, dim3(ny), dim3(256), 0, st, it, act, t, dir, pass, pass == npass - 1 ? 1 : 0);
@@ -920,6 +924,10 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
         if (value != 8 && value != 16) break;
         ctx->tune_mm_waves = value;
         return TTFP_OK;
+    case TTFP_TUNE_GRAM_THREADS:
+        if (value != 512 && value != 1024) break;
+        ctx->tune_gram_threads = value;
+        return TTFP_OK;
     default:
         break;
     }
@@ -937,6 +945,7 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value)
     case TTFP_TUNE_QR: *value = ctx->tune_qr; return TTFP_OK;
     case TTFP_TUNE_MAXVOL_WARM: *value = ctx->tune_maxvol_warm; return TTFP_OK;
     case TTFP_TUNE_MM_WAVES: *value = ctx->tune_mm_waves; return TTFP_OK;
+    case TTFP_TUNE_GRAM_THREADS: *value = ctx->tune_gram_threads; return TTFP_OK;
     default: return TTFP_EINVAL;
     }
 }

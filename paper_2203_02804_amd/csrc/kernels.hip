@@ -949,15 +949,18 @@ __device__ __forceinline__ int gram_blocks(int rows) { return (rows + GRAM_ROWS 
 // accumulators are rescaled exactly when a later chunk raises it; e_blk goes to it.Ge[block]);
 // passes 1 and 2 read Q unscaled. A chunk of rows is staged in LDS as separate real and
 // imaginary planes whose row stride (NCPAD doubles, 32 banks mod 64) lets the two rows a half
-// wave reads fall on disjoint banks; the next chunk is loaded into registers meanwhile. Eight
-// waves take two tiles each. Complex products by three real ones (Gauss): with X = Xr + i Xi,
+// wave reads fall on disjoint banks; the next chunk is loaded into registers meanwhile. Each wave
+// takes one or two tiles (GRAM_THREADS below). Complex products by three real ones (Gauss): with X = Xr + i Xi,
 // Y = Yr + i Yi, X^H Y = (t1 + t2) + i (t3 - t1 + t2), t1 = Xr^T Yr, t2 = Xi^T Yi,
 // t3 = (Xr - Xi)^T (Yr + Yi): three independent accumulators per tile.
-constexpr int GRAM_THREADS = 512;
-__global__ __launch_bounds__(GRAM_THREADS) void k_gram(Item *items, const int *active, int t, int dir, int pass)
+// GRAM_THREADS 512 (two tiles per wave) or 1024 (one tile per wave: half the critical path of a
+// chunk): a launch tuning that leaves every result bit unchanged (each tile sums the same rows in
+// the same order).
+template <int GRAM_THREADS>
+__global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_gram(Item *items, const int *active, int t, int dir, int pass)
 {
     constexpr int PER = (GRAM_CHUNK * MAXNC + GRAM_THREADS - 1) / GRAM_THREADS;   // chunk entries per thread
-    constexpr int NW = GRAM_THREADS / 64, TPW = 2;                                 // waves, tiles per wave
+    constexpr int NW = GRAM_THREADS / 64, TPW = 1024 / GRAM_THREADS;               // waves, tiles per wave
     __shared__ double cre[GRAM_CHUNK][NCPAD], cim[GRAM_CHUNK][NCPAD];
     __shared__ double wmax[NW];
     const int item = blockIdx.y;
@@ -1084,6 +1087,8 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(Item *items, const int *a
     }
     if (tid == 0) it.Ge[blk] = pass == 0 ? e_blk : 0;
 }
+template __global__ void k_gram<512>(Item *, const int *, int, int, int);
+template __global__ void k_gram<1024>(Item *, const int *, int, int, int);
 
 // Packed upper-triangular storage of an n x n matrix: row i starts at i n - i (i - 1) / 2.
 __device__ __forceinline__ int up_off(int i, int n) { return i * n - (i * (i - 1)) / 2; }

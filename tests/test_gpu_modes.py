@@ -70,18 +70,22 @@ def test_autotuner_picks_a_valid_setting(pricer, tmp_path):
     opts, g = _batch()
     best, timings = tuning.tune(pricer, opts, g, reps=1, path=str(tmp_path / "t.json"))
     assert set(best) == set(tuning.CANDIDATES)
-    assert len(timings) == 4
+    assert len(timings) == 8
     entry = tuning.apply(pricer, opts[0]["d"], g["N"], g["max_rank"], path=str(tmp_path / "t.json"))
     assert entry is not None and pricer.get_tuning()["mm_waves"] == best["mm_waves"]
-    pricer.set_tuning(graph=1, mm_waves=8)
+    pricer.set_tuning(graph=1, mm_waves=8, gram_threads=512)
 
 
 def test_tile_shapes_agree_bit_for_bit(pricer):
-    # the basis and interpolation products with 8 or 16 row panels per workgroup: same prices
+    # the basis and interpolation products with 8 or 16 row panels per workgroup and the Gram
+    # products with one or two tiles per wave: the same prices bit for bit
     opts, g = _batch()
-    pricer.set_tuning(mm_waves=8)
-    p8, s8 = pricer.price_batch(opts, g)
-    pricer.set_tuning(mm_waves=16)
-    p16, s16 = pricer.price_batch(opts, g)
-    pricer.set_tuning(mm_waves=8)
-    assert np.array_equal(p8, p16) and np.array_equal(s8, s16)
+    pricer.autotune = False
+    pricer.set_tuning(mm_waves=8, gram_threads=512)
+    p0, s0 = pricer.price_batch(opts, g)
+    for mw, gt in ((16, 512), (8, 1024), (16, 1024)):
+        pricer.set_tuning(mm_waves=mw, gram_threads=gt)
+        p1, s1 = pricer.price_batch(opts, g)
+        assert np.array_equal(p0, p1) and np.array_equal(s0, s1), (mw, gt)
+    pricer.set_tuning(mm_waves=8, gram_threads=512)
+    pricer.autotune = True
