@@ -404,6 +404,9 @@ def main():
     ap.add_argument("--mm-waves", type=int, default=None, choices=(8, 16),
                     help="16-row panels per workgroup of the basis and interpolation products (default: the "
                          "autotuner's stored choice for the workload's shape, else 8)")
+    ap.add_argument("--mm-panels", type=int, default=None, choices=(1, 2),
+                    help="16-row panels per wave of the basis and interpolation products (default: the autotuner's "
+                         "stored choice, else 1)")
     ap.add_argument("--gram-threads", type=int, default=None, choices=(512, 1024),
                     help="threads per Gram workgroup (default: the autotuner's stored choice, else 512)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -440,10 +443,12 @@ def main():
     pricer = ttfp.Pricer(0)
     pricer.set_tuning(qr={"cholqr": 0, "tsqr": 1, "cholqr2": 2, "cholqr3": 3}[args.qr], maxvol_rounds=args.mv_rounds,
                       maxvol_warm=args.mv_warm)
-    if args.mm_waves is not None or args.gram_threads is not None:
+    if args.mm_waves is not None or args.gram_threads is not None or args.mm_panels is not None:
         pricer.autotune = False
         if args.mm_waves is not None:
             pricer.set_tuning(mm_waves=args.mm_waves)
+        if args.mm_panels is not None:
+            pricer.set_tuning(mm_panels=args.mm_panels)
         if args.gram_threads is not None:
             pricer.set_tuning(gram_threads=args.gram_threads)
     log(f"bench: d=5 Sigma(0.5) N={args.N} R={args.max_rank} batch={B} warmup={args.warmup} steps={args.steps}")

@@ -288,9 +288,12 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
  *  TTFP_TUNE_GRAM_THREADS    512 (default) or 1024 threads per workgroup of the Cholesky QR's Gram
  *                            products (two 16 x 16 tiles per wave or one); the same results bit
  *                            for bit (each tile sums the same rows in the same order)
+ *  TTFP_TUNE_MM_PANELS       1 (default) or 2: 16-row panels per wave of the basis and
+ *                            interpolation products (rows per workgroup = 16 x waves x panels);
+ *                            the same results bit for bit
  * Returns TTFP_EINVAL for an unknown parameter or value. */
 enum { TTFP_TUNE_MAXVOL_ROUNDS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2, TTFP_TUNE_QR = 3,
-       TTFP_TUNE_MAXVOL_WARM = 4, TTFP_TUNE_MM_WAVES = 5, TTFP_TUNE_GRAM_THREADS = 6 };
+       TTFP_TUNE_MAXVOL_WARM = 4, TTFP_TUNE_MM_WAVES = 5, TTFP_TUNE_GRAM_THREADS = 6, TTFP_TUNE_MM_PANELS = 7 };
 int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value);
 int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
 

@@ -24,10 +24,10 @@ __global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, i
 template <int W> __global__ void k_gram(Item *items, const int *active, int t, int dir, int pass);
 __global__ void k_chol(Item *items, const int *active, int t, int dir, int pass, int last);
 __global__ void k_xform(Item *items, const int *active, int t, int dir, int pass);
-template <int W> __global__ void k_basis(Item *items, const int *active, int t, int dir);
+template <int W, int P> __global__ void k_basis(Item *items, const int *active, int t, int dir);
 __global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm);
 __global__ void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax);
-template <int W> __global__ void k_interp(Item *items, const int *active, int t, int dir, int mode);
+template <int W, int P> __global__ void k_interp(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_finish(Item *items, const int *active, int t, int dir);
 __global__ void k_core_sum(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_contract(Item *items, const int *active);
@@ -67,6 +67,7 @@ struct ttfp_ctx {
     int tune_maxvol_warm = 1;             // maxvol starts from the previous same-direction pivots
     int tune_mm_waves = 8;                // 16-row panels per workgroup of the basis and interpolation products
     int tune_gram_threads = 512;          // threads of a Gram workgroup (two tiles or one tile per wave)
+    int tune_mm_panels = 1;               // 16-row panels per wave of the basis and interpolation products
     int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 1;                   // graph replay whenever the stream is not the null stream
@@ -493,22 +494,35 @@ void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int 
     }
 }
 
-// The basis and interpolation products with TTFP_TUNE_MM_WAVES 16-row panels per workgroup.
+// The basis and interpolation products with TTFP_TUNE_MM_WAVES waves per workgroup and
+// TTFP_TUNE_MM_PANELS 16-row panels per wave.
+template <int W, int P>
+void launch_basis_t(hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir)
+{
+    hipLaunchKernelGGL((k_basis<W, P>), dim3(cdivu(rows, 16 * W * P), ny), dim3(64 * W), 0, st, it, act, t, dir);
+}
 void launch_basis(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir)
 {
-    if (ctx->tune_mm_waves == 16)
-        hipLaunchKernelGGL(k_basis<16>, dim3(cdivu(rows, 16 * 16), ny), dim3(64 * 16), 0, st, it, act, t, dir);
-    else
-        hipLaunchKernelGGL(k_basis<8>, dim3(cdivu(rows, 16 * 8), ny), dim3(64 * 8), 0, st, it, act, t, dir);
+    const bool w16 = ctx->tune_mm_waves == 16, p2 = ctx->tune_mm_panels == 2;
+    if (w16 && p2) launch_basis_t<16, 2>(st, it, act, rows, ny, t, dir);
+    else if (w16) launch_basis_t<16, 1>(st, it, act, rows, ny, t, dir);
+    else if (p2) launch_basis_t<8, 2>(st, it, act, rows, ny, t, dir);
+    else launch_basis_t<8, 1>(st, it, act, rows, ny, t, dir);
 }
 
+template <int W, int P>
+void launch_interp_t(hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir, int mode)
+{
+    hipLaunchKernelGGL((k_interp<W, P>), dim3(cdivu(rows, 16 * W * P), ny), dim3(64 * W), 0, st, it, act, t, dir, mode);
+}
 void launch_interp(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir,
                    int mode)
 {
-    if (ctx->tune_mm_waves == 16)
-        hipLaunchKernelGGL(k_interp<16>, dim3(cdivu(rows, 16 * 16), ny), dim3(64 * 16), 0, st, it, act, t, dir, mode);
-    else
-        hipLaunchKernelGGL(k_interp<8>, dim3(cdivu(rows, 16 * 8), ny), dim3(64 * 8), 0, st, it, act, t, dir, mode);
+    const bool w16 = ctx->tune_mm_waves == 16, p2 = ctx->tune_mm_panels == 2;
+    if (w16 && p2) launch_interp_t<16, 2>(st, it, act, rows, ny, t, dir, mode);
+    else if (w16) launch_interp_t<16, 1>(st, it, act, rows, ny, t, dir, mode);
+    else if (p2) launch_interp_t<8, 2>(st, it, act, rows, ny, t, dir, mode);
+    else launch_interp_t<8, 1>(st, it, act, rows, ny, t, dir, mode);
 }
 
 int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
@@ -928,6 +942,10 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
         if (value != 512 && value != 1024) break;
         ctx->tune_gram_threads = value;
         return TTFP_OK;
+    case TTFP_TUNE_MM_PANELS:
+        if (value != 1 && value != 2) break;
+        ctx->tune_mm_panels = value;
+        return TTFP_OK;
     default:
         break;
     }
@@ -946,6 +964,7 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value)
     case TTFP_TUNE_MAXVOL_WARM: *value = ctx->tune_maxvol_warm; return TTFP_OK;
     case TTFP_TUNE_MM_WAVES: *value = ctx->tune_mm_waves; return TTFP_OK;
     case TTFP_TUNE_GRAM_THREADS: *value = ctx->tune_gram_threads; return TTFP_OK;
+    case TTFP_TUNE_MM_PANELS: *value = ctx->tune_mm_panels; return TTFP_OK;
     default: return TTFP_EINVAL;
     }
 }

@@ -1441,10 +1441,10 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
 // 16-row panel as up to four 16 x 16 complex tiles, three real MFMA products each); the
 // triangular inverse is held in LDS with its zero lower part. Each row's squared norm goes to
 // its key (the start of maxvol reads them).
-// PANEL_WAVES 16-row panels per workgroup, 8 or 16: a launch tuning that leaves every result bit
-// unchanged (a row's product does not depend on the workgroup it falls in). With 16 the 64 KiB
-// staging of R^-1 serves twice the rows.
-template <int PANEL_WAVES>
+// PANEL_WAVES waves per workgroup (8 or 16) and PPW 16-row panels per wave (1 or 2): a launch
+// tuning that leaves every result bit unchanged (a row's product does not depend on the workgroup
+// or wave it falls in). More rows per workgroup spread the 64 KiB staging of R^-1 over more rows.
+template <int PANEL_WAVES, int PPW>
 __global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, const int *active, int t, int dir)
 {
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
@@ -1455,65 +1455,70 @@ __global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, cons
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
     const int r = it.rsel, nc = s.nc, m = s.rows;
-    const int rows_per_wg = 16 * PANEL_WAVES;
+    const int rows_per_wg = 16 * PANEL_WAVES * PPW;
     if (blockIdx.x * rows_per_wg >= m) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_BASIS] += 4.0 * (double)m * r * r;
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ri[e] = it.Rinv[e];
     for (int e = threadIdx.x; e < r; e += blockDim.x) pm[e] = it.perm[e];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * rows_per_wg + wave * 16;
-    if (row0 >= m) return;
-    const int li = lane & 15, lk = lane >> 4;
-    const int ntile = (r + 15) / 16;
-    // complex products by three real ones (Gauss): prr = Ar Br, pii = Ai Bi, pss = (Ar + Ai)(Br + Bi);
-    // re = prr - pii, im = pss - prr - pii
-    double4_t prr[4], pii[4], pss[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-        pii[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-        pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-    }
-    const int arow = row0 + li;
-    // the left operand of the next k-step is loaded while this one's products run
-    cplx an = (arow < m && lk < r) ? it.F[(size_t)arow * nc + pm[lk]] : cplx{0.0, 0.0};
-    for (int k0 = 0; k0 < r; k0 += 4) {
-        const int kk = k0 + lk;
-        const cplx a = an;
-        if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? it.F[(size_t)arow * nc + pm[kk + 4]] : cplx{0.0, 0.0};
+#pragma unroll 1
+    for (int pp = 0; pp < PPW; ++pp) {
+        const int row0 = blockIdx.x * rows_per_wg + (pp * PANEL_WAVES + wave) * 16;
+        if (row0 >= m) break;
+        const int li = lane & 15, lk = lane >> 4;
+        const int ntile = (r + 15) / 16;
+        // complex products by three real ones (Gauss): prr = Ar Br, pii = Ai Bi, pss = (Ar + Ai)(Br + Bi);
+        // re = prr - pii, im = pss - prr - pii
+        double4_t prr[4], pii[4], pss[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (q >= ntile) break;
-            const int jj = 16 * q + li;
-            const cplx b = (kk < r && jj < r) ? Ri[kk * r + jj] : cplx{0.0, 0.0};
-            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
-            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
-            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+            prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+            pii[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+            pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
         }
-    }
+        const int arow = row0 + li;
+        // the left operand of the next k-step is loaded while this one's products run
+        cplx an = (arow < m && lk < r) ? it.F[(size_t)arow * nc + pm[lk]] : cplx{0.0, 0.0};
+        for (int k0 = 0; k0 < r; k0 += 4) {
+            const int kk = k0 + lk;
+            const cplx a = an;
+            if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? it.F[(size_t)arow * nc + pm[kk + 4]] : cplx{0.0, 0.0};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int row = row0 + lk + 4 * v;
-        double nrm = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q >= ntile) break;
-            const int col = 16 * q + li;
-            const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
-            nrm += (row < m && col < r) ? cabs2(val) : 0.0;
-            if (row < m && col < r) it.Y[(size_t)row * r + col] = val;
+            for (int q = 0; q < 4; ++q) {
+                if (q >= ntile) break;
+                const int jj = 16 * q + li;
+                const cplx b = (kk < r && jj < r) ? Ri[kk * r + jj] : cplx{0.0, 0.0};
+                prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
+                pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
+                pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+            }
         }
-        // the row's squared norm: the lane's columns li + 16 q, then the 16 lanes of the row
-        nrm += __shfl_xor(nrm, 1, 64);
-        nrm += __shfl_xor(nrm, 2, 64);
-        nrm += __shfl_xor(nrm, 4, 64);
-        nrm += __shfl_xor(nrm, 8, 64);
-        if (row < m && li == 0) it.keys[row] = (float)nrm;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = row0 + lk + 4 * v;
+            double nrm = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= ntile) break;
+                const int col = 16 * q + li;
+                const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
+                nrm += (row < m && col < r) ? cabs2(val) : 0.0;
+                if (row < m && col < r) it.Y[(size_t)row * r + col] = val;
+            }
+            // the row's squared norm: the lane's columns li + 16 q, then the 16 lanes of the row
+            nrm += __shfl_xor(nrm, 1, 64);
+            nrm += __shfl_xor(nrm, 2, 64);
+            nrm += __shfl_xor(nrm, 4, 64);
+            nrm += __shfl_xor(nrm, 8, 64);
+            if (row < m && li == 0) it.keys[row] = (float)nrm;
+        }
     }
 }
-template __global__ void k_basis<8>(Item *, const int *, int, int);
-template __global__ void k_basis<16>(Item *, const int *, int, int);
+template __global__ void k_basis<8, 1>(Item *, const int *, int, int);
+template __global__ void k_basis<16, 1>(Item *, const int *, int, int);
+template __global__ void k_basis<8, 2>(Item *, const int *, int, int);
+template __global__ void k_basis<16, 2>(Item *, const int *, int, int);
 
 // ------------------------------------------------------------------ maxvol
 // block-wide argmax (ties: lowest flat index); every thread receives the result: within each wave
@@ -2247,8 +2252,8 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const in
 // refinement that moved a pivot; mode 2: the final pass over every item, which stores B (into the
 // core slot) and marks nothing. Only the final pass writes B: a checking pass reads Y and writes
 // the marks alone.
-// INTERP_WAVES 16-row panels per workgroup: 8 or 16, as for k_basis.
-template <int INTERP_WAVES>
+// INTERP_WAVES waves per workgroup, PPW 16-row panels per wave, as for k_basis.
+template <int INTERP_WAVES, int PPW>
 __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, const int *active, int t, int dir, int mode)
 {
     __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
@@ -2260,7 +2265,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
     if (mode == 1 && !it.mv_dirty) return;
     const bool store = mode == 2;
     const int r = it.rsel, m = s.rows;
-    const int rows_per_wg = 16 * INTERP_WAVES;
+    const int rows_per_wg = 16 * INTERP_WAVES * PPW;
     if (blockIdx.x * rows_per_wg >= m) return;
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     // A checking pass skips the rows that cannot violate: |B_ij|^2 <= |y_i|^2 max_j |A^{-1} e_j|^2
@@ -2276,72 +2281,77 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ai[e] = it.Ai[e];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * rows_per_wg + wave * 16;
-    if (row0 >= m) return;
-    const int li = lane & 15, lk = lane >> 4;
-    if (check) {
-        const int row = row0 + li;
-        if (!__any(row < m && !((double)it.keys[row] * cm <= lim))) return;
-    }
-    // the work done: this panel's rows
-    if (lane == 0) atomicAdd(&it.work[TTFP_KERNEL_INTERP], 8.0 * (double)min(16, m - row0) * r * r);
-    const int ntile = (r + 15) / 16;
-    const cplx *Y = it.Y;
-    // complex products by three real ones (Gauss): prr = Ar Br, pii = Ai Bi, pss = (Ar + Ai)(Br + Bi);
-    // re = prr - pii, im = pss - prr - pii
-    double4_t prr[4], pii[4], pss[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-        pii[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-        pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
-    }
-    const int arow = row0 + li;
-    // the left operand of the next k-step is loaded while this one's products run
-    cplx an = (arow < m && lk < r) ? Y[(size_t)arow * r + lk] : cplx{0.0, 0.0};
-    for (int k0 = 0; k0 < r; k0 += 4) {
-        const int kk = k0 + lk;
-        const cplx a = an;
-        if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? Y[(size_t)arow * r + kk + 4] : cplx{0.0, 0.0};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q >= ntile) break;
-            const int jj = 16 * q + li;
-            const cplx b = (kk < r && jj < r) ? Ai[kk * r + jj] : cplx{0.0, 0.0};
-            prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
-            pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
-            pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+#pragma unroll 1
+    for (int pp = 0; pp < PPW; ++pp) {
+        const int row0 = blockIdx.x * rows_per_wg + (pp * INTERP_WAVES + wave) * 16;
+        if (row0 >= m) break;
+        const int li = lane & 15, lk = lane >> 4;
+        if (check) {
+            const int row = row0 + li;
+            if (!__any(row < m && !((double)it.keys[row] * cm <= lim))) continue;
         }
-    }
-    // the core slot holds B itself for a left-to-right step (rows (a, i), columns b: the core's
-    // a x N x b layout) and B transposed for a right-to-left one (rows (i, b), columns a);
-    // the raw entry point's B is row-major in Bt
-    cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int row = row0 + lk + 4 * v;
-        double mx = 0.0;
+        // the work done: this panel's rows
+        if (lane == 0) atomicAdd(&it.work[TTFP_KERNEL_INTERP], 8.0 * (double)min(16, m - row0) * r * r);
+        const int ntile = (r + 15) / 16;
+        const cplx *Y = it.Y;
+        // complex products by three real ones (Gauss): prr = Ar Br, pii = Ai Bi, pss = (Ar + Ai)(Br + Bi);
+        // re = prr - pii, im = pss - prr - pii
+        double4_t prr[4], pii[4], pss[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (q >= ntile) break;
-            const int col = 16 * q + li;
-            if (row < m && col < r) {
-                const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
-                if (store) B[dir == 1 ? (size_t)col * m + row : (size_t)row * r + col] = val;
-                mx = fmax(mx, cabs2(val));
+            prr[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+            pii[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+            pss[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+        }
+        const int arow = row0 + li;
+        // the left operand of the next k-step is loaded while this one's products run
+        cplx an = (arow < m && lk < r) ? Y[(size_t)arow * r + lk] : cplx{0.0, 0.0};
+        for (int k0 = 0; k0 < r; k0 += 4) {
+            const int kk = k0 + lk;
+            const cplx a = an;
+            if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? Y[(size_t)arow * r + kk + 4] : cplx{0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= ntile) break;
+                const int jj = 16 * q + li;
+                const cplx b = (kk < r && jj < r) ? Ai[kk * r + jj] : cplx{0.0, 0.0};
+                prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
+                pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
+                pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
             }
         }
-        if (store) continue;
-        // largest entry of the row over the 16 lanes that hold its columns
-        for (int o = 8; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if (li == 0 && row < m && mx > lim && mx <= 1e300) {
-            atomicMax(reinterpret_cast<unsigned int *>(it.viol + row), __float_as_uint((float)mx));
-            it.mv_viol = 1;
+        // the core slot holds B itself for a left-to-right step (rows (a, i), columns b: the core's
+        // a x N x b layout) and B transposed for a right-to-left one (rows (i, b), columns a);
+        // the raw entry point's B is row-major in Bt
+        cplx *B = (dir != 2) ? it.cores + (size_t)s.k * it.R * it.N * it.R : it.Bt;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = row0 + lk + 4 * v;
+            double mx = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= ntile) break;
+                const int col = 16 * q + li;
+                if (row < m && col < r) {
+                    const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
+                    if (store) B[dir == 1 ? (size_t)col * m + row : (size_t)row * r + col] = val;
+                    mx = fmax(mx, cabs2(val));
+                }
+            }
+            if (store) continue;
+            // largest entry of the row over the 16 lanes that hold its columns
+            for (int o = 8; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+            if (li == 0 && row < m && mx > lim && mx <= 1e300) {
+                atomicMax(reinterpret_cast<unsigned int *>(it.viol + row), __float_as_uint((float)mx));
+                it.mv_viol = 1;
+            }
         }
     }
 }
-template __global__ void k_interp<8>(Item *, const int *, int, int, int);
-template __global__ void k_interp<16>(Item *, const int *, int, int, int);
+template __global__ void k_interp<8, 1>(Item *, const int *, int, int, int);
+template __global__ void k_interp<16, 1>(Item *, const int *, int, int, int);
+template __global__ void k_interp<8, 2>(Item *, const int *, int, int, int);
+template __global__ void k_interp<16, 2>(Item *, const int *, int, int, int);
 
 // ------------------------------------------------------------------ index sets and core placement
 __global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, int t, int dir)

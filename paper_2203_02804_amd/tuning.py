@@ -2,7 +2,8 @@
 
 For a workload shape (d, N, max rank) it times every candidate setting of the launch
 parameters that leave the result unchanged bit for bit (graph replay or eager launches; the
-tile shapes of the basis and interpolation products, 8 or 16 row panels per workgroup, and of the
+tile shapes of the basis and interpolation products, 8 or 16 waves per workgroup with 1 or 2 row
+panels per wave, and of the
 Gram products, one or two tiles per wave; with the
 Householder QR selected, the LDS budget of a TSQR workgroup, which sets its leaf and merge
 shapes) on a sample batch of options of that shape, and keeps the fastest. Results are stored in
@@ -22,6 +23,7 @@ TABLE = os.path.join(HERE, "tuning_table.json")
 CANDIDATES = {
     "graph": (0, 1),
     "mm_waves": (8, 16),
+    "mm_panels": (1, 2),
     "gram_threads": (512, 1024),
 }
 TSQR_CANDIDATES = {"tsqr_lds_kb": (48, 76, 152)}      # only with the Householder QR (qr = 1)

@@ -70,10 +70,10 @@ def test_autotuner_picks_a_valid_setting(pricer, tmp_path):
     opts, g = _batch()
     best, timings = tuning.tune(pricer, opts, g, reps=1, path=str(tmp_path / "t.json"))
     assert set(best) == set(tuning.CANDIDATES)
-    assert len(timings) == 8
+    assert len(timings) == 16
     entry = tuning.apply(pricer, opts[0]["d"], g["N"], g["max_rank"], path=str(tmp_path / "t.json"))
     assert entry is not None and pricer.get_tuning()["mm_waves"] == best["mm_waves"]
-    pricer.set_tuning(graph=1, mm_waves=8, gram_threads=512)
+    pricer.set_tuning(graph=1, mm_waves=8, mm_panels=1, gram_threads=512)
 
 
 def test_tile_shapes_agree_bit_for_bit(pricer):
@@ -83,9 +83,9 @@ def test_tile_shapes_agree_bit_for_bit(pricer):
     pricer.autotune = False
     pricer.set_tuning(mm_waves=8, gram_threads=512)
     p0, s0 = pricer.price_batch(opts, g)
-    for mw, gt in ((16, 512), (8, 1024), (16, 1024)):
-        pricer.set_tuning(mm_waves=mw, gram_threads=gt)
+    for mw, mp, gt in ((16, 1, 512), (8, 2, 512), (16, 2, 1024), (8, 1, 1024)):
+        pricer.set_tuning(mm_waves=mw, mm_panels=mp, gram_threads=gt)
         p1, s1 = pricer.price_batch(opts, g)
-        assert np.array_equal(p0, p1) and np.array_equal(s0, s1), (mw, gt)
-    pricer.set_tuning(mm_waves=8, gram_threads=512)
+        assert np.array_equal(p0, p1) and np.array_equal(s0, s1), (mw, mp, gt)
+    pricer.set_tuning(mm_waves=8, mm_panels=1, gram_threads=512)
     pricer.autotune = True
