@@ -291,9 +291,14 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
  *  TTFP_TUNE_MM_PANELS       1 (default) or 2: 16-row panels per wave of the basis and
  *                            interpolation products (rows per workgroup = 16 x waves x panels);
  *                            the same results bit for bit
+ *  TTFP_TUNE_INTERP_BOUND    1 (default): the checking passes of the interpolation matrix skip the
+ *                            rows that cannot exceed the dominance bound, |B_ij|^2 <= |y_i|^2
+ *                            max_j |A^-1 e_j|^2; 0: every row is formed. The same results bit for
+ *                            bit (a skipped row could not have been marked)
  * Returns TTFP_EINVAL for an unknown parameter or value. */
 enum { TTFP_TUNE_MAXVOL_ROUNDS = 0, TTFP_TUNE_TSQR_LDS_KB = 1, TTFP_TUNE_GRAPH = 2, TTFP_TUNE_QR = 3,
-       TTFP_TUNE_MAXVOL_WARM = 4, TTFP_TUNE_MM_WAVES = 5, TTFP_TUNE_GRAM_THREADS = 6, TTFP_TUNE_MM_PANELS = 7 };
+       TTFP_TUNE_MAXVOL_WARM = 4, TTFP_TUNE_MM_WAVES = 5, TTFP_TUNE_GRAM_THREADS = 6, TTFP_TUNE_MM_PANELS = 7,
+       TTFP_TUNE_INTERP_BOUND = 8 };
 int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value);
 int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
 

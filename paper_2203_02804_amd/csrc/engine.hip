@@ -27,7 +27,7 @@ __global__ void k_xform(Item *items, const int *active, int t, int dir, int pass
 template <int W, int P> __global__ void k_basis(Item *items, const int *active, int t, int dir);
 __global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm);
 __global__ void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax);
-template <int W, int P> __global__ void k_interp(Item *items, const int *active, int t, int dir, int mode);
+template <int W, int P> __global__ void k_interp(Item *items, const int *active, int t, int dir, int mode, int bound);
 __global__ void k_finish(Item *items, const int *active, int t, int dir);
 __global__ void k_core_sum(Item *items, const int *active, int t, int dir, int mode);
 __global__ void k_contract(Item *items, const int *active);
@@ -68,6 +68,7 @@ struct ttfp_ctx {
     int tune_mm_waves = 8;                // 16-row panels per workgroup of the basis and interpolation products
     int tune_gram_threads = 512;          // threads of a Gram workgroup (two tiles or one tile per wave)
     int tune_mm_panels = 1;               // 16-row panels per wave of the basis and interpolation products
+    int tune_interp_bound = 1;            // checking passes skip rows that the row bound clears
     int n_cu = 256;
     int tune_tsqr_lds_kb = 152;
     int tune_graph = 1;                   // graph replay whenever the stream is not the null stream
@@ -511,18 +512,21 @@ void launch_basis(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act,
 }
 
 template <int W, int P>
-void launch_interp_t(hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir, int mode)
+void launch_interp_t(hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir, int mode,
+                     int bound)
 {
-    hipLaunchKernelGGL((k_interp<W, P>), dim3(cdivu(rows, 16 * W * P), ny), dim3(64 * W), 0, st, it, act, t, dir, mode);
+    hipLaunchKernelGGL((k_interp<W, P>), dim3(cdivu(rows, 16 * W * P), ny), dim3(64 * W), 0, st, it, act, t, dir, mode,
+                       bound);
 }
 void launch_interp(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir,
                    int mode)
 {
     const bool w16 = ctx->tune_mm_waves == 16, p2 = ctx->tune_mm_panels == 2;
-    if (w16 && p2) launch_interp_t<16, 2>(st, it, act, rows, ny, t, dir, mode);
-    else if (w16) launch_interp_t<16, 1>(st, it, act, rows, ny, t, dir, mode);
-    else if (p2) launch_interp_t<8, 2>(st, it, act, rows, ny, t, dir, mode);
-    else launch_interp_t<8, 1>(st, it, act, rows, ny, t, dir, mode);
+    const int b = ctx->tune_interp_bound;
+    if (w16 && p2) launch_interp_t<16, 2>(st, it, act, rows, ny, t, dir, mode, b);
+    else if (w16) launch_interp_t<16, 1>(st, it, act, rows, ny, t, dir, mode, b);
+    else if (p2) launch_interp_t<8, 2>(st, it, act, rows, ny, t, dir, mode, b);
+    else launch_interp_t<8, 1>(st, it, act, rows, ny, t, dir, mode, b);
 }
 
 int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
@@ -946,6 +950,10 @@ int ttfp_set_tuning(ttfp_ctx *ctx, int param, int value)
         if (value != 1 && value != 2) break;
         ctx->tune_mm_panels = value;
         return TTFP_OK;
+    case TTFP_TUNE_INTERP_BOUND:
+        if (value != 0 && value != 1) break;
+        ctx->tune_interp_bound = value;
+        return TTFP_OK;
     default:
         break;
     }
@@ -965,6 +973,7 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value)
     case TTFP_TUNE_MM_WAVES: *value = ctx->tune_mm_waves; return TTFP_OK;
     case TTFP_TUNE_GRAM_THREADS: *value = ctx->tune_gram_threads; return TTFP_OK;
     case TTFP_TUNE_MM_PANELS: *value = ctx->tune_mm_panels; return TTFP_OK;
+    case TTFP_TUNE_INTERP_BOUND: *value = ctx->tune_interp_bound; return TTFP_OK;
     default: return TTFP_EINVAL;
     }
 }

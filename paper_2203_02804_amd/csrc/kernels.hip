@@ -2254,7 +2254,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const in
 // the marks alone.
 // INTERP_WAVES waves per workgroup, PPW 16-row panels per wave, as for k_basis.
 template <int INTERP_WAVES, int PPW>
-__global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, const int *active, int t, int dir, int mode)
+__global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, const int *active, int t, int dir, int mode, int bound)
 {
     __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
     const int item = blockIdx.y;
@@ -2271,7 +2271,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
     // A checking pass skips the rows that cannot violate: |B_ij|^2 <= |y_i|^2 max_j |A^{-1} e_j|^2
     // (the row norms from k_basis, held as floats: the margin covers their rounding). A workgroup
     // whose rows all stay below the bound returns before staging A^{-1}; so does a wave.
-    const bool check = !store && dir != 2;
+    const bool check = !store && dir != 2 && bound;
     const double cm = 1.001 * it.mv_colmax;
     if (check) {
         const int row = blockIdx.x * rows_per_wg + (int)threadIdx.x;
@@ -2348,10 +2348,10 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
         }
     }
 }
-template __global__ void k_interp<8, 1>(Item *, const int *, int, int, int);
-template __global__ void k_interp<16, 1>(Item *, const int *, int, int, int);
-template __global__ void k_interp<8, 2>(Item *, const int *, int, int, int);
-template __global__ void k_interp<16, 2>(Item *, const int *, int, int, int);
+template __global__ void k_interp<8, 1>(Item *, const int *, int, int, int, int);
+template __global__ void k_interp<16, 1>(Item *, const int *, int, int, int, int);
+template __global__ void k_interp<8, 2>(Item *, const int *, int, int, int, int);
+template __global__ void k_interp<16, 2>(Item *, const int *, int, int, int, int);
 
 // ------------------------------------------------------------------ index sets and core placement
 __global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, int t, int dir)

@@ -89,3 +89,17 @@ def test_tile_shapes_agree_bit_for_bit(pricer):
         assert np.array_equal(p0, p1) and np.array_equal(s0, s1), (mw, mp, gt)
     pricer.set_tuning(mm_waves=8, mm_panels=1, gram_threads=512)
     pricer.autotune = True
+
+
+def test_row_bound_of_the_checking_passes_is_exact(pricer):
+    # skipping the rows that |B_ij|^2 <= |y_i|^2 max_j |A^-1 e_j|^2 clears changes nothing: the
+    # same prices and statuses bit for bit, also on the headline workload's shape
+    pricer.autotune = False
+    for opts, g in (_batch(), (W.config2_batch(6, seed=2203, corr_kind="beta"),
+                               W.grid(256, tol=1e-8, max_rank=64, max_sweeps=4))):
+        pricer.set_tuning(interp_bound=0)
+        p0, s0 = pricer.price_batch(opts, g)
+        pricer.set_tuning(interp_bound=1)
+        p1, s1 = pricer.price_batch(opts, g)
+        assert np.array_equal(p0, p1) and np.array_equal(s0, s1)
+    pricer.autotune = True
