@@ -1537,23 +1537,27 @@ __device__ ArgMax block_argmax(ArgMax a, ArgMax *scratch)
 
 // Dominant r x r submatrix of Y (rows x r) and the interpolation matrix B = Y Y[piv]^{-1}.
 //
-// k_maxvol works on a block of candidate rows only: the K rows of largest norm (Y has
-// orthonormal columns, so these are the rows of largest leverage), K = min(512, max(4 r, 64)).
-//  1. start: greedy volume selection on the block (pivoted Gram-Schmidt on rows); when the
-//     block is numerically rank deficient, the same selection over all m rows.
-//  2. A^{-1} = Y[piv]^{-1} by Gauss-Jordan with partial pivoting (LDS), and the block's rows of
-//     B, Bc = Y[cand] A^{-1}.
+// k_maxvol works on a block of candidate rows: the K = min(512, m) rows of largest norm (Y has
+// orthonormal columns, so these are the rows of largest leverage).
+//  1. start: from the second half sweep in a direction on, the pivots of the previous half sweep
+//     in that direction mapped onto this fiber's rows, when all r of them map and their block is
+//     not near-singular; otherwise Gaussian elimination with partial pivoting on the candidate
+//     block (blocked by panels in LDS), continued over all m rows through their residuals when
+//     the block is numerically rank deficient.
+//  2. A^{-1} = Y[piv]^{-1} by Gauss-Jordan with partial pivoting (A in registers, A^{-1} in LDS),
+//     and the block's rows of B, Bc = Y[cand] A^{-1}, on the matrix cores.
 //  3. maxvol swaps on Bc: while its entry of largest modulus exceeds 1 + delta, that row
 //     replaces the pivot of its column and Bc takes the rank-one update
 //     Bc -= Bc[:,j] (Bc[i,:] - e_j) / Bc[i,j]. Each swap multiplies |det Y[piv]| by more than
 //     1 + delta; at most 4 r + 16 swaps.
 //  4. A^{-1} of the final pivots, stored for k_interp: the inverse of step 2 carried through
 //     the swaps by the same rank-one updates (Sherman-Morrison), or recomputed by Gauss-Jordan
-//     after more than MV_SM_MAX swaps.
-// k_interp forms B for every row (a tiled product spread over the whole chip) and marks the
-// rows whose largest |B_ij| exceeds 1 + delta. k_maxvol_refine puts the pivots and the worst
-// such rows into a new block and repeats 3-4, after which k_interp runs again; when no row
-// violates, both return at once. The result is dominant over every row once no row violates.
+//     after more than MV_SM_MAX swaps; with it the largest squared column norm of A^{-1}.
+// k_interp's checking passes form B for every row that the row bound does not clear (a tiled
+// product spread over the whole chip) and mark the rows whose largest |B_ij| exceeds 1 + delta.
+// k_maxvol_refine puts the pivots and the worst such rows into a new block and repeats 3-4,
+// after which a checking pass runs again; when no row violates, both return at once. The result
+// is dominant over every row once no row violates; k_interp's final pass stores B.
 constexpr int MV_KMAX = 512;
 
 // Up to K indices g < n of largest value v[g * stride] (nonnegative floats, largest vmax), among
@@ -1634,10 +1638,9 @@ __device__ int select_largest(const float *v, int stride, int n, int K, float lo
 // flag_singular). Returns the smallest squared modulus of the pivots (the same in every thread).
 constexpr int GJ_THREADS = 1024;
 static_assert(GJ_THREADS == 16 * TTFP_MAX_RANK, "one row of A per 16 threads");
-__device__ double gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ai, cplx *vec, int *shi, Item &it,
+__device__ double gj_inverse(const cplx *Y, const int *piv, int r, int m, cplx *Ai, cplx *vec, Item &it,
                              bool flag_singular = true)
 {
-    (void)shi;
     cplx *pa = vec, *pi = vec + r, *ja = vec + 2 * r, *ji = vec + 3 * r, *fcol = vec + 4 * r;
     const int a = threadIdx.x >> 4, c0 = threadIdx.x & 15;
     const bool arow = a < r;
@@ -2016,33 +2019,31 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *acti
     int K = MV_KMAX;
     K = min(K, nk);
     float *key = (float *)Abuf;
-    // the group keys in Abuf; returns their largest value, in every thread
-    auto group_keys = [&](bool clear_marks) -> float {
-        float kx = 0.0f;
-        for (int g = threadIdx.x; g < nk; g += nthr) {
-            float best = -1.0f;
-            for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
-                float q;
-                if (dir != 2) {
-                    q = it.keys[i];                          // the row norm written by k_basis
-                } else {
-                    const cplx *y = Y + (size_t)i * r;
-                    double qq = 0.0;
-                    for (int c = 0; c < r; ++c) qq += cabs2(y[c]);
-                    q = (float)qq;
-                }
-                if (clear_marks) it.viol[i] = 0.0f;
-                if (!(q >= 0.0f && q <= 3.0e38f)) q = 0.0f;     // a non-finite row is never a pivot
-                best = fmaxf(best, q);
+    float kmax = 0.0f;
+    for (int g = threadIdx.x; g < nk; g += nthr) {
+        float best = -1.0f;
+        for (int i = g * gsz; i < min(m, (g + 1) * gsz); ++i) {
+            float q;
+            if (dir != 2) {
+                q = it.keys[i];                          // the row norm written by k_basis
+            } else {
+                const cplx *y = Y + (size_t)i * r;
+                double qq = 0.0;
+                for (int c = 0; c < r; ++c) qq += cabs2(y[c]);
+                q = (float)qq;
             }
-            key[g] = fmaxf(best, 0.0f);
-            kx = fmaxf(kx, key[g]);
+            it.viol[i] = 0.0f;
+            if (!(q >= 0.0f && q <= 3.0e38f)) q = 0.0f;     // a non-finite row is never a pivot
+            best = fmaxf(best, q);
         }
-        ArgMax a = {(double)kx, 0};
+        key[g] = fmaxf(best, 0.0f);
+        kmax = fmaxf(kmax, key[g]);
+    }
+    {
+        ArgMax a = {(double)kmax, 0};
         a = block_argmax(a, red);
-        return (float)a.v;
-    };
-    float kmax = group_keys(true);
+        kmax = (float)a.v;
+    }
     // ---- 1b. the K largest groups, resolved to their largest-norm row
     const int Kc = select_largest(key, 1, nk, K, 0.0f, kmax, cand, red, shi, shf);
     for (int q = threadIdx.x; q < Kc; q += nthr) {
@@ -2071,7 +2072,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *acti
     // the elimination start is then skipped and A^{-1} is already formed.
     bool warm_ok = false;
     if (warm && dir != 2 && it.half >= 2 + dir && map_previous_pivots(it, s, dir, piv, shi) == r)
-        warm_ok = gj_inverse(Y, piv, r, m, Ai, colv, shi, it, false) > ptol2;
+        warm_ok = gj_inverse(Y, piv, r, m, Ai, colv, it, false) > ptol2;
     if (!warm_ok) {
         cplx *S = W;
         for (long long e = threadIdx.x; e < (long long)Kc * r; e += nthr)
@@ -2143,7 +2144,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *acti
         }
         __syncthreads();
         // ---- 2. A^{-1} (unless the warm start formed it)
-        gj_inverse(Y, piv, r, m, Ai, colv, shi, it);
+        gj_inverse(Y, piv, r, m, Ai, colv, it);
     }
     // the block's rows of B (in W, over the start's copy)
     cplx *Bc = W;
@@ -2152,7 +2153,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *acti
     // ---- 3. swaps within the block, 4. A^{-1} of the final pivots
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red, Ai, fcol);
-    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ai, colv, shi, it);
+    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ai, colv, it);
     __syncthreads();
     for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
     for (int c = threadIdx.x; c < r; c += nthr) it.piv[c] = piv[c];
@@ -2225,7 +2226,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const in
     __syncthreads();
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     const int swaps = swap_block(Bc, Kc, r, cand, piv, lim, 4 * r + 16, prow, colv, red, Ai, fcol);
-    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ai, colv, shi, it);
+    if (swaps > MV_SM_MAX) gj_inverse(Y, piv, r, m, Ai, colv, it);
     __syncthreads();
     if (swaps > 0) {
         for (int e = threadIdx.x; e < r * r; e += nthr) it.Ai[e] = Ai[e];
