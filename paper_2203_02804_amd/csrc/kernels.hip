@@ -1149,37 +1149,36 @@ __global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, in
     tr = 0.0;
     for (int w = 0; w < nthr / 64; ++w) tr += red[w];
     double shift = 10.0 * nc * 2.220446049250313e-16 * tr;
-    // Cholesky of G + shift I by wave 0 (right-looking, packed rows), redone with a larger shift
-    // after a non-positive pivot
+    // Cholesky of G + shift I (right-looking, packed rows; the trailing rows of a step spread over
+    // the waves, their columns over the lanes), redone with a larger shift after a non-positive
+    // pivot
+    const int nw = nthr / 64;
     for (int attempt = 0; attempt < 6; ++attempt) {
         for (int e = threadIdx.x; e < np; e += nthr) Rp[e] = Xp[e];
         __syncthreads();
         for (int i = threadIdx.x; i < nc; i += nthr) Rp[up_off(i, nc)].x += shift;
         __syncthreads();
-        if (wave == 0) {
-            int fail = 0;
-            for (int j = 0; j < nc && !fail; ++j) {
-                const int oj = up_off(j, nc);
-                const double dj = Rp[oj].x;
-                if (!(dj > 0.0) || !(dj < INFINITY)) { fail = 1; break; }
-                const double rjj = sqrt(dj), inv = 1.0 / rjj;
-                wave_lds_order();
-                for (int k = j + 1 + lane; k < nc; k += 64) Rp[oj + k - j] = {Rp[oj + k - j].x * inv, Rp[oj + k - j].y * inv};
-                if (lane == 0) Rp[oj] = {rjj, 0.0};
-                wave_lds_order();
-                // trailing update of rows i > j: R_ik -= conj(R_ji) R_jk, k >= i
-                const int n2 = nc - j - 1;
-                for (int e = lane; e < n2 * n2; e += 64) {
-                    const int ii = j + 1 + e / n2, kk = j + 1 + e % n2;
-                    if (kk < ii) continue;
-                    const cplx rji = Rp[oj + ii - j], rjk = Rp[oj + kk - j];
-                    cplx &w = Rp[up_off(ii, nc) + kk - ii];
-                    w = csub(w, cmulc(rji, rjk));
+        int fail = 0;
+        for (int j = 0; j < nc; ++j) {
+            const int oj = up_off(j, nc);
+            const double dj = Rp[oj].x;                 // the same value in every thread
+            if (!(dj > 0.0) || !(dj < INFINITY)) { fail = 1; break; }
+            const double rjj = sqrt(dj), inv = 1.0 / rjj;
+            for (int k = j + 1 + threadIdx.x; k < nc; k += nthr) Rp[oj + k - j] = {Rp[oj + k - j].x * inv, Rp[oj + k - j].y * inv};
+            __syncthreads();
+            if (threadIdx.x == 0) Rp[oj] = {rjj, 0.0};
+            // trailing update of rows i > j: R_ik -= conj(R_ji) R_jk, k >= i
+            for (int ii = j + 1 + wave; ii < nc; ii += nw) {
+                const cplx rji = Rp[oj + ii - j];
+                const int oi = up_off(ii, nc);
+                for (int kk = ii + lane; kk < nc; kk += 64) {
+                    cplx &w = Rp[oi + kk - ii];
+                    w = csub(w, cmulc(rji, Rp[oj + kk - j]));
                 }
-                wave_lds_order();
             }
-            if (lane == 0) sh_fail = fail;
+            __syncthreads();
         }
+        if (threadIdx.x == 0) sh_fail = fail;
         __syncthreads();
         if (!sh_fail) break;
         if (tr <= 0.0 || !(tr < INFINITY)) break;
@@ -1191,25 +1190,38 @@ __global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, in
         for (int e = threadIdx.x; e < np; e += nthr) Rp[e] = {0.0, 0.0};
         __syncthreads();
     }
-    // X = R^{-1}: column c by back substitution (one thread per column)
-    for (int c = threadIdx.x; c < nc; c += nthr) {
-        const cplx rcc = Rp[up_off(c, nc)];
-        const bool zero = rcc.x == 0.0;
-        Xp[up_off(c, nc)] = zero ? cplx{0.0, 0.0} : cplx{1.0 / rcc.x, 0.0};
-        for (int i = c - 1; i >= 0; --i) {
-            const int oi = up_off(i, nc);
-            cplx acc = {0.0, 0.0};
-            for (int l = i + 1; l <= c; ++l) acc = cadd(acc, cmul(Rp[oi + l - i], Xp[up_off(l, nc) + c - l]));
-            const double rii = Rp[oi].x;
-            Xp[oi + c - i] = (rii == 0.0 || zero) ? cplx{0.0, 0.0} : cplx{-acc.x / rii, -acc.y / rii};
+    // X = R^{-1} (only the transform of the next pass needs it), a row at a time from the bottom:
+    // row l of R X = I gives X_lc = (delta_lc - sum_{k>l} R_lk X_kc) / R_ll, and once row l is
+    // known its terms leave the rows above it (rows over the waves, columns over the lanes). A
+    // zero diagonal entry R_cc (a zero fiber column) gives a zero column of X.
+    if (!last) {
+        for (int e = threadIdx.x; e < np; e += nthr) Xp[e] = {0.0, 0.0};
+        __syncthreads();
+        for (int l = nc - 1; l >= 0; --l) {
+            const int ol = up_off(l, nc);
+            const double rll = Rp[ol].x;
+            for (int c = l + threadIdx.x; c < nc; c += nthr) {
+                const cplx tlc = Xp[ol + c - l];
+                const double v = c == l ? 1.0 : 0.0;
+                const bool zero = rll == 0.0 || Rp[up_off(c, nc)].x == 0.0;
+                Xp[ol + c - l] = zero ? cplx{0.0, 0.0} : cplx{(v + tlc.x) / rll, tlc.y / rll};
+            }
+            __syncthreads();
+            for (int i = wave; i < l; i += nw) {
+                const int oi = up_off(i, nc);
+                const cplx ril = Rp[oi + l - i];
+                for (int c = l + lane; c < nc; c += 64) {
+                    cplx &x = Xp[oi + c - i];
+                    x = csub(x, cmul(ril, Xp[ol + c - l]));
+                }
+            }
+            __syncthreads();
         }
-    }
-    __syncthreads();
-    if (!last)
         for (int e = threadIdx.x; e < nc * nc; e += nthr) {
             const int i = e / nc, j = e % nc;
             it.Xf[e] = j >= i ? Xp[up_off(i, nc) + j - i] : cplx{0.0, 0.0};
         }
+    }
     // running factor: Rf <- R (pass 0) or R Rf (the previous Rf staged in Xp, packed); the last
     // pass also undoes the scaling
     const double unscale = last ? ldexp(1.0, it.gram_e == GRAM_NOSCALE ? 0 : it.gram_e) : 1.0;
