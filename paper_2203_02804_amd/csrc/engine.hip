@@ -109,6 +109,12 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Launch {
     int BR, G, nlev, maxd, maxrows, maxnc, maxR, maxN;
     double min_rank_eps;       // smallest relative rank threshold of the batch's items
+    // Step t of a half sweep (either direction) has at most left[t] = min(R, N^t) row groups of N
+    // fiber rows: the index sets grow from one multi-index by at most a factor N per core and
+    // never past the rank cap (k_init, k_qrcp). The row-parallel launches of step t are sized by
+    // rows[t] = N left[t], not by the buffers' R N rows, so that the first and last cores (N rows)
+    // do not launch workgroups that have no rows.
+    int left[MAXD], rows[MAXD];
 };
 
 // TSQR geometry: leaf blocks of BR = Gl nc rows of the fiber, padded row-major (odd stride
@@ -291,7 +297,21 @@ int build_items(ttfp_ctx *ctx, const std::vector<const OptionPlan *> &plans, con
         const double eps = g->rank_tol > 0 ? g->rank_tol : 0.1 * g->tol / std::sqrt((double)std::max(plans[o]->d - 1, 1));
         min_eps = std::min(min_eps, eps);
     }
-    b.geo = {BR, G, tsqr_levels(maxrows, BR, G), maxd, maxrows, maxnc, maxR, maxN, min_eps};
+    b.geo = {BR, G, tsqr_levels(maxrows, BR, G), maxd, maxrows, maxnc, maxR, maxN, min_eps, {}, {}};
+    for (int t = 0; t < MAXD; ++t) {
+        int left = 0, rows = 0;
+        for (size_t o = 0; o < plans.size(); ++o) {
+            const ttfp_grid *g = grids[o];
+            if (t > plans[o]->d - 2) continue;
+            long long l = 1;
+            for (int q = 0; q < t && l < g->max_rank; ++q) l *= g->N;
+            l = std::min<long long>(l, g->max_rank);
+            left = std::max(left, (int)l);
+            rows = std::max(rows, (int)l * g->N);
+        }
+        b.geo.left[t] = std::max(left, 1);
+        b.geo.rows[t] = std::max(rows, 1);
+    }
     // layout
     std::vector<ItemSizes> sz;
     size_t total = 0;
@@ -537,13 +557,14 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     const unsigned ny = (unsigned)n_items;
     {
         ProfScope ps(ctx, TTFP_KERNEL_FIBER);
-        hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.maxR * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
+        hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.left[t] * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
     }
+    const int rows = g.rows[t];
     if (ctx->tune_qr != 1) {
-        launch_cholqr(ctx, st, it, act, g.maxrows, ny, t, dir, cholqr_passes(ctx, g.min_rank_eps));
+        launch_cholqr(ctx, st, it, act, rows, ny, t, dir, cholqr_passes(ctx, g.min_rank_eps));
     } else {
         ProfScope ps(ctx, TTFP_KERNEL_TSQR);
-        int n = (g.maxrows + g.BR - 1) / g.BR;
+        int n = (rows + g.BR - 1) / g.BR;
         const size_t lds = tsqr_lds_bytes(g.BR, g.G, g.maxnc);
         for (int level = 0; level < g.nlev; ++level) {
             hipLaunchKernelGGL(k_tsqr, dim3((unsigned)std::max(n, 1), ny), dim3(TSQR_THREADS), lds, st, it, act, t, dir, level, g.BR, g.G);
@@ -556,7 +577,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_BASIS);
-        launch_basis(ctx, st, it, act, g.maxrows, ny, t, dir);
+        launch_basis(ctx, st, it, act, rows, ny, t, dir);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
@@ -570,7 +591,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     for (int round = 0; round < ctx->tune_maxvol_rounds; ++round) {
         {
             ProfScope ps(ctx, TTFP_KERNEL_INTERP);
-            launch_interp(ctx, st, it, act, g.maxrows, ny, t, dir, round > 0 ? 1 : 0);
+            launch_interp(ctx, st, it, act, rows, ny, t, dir, round > 0 ? 1 : 0);
         }
         ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
         const int rm = std::max(g.maxR, 2);
@@ -579,7 +600,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_INTERP);
-        launch_interp(ctx, st, it, act, g.maxrows, ny, t, dir, 2);
+        launch_interp(ctx, st, it, act, rows, ny, t, dir, 2);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_FINISH);
@@ -587,7 +608,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_CORESUM);
-        hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
+        hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.left[t] * g.maxR, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
     }
     HIPCHK(hipGetLastError());
     return TTFP_OK;

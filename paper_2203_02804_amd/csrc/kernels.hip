@@ -16,6 +16,21 @@
 namespace ttfp {
 
 // ------------------------------------------------------------------ complex helpers
+// Global memory through its own address space. The items hold generic pointers, and loads and
+// stores through generic pointers compile to flat instructions, which count against the same wait
+// counter as LDS accesses: a loop that waits for its LDS operands would also wait for every global
+// load it issued ahead of time. The hot loops load and store through these instead.
+#define GLOBAL_AS __attribute__((address_space(1)))
+typedef double gdbl2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cplx gld(const cplx *p)
+{
+    const gdbl2_t v = *(const GLOBAL_AS gdbl2_t *)p;
+    return {v.x, v.y};
+}
+__device__ __forceinline__ float gld(const float *p) { return *(const GLOBAL_AS float *)p; }
+__device__ __forceinline__ void gst(cplx *p, cplx v) { *(GLOBAL_AS gdbl2_t *)p = gdbl2_t{v.x, v.y}; }
+__device__ __forceinline__ void gst(float *p, float v) { *(GLOBAL_AS float *)p = v; }
+
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
@@ -973,7 +988,8 @@ __global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_
     if (blk == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_GRAM] += 4.0 * m * (double)nc * nc;
     const cplx *src = pass == 0 ? it.F : it.Qb;
     const int T = (nc + 15) / 16, ntiles = T * (T + 1) / 2;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // this wave's tiles: q = wave, wave + NW in the order (0,0) (0,1) .. (0,T-1) (1,1) ..
     int tI[TPW], tJ[TPW];
 #pragma unroll
@@ -985,13 +1001,13 @@ __global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_
     }
     const int nt = ntiles > wave ? min(TPW, (ntiles - wave + NW - 1) / NW) : 0;
     // entry e = tid + GRAM_THREADS q of a chunk is row e / nc, column e % nc (rows of a chunk are
-    // contiguous in the fiber, so a chunk is one coalesced sweep)
-    int er[PER], ec[PER];
+    // contiguous in the fiber, so a chunk is one coalesced sweep); lo[q] is its place in the LDS
+    // planes, -1 past the chunk
+    int lo[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int e = tid + GRAM_THREADS * q;
-        er[q] = e / nc;
-        ec[q] = e - er[q] * nc;
+        const int e = tid + GRAM_THREADS * q, er = e / nc;
+        lo[q] = er < GRAM_CHUNK ? er * NCPAD + (e - er * nc) : -1;
     }
     // padding columns nc .. 16 T - 1 stay zero for every chunk
     for (int e = tid; e < GRAM_CHUNK * 16 * T; e += GRAM_THREADS) {
@@ -1018,7 +1034,7 @@ __global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + GRAM_THREADS * q;
-            pre[q] = e < n ? g[e] : cplx{0.0, 0.0};
+            pre[q] = e < n ? gld(g + e) : cplx{0.0, 0.0};
         }
     };
     fetch(r0);
@@ -1033,8 +1049,7 @@ __global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_
         }
         __syncthreads();                         // the previous chunk has been multiplied
         if (pass == 0) {
-            double mx = 0.0;
-            for (int w = 0; w < NW; ++w) mx = fmax(mx, wmax[w]);
+            double mx = wave_max(lane < NW ? wmax[lane] : 0.0);
             if (mx > 0.0) {
                 int e;
                 frexp(mx, &e);
@@ -1055,9 +1070,9 @@ __global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q)
-            if (er[q] < GRAM_CHUNK) {                // rows past nr were loaded as zeros
-                cre[er[q]][ec[q]] = pre[q].x * sc;
-                cim[er[q]][ec[q]] = pre[q].y * sc;
+            if (lo[q] >= 0) {                        // rows past nr were loaded as zeros
+                (&cre[0][0])[lo[q]] = pre[q].x * sc;
+                (&cim[0][0])[lo[q]] = pre[q].y * sc;
             }
         __syncthreads();
         if (c0 + GRAM_CHUNK < r1) fetch(c0 + GRAM_CHUNK);
@@ -1303,11 +1318,11 @@ __global__ __launch_bounds__(64 * XF_WAVES) void k_xform(Item *items, const int 
     }
     const int arow = row0 + li;
     // the left operand of the next k-step is loaded while this one's products run
-    cplx an = (arow < m && lk < nc) ? src[(size_t)arow * nc + lk] : cplx{0.0, 0.0};
+    cplx an = (arow < m && lk < nc) ? gld(src + (size_t)arow * nc + lk) : cplx{0.0, 0.0};
     for (int k0 = 0; k0 < nc; k0 += 4) {
         const int kk = k0 + lk;
         const cplx a = an;
-        if (k0 + 4 < nc) an = (arow < m && kk + 4 < nc) ? src[(size_t)arow * nc + kk + 4] : cplx{0.0, 0.0};
+        if (k0 + 4 < nc) an = (arow < m && kk + 4 < nc) ? gld(src + (size_t)arow * nc + kk + 4) : cplx{0.0, 0.0};
         const double ar = a.x * sc, ai = a.y * sc, as = ar + ai;
         const int kr = kk < nc ? kk : 0;           // rows of Xf past nc: the operand is zero anyway
 #pragma unroll
@@ -1328,7 +1343,7 @@ __global__ __launch_bounds__(64 * XF_WAVES) void k_xform(Item *items, const int 
             if (q >= T) break;
             const int col = 16 * q + li;
             if (row < m && col < nc)
-                it.Qb[(size_t)row * nc + col] = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
+                gst(it.Qb + (size_t)row * nc + col, cplx{prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]});
         }
     }
 }
@@ -1491,11 +1506,11 @@ __global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, cons
         }
         const int arow = row0 + li;
         // the left operand of the next k-step is loaded while this one's products run
-        cplx an = (arow < m && lk < r) ? it.F[(size_t)arow * nc + pm[lk]] : cplx{0.0, 0.0};
+        cplx an = (arow < m && lk < r) ? gld(it.F + (size_t)arow * nc + pm[lk]) : cplx{0.0, 0.0};
         for (int k0 = 0; k0 < r; k0 += 4) {
             const int kk = k0 + lk;
             const cplx a = an;
-            if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? it.F[(size_t)arow * nc + pm[kk + 4]] : cplx{0.0, 0.0};
+            if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? gld(it.F + (size_t)arow * nc + pm[kk + 4]) : cplx{0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (q >= ntile) break;
@@ -1516,14 +1531,14 @@ __global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, cons
                 const int col = 16 * q + li;
                 const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
                 nrm += (row < m && col < r) ? cabs2(val) : 0.0;
-                if (row < m && col < r) it.Y[(size_t)row * r + col] = val;
+                if (row < m && col < r) gst(it.Y + (size_t)row * r + col, val);
             }
             // the row's squared norm: the lane's columns li + 16 q, then the 16 lanes of the row
             nrm += __shfl_xor(nrm, 1, 64);
             nrm += __shfl_xor(nrm, 2, 64);
             nrm += __shfl_xor(nrm, 4, 64);
             nrm += __shfl_xor(nrm, 8, 64);
-            if (row < m && li == 0) it.keys[row] = (float)nrm;
+            if (row < m && li == 0) gst(it.keys + row, (float)nrm);
         }
     }
 }
@@ -2288,7 +2303,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
     const double cm = 1.001 * it.mv_colmax;
     if (check) {
         const int row = blockIdx.x * rows_per_wg + (int)threadIdx.x;
-        const bool need = (int)threadIdx.x < rows_per_wg && row < m && !((double)it.keys[row] * cm <= lim);
+        const bool need = (int)threadIdx.x < rows_per_wg && row < m && !((double)gld(it.keys + row) * cm <= lim);
         if (!__syncthreads_or(need)) return;
     }
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ai[e] = it.Ai[e];
@@ -2301,7 +2316,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
         const int li = lane & 15, lk = lane >> 4;
         if (check) {
             const int row = row0 + li;
-            if (!__any(row < m && !((double)it.keys[row] * cm <= lim))) continue;
+            if (!__any(row < m && !((double)gld(it.keys + row) * cm <= lim))) continue;
         }
         // the work done: this panel's rows
         if (lane == 0) atomicAdd(&it.work[TTFP_KERNEL_INTERP], 8.0 * (double)min(16, m - row0) * r * r);
@@ -2318,11 +2333,11 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
         }
         const int arow = row0 + li;
         // the left operand of the next k-step is loaded while this one's products run
-        cplx an = (arow < m && lk < r) ? Y[(size_t)arow * r + lk] : cplx{0.0, 0.0};
+        cplx an = (arow < m && lk < r) ? gld(Y + (size_t)arow * r + lk) : cplx{0.0, 0.0};
         for (int k0 = 0; k0 < r; k0 += 4) {
             const int kk = k0 + lk;
             const cplx a = an;
-            if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? Y[(size_t)arow * r + kk + 4] : cplx{0.0, 0.0};
+            if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? gld(Y + (size_t)arow * r + kk + 4) : cplx{0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (q >= ntile) break;
@@ -2347,7 +2362,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
                 const int col = 16 * q + li;
                 if (row < m && col < r) {
                     const cplx val = {prr[q][v] - pii[q][v], pss[q][v] - prr[q][v] - pii[q][v]};
-                    if (store) B[dir == 1 ? (size_t)col * m + row : (size_t)row * r + col] = val;
+                    if (store) gst(B + (dir == 1 ? (size_t)col * m + row : (size_t)row * r + col), val);
                     mx = fmax(mx, cabs2(val));
                 }
             }
