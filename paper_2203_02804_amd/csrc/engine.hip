@@ -17,20 +17,20 @@
 
 namespace ttfp {
 __global__ void k_init(Item *items, int n_items);
-__global__ void k_fiber(Item *items, const int *active, int t, int dir, int mode);
+__global__ void k_fiber(Item *items, ItemList work, int t, int dir, int mode);
 __global__ void k_eval_points(const Item *items, long long npts, const int *idx, cplx *out);
-__global__ void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G);
-__global__ void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G);
-template <int W> __global__ void k_gram(Item *items, const int *active, int t, int dir, int pass);
-__global__ void k_chol(Item *items, const int *active, int t, int dir, int pass, int last);
-__global__ void k_xform(Item *items, const int *active, int t, int dir, int pass);
-template <int W, int P> __global__ void k_basis(Item *items, const int *active, int t, int dir);
-__global__ void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm);
-__global__ void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax);
-template <int W, int P> __global__ void k_interp(Item *items, const int *active, int t, int dir, int mode, int bound);
-__global__ void k_finish(Item *items, const int *active, int t, int dir);
-__global__ void k_core_sum(Item *items, const int *active, int t, int dir, int mode);
-__global__ void k_contract(Item *items, const int *active);
+__global__ void k_tsqr(Item *items, ItemList work, int t, int dir, int level, int BR, int G);
+__global__ void k_qrcp(Item *items, ItemList work, int t, int dir, int BR, int G);
+template <int W> __global__ void k_gram(Item *items, ItemList work, int t, int dir, int pass);
+__global__ void k_chol(Item *items, ItemList work, int t, int dir, int pass, int last);
+__global__ void k_xform(Item *items, ItemList work, int t, int dir, int pass);
+template <int W, int P> __global__ void k_basis(Item *items, ItemList work, int t, int dir);
+__global__ void k_maxvol(Item *items, ItemList work, int t, int dir, int rmax, int warm);
+__global__ void k_maxvol_refine(Item *items, ItemList work, int t, int dir, int rmax);
+template <int W, int P> __global__ void k_interp(Item *items, ItemList work, int t, int dir, int mode, int bound);
+__global__ void k_finish(Item *items, ItemList work, int t, int dir);
+__global__ void k_core_sum(Item *items, ItemList work, int t, int dir, int mode);
+__global__ void k_contract(Item *items, ItemList work);
 __global__ void k_core_moments(Item *items, const int *active);
 __global__ void k_moments(Item *items, const int *active, cplx *out, int stride);
 __global__ void k_tt_values(const Item *items, int item, long long npts, const int *idx, cplx *out);
@@ -76,6 +76,13 @@ struct ttfp_ctx {
     // the half-sweep flags of the device-side convergence test, read one half sweep behind
     int *h_flags = nullptr;               // pinned host memory, MAX_HALF + 1 ints
     hipEvent_t ev_flag[2] = {nullptr, nullptr};
+    // item lists of the half sweeps (launches over the items still active two half sweeps
+    // earlier): the device list, and pinned staging for the activity flags read back behind each
+    // half sweep and for the lists sent ahead, two of each (list_cap ints apiece)
+    int *d_list = nullptr;
+    int *h_act = nullptr;
+    int *h_list = nullptr;
+    size_t list_cap = 0;
     // allocation-free mode (ttfp_price_batch_noalloc): this device's static scratch array
     char *scratch = nullptr;
     bool noalloc = false;
@@ -495,7 +502,7 @@ int cholqr_passes(const ttfp_ctx *ctx, double eps)
 }
 
 // The fiber's triangular factor by passes of shifted Cholesky QR (k_gram, k_chol, k_xform).
-void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int maxrows, unsigned ny, int t, int dir, int npass)
+void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, ItemList act, int maxrows, unsigned ny, int t, int dir, int npass)
 {
     const unsigned gb = cdivu(maxrows, GRAM_ROWS_HOST), gx = cdivu(maxrows, 16 * XF_WAVES_HOST);
     for (int pass = 0; pass < npass; ++pass) {
@@ -518,11 +525,11 @@ void launch_cholqr(ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, int 
 // The basis and interpolation products with TTFP_TUNE_MM_WAVES waves per workgroup and
 // TTFP_TUNE_MM_PANELS 16-row panels per wave.
 template <int W, int P>
-void launch_basis_t(hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir)
+void launch_basis_t(hipStream_t st, Item *it, ItemList act, long long rows, unsigned ny, int t, int dir)
 {
     hipLaunchKernelGGL((k_basis<W, P>), dim3(cdivu(rows, 16 * W * P), ny), dim3(64 * W), 0, st, it, act, t, dir);
 }
-void launch_basis(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir)
+void launch_basis(const ttfp_ctx *ctx, hipStream_t st, Item *it, ItemList act, long long rows, unsigned ny, int t, int dir)
 {
     const bool w16 = ctx->tune_mm_waves == 16, p2 = ctx->tune_mm_panels == 2;
     if (w16 && p2) launch_basis_t<16, 2>(st, it, act, rows, ny, t, dir);
@@ -532,13 +539,13 @@ void launch_basis(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act,
 }
 
 template <int W, int P>
-void launch_interp_t(hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir, int mode,
+void launch_interp_t(hipStream_t st, Item *it, ItemList act, long long rows, unsigned ny, int t, int dir, int mode,
                      int bound)
 {
     hipLaunchKernelGGL((k_interp<W, P>), dim3(cdivu(rows, 16 * W * P), ny), dim3(64 * W), 0, st, it, act, t, dir, mode,
                        bound);
 }
-void launch_interp(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act, long long rows, unsigned ny, int t, int dir,
+void launch_interp(const ttfp_ctx *ctx, hipStream_t st, Item *it, ItemList act, long long rows, unsigned ny, int t, int dir,
                    int mode)
 {
     const bool w16 = ctx->tune_mm_waves == 16, p2 = ctx->tune_mm_panels == 2;
@@ -549,12 +556,35 @@ void launch_interp(const ttfp_ctx *ctx, hipStream_t st, Item *it, const int *act
     else launch_interp_t<8, 1>(st, it, act, rows, ny, t, dir, mode, b);
 }
 
-int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int sweep)
+// Buffers of the item lists for n items; false (launches over every item) when they cannot be
+// allocated.
+bool ensure_lists(ttfp_ctx *ctx, size_t n)
+{
+    if (n <= ctx->list_cap) return true;
+    if (ctx->h_act) (void)hipHostFree(ctx->h_act);
+    if (ctx->h_list) (void)hipHostFree(ctx->h_list);
+    if (ctx->d_list) (void)hipFree(ctx->d_list);
+    ctx->h_act = ctx->h_list = ctx->d_list = nullptr;
+    ctx->list_cap = 0;
+    const size_t cap = std::max(n, (size_t)64);
+    if (hipHostMalloc((void **)&ctx->h_act, 2 * cap * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_list, 2 * cap * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&ctx->d_list, cap * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ctx->h_act) (void)hipHostFree(ctx->h_act);
+        if (ctx->h_list) (void)hipHostFree(ctx->h_list);
+        if (ctx->d_list) (void)hipFree(ctx->d_list);
+        ctx->h_act = ctx->h_list = ctx->d_list = nullptr;
+        return false;
+    }
+    ctx->list_cap = cap;
+    return true;
+}
+
+int launch_step(ttfp_ctx *ctx, const Launch &g, ItemList act, unsigned ny, int t, int dir, int sweep)
 {
     hipStream_t st = ctx->stream;
     Item *it = ctx->d_items;
-    int *act = ctx->d_active;
-    const unsigned ny = (unsigned)n_items;
     {
         ProfScope ps(ctx, TTFP_KERNEL_FIBER);
         hipLaunchKernelGGL(k_fiber, dim3(cdivu((long long)g.left[t] * g.maxnc, 256), ny), dim3(256), 0, st, it, act, t, dir, 0);
@@ -614,21 +644,20 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, int n_items, int t, int dir, int
     return TTFP_OK;
 }
 
-int launch_edge(ttfp_ctx *ctx, const Launch &g, int n_items, int dir, int sweep)
+int launch_edge(ttfp_ctx *ctx, const Launch &g, ItemList act, unsigned ny, int dir, int sweep)
 {
     hipStream_t st = ctx->stream;
-    const unsigned ny = (unsigned)n_items;
     {
         ProfScope ps(ctx, TTFP_KERNEL_FIBER);
-        hipLaunchKernelGGL(k_fiber, dim3(cdivu(g.maxR, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1);
+        hipLaunchKernelGGL(k_fiber, dim3(cdivu(g.maxR, 256), ny), dim3(256), 0, st, ctx->d_items, act, 0, dir, 1);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_CORESUM);
-        hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, ctx->d_items, ctx->d_active, 0, dir, 1);
+        hipLaunchKernelGGL(k_core_sum, dim3(cdivu((long long)g.maxR * g.maxR, 256), ny), dim3(256), 0, st, ctx->d_items, act, 0, dir, 1);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_CONTRACT);
-        hipLaunchKernelGGL(k_contract, dim3(ny), dim3(64), 0, st, ctx->d_items, ctx->d_active);
+        hipLaunchKernelGGL(k_contract, dim3(ny), dim3(64), 0, st, ctx->d_items, act);
     }
     HIPCHK(hipGetLastError());
     return TTFP_OK;
@@ -696,15 +725,17 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
         HIPCHK(hipStreamSynchronize(ctx->stream));    // the staging vectors go out of scope
     }
     std::vector<Item> host_items(n_items);
-    // one half sweep: the steps of every core, the edge core and the contraction, then the
-    // convergence test that switches off the items of finished options
-    auto launch_half = [&](int dir, int sweep) -> int {
-        for (int t = 0; t + 1 < b.geo.maxd; ++t) {
-            int rc = launch_step(ctx, b.geo, n_items, t, dir, sweep);
+    // one half sweep over the items of w (ny of them): the steps of every core, the edge core and
+    // the contraction, then the convergence test that switches off the items of finished options
+    auto launch_half = [&](ItemList w, unsigned ny, int dir, int sweep) -> int {
+        for (int t = 0; ny > 0 && t + 1 < b.geo.maxd; ++t) {
+            int rc = launch_step(ctx, b.geo, w, ny, t, dir, sweep);
             if (rc) return rc;
         }
-        int rc = launch_edge(ctx, b.geo, n_items, dir, sweep);
-        if (rc) return rc;
+        if (ny > 0) {
+            int rc = launch_edge(ctx, b.geo, w, ny, dir, sweep);
+            if (rc) return rc;
+        }
         hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, ctx->stream, ctx->d_items, ctx->d_active, b.d_os, n_opts, b.d_scale,
                            b.d_flags);
         HIPCHK(hipGetLastError());
@@ -725,6 +756,7 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
         }
     } graphs;
     const bool use_graph = ctx->tune_graph && ctx->stream != nullptr && !ctx->noalloc && !ctx->prof;
+    const bool compact = !use_graph && !ctx->noalloc && ensure_lists(ctx, (size_t)n_items);
     // Half sweeps are queued back to back; after queueing half h the host waits for the flag
     // of half h - 1 (copied into pinned memory behind it), so one half sweep stays queued while
     // the host decides, and the run ends when no option was active after a half sweep.
@@ -733,7 +765,7 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
         if (use_graph) {
             if (!graphs.x[dir]) {
                 HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-                int rc = launch_half(dir, sweep);
+                int rc = launch_half(ItemList(ctx->d_active), (unsigned)n_items, dir, sweep);
                 hipGraph_t gr = nullptr;
                 hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
                 if (rc) return rc;
@@ -743,10 +775,26 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
             }
             HIPCHK(hipGraphLaunch(graphs.x[dir], ctx->stream));
         } else {
-            int rc = launch_half(dir, sweep);
+            ItemList w(ctx->d_active);
+            unsigned ny = (unsigned)n_items;
+            if (compact && h >= 2) {
+                // the items still active after half h - 2, whose flags came back with that half's
+                // flag (the host has waited for it); items that finished since return at once
+                const int *fl = ctx->h_act + (size_t)(h & 1) * ctx->list_cap;
+                int *lst = ctx->h_list + (size_t)(h & 1) * ctx->list_cap;
+                ny = 0;
+                for (int i = 0; i < n_items; ++i)
+                    if (fl[i]) lst[ny++] = i;
+                if (ny > 0) HIPCHK(hipMemcpyAsync(ctx->d_list, lst, ny * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+                w = ItemList(ctx->d_active, ctx->d_list);
+            }
+            int rc = launch_half(w, ny, dir, sweep);
             if (rc) return rc;
         }
         HIPCHK(hipMemcpyAsync(ctx->h_flags + h, b.d_flags + h, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        if (compact)
+            HIPCHK(hipMemcpyAsync(ctx->h_act + (size_t)(h & 1) * ctx->list_cap, ctx->d_active, n_items * sizeof(int),
+                                  hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipEventRecord(ctx->ev_flag[h & 1], ctx->stream));
         if (h >= 1) {
             HIPCHK(hipEventSynchronize(ctx->ev_flag[(h - 1) & 1]));
@@ -1033,6 +1081,9 @@ int ttfp_destroy(ttfp_ctx *ctx)
     for (auto e : ctx->ev_flag)
         if (e) (void)hipEventDestroy(e);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+    if (ctx->h_act) (void)hipHostFree(ctx->h_act);
+    if (ctx->h_list) (void)hipHostFree(ctx->h_list);
+    if (ctx->d_list) (void)hipFree(ctx->d_list);
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->d_items) (void)hipFree(ctx->d_items);
     if (ctx->d_active) (void)hipFree(ctx->d_active);

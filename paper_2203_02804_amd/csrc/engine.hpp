@@ -93,6 +93,17 @@ struct OptState {
     double hist[64];                  // relative change after each half sweep
 };
 
+// The items a launch works on: block b of the launch's item dimension takes item list[b], or item
+// b when the launch has no list; an item whose activity flag is 0 returns at once. The half sweeps
+// launch over the items that were still active a little earlier (the flags only ever turn off), so
+// that finished options cost no workgroups.
+struct ItemList {
+    const int *active;
+    const int *list;
+    __host__ __device__ ItemList(const int *a, const int *l = nullptr) : active(a), list(l) {}
+    __device__ int item(int b) const { return list ? list[b] : b; }
+};
+
 // Step addressing: dir 0 = left-to-right (core k = t), dir 1 = right-to-left (core k = d-1-t).
 __host__ __device__ inline int step_core(const Item &it, int t, int dir) { return dir == 0 ? t : it.d - 1 - t; }
 

@@ -442,13 +442,13 @@ __global__ void k_init(Item *items, int n_items)
 // with c_k and h_k tabulated per node in LDS. With Merton jumps the exponent gains
 // lamT (exp(J_0 + z_k tau_J + j_k(i)) - 1), J_0, tau_J and j_k formed from mJ and CJ the same way:
 // one more exp and sincos per entry.
-__global__ __launch_bounds__(256) void k_fiber(Item *items, const int *active, int t, int dir, int mode)
+__global__ __launch_bounds__(256) void k_fiber(Item *items, ItemList work, int t, int dir, int mode)
 {
     __shared__ cplx ctab[MAXN];
     __shared__ cplx htab[MAXN];
     __shared__ cplx jtab[MAXN];
-    const int item = blockIdx.y;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.y);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, mode);
     if (!s.valid) return;
@@ -866,13 +866,13 @@ __device__ __forceinline__ int tsqr_final_level(int rows, int BR, int G)
 // One TSQR level: level 0 reduces row blocks of the fiber (BR rows, padded row-major in LDS),
 // level L > 0 groups of G triangular factors of level L-1 (packed by rows in LDS). Writes
 // nc x nc factors into buffer (level % 2).
-__global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, const int *active, int t, int dir, int level, int BR, int G)
+__global__ __launch_bounds__(TSQR_THREADS) void k_tsqr(Item *items, ItemList work, int t, int dir, int level, int BR, int G)
 {
     extern __shared__ cplx lds[];
     __shared__ cplx alph[MAXNC];
     __shared__ double tau[MAXNC];
-    const int item = blockIdx.y;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.y);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -972,14 +972,14 @@ __device__ __forceinline__ int gram_blocks(int rows) { return (rows + GRAM_ROWS 
 // chunk): a launch tuning that leaves every result bit unchanged (each tile sums the same rows in
 // the same order).
 template <int GRAM_THREADS>
-__global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_gram(Item *items, const int *active, int t, int dir, int pass)
+__global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_gram(Item *items, ItemList work, int t, int dir, int pass)
 {
     constexpr int PER = (GRAM_CHUNK * MAXNC + GRAM_THREADS - 1) / GRAM_THREADS;   // chunk entries per thread
     constexpr int NW = GRAM_THREADS / 64, TPW = 1024 / GRAM_THREADS;               // waves, tiles per wave
     __shared__ double cre[GRAM_CHUNK][NCPAD], cim[GRAM_CHUNK][NCPAD];
     __shared__ double wmax[NW];
-    const int item = blockIdx.y;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.y);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -1102,8 +1102,8 @@ __global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_
     }
     if (tid == 0) it.Ge[blk] = pass == 0 ? e_blk : 0;
 }
-template __global__ void k_gram<512>(Item *, const int *, int, int, int);
-template __global__ void k_gram<1024>(Item *, const int *, int, int, int);
+template __global__ void k_gram<512>(Item *, ItemList, int, int, int);
+template __global__ void k_gram<1024>(Item *, ItemList, int, int, int);
 
 // Packed upper-triangular storage of an n x n matrix: row i starts at i n - i (i - 1) / 2.
 __device__ __forceinline__ int up_off(int i, int n) { return i * n - (i * (i - 1)) / 2; }
@@ -1123,14 +1123,14 @@ __device__ __forceinline__ int up_row(int e, int n)
 // row-major with zeros below the diagonal) and the running factor it.Rf: R in pass 0, R Rf after.
 // The last pass leaves Rf / s = the triangular factor of F (nc x nc, row-major), which the
 // column-pivoted QR reads.
-__global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, int t, int dir, int pass, int last)
+__global__ __launch_bounds__(256) void k_chol(Item *items, ItemList work, int t, int dir, int pass, int last)
 {
     __shared__ cplx Rp[MAXNC * (MAXNC + 1) / 2];   // G, then its Cholesky factor (packed upper)
     __shared__ cplx Xp[MAXNC * (MAXNC + 1) / 2];   // R^{-1}, then the factor product (packed upper)
     __shared__ double red[256 / 64];
     __shared__ int sh_fail;
-    const int item = blockIdx.x;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.x);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -1285,11 +1285,11 @@ __global__ __launch_bounds__(256) void k_chol(Item *items, const int *active, in
 // stride of NCPAD doubles (the two k-rows a half wave reads fall on disjoint banks); complex
 // products by three real ones (Gauss) into three independent accumulators per tile.
 constexpr int XF_WAVES = 12;                       // 16-row panels per workgroup
-__global__ __launch_bounds__(64 * XF_WAVES) void k_xform(Item *items, const int *active, int t, int dir, int pass)
+__global__ __launch_bounds__(64 * XF_WAVES) void k_xform(Item *items, ItemList work, int t, int dir, int pass)
 {
     __shared__ double Xr[MAXNC][NCPAD], Xi[MAXNC][NCPAD];
-    const int item = blockIdx.y;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.y);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -1349,7 +1349,7 @@ __global__ __launch_bounds__(64 * XF_WAVES) void k_xform(Item *items, const int 
 }
 
 // ------------------------------------------------------------------ pivoted QR of R, rank, inverse
-__global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *active, int t, int dir, int BR, int G)
+__global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, ItemList work, int t, int dir, int BR, int G)
 {
     __shared__ cplx A[MAXNC * (MAXNC | 1)];
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
@@ -1358,8 +1358,8 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
     __shared__ int perm[MAXNC];
     __shared__ cplx alph[MAXNC];
     __shared__ int shi[4];
-    const int item = blockIdx.x;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.x);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -1472,12 +1472,12 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, const int *a
 // tuning that leaves every result bit unchanged (a row's product does not depend on the workgroup
 // or wave it falls in). More rows per workgroup spread the 64 KiB staging of R^-1 over more rows.
 template <int PANEL_WAVES, int PPW>
-__global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, const int *active, int t, int dir)
+__global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, ItemList work, int t, int dir)
 {
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
     __shared__ int pm[TTFP_MAX_RANK];
-    const int item = blockIdx.y;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.y);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -1542,10 +1542,10 @@ __global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, cons
         }
     }
 }
-template __global__ void k_basis<8, 1>(Item *, const int *, int, int);
-template __global__ void k_basis<16, 1>(Item *, const int *, int, int);
-template __global__ void k_basis<8, 2>(Item *, const int *, int, int);
-template __global__ void k_basis<16, 2>(Item *, const int *, int, int);
+template __global__ void k_basis<8, 1>(Item *, ItemList, int, int);
+template __global__ void k_basis<16, 1>(Item *, ItemList, int, int);
+template __global__ void k_basis<8, 2>(Item *, ItemList, int, int);
+template __global__ void k_basis<16, 2>(Item *, ItemList, int, int);
 
 // ------------------------------------------------------------------ maxvol
 // block-wide argmax (ties: lowest flat index); every thread receives the result: within each wave
@@ -2008,7 +2008,7 @@ __device__ void store_colmax(const cplx *Ai, int r, Item &it)
 // of the launch): the key buffer of the start, the blocked elimination's panel, then A^{-1} (the
 // Gauss-Jordan inverse keeps A itself in registers). With the static arrays a workgroup takes
 // under 80 KiB, so two run on a CU. 1024 threads.
-__global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *active, int t, int dir, int rmax, int warm)
+__global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, ItemList work, int t, int dir, int rmax, int warm)
 {
     extern __shared__ cplx Abuf[];
     const int cap = max(rmax * rmax, MV_KMAX * (MV_NB + 1));   // entries of Abuf
@@ -2025,8 +2025,8 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *acti
     __shared__ ArgMax red[17];
     __shared__ int shi[4];
     __shared__ float shf[2];
-    const int item = blockIdx.x;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.x);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -2198,7 +2198,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, const int *acti
 
 // Refinement round: the pivots and up to MV_KMAX - r rows that k_interp found violating (largest
 // first) form the block; swaps as in k_maxvol. Returns at once when no row violated.
-__global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const int *active, int t, int dir, int rmax)
+__global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, ItemList work, int t, int dir, int rmax)
 {
     extern __shared__ cplx Abuf[];
     cplx *Ai = Abuf;                                 // rmax^2 entries
@@ -2210,8 +2210,8 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const in
     __shared__ ArgMax red[17];
     __shared__ int shi[4];
     __shared__ float shf[2];
-    const int item = blockIdx.x;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.x);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -2282,11 +2282,11 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, const in
 // the marks alone.
 // INTERP_WAVES waves per workgroup, PPW 16-row panels per wave, as for k_basis.
 template <int INTERP_WAVES, int PPW>
-__global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, const int *active, int t, int dir, int mode, int bound)
+__global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, ItemList work, int t, int dir, int mode, int bound)
 {
     __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
-    const int item = blockIdx.y;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.y);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -2376,16 +2376,16 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, co
         }
     }
 }
-template __global__ void k_interp<8, 1>(Item *, const int *, int, int, int, int);
-template __global__ void k_interp<16, 1>(Item *, const int *, int, int, int, int);
-template __global__ void k_interp<8, 2>(Item *, const int *, int, int, int, int);
-template __global__ void k_interp<16, 2>(Item *, const int *, int, int, int, int);
+template __global__ void k_interp<8, 1>(Item *, ItemList, int, int, int, int);
+template __global__ void k_interp<16, 1>(Item *, ItemList, int, int, int, int);
+template __global__ void k_interp<8, 2>(Item *, ItemList, int, int, int, int);
+template __global__ void k_interp<16, 2>(Item *, ItemList, int, int, int, int);
 
 // ------------------------------------------------------------------ index sets and core placement
-__global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, int t, int dir)
+__global__ __launch_bounds__(256) void k_finish(Item *items, ItemList work, int t, int dir)
 {
-    const int item = blockIdx.y;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.y);
+    if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -2424,10 +2424,10 @@ __global__ __launch_bounds__(256) void k_finish(Item *items, const int *active, 
 
 // ------------------------------------------------------------------ core sums and contraction
 // M_k = sum_i core_k[:, i, :] (the quadrature weights eta_k are applied on the host).
-__global__ __launch_bounds__(256) void k_core_sum(Item *items, const int *active, int t, int dir, int mode)
+__global__ __launch_bounds__(256) void k_core_sum(Item *items, ItemList work, int t, int dir, int mode)
 {
-    const int item = blockIdx.y;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.y);
+    if (!work.active[item]) return;
     Item &it = items[item];
     int k;
     if (mode == 0) {
@@ -2447,11 +2447,11 @@ __global__ __launch_bounds__(256) void k_core_sum(Item *items, const int *active
 }
 
 // P = 1^T M_0 M_1 ... M_{d-1} 1
-__global__ __launch_bounds__(64) void k_contract(Item *items, const int *active)
+__global__ __launch_bounds__(64) void k_contract(Item *items, ItemList work)
 {
     __shared__ cplx v[TTFP_MAX_RANK], w[TTFP_MAX_RANK];
-    const int item = blockIdx.x;
-    if (!active[item]) return;
+    const int item = work.item(blockIdx.x);
+    if (!work.active[item]) return;
     Item &it = items[item];
     if (threadIdx.x == 0) v[0] = {1.0, 0.0};
     __syncthreads();
