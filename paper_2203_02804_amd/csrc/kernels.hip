@@ -2440,9 +2440,18 @@ __global__ __launch_bounds__(256) void k_core_sum(Item *items, ItemList work, in
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a_n * b_n) return;
     const int a = e / b_n, b = e % b_n;
-    const cplx *core = it.cores + (size_t)k * R * N * R;
+    const cplx *col = it.cores + (size_t)k * R * N * R + (size_t)a * N * b_n + b;
+    // the sum runs over i in order; the loads are issued eight at a time ahead of the additions
     cplx acc = {0.0, 0.0};
-    for (int i = 0; i < N; ++i) acc = cadd(acc, core[((size_t)a * N + i) * b_n + b]);
+    int i = 0;
+    for (; i + 8 <= N; i += 8) {
+        cplx v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = gld(col + (size_t)(i + u) * b_n);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
+    }
+    for (; i < N; ++i) acc = cadd(acc, gld(col + (size_t)i * b_n));
     it.M[(size_t)k * R * R + e] = acc;
 }
 
