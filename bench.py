@@ -395,6 +395,9 @@ def main():
     ap.add_argument("--no-cpu-ttcross", action="store_true", help="skip the CPU TT-cross timing")
     ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's call-on-min experiment")
     ap.add_argument("--no-ladder", action="store_true", help="skip the market-ladder leg")
+    ap.add_argument("--no-diag", action="store_true",
+                    help="skip the per-option diagnostics after the timed region (so that a kernel trace of the "
+                         "run holds the batches' launches only)")
     ap.add_argument("--qr", choices=["cholqr", "tsqr", "cholqr2", "cholqr3"], default="cholqr",
                     help="triangular factor of the fibers: shifted Cholesky QR on the matrix cores with passes "
                          "chosen by the rank threshold, Householder TSQR, or two / three Cholesky QR passes")
@@ -491,7 +494,7 @@ def main():
 
     # per-option diagnostics of two options (outside the timed region)
     diag = []
-    for o in batches[args.warmup][:2]:
+    for o in ([] if args.no_diag else batches[args.warmup][:2]):
         _, ranks, info, rc = pricer.price(o, grid)
         diag.append(dict(max_rank_reached=int(ranks.max()), n_evals=info["n_evals"], half_sweeps=info["sweeps"],
                          maxvol_swaps=info["maxvol_swaps"], maxvol_full_starts=info["maxvol_full_starts"],

@@ -309,14 +309,15 @@ int ttfp_get_tuning(ttfp_ctx *ctx, int param, int *value);
  * Cholesky QR's Gram products (4 m n^2 per pass: the Hermitian half of X^H X, m fiber rows,
  * n columns) and triangular transforms (4 m n^2 per pass: X R^{-1} with R^{-1} triangular),
  * basis (4 m r^2), maxvol on its candidate block of K rows (8 K r^2 for the block, 8 (K + r) r
- * per swap for the rank-one updates of the block and of A^{-1}, 8 r^3 per Gauss-Jordan inverse)
+ * per swap for the rank-one updates of the block and of A^{-1}, 8 r^3 per Gauss-Jordan inverse;
+ * its refinement rounds on blocks of the pivots and violating rows are a family of their own)
  * and the interpolation matrix (8 m r^2), the ladder's per-point node contractions (8 S N r_{k-1} r_k
  * per core for S points); 0 where not counted). */
 enum {
     TTFP_KERNEL_FIBER = 0, TTFP_KERNEL_TSQR = 1, TTFP_KERNEL_QRCP = 2, TTFP_KERNEL_BASIS = 3,
     TTFP_KERNEL_MAXVOL = 4, TTFP_KERNEL_FINISH = 5, TTFP_KERNEL_CORESUM = 6, TTFP_KERNEL_CONTRACT = 7,
     TTFP_KERNEL_INTERP = 8, TTFP_KERNEL_ERREST = 9, TTFP_KERNEL_GRAM = 10, TTFP_KERNEL_CHOL = 11,
-    TTFP_KERNEL_XFORM = 12, TTFP_KERNEL_LADDER = 13, TTFP_KERNEL_COUNT = 14
+    TTFP_KERNEL_XFORM = 12, TTFP_KERNEL_LADDER = 13, TTFP_KERNEL_REFINE = 14, TTFP_KERNEL_COUNT = 15
 };
 int ttfp_profile_enable(ttfp_ctx *ctx, int enable);
 int ttfp_profile_read(ttfp_ctx *ctx, int kernel, int64_t *launches, double *total_ms, double *work);

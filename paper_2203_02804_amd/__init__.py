@@ -61,7 +61,7 @@ EXPORTS = ["ttfp_create", "ttfp_destroy", "ttfp_plan", "ttfp_price", "ttfp_price
            "ttfp_mlp_get_params", "ttfp_mlp_set_params", "ttfp_mlp_forward", "ttfp_mlp_grad", "ttfp_mlp_train_step",
            "ttfp_mlp_last_error"]
 KERNELS = ["fiber", "tsqr", "qrcp", "basis", "maxvol", "finish", "core_sum", "contract", "interp", "err_est",
-           "gram", "chol", "xform", "ladder"]
+           "gram", "chol", "xform", "ladder", "refine"]
 TUNING = {"maxvol_rounds": 0, "tsqr_lds_kb": 1, "graph": 2, "qr": 3, "maxvol_warm": 4, "mm_waves": 5, "gram_threads": 6, "mm_panels": 7, "interp_bound": 8}
 
 _lib = None

@@ -623,7 +623,7 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, ItemList act, unsigned ny, int t
             ProfScope ps(ctx, TTFP_KERNEL_INTERP);
             launch_interp(ctx, st, it, act, rows, ny, t, dir, round > 0 ? 1 : 0);
         }
-        ProfScope ps(ctx, TTFP_KERNEL_MAXVOL);
+        ProfScope ps(ctx, TTFP_KERNEL_REFINE);
         const int rm = std::max(g.maxR, 2);
         const size_t lds = (size_t)rm * rm * sizeof(cplx);
         hipLaunchKernelGGL(k_maxvol_refine, dim3(ny), dim3(MAXVOL_THREADS), lds, st, it, act, t, dir, rm);

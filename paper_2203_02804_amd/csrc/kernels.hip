@@ -2264,7 +2264,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, ItemList
         it.mv_iters += swaps;
         it.mv_viol = 0;
         it.mv_dirty = swaps > 0;
-        it.work[TTFP_KERNEL_MAXVOL] += 8.0 * (Kc + r) * (double)r * swaps + (swaps > MV_SM_MAX ? 8.0 * (double)r * r * r : 0.0);
+        it.work[TTFP_KERNEL_REFINE] += 8.0 * (Kc + r) * (double)r * swaps + (swaps > MV_SM_MAX ? 8.0 * (double)r * r * r : 0.0);
     }
 }
 
