@@ -447,7 +447,7 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, ItemList work, int t
     __shared__ cplx ctab[MAXN];
     __shared__ cplx htab[MAXN];
     __shared__ cplx jtab[MAXN];
-    const int item = work.item(blockIdx.y);
+    const int item = work.item(blockIdx.x);
     if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, mode);
@@ -455,9 +455,9 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, ItemList work, int t
     const int d = it.d, N = it.N, R = it.R, k = s.k;
     const int ng = (dir == 0) ? s.rows / N : it.nJ[k + 1];     // row groups
     const long long pairs = (long long)ng * s.nc;
-    if ((long long)blockIdx.x * blockDim.x >= pairs) return;
+    if ((long long)blockIdx.y * blockDim.x >= pairs) return;
     const long long total = (long long)s.rows * s.nc;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.y == 0 && threadIdx.x == 0) {
         if (mode == 1) {
             if (dir == 0) { it.crow[k] = it.nI[k]; it.ccol[k] = 1; }
             else { it.crow[k] = 1; it.ccol[k] = it.nJ[1]; }
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, ItemList work, int t
         }
     }
     __syncthreads();
-    const long long pidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long pidx = (long long)blockIdx.y * blockDim.x + threadIdx.x;
     if (pidx >= pairs) return;
     const int g = (int)(pidx / s.nc), c = (int)(pidx % s.nc);
     const int a = (dir == 0) ? g : c;          // left multi-index
@@ -978,12 +978,12 @@ __global__ __launch_bounds__(GRAM_THREADS, GRAM_THREADS == 1024 ? 8 : 4) void k_
     constexpr int NW = GRAM_THREADS / 64, TPW = 1024 / GRAM_THREADS;               // waves, tiles per wave
     __shared__ double cre[GRAM_CHUNK][NCPAD], cim[GRAM_CHUNK][NCPAD];
     __shared__ double wmax[NW];
-    const int item = work.item(blockIdx.y);
+    const int item = work.item(blockIdx.x);
     if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
-    const int m = s.rows, nc = s.nc, blk = blockIdx.x;
+    const int m = s.rows, nc = s.nc, blk = blockIdx.y;
     if (blk >= gram_blocks(m)) return;
     if (blk == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_GRAM] += 4.0 * m * (double)nc * nc;
     const cplx *src = pass == 0 ? it.F : it.Qb;
@@ -1476,22 +1476,22 @@ __global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, Item
 {
     __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
     __shared__ int pm[TTFP_MAX_RANK];
-    const int item = work.item(blockIdx.y);
+    const int item = work.item(blockIdx.x);
     if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
     const int r = it.rsel, nc = s.nc, m = s.rows;
     const int rows_per_wg = 16 * PANEL_WAVES * PPW;
-    if (blockIdx.x * rows_per_wg >= m) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_BASIS] += 4.0 * (double)m * r * r;
+    if (blockIdx.y * rows_per_wg >= m) return;
+    if (blockIdx.y == 0 && threadIdx.x == 0) it.work[TTFP_KERNEL_BASIS] += 4.0 * (double)m * r * r;
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) Ri[e] = it.Rinv[e];
     for (int e = threadIdx.x; e < r; e += blockDim.x) pm[e] = it.perm[e];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll 1
     for (int pp = 0; pp < PPW; ++pp) {
-        const int row0 = blockIdx.x * rows_per_wg + (pp * PANEL_WAVES + wave) * 16;
+        const int row0 = blockIdx.y * rows_per_wg + (pp * PANEL_WAVES + wave) * 16;
         if (row0 >= m) break;
         const int li = lane & 15, lk = lane >> 4;
         const int ntile = (r + 15) / 16;
@@ -2285,7 +2285,7 @@ template <int INTERP_WAVES, int PPW>
 __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, ItemList work, int t, int dir, int mode, int bound)
 {
     __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
-    const int item = work.item(blockIdx.y);
+    const int item = work.item(blockIdx.x);
     if (!work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
@@ -2294,7 +2294,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, It
     const bool store = mode == 2;
     const int r = it.rsel, m = s.rows;
     const int rows_per_wg = 16 * INTERP_WAVES * PPW;
-    if (blockIdx.x * rows_per_wg >= m) return;
+    if (blockIdx.y * rows_per_wg >= m) return;
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     // A checking pass skips the rows that cannot violate: |B_ij|^2 <= |y_i|^2 max_j |A^{-1} e_j|^2
     // (the row norms from k_basis, held as floats: the margin covers their rounding). A workgroup
@@ -2302,7 +2302,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, It
     const bool check = !store && dir != 2 && bound;
     const double cm = 1.001 * it.mv_colmax;
     if (check) {
-        const int row = blockIdx.x * rows_per_wg + (int)threadIdx.x;
+        const int row = blockIdx.y * rows_per_wg + (int)threadIdx.x;
         const bool need = (int)threadIdx.x < rows_per_wg && row < m && !((double)gld(it.keys + row) * cm <= lim);
         if (!__syncthreads_or(need)) return;
     }
@@ -2311,7 +2311,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, It
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll 1
     for (int pp = 0; pp < PPW; ++pp) {
-        const int row0 = blockIdx.x * rows_per_wg + (pp * INTERP_WAVES + wave) * 16;
+        const int row0 = blockIdx.y * rows_per_wg + (pp * INTERP_WAVES + wave) * 16;
         if (row0 >= m) break;
         const int li = lane & 15, lk = lane >> 4;
         if (check) {
@@ -2426,7 +2426,7 @@ __global__ __launch_bounds__(256) void k_finish(Item *items, ItemList work, int 
 // M_k = sum_i core_k[:, i, :] (the quadrature weights eta_k are applied on the host).
 __global__ __launch_bounds__(256) void k_core_sum(Item *items, ItemList work, int t, int dir, int mode)
 {
-    const int item = work.item(blockIdx.y);
+    const int item = work.item(blockIdx.x);
     if (!work.active[item]) return;
     Item &it = items[item];
     int k;
@@ -2437,7 +2437,7 @@ __global__ __launch_bounds__(256) void k_core_sum(Item *items, ItemList work, in
         k = dir == 0 ? it.d - 1 : 0;
     }
     const int a_n = it.crow[k], b_n = it.ccol[k], N = it.N, R = it.R;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = blockIdx.y * blockDim.x + threadIdx.x;
     if (e >= a_n * b_n) return;
     const int a = e / b_n, b = e % b_n;
     const cplx *col = it.cores + (size_t)k * R * N * R + (size_t)a * N * b_n + b;
