@@ -1466,7 +1466,8 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, ItemList wor
 // ------------------------------------------------------------------ basis of the kept columns
 // Y = F[:, perm[:r]] R2^{-1} on the FP64 matrix cores, laid out as in k_interp (a wave forms a
 // 16-row panel as up to four 16 x 16 complex tiles, three real MFMA products each); the
-// triangular inverse is held in LDS with its zero lower part. Each row's squared norm goes to
+// triangular inverse is held in LDS with its zero lower part, and output tile q takes only the
+// k-steps of rows k < 16 (q + 1). Each row's squared norm goes to
 // its key (the start of maxvol reads them).
 // PANEL_WAVES waves per workgroup (8 or 16) and PPW 16-row panels per wave (1 or 2): a launch
 // tuning that leaves every result bit unchanged (a row's product does not depend on the workgroup
@@ -1507,18 +1508,23 @@ __global__ __launch_bounds__(64 * PANEL_WAVES, 4) void k_basis(Item *items, Item
         const int arow = row0 + li;
         // the left operand of the next k-step is loaded while this one's products run
         cplx an = (arow < m && lk < r) ? gld(it.F + (size_t)arow * nc + pm[lk]) : cplx{0.0, 0.0};
-        for (int k0 = 0; k0 < r; k0 += 4) {
-            const int kk = k0 + lk;
-            const cplx a = an;
-            if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? gld(it.F + (size_t)arow * nc + pm[kk + 4]) : cplx{0.0, 0.0};
+        // k-steps by 16-row blocks kb of R2^-1: block kb meets only the tiles q >= kb
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q >= ntile) break;
-                const int jj = 16 * q + li;
-                const cplx b = (kk < r && jj < r) ? Ri[kk * r + jj] : cplx{0.0, 0.0};
-                prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
-                pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
-                pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+        for (int kb = 0; kb < 4; ++kb) {
+            if (kb >= ntile) break;
+            for (int k0 = 16 * kb; k0 < min(r, 16 * kb + 16); k0 += 4) {
+                const int kk = k0 + lk;
+                const cplx a = an;
+                if (k0 + 4 < r) an = (arow < m && kk + 4 < r) ? gld(it.F + (size_t)arow * nc + pm[kk + 4]) : cplx{0.0, 0.0};
+#pragma unroll
+                for (int q = kb; q < 4; ++q) {
+                    if (q >= ntile) break;
+                    const int jj = 16 * q + li;
+                    const cplx b = (kk < r && jj < r) ? Ri[kk * r + jj] : cplx{0.0, 0.0};
+                    prr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr[q], 0, 0, 0);
+                    pii[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii[q], 0, 0, 0);
+                    pss[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, pss[q], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
