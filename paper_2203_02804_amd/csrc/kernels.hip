@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256) void k_fiber(Item *items, ItemList work, int t
         cplx v = cmul(cexp_(ex), cmul(H, htab[i]));
         if (strip) v = cmul(v, strip_joint(d, cadd(zrest, zk)));
         const size_t row = (dir == 0) ? (size_t)g * N + i : (size_t)i * ng + g;
-        out[row * nc + c] = v;
+        gst(out + row * nc + c, v);
     }
 }
 
@@ -1778,7 +1778,7 @@ __device__ void block_times_inverse(const cplx *Y, const int *cand, int Kc, int 
         const cplx *y = Y + (size_t)cand[min(arow, Kc - 1)] * r;
         for (int k0 = 0; k0 < r; k0 += 4) {
             const int kk = k0 + lk;
-            const cplx a = (arow < Kc && kk < r) ? y[kk] : cplx{0.0, 0.0};
+            const cplx a = (arow < Kc && kk < r) ? gld(y + kk) : cplx{0.0, 0.0};
             const cplx b = (kk < r && jj < r) ? Ai[kk * r + jj] : cplx{0.0, 0.0};
             prr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, prr, 0, 0, 0);
             pii = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, pii, 0, 0, 0);
@@ -1787,7 +1787,7 @@ __device__ void block_times_inverse(const cplx *Y, const int *cand, int Kc, int 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = g0 + lk + 4 * v;
-            if (row < Kc && jj < r) Bc[(size_t)row * r + jj] = {prr[v] - pii[v], pss[v] - prr[v] - pii[v]};
+            if (row < Kc && jj < r) gst(Bc + (size_t)row * r + jj, cplx{prr[v] - pii[v], pss[v] - prr[v] - pii[v]});
         }
     }
 }
@@ -1806,20 +1806,20 @@ __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, do
     // the entry of largest modulus; after each swap it is found in the update pass itself
     ArgMax a = {-1.0, 0x7fffffff};
     for (long long e = threadIdx.x; e < tot; e += nthr) {
-        const double v = cabs2(Bc[e]);
+        const double v = cabs2(gld(Bc + e));
         a = better(a, ArgMax{v <= 1e300 ? v : -1.0, (int)e});
     }
     a = block_argmax(a, red);
     while (swaps < maxit) {
         if (!(a.v > lim) || a.i < 0 || a.i >= tot) break;
         const int qs = a.i / r, js = a.i % r;
-        const cplx b = Bc[(size_t)qs * r + js];
+        const cplx b = gld(Bc + (size_t)qs * r + js);
         for (int c = threadIdx.x; c < r; c += nthr) {
-            cplx w = Bc[(size_t)qs * r + c];
+            cplx w = gld(Bc + (size_t)qs * r + c);
             if (c == js) w.x -= 1.0;
             prow[c] = w;
         }
-        for (int q = threadIdx.x; q < Kc; q += nthr) colv[q] = cdiv(Bc[(size_t)q * r + js], b);
+        for (int q = threadIdx.x; q < Kc; q += nthr) colv[q] = cdiv(gld(Bc + (size_t)q * r + js), b);
         if (Ai)
             for (int i = threadIdx.x; i < r; i += nthr) acol[i] = cdiv(Ai[i * r + js], b);
         if (threadIdx.x == 0) piv[js] = cand[qs];
@@ -1827,8 +1827,8 @@ __device__ int swap_block(cplx *Bc, int Kc, int r, const int *cand, int *piv, do
         ArgMax an = {-1.0, 0x7fffffff};
         for (long long e = threadIdx.x; e < tot; e += nthr) {
             const int q = (int)(e / r), c = (int)(e % r);
-            const cplx v = csub(Bc[e], cmul(colv[q], prow[c]));
-            Bc[e] = v;
+            const cplx v = csub(gld(Bc + e), cmul(colv[q], prow[c]));
+            gst(Bc + e, v);
             const double v2 = cabs2(v);
             an = better(an, ArgMax{v2 <= 1e300 ? v2 : -1.0, (int)e});
         }
