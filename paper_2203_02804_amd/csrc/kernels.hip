@@ -1352,7 +1352,6 @@ __global__ __launch_bounds__(64 * XF_WAVES) void k_xform(Item *items, ItemList w
 __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, ItemList work, int t, int dir, int BR, int G)
 {
     __shared__ cplx A[MAXNC * (MAXNC | 1)];
-    __shared__ cplx Ri[TTFP_MAX_RANK * TTFP_MAX_RANK];
     __shared__ double nrm[MAXNC];
     __shared__ double tauq[MAXNC];
     __shared__ int perm[MAXNC];
@@ -1442,23 +1441,29 @@ __global__ __launch_bounds__(QRCP_THREADS) void k_qrcp(Item *items, ItemList wor
     }
     __syncthreads();
     const int r = shi[1];
-    // inverse of the leading r x r block of the pivoted factor (columns by back substitution)
+    // inverse of the leading r x r block of the pivoted factor (columns by back substitution).
+    // The reflectors below the diagonal are no longer needed: entry (i, c), i <= c, of the inverse
+    // is kept transposed at row c + 1, column i of A (c + 1 <= r <= MAXNC - 1 when r < nc, and
+    // r <= 64 < nc otherwise), clear of the strict upper triangle that the substitution reads, so
+    // that the kernel's LDS leaves room for two workgroups per CU.
     for (int c = threadIdx.x; c < r; c += blockDim.x) {
+        cplx *X = A + (c + 1) * ncp;               // column c of the inverse: X[i] = (R^-1)_{ic}
         cplx rcc = alph[c];
-        Ri[c * r + c] = (rcc.x == 0.0 && rcc.y == 0.0) ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, rcc);
+        X[c] = (rcc.x == 0.0 && rcc.y == 0.0) ? cplx{0.0, 0.0} : cdiv({1.0, 0.0}, rcc);
         for (int i = c - 1; i >= 0; --i) {
             cplx acc = {0.0, 0.0};
-            for (int l = i + 1; l <= c; ++l) {
-                cplx ril = (l == i) ? alph[i] : A[i * ncp + l];
-                acc = cadd(acc, cmul(ril, Ri[l * r + c]));
-            }
+            for (int l = i + 1; l <= c; ++l) acc = cadd(acc, cmul(A[i * ncp + l], X[l]));
             cplx rii = alph[i];
-            Ri[i * r + c] = (rii.x == 0.0 && rii.y == 0.0) ? cplx{0.0, 0.0} : cplx{-cdiv(acc, rii).x, -cdiv(acc, rii).y};
+            X[i] = (rii.x == 0.0 && rii.y == 0.0) ? cplx{0.0, 0.0} : cplx{-cdiv(acc, rii).x, -cdiv(acc, rii).y};
         }
-        for (int i = c + 1; i < r; ++i) Ri[i * r + c] = {0.0, 0.0};
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < r * r; e += blockDim.x) it.Rinv[e] = Ri[e];
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+        const int i = e / r, c = e - i * r;
+        cplx v = {0.0, 0.0};
+        if (i <= c) v = A[(c + 1) * ncp + i];
+        it.Rinv[e] = v;
+    }
     for (int c = threadIdx.x; c < r; c += blockDim.x) it.perm[c] = perm[c];
     if (threadIdx.x == 0) it.rsel = r;
 }
