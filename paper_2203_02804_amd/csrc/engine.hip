@@ -26,7 +26,8 @@ __global__ void k_chol(Item *items, ItemList work, int t, int dir, int pass, int
 __global__ void k_xform(Item *items, ItemList work, int t, int dir, int pass);
 template <int W, int P> __global__ void k_basis(Item *items, ItemList work, int t, int dir);
 __global__ void k_maxvol(Item *items, ItemList work, int t, int dir, int rmax, int warm);
-__global__ void k_maxvol_refine(Item *items, ItemList work, int t, int dir, int rmax);
+__global__ void k_maxvol_refine(Item *items, ItemList work, int t, int dir, int rmax, int *moved);
+__global__ void k_clear_moved(int *moved);
 template <int W, int P> __global__ void k_interp(Item *items, ItemList work, int t, int dir, int mode, int bound);
 __global__ void k_finish(Item *items, ItemList work, int t, int dir);
 __global__ void k_core_sum(Item *items, ItemList work, int t, int dir, int mode);
@@ -83,6 +84,10 @@ struct ttfp_ctx {
     int *h_act = nullptr;
     int *h_list = nullptr;
     size_t list_cap = 0;
+    // the items whose pivots moved in a refinement round (length first, list_cap entries after),
+    // which the next checking pass takes as its item list; used where the item lists are
+    int *d_moved = nullptr;
+    bool use_moved = false;
     // allocation-free mode (ttfp_price_batch_noalloc): this device's static scratch array
     char *scratch = nullptr;
     bool noalloc = false;
@@ -551,7 +556,10 @@ template <int W, int P>
 void launch_interp_t(hipStream_t st, Item *it, ItemList act, long long rows, unsigned ny, int t, int dir, int mode,
                      int bound)
 {
-    hipLaunchKernelGGL((k_interp<W, P>), dim3(ny, cdivu(rows, 16 * W * P)), dim3(64 * W), 0, st, it, act, t, dir, mode,
+    // item-major, except over a list of moved items with a device-side length (block-major: the
+    // blocks past its length come last)
+    const unsigned nb = cdivu(rows, 16 * W * P);
+    hipLaunchKernelGGL((k_interp<W, P>), act.count ? dim3(nb, ny) : dim3(ny, nb), dim3(64 * W), 0, st, it, act, t, dir, mode,
                        bound);
 }
 void launch_interp(const ttfp_ctx *ctx, hipStream_t st, Item *it, ItemList act, long long rows, unsigned ny, int t, int dir,
@@ -573,17 +581,20 @@ bool ensure_lists(ttfp_ctx *ctx, size_t n)
     if (ctx->h_act) (void)hipHostFree(ctx->h_act);
     if (ctx->h_list) (void)hipHostFree(ctx->h_list);
     if (ctx->d_list) (void)hipFree(ctx->d_list);
-    ctx->h_act = ctx->h_list = ctx->d_list = nullptr;
+    if (ctx->d_moved) (void)hipFree(ctx->d_moved);
+    ctx->h_act = ctx->h_list = ctx->d_list = ctx->d_moved = nullptr;
     ctx->list_cap = 0;
     const size_t cap = std::max(n, (size_t)64);
     if (hipHostMalloc((void **)&ctx->h_act, 2 * cap * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_list, 2 * cap * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void **)&ctx->d_list, cap * sizeof(int)) != hipSuccess) {
+        hipMalloc((void **)&ctx->d_list, cap * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&ctx->d_moved, (cap + 1) * sizeof(int)) != hipSuccess) {
         (void)hipGetLastError();
         if (ctx->h_act) (void)hipHostFree(ctx->h_act);
         if (ctx->h_list) (void)hipHostFree(ctx->h_list);
         if (ctx->d_list) (void)hipFree(ctx->d_list);
-        ctx->h_act = ctx->h_list = ctx->d_list = nullptr;
+        if (ctx->d_moved) (void)hipFree(ctx->d_moved);
+        ctx->h_act = ctx->h_list = ctx->d_list = ctx->d_moved = nullptr;
         return false;
     }
     ctx->list_cap = cap;
@@ -627,15 +638,20 @@ int launch_step(ttfp_ctx *ctx, const Launch &g, ItemList act, unsigned ny, int t
     // checking passes of the interpolation matrix over every row, each followed by a refinement
     // round (both return at once for an item whose rows all satisfy the dominance bound), then the
     // pass that stores B
+    // (with the moved-item list, a checking pass after a refinement round runs over the items
+    // whose pivots that round moved)
+    int *moved = ctx->use_moved ? ctx->d_moved : nullptr;
     for (int round = 0; round < ctx->tune_maxvol_rounds; ++round) {
         {
             ProfScope ps(ctx, TTFP_KERNEL_INTERP);
-            launch_interp(ctx, st, it, act, rows, ny, t, dir, round > 0 ? 1 : 0);
+            const ItemList w = round > 0 && moved ? ItemList(act.active, moved + 1, moved) : act;
+            launch_interp(ctx, st, it, w, rows, ny, t, dir, round > 0 ? 1 : 0);
         }
         ProfScope ps(ctx, TTFP_KERNEL_REFINE);
         const int rm = std::max(g.maxR, 2);
         const size_t lds = (size_t)rm * rm * sizeof(cplx);
-        hipLaunchKernelGGL(k_maxvol_refine, dim3(ny), dim3(MAXVOL_THREADS), lds, st, it, act, t, dir, rm);
+        if (moved) hipLaunchKernelGGL(k_clear_moved, dim3(1), dim3(64), 0, st, moved);
+        hipLaunchKernelGGL(k_maxvol_refine, dim3(ny), dim3(MAXVOL_THREADS), lds, st, it, act, t, dir, rm, moved);
     }
     {
         ProfScope ps(ctx, TTFP_KERNEL_INTERP);
@@ -766,6 +782,7 @@ int run_batch(ttfp_ctx *ctx, Batch &b, const std::vector<const ttfp_grid *> &gri
     } graphs;
     const bool use_graph = ctx->tune_graph && ctx->stream != nullptr && !ctx->noalloc && !ctx->prof;
     const bool compact = !use_graph && !ctx->noalloc && ensure_lists(ctx, (size_t)n_items);
+    ctx->use_moved = compact;
     // Half sweeps are queued back to back; after queueing half h the host waits for the flag
     // of half h - 1 (copied into pinned memory behind it), so one half sweep stays queued while
     // the host decides, and the run ends when no option was active after a half sweep.
@@ -1093,6 +1110,7 @@ int ttfp_destroy(ttfp_ctx *ctx)
     if (ctx->h_act) (void)hipHostFree(ctx->h_act);
     if (ctx->h_list) (void)hipHostFree(ctx->h_list);
     if (ctx->d_list) (void)hipFree(ctx->d_list);
+    if (ctx->d_moved) (void)hipFree(ctx->d_moved);
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->d_items) (void)hipFree(ctx->d_items);
     if (ctx->d_active) (void)hipFree(ctx->d_active);
@@ -1756,7 +1774,7 @@ int ttfp_maxvol(ttfp_ctx *ctx, int32_t m, int32_t r, const double *A, double del
         // once when none violates)
         for (int round = 0; round < 8; ++round) {
             launch_interp(ctx, ctx->stream, dit, act, m, 1, 0, 2, round > 0 ? 1 : 0);
-            hipLaunchKernelGGL(k_maxvol_refine, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm);
+            hipLaunchKernelGGL(k_maxvol_refine, dim3(1), dim3(th), lds, ctx->stream, dit, act, 0, 2, rm, (int *)nullptr);
         }
         launch_interp(ctx, ctx->stream, dit, act, m, 1, 0, 2, 2);
         e = hipGetLastError();

@@ -97,11 +97,13 @@ struct OptState {
 // b when the launch has no list; an item whose activity flag is 0 returns at once. The half sweeps
 // launch over the items that were still active a little earlier (the flags only ever turn off), so
 // that finished options cost no workgroups.
+// A list may also carry a device-side length (count): block b >= *count then has no item (-1).
 struct ItemList {
     const int *active;
     const int *list;
-    __host__ __device__ ItemList(const int *a, const int *l = nullptr) : active(a), list(l) {}
-    __device__ int item(int b) const { return list ? list[b] : b; }
+    const int *count;
+    __host__ __device__ ItemList(const int *a, const int *l = nullptr, const int *n = nullptr) : active(a), list(l), count(n) {}
+    __device__ int item(int b) const { return list ? (count && b >= *count ? -1 : list[b]) : b; }
 };
 
 // Step addressing: dir 0 = left-to-right (core k = t), dir 1 = right-to-left (core k = d-1-t).

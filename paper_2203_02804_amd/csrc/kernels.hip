@@ -2209,7 +2209,7 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol(Item *items, ItemList work, 
 
 // Refinement round: the pivots and up to MV_KMAX - r rows that k_interp found violating (largest
 // first) form the block; swaps as in k_maxvol. Returns at once when no row violated.
-__global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, ItemList work, int t, int dir, int rmax)
+__global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, ItemList work, int t, int dir, int rmax, int *moved)
 {
     extern __shared__ cplx Abuf[];
     cplx *Ai = Abuf;                                 // rmax^2 entries
@@ -2275,8 +2275,15 @@ __global__ __launch_bounds__(1024, 8) void k_maxvol_refine(Item *items, ItemList
         it.mv_iters += swaps;
         it.mv_viol = 0;
         it.mv_dirty = swaps > 0;
+        if (swaps > 0 && moved) moved[1 + atomicAdd(moved, 1)] = item;
         it.work[TTFP_KERNEL_REFINE] += 8.0 * (Kc + r) * (double)r * swaps + (swaps > MV_SM_MAX ? 8.0 * (double)r * r * r : 0.0);
     }
+}
+
+// Empties the list of items whose pivots moved (its length in moved[0]) before a refinement round.
+__global__ void k_clear_moved(int *moved)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) moved[0] = 0;
 }
 
 // B = Y A^{-1} for every row on the FP64 matrix cores: a wave forms a 16-row panel of B (all r
@@ -2296,8 +2303,11 @@ template <int INTERP_WAVES, int PPW>
 __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, ItemList work, int t, int dir, int mode, int bound)
 {
     __shared__ cplx Ai[TTFP_MAX_RANK * TTFP_MAX_RANK];
-    const int item = work.item(blockIdx.x);
-    if (!work.active[item]) return;
+    // a checking pass over the items whose pivots moved (a list with a device-side length) runs in
+    // block-major order, so that the blocks past the list's length come at the end of the launch
+    const bool moved_list = work.count != nullptr;
+    const int item = work.item(moved_list ? blockIdx.y : blockIdx.x), wblk = moved_list ? blockIdx.x : blockIdx.y;
+    if (item < 0 || !work.active[item]) return;
     Item &it = items[item];
     StepShape s = step_shape(it, t, dir, 0);
     if (!s.valid) return;
@@ -2305,7 +2315,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, It
     const bool store = mode == 2;
     const int r = it.rsel, m = s.rows;
     const int rows_per_wg = 16 * INTERP_WAVES * PPW;
-    if (blockIdx.y * rows_per_wg >= m) return;
+    if (wblk * rows_per_wg >= m) return;
     const double lim = (1.0 + it.delta) * (1.0 + it.delta);
     // A checking pass skips the rows that cannot violate: |B_ij|^2 <= |y_i|^2 max_j |A^{-1} e_j|^2
     // (the row norms from k_basis, held as floats: the margin covers their rounding). A workgroup
@@ -2313,7 +2323,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, It
     const bool check = !store && dir != 2 && bound;
     const double cm = 1.001 * it.mv_colmax;
     if (check) {
-        const int row = blockIdx.y * rows_per_wg + (int)threadIdx.x;
+        const int row = wblk * rows_per_wg + (int)threadIdx.x;
         const bool need = (int)threadIdx.x < rows_per_wg && row < m && !((double)gld(it.keys + row) * cm <= lim);
         if (!__syncthreads_or(need)) return;
     }
@@ -2322,7 +2332,7 @@ __global__ __launch_bounds__(64 * INTERP_WAVES, 4) void k_interp(Item *items, It
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll 1
     for (int pp = 0; pp < PPW; ++pp) {
-        const int row0 = blockIdx.y * rows_per_wg + (pp * INTERP_WAVES + wave) * 16;
+        const int row0 = wblk * rows_per_wg + (pp * INTERP_WAVES + wave) * 16;
         if (row0 >= m) break;
         const int li = lane & 15, lk = lane >> 4;
         if (check) {
